@@ -1,0 +1,303 @@
+"""Pins for the oracle: each function checks one part of the oracle against
+something the paper or the mathematics fixes independently of it, and
+raises AssertionError when the oracle disagrees.
+
+test_oracle_pins.py asserts that they all pass; test_oracle_planted.py
+plants plausible mistakes in the oracle and asserts that each one makes at
+least one pin fail.
+"""
+
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import scipy.integrate as si
+import scipy.special as ss
+
+import synth
+from conftest import load_golden
+from oracle import coefficients as C
+from oracle import dense as D
+from oracle import errors as E
+from oracle import propagation as PR
+from oracle import truncation as T
+
+GP_CASES = [("ppr", 0.2), ("ppr", 0.05), ("ppr", 0.5), ("hkpr", 0.7), ("hkpr", 5.0), ("hkpr", 12.0)]
+
+
+def tiny_graphs():
+    """Small graphs with varied spectra: irregular, bipartite, long-diameter."""
+    return [
+        synth.erdos_renyi(40, 0.15, seed=3),
+        synth.barbell_with_tail(6, 5),
+        synth.star(7),
+        synth.path(9),
+        synth.erdos_renyi(120, 0.05, seed=11),
+    ]
+
+
+def _connected_node(g, seed=0):
+    deg = g.degrees
+    return int(np.flatnonzero(deg > 0)[seed % int(np.sum(deg > 0))])
+
+
+# ---------------------------------------------------------------- recurrence
+
+
+def pin_star_example():
+    """Sec. 4.2 worked example (tests/golden/star_example.txt)."""
+    gold = load_golden("star_example.txt")
+    g = synth.star(3)
+    P = PR.transition_matrix(g.row_ptr, g.col_idx)
+    r = PR.chebyshev_vectors(P, 1, 3)
+    np.testing.assert_allclose(-r[0], gold["minus_T0"], atol=1e-15)
+    np.testing.assert_allclose(r[1], gold["T1"], atol=1e-15)
+    np.testing.assert_allclose(r[2], gold["T2"], atol=1e-15)
+    np.testing.assert_allclose(r[3], gold["T3"], atol=1e-15)
+
+
+def pin_chebyshev_vectors_eigen():
+    """T_k(P) e_s from the recurrence vs cos(k arccos lambda) on A~'s
+    spectrum (Def. 6 + Lemma 1 proof), irregular graphs."""
+    for g in tiny_graphs():
+        A = D.adjacency(g.row_ptr, g.col_idx)
+        if np.any(A.sum(0) == 0):
+            continue
+        P = PR.transition_matrix(g.row_ptr, g.col_idx)
+        s = _connected_node(g, 5)
+        r = PR.chebyshev_vectors(P, s, 12)
+        for k in range(13):
+            Tk = D.chebyshev_matrix_eigen(A, k)
+            np.testing.assert_allclose(r[k], Tk[:, s], atol=1e-11, err_msg=f"{g.name} k={k}")
+
+
+def pin_mass():
+    """Property 1: sum_u T_k(P) e_s (u) = 1 for every k."""
+    g = synth.chung_lu(3000, 12000, 2.4, seed=5)
+    P = PR.transition_matrix(g.row_ptr, g.col_idx)
+    s = _connected_node(g, 17)
+    _, st = PR.cheby_power(P, s, C.chebyshev_coeffs("ppr", 0.2, 30), 30, stats=True)
+    np.testing.assert_allclose(st["sum_r"], 1.0, atol=1e-10)
+
+
+def pin_cycle_closed_form():
+    """Cycle C_n: P is the circulant (shift + shift^-1)/2 with eigenvalues
+    cos(2 pi j / n); f(P) e_s(u) = (1/n) sum_j f(cos(2 pi j/n)) cos(2 pi j (u-s)/n)."""
+    n = 17
+    g = synth.cycle(n)
+    P = PR.transition_matrix(g.row_ptr, g.col_idx)
+    s = 4
+    for kind, p in [("ppr", 0.15), ("hkpr", 3.0)]:
+        f = C.gp_function(kind, p)
+        j = np.arange(n)
+        u = np.arange(n)
+        exact = (f(np.cos(2 * np.pi * j / n))[None, :] *
+                 np.cos(2 * np.pi * np.outer(u - s, j) / n)).sum(1) / n
+        K = T.choose_K(kind, p, 1e-14, mode="tail")
+        y = PR.cheby_power(P, s, C.chebyshev_coeffs(kind, p, K), K)
+        np.testing.assert_allclose(y, exact, atol=1e-13)
+
+
+def pin_complete_closed_form():
+    """K_n: P = (J - I)/(n-1), eigenvalue 1 on the constant vector and
+    -1/(n-1) elsewhere: f(P) e_s = f(1)/n 1 + f(-1/(n-1)) (e_s - 1/n)."""
+    n = 9
+    g = synth.complete(n)
+    P = PR.transition_matrix(g.row_ptr, g.col_idx)
+    s = 2
+    for kind, p in [("ppr", 0.3), ("hkpr", 2.0)]:
+        f = C.gp_function(kind, p)
+        e = np.zeros(n)
+        e[s] = 1.0
+        exact = f(1.0) / n + f(-1.0 / (n - 1)) * (e - 1.0 / n)
+        K = T.choose_K(kind, p, 1e-14, mode="tail")
+        y = PR.cheby_power(P, s, C.chebyshev_coeffs(kind, p, K), K)
+        np.testing.assert_allclose(y, exact, atol=1e-13)
+
+
+# ---------------------------------------------------------------- coefficients
+
+
+def pin_ppr_closed_values():
+    """Lemma 2 at alpha = 0.2 (tests/golden/ppr_alpha_0_2.txt)."""
+    gold = load_golden("ppr_alpha_0_2.txt")
+    g, b = C.ppr_gamma_beta(0.2)
+    assert abs(g - gold["gamma"][0]) < 1e-15 and abs(b - gold["beta"][0]) < 1e-15
+    np.testing.assert_allclose(C.ppr_chebyshev_coeffs(0.2, 4), gold["c0_to_c4"], rtol=1e-14)
+    c = C.ppr_chebyshev_coeffs(0.2, 200)
+    alt = np.sum(c * (-1.0) ** np.arange(201))
+    assert abs(alt - gold["f_minus_one"][0]) < 1e-14
+
+
+def pin_coefficient_integrals():
+    """Lemma 1's definition integrated numerically in theta = arccos x:
+    c_k = (2/pi) int_0^pi f(cos th) cos(k th) dth (1/pi for k = 0)."""
+    for kind, p in GP_CASES:
+        f = C.gp_function(kind, p)
+        c = C.chebyshev_coeffs(kind, p, 12)
+        for k in range(13):
+            val, _ = si.quad(lambda th: float(f(math.cos(th))) * math.cos(k * th), 0.0, math.pi,
+                             epsabs=1e-14, epsrel=1e-12, limit=400)
+            ref = val * (1.0 if k == 0 else 2.0) / math.pi
+            assert abs(c[k] - ref) <= 1e-12 + 1e-10 * abs(ref), (kind, p, k, c[k], ref)
+
+
+def pin_hkpr_library():
+    """Lemma 3 vs scipy's exponentially scaled Bessel function ive."""
+    for t in (0.3, 1.0, 5.0, 10.0, 30.0):
+        c = C.hkpr_chebyshev_coeffs(t, 60)
+        ref = np.r_[ss.ive(0, t), 2.0 * ss.ive(np.arange(1, 61), t)]
+        np.testing.assert_allclose(c, ref, atol=2e-15, rtol=1e-12)
+
+
+def pin_coefficient_sums():
+    """f(1) = 1 (coefficients sum to one, Lemma 4 proof) and
+    sum (-1)^k c_k = f(-1) (T_k(-1) = (-1)^k)."""
+    for kind, p in GP_CASES:
+        f = C.gp_function(kind, p)
+        K = T.choose_K(kind, p, 1e-14, mode="tail") + 10
+        c = C.chebyshev_coeffs(kind, p, K)
+        assert abs(c.sum() - 1.0) < 1e-13, (kind, p, c.sum())
+        assert abs(np.sum(c * (-1.0) ** np.arange(K + 1)) - float(f(-1.0))) < 1e-13
+
+
+def pin_expansion_pointwise():
+    """Lemma 1: |f(l) - sum_{k<=K} c_k T_k(l)| <= tail(K) on [-1, 1], with
+    T_k(l) = cos(k arccos l) (Def. 6 closed form, not the recurrence)."""
+    lam = np.linspace(-1.0, 1.0, 201)
+    for kind, p in GP_CASES:
+        f = C.gp_function(kind, p)
+        tails = T.chebyshev_tails(kind, p, 40)
+        c = C.chebyshev_coeffs(kind, p, 40)
+        for K in (1, 2, 5, 10, 20, 40):
+            approx = sum(c[k] * np.cos(k * np.arccos(lam)) for k in range(K + 1))
+            err = np.max(np.abs(f(lam) - approx))
+            assert err <= tails[K] * (1 + 1e-9) + 1e-14, (kind, p, K, err, tails[K])
+
+
+def pin_taylor_sums():
+    """Def. 3 / Def. 4 Taylor coefficients sum to f(1) = 1."""
+    for kind, p in GP_CASES:
+        N = T.pwmethod_steps(kind, p, 1e-16)
+        z = C.taylor_coeffs(kind, p, N + 50)
+        assert abs(z.sum() - 1.0) < 1e-13
+
+
+# ---------------------------------------------------------------- results
+
+
+def pin_dense_definitions():
+    """ChebyPower (Alg. 3) at a K whose tail is 1e-14 vs the definitions:
+    dense inverse (Def. 3), expm (Def. 4), eigen route (Lemma 1)."""
+    for g in tiny_graphs():
+        A = D.adjacency(g.row_ptr, g.col_idx)
+        P = PR.transition_matrix(g.row_ptr, g.col_idx)
+        s = _connected_node(g, 3)
+        for kind, p in GP_CASES:
+            L = T.certified_multiplier(g.nnz, g.degrees[s])
+            K = T.choose_K(kind, p, 1e-13, mode="certified", vol=g.nnz, d_s=g.degrees[s])
+            y = PR.cheby_power(P, s, C.chebyshev_coeffs(kind, p, K), K)
+            ref = D.ppr_solve(A, s, p) if kind == "ppr" else D.hkpr_expm(A, s, p)
+            eig = D.matrix_function_eigen(A, s, C.gp_function(kind, p))
+            assert E.l1(y, ref) < 1e-12, (g.name, kind, p, E.l1(y, ref))
+            assert E.l1(eig, ref) < 1e-11, (g.name, kind, p)
+            assert L >= 1.0
+
+
+def pin_truncated_series_eigen():
+    """y^_K of Alg. 3 equals sum_{k<=K} c_k T_k(P) e_s, formed on A~'s
+    spectrum with T_k(l) = cos(k arccos l), for every small K."""
+    for g in tiny_graphs()[:3]:
+        A = D.adjacency(g.row_ptr, g.col_idx)
+        P = PR.transition_matrix(g.row_ptr, g.col_idx)
+        s = _connected_node(g, 1)
+        for kind, p in [("ppr", 0.2), ("hkpr", 5.0)]:
+            for K in range(1, 9):
+                c = C.chebyshev_coeffs(kind, p, K)
+                pK = lambda lam, c=c, K=K: sum(c[k] * np.cos(k * np.arccos(lam)) for k in range(K + 1))
+                ref = D.matrix_function_eigen(A, s, pK)
+                y = PR.cheby_power(P, s, c, K)
+                np.testing.assert_allclose(y, ref, atol=1e-12, err_msg=f"{g.name} {kind} K={K}")
+
+
+def pin_pwmethod_exact_tail():
+    """Alg. 1 after N terms misses exactly sum_{k>=N} zeta_k in l1."""
+    g = synth.erdos_renyi(60, 0.12, seed=8)
+    A = D.adjacency(g.row_ptr, g.col_idx)
+    P = PR.transition_matrix(g.row_ptr, g.col_idx)
+    s = _connected_node(g, 2)
+    for kind, p in [("ppr", 0.2), ("hkpr", 4.0)]:
+        ref = D.ppr_solve(A, s, p) if kind == "ppr" else D.hkpr_expm(A, s, p)
+        for N in (3, 10, 25):
+            y = PR.power_method(P, s, C.taylor_coeffs(kind, p, N), N)
+            tail = T.taylor_tail(kind, p, N)
+            assert abs(E.l1(y, ref) - tail) <= 1e-12 + 1e-9 * tail, (kind, N, E.l1(y, ref), tail)
+            assert np.all(ref - y >= -1e-14)
+
+
+def pin_certified_bound_and_certificate():
+    """||y - y^_K||_1 <= sqrt(vol/d_s) tail(K) for all K, and the PPR
+    fixed-point certificate bounds the true l1 error from above."""
+    g = synth.chung_lu(2000, 9000, 2.3, seed=21)
+    P = PR.transition_matrix(g.row_ptr, g.col_idx)
+    s = _connected_node(g, 40)
+    for kind, p in [("ppr", 0.2), ("hkpr", 5.0)]:
+        ref = PR.ground_truth(P, s, kind, p)
+        tails = T.chebyshev_tails(kind, p, 40)
+        L = T.certified_multiplier(g.nnz, g.degrees[s])
+        for K in (2, 5, 10, 20, 30):
+            y = PR.cheby_power(P, s, C.chebyshev_coeffs(kind, p, K), K)
+            err = E.l1(y, ref)
+            assert err <= L * tails[K] + 1e-13, (kind, K, err, L * tails[K])
+            if kind == "ppr":
+                cert = E.ppr_certificate(P, s, p, y)
+                assert cert >= err * (1 - 1e-9) - 1e-15, (K, cert, err)
+
+
+def pin_convergence_rate():
+    """Lemma 4: l1 error falls like beta^K.  On a bipartite graph
+    (eigenvalue -1 present) the error after K terms is dominated by
+    c_{K+1} T_{K+1}(-1), so log(err) has slope log(beta) in K."""
+    g = synth.star(5)
+    P = PR.transition_matrix(g.row_ptr, g.col_idx)
+    A = D.adjacency(g.row_ptr, g.col_idx)
+    s = 2
+    for alpha in (0.2, 0.05):
+        ref = D.ppr_solve(A, s, alpha)
+        _, beta = C.ppr_gamma_beta(alpha)
+        Ks = np.arange(6, 30, 2)
+        errs = [E.l1(PR.cheby_power(P, s, C.ppr_chebyshev_coeffs(alpha, K), K), ref) for K in Ks]
+        slope = np.polyfit(Ks, np.log(errs), 1)[0]
+        assert abs(slope - math.log(beta)) < 0.05 * abs(math.log(beta)), (alpha, slope, math.log(beta))
+
+
+ALL_PINS = [
+    pin_star_example,
+    pin_chebyshev_vectors_eigen,
+    pin_mass,
+    pin_cycle_closed_form,
+    pin_complete_closed_form,
+    pin_ppr_closed_values,
+    pin_coefficient_integrals,
+    pin_hkpr_library,
+    pin_coefficient_sums,
+    pin_expansion_pointwise,
+    pin_taylor_sums,
+    pin_dense_definitions,
+    pin_truncated_series_eigen,
+    pin_pwmethod_exact_tail,
+    pin_certified_bound_and_certificate,
+    pin_convergence_rate,
+]
+
+
+def failing_pins(pins=None):
+    """Names of the pins that raise AssertionError (or any error)."""
+    bad = []
+    for fn in pins or ALL_PINS:
+        try:
+            fn()
+        except Exception:  # noqa: BLE001 - a planted mistake may break in any way
+            bad.append(fn.__name__)
+    return bad

@@ -1,0 +1,85 @@
+"""Plausible mistakes planted in the oracle (on the CPU) must each make at
+least one pin fail, so that the pins are known to constrain the oracle."""
+
+import numpy as np
+import pytest
+
+import pins
+from oracle import coefficients as C
+from oracle import propagation as PR
+
+
+def _wrong_sign_step(P, r_k, r_km1):
+    return 2.0 * (P @ r_k) + r_km1
+
+
+def _missing_factor_two_step(P, r_k, r_km1):
+    return (P @ r_k) - r_km1
+
+
+def _row_stochastic(row_ptr, col_idx):
+    # D^{-1} A instead of A D^{-1}: the transposed random-walk matrix
+    P = PR.__dict__["_orig_transition_matrix"](row_ptr, col_idx)
+    return P.T.tocsr()
+
+
+def _ppr_without_two(alpha, K):
+    gamma, beta = C.ppr_gamma_beta(alpha)
+    return np.array([gamma] + [gamma * beta**k for k in range(1, K + 1)])
+
+
+def _ppr_shifted(alpha, K):
+    gamma, beta = C.ppr_gamma_beta(alpha)
+    return np.array([gamma] + [2 * gamma * beta ** (k + 1) for k in range(1, K + 1)])
+
+
+def _hkpr_shifted(t, K):
+    i = C.scaled_bessel_I(t, K + 1)
+    c = 2.0 * i[1:]
+    c[0] = i[0]
+    return c
+
+
+def _cheby_power_drop_last(P, s, c, K, stats=False):
+    c = np.array(c, dtype=np.float64)
+    c[K] = 0.0
+    return PR.__dict__["_orig_cheby_power"](P, s, c, K, stats=stats)
+
+
+def _cheby_power_off_by_one(P, s, c, K, stats=False):
+    c = np.array(c, dtype=np.float64)
+    c2 = np.r_[c[0], c[2:], 0.0]
+    return PR.__dict__["_orig_cheby_power"](P, s, c2, K, stats=stats)
+
+
+def _power_method_extra_step(P, s, zeta, N):
+    return PR.__dict__["_orig_power_method"](P, s, np.r_[zeta, 0.0][: N + 1] if len(zeta) > N else np.r_[zeta, zeta[-1:]], N + 1)
+
+
+MISTAKES = {
+    "recurrence sign": ("propagation", "_chebyshev_step", _wrong_sign_step),
+    "recurrence factor 2": ("propagation", "_chebyshev_step", _missing_factor_two_step),
+    "transposed P": ("propagation", "transition_matrix", _row_stochastic),
+    "PPR coefficient without 2": ("coefficients", "ppr_chebyshev_coeffs", _ppr_without_two),
+    "PPR coefficient index shift": ("coefficients", "ppr_chebyshev_coeffs", _ppr_shifted),
+    "HKPR Bessel index shift": ("coefficients", "hkpr_chebyshev_coeffs", _hkpr_shifted),
+    "last term c_K r_K dropped": ("propagation", "cheby_power", _cheby_power_drop_last),
+    "coefficient/term off by one": ("propagation", "cheby_power", _cheby_power_off_by_one),
+    "PwMethod extra term": ("propagation", "power_method", _power_method_extra_step),
+}
+
+
+@pytest.mark.parametrize("name", list(MISTAKES))
+def test_planted_mistake_is_caught(name, monkeypatch):
+    import oracle
+
+    modname, attr, fake = MISTAKES[name]
+    mod = getattr(oracle, modname)
+    # keep the real function reachable for wrappers that delegate to it
+    monkeypatch.setitem(PR.__dict__, "_orig_" + attr, getattr(mod, attr))
+    monkeypatch.setattr(mod, attr, fake)
+    if modname == "coefficients" and attr in ("ppr_chebyshev_coeffs", "hkpr_chebyshev_coeffs"):
+        # chebyshev_coeffs dispatches through module globals: patched above
+        pass
+    bad = pins.failing_pins()
+    assert bad, f"planted mistake '{name}' passed every pin"
