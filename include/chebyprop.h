@@ -1,0 +1,176 @@
+/* chebyprop.h - C ABI of the MI355X (gfx950) ChebyPower library.
+ *
+ * Computes graph-propagation vectors y = f(P) e_s on an undirected graph,
+ * P = A D^{-1} (Sec. 2.1, Eq. 1), for
+ *   CP_PPR  : f(x) = alpha / (1 - (1-alpha) x), alpha in (0,1)   (Def. 3)
+ *   CP_HKPR : f(x) = exp(-t (1 - x)),           t > 0            (Def. 4)
+ * by ChebyPower (Alg. 3): the truncated Chebyshev expansion
+ *   y_K = sum_{k=0..K} c_k T_k(P) e_s                            (Lemma 1)
+ * with the closed-form coefficients of Lemma 2 (PPR) and Lemma 3 (HKPR),
+ * evaluated with the three-term recurrence r_{k+1} = 2 P r_k - r_{k-1}
+ * (Eq. 6).
+ *
+ * Conventions for every call
+ *  - Return value: cp_status (CP_OK = 0, errors < 0).  No C++ exception
+ *    crosses the ABI.  After CP_EHIP, cp_last_hip_error() gives the raw
+ *    hipError_t of the failing HIP call (thread-local).
+ *  - Pointers marked "device" are HIP device pointers (e.g. the data_ptr()
+ *    of a torch tensor on the GPU); "host" pointers are ordinary memory.
+ *    The caller owns every buffer it passes; the library never frees them.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    Device work is enqueued on it and is complete when the stream is.
+ *    Calls return without waiting for the GPU unless a query sets
+ *    CP_Q_STATS or CP_Q_TIMING.
+ *  - A cp_graph is immutable after creation; concurrent queries on one
+ *    graph from different streams are allowed as long as each uses its own
+ *    output and workspace buffers.
+ */
+#ifndef CHEBYPROP_H
+#define CHEBYPROP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  CP_OK = 0,
+  CP_EINVAL = -1,     /* bad argument (NULL pointer, size, parameter domain, K < 1) */
+  CP_ESOURCE = -2,    /* source id outside [0, n) */
+  CP_EISOLATED = -3,  /* source has degree 0: P = A D^{-1} is undefined there */
+  CP_ENOMEM = -4,     /* device or host allocation failed */
+  CP_EHIP = -5,       /* a HIP runtime call failed, see cp_last_hip_error() */
+  CP_EKMAX = -6,      /* the tolerance needs more than the allowed number of terms */
+  CP_EBUSY = -7,      /* server: admission refused (HBM budget or queue full) */
+  CP_ECANCELLED = -8, /* server: query was cancelled */
+  CP_ENOTFOUND = -9,  /* server: unknown ticket */
+  CP_EGRAPH = -10,    /* graph validation failed (see cp_graph_create) */
+  CP_EPENDING = -11,  /* server: query not finished yet */
+  CP_EWORKSPACE = -12 /* workspace missing or smaller than cp_workspace_bytes() */
+} cp_status;
+
+typedef enum { CP_PPR = 0, CP_HKPR = 1 } cp_kind;
+
+/* Vector storage precision.  CP_F64: double vectors, double accumulation.
+ * CP_F32: float vectors, float accumulation.  CP_BF16: bfloat16 storage of
+ * the recurrence vectors, float accumulation and float estimate.  Output y
+ * is double for CP_F64 and float otherwise. */
+typedef enum { CP_F64 = 0, CP_F32 = 1, CP_BF16 = 2 } cp_prec;
+
+/* How K is chosen for a tolerance `tol` (Thm. 2 and its l1 reading):
+ *  CP_K_CERTIFIED: smallest K >= 1 with sqrt(vol(G)/d_s) * tail(K) <= tol,
+ *                  tail(K) = sum_{k>K} |c_k|.  Because
+ *                  ||T_k(P) e_s||_1 <= sqrt(vol/d_s), this bounds the l1
+ *                  truncation error by tol.
+ *  CP_K_TAIL:      Thm. 2 as printed: tail(K) <= tol.
+ *  CP_K_PAPER:     the experiments' K = ceil(ln(1/tol)/sqrt(alpha)) for PPR
+ *                  and ceil(sqrt(t) ln(1/tol)) for HKPR (Sec. 6.1, 6.2).
+ *  CP_K_FIXED:     K = K_fixed (must be >= 1). */
+typedef enum { CP_K_CERTIFIED = 0, CP_K_TAIL = 1, CP_K_PAPER = 2, CP_K_FIXED = 3 } cp_kmode;
+
+/* cp_graph_create flags */
+#define CP_GRAPH_BORROW 0x1   /* keep using the caller's CSR buffers (caller keeps
+                                 them alive until cp_graph_destroy); ignored when
+                                 CP_GRAPH_REORDER is set */
+#define CP_GRAPH_VALIDATE 0x2 /* O(nnz) checks: monotone offsets, ids in range, no
+                                 self-loops, no duplicate arcs, symmetry */
+#define CP_GRAPH_REORDER 0x4  /* relabel nodes internally by decreasing degree
+                                 (results are still returned in caller ids) */
+#define CP_GRAPH_HOST 0x8     /* row_ptr / col_idx are host pointers */
+
+/* cp_query.flags */
+#define CP_Q_STATS 0x1  /* after the run, synchronize and fill cp_info.mass */
+#define CP_Q_TIMING 0x2 /* time the run and each Chebyshev step with HIP events
+                           (synchronizes; fills elapsed_ms, step_ms) */
+
+typedef struct cp_graph cp_graph;
+
+typedef struct {
+  int32_t kind;    /* cp_kind */
+  int32_t kmode;   /* cp_kmode */
+  double param;    /* alpha (PPR) or t (HKPR) */
+  double tol;      /* l1 tolerance in (0,1); unused for CP_K_FIXED */
+  int64_t source;  /* s, in the caller's node ids */
+  int32_t K_fixed; /* K for CP_K_FIXED */
+  int32_t flags;   /* CP_Q_* */
+} cp_query;
+
+typedef struct {
+  int32_t K;            /* truncation step used (number of P-products) */
+  int32_t steps;        /* Chebyshev step launches (K - 1) */
+  double tail;          /* sum_{k>K} |c_k| */
+  double tail_bound_l1; /* sqrt(vol/d_s) * tail: bound on the l1 truncation error */
+  double mass;          /* sum_u y(u) (CP_Q_STATS; 1 up to truncation and rounding) */
+  double elapsed_ms;    /* whole query on the device (CP_Q_TIMING) */
+  double step_ms;       /* sum of the Chebyshev step kernels' durations (CP_Q_TIMING) */
+} cp_info;
+
+typedef struct {
+  int64_t n, nnz, d_max;
+  int64_t blocks;       /* work blocks of the step kernel */
+  int64_t long_rows;    /* rows streamed by a whole workgroup */
+  int64_t hub_rows;     /* rows split over several workgroups */
+  int64_t device_bytes; /* graph bytes held in HBM by the library */
+  int32_t reordered;
+  int32_t borrowed;
+} cp_graph_stats;
+
+/* Build a graph from symmetric CSR (Sec. 2.1: undirected, A in {0,1}):
+ * row v lists N(v); d_v = row_ptr[v+1] - row_ptr[v].
+ *   n        nodes (1 <= n < 2^31)
+ *   nnz      arcs = 2 m (row_ptr[n]); int32 column ids
+ *   row_ptr  int64[n+1], device (host with CP_GRAPH_HOST)
+ *   col_idx  int32[nnz], device (host with CP_GRAPH_HOST)
+ *   flags    CP_GRAPH_*
+ * Errors: CP_EINVAL (sizes, NULL), CP_EGRAPH (CP_GRAPH_VALIDATE failed),
+ * CP_ENOMEM, CP_EHIP.  Synchronizes `stream`.  Nodes with degree 0 are
+ * allowed (they are never reached and get y = 0) but cannot be sources. */
+cp_status cp_graph_create(int64_t n, int64_t nnz, const int64_t* row_ptr, const int32_t* col_idx,
+                          int32_t flags, void* stream, cp_graph** out);
+cp_status cp_graph_destroy(cp_graph* g);
+cp_status cp_graph_get_stats(const cp_graph* g, cp_graph_stats* out);
+
+/* Chebyshev coefficients c_0..c_K into host c_out[K+1], FP64
+ * (Lemma 2: c_0 = gamma, c_k = 2 gamma beta^k;
+ *  Lemma 3: c_0 = e^{-t} I_0(t), c_k = 2 e^{-t} I_k(t)).
+ * Pure host code.  Errors: CP_EINVAL. */
+cp_status cp_coeffs(int32_t kind, double param, int32_t K, double* c_out);
+
+/* Truncation step for a tolerance (see cp_kmode); vol = sum of degrees,
+ * d_s = degree of the source (only used by CP_K_CERTIFIED).  Writes K and
+ * tail(K).  Pure host code.  Errors: CP_EINVAL, CP_EKMAX (K > K_max). */
+cp_status cp_choose_K(int32_t kind, double param, double tol, int32_t kmode, int32_t K_fixed,
+                      double vol, double d_s, int32_t K_max, int32_t* K_out, double* tail_out);
+
+/* Device workspace needed by cp_power (nq = 1) or cp_power_batch (nq
+ * queries) at precision `prec`.  Returns 0 for invalid arguments. */
+size_t cp_workspace_bytes(const cp_graph* g, int32_t nq, int32_t prec);
+
+/* One query (Alg. 3): y = sum_{k<=K} c_k T_k(P) e_s.
+ *   y     device, n elements (double for CP_F64, float otherwise), caller ids
+ *   ws    device workspace of at least cp_workspace_bytes(g, 1, prec) bytes,
+ *         256-byte aligned; contents are scratch
+ *   info  host, may be NULL; K/steps/tail fields are valid on return, the
+ *         rest after the stream completes (or on return with CP_Q_STATS /
+ *         CP_Q_TIMING, which synchronize)
+ * Errors: CP_EINVAL, CP_ESOURCE, CP_EISOLATED, CP_EKMAX, CP_EWORKSPACE, CP_EHIP. */
+cp_status cp_power(const cp_graph* g, const cp_query* q, int32_t prec, void* y, void* ws,
+                   size_t ws_bytes, void* stream, cp_info* info);
+
+/* nq queries at once (each with its own kind, parameter, tolerance and K):
+ * the batched form of Alg. 3.  Y is device [n][nq] row-major in caller ids
+ * (double for CP_F64, float otherwise); infos is host [nq] or NULL.
+ * Errors as cp_power; no output is written if any query is invalid. */
+cp_status cp_power_batch(const cp_graph* g, int32_t nq, const cp_query* q, int32_t prec, void* Y,
+                         void* ws, size_t ws_bytes, void* stream, cp_info* infos);
+
+const char* cp_status_str(int32_t st);
+int32_t cp_last_hip_error(void);
+const char* cp_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CHEBYPROP_H */

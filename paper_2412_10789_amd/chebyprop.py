@@ -1,0 +1,293 @@
+"""Python binding of the C ABI in include/chebyprop.h (argument marshalling
+only: every step of the computation runs in the HIP library).
+
+The functions ``cp_*`` mirror the C calls one to one.  ``Graph`` is a thin
+convenience wrapper that uses PyTorch for device memory and streams.  If
+``libchebyprop.so`` has not been built the import fails loudly: there is no
+CPU fallback.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libchebyprop.so")
+
+# status codes
+CP_OK = 0
+CP_EINVAL = -1
+CP_ESOURCE = -2
+CP_EISOLATED = -3
+CP_ENOMEM = -4
+CP_EHIP = -5
+CP_EKMAX = -6
+CP_EBUSY = -7
+CP_ECANCELLED = -8
+CP_ENOTFOUND = -9
+CP_EGRAPH = -10
+CP_EPENDING = -11
+CP_EWORKSPACE = -12
+
+CP_PPR, CP_HKPR = 0, 1
+CP_F64, CP_F32, CP_BF16 = 0, 1, 2
+CP_K_CERTIFIED, CP_K_TAIL, CP_K_PAPER, CP_K_FIXED = 0, 1, 2, 3
+CP_GRAPH_BORROW, CP_GRAPH_VALIDATE, CP_GRAPH_REORDER, CP_GRAPH_HOST = 0x1, 0x2, 0x4, 0x8
+CP_Q_STATS, CP_Q_TIMING = 0x1, 0x2
+
+KINDS = {"ppr": CP_PPR, "hkpr": CP_HKPR}
+PRECS = {"f64": CP_F64, "f32": CP_F32, "bf16": CP_BF16}
+KMODES = {"certified": CP_K_CERTIFIED, "tail": CP_K_TAIL, "paper": CP_K_PAPER, "fixed": CP_K_FIXED}
+
+# every symbol the header declares
+EXPORTED = [
+    "cp_graph_create", "cp_graph_destroy", "cp_graph_get_stats", "cp_coeffs", "cp_choose_K",
+    "cp_workspace_bytes", "cp_power", "cp_power_batch", "cp_status_str", "cp_last_hip_error",
+    "cp_version",
+]
+
+
+class cp_query(ctypes.Structure):
+    _fields_ = [
+        ("kind", ctypes.c_int32),
+        ("kmode", ctypes.c_int32),
+        ("param", ctypes.c_double),
+        ("tol", ctypes.c_double),
+        ("source", ctypes.c_int64),
+        ("K_fixed", ctypes.c_int32),
+        ("flags", ctypes.c_int32),
+    ]
+
+
+class cp_info(ctypes.Structure):
+    _fields_ = [
+        ("K", ctypes.c_int32),
+        ("steps", ctypes.c_int32),
+        ("tail", ctypes.c_double),
+        ("tail_bound_l1", ctypes.c_double),
+        ("mass", ctypes.c_double),
+        ("elapsed_ms", ctypes.c_double),
+        ("step_ms", ctypes.c_double),
+    ]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class cp_graph_stats(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int64),
+        ("nnz", ctypes.c_int64),
+        ("d_max", ctypes.c_int64),
+        ("blocks", ctypes.c_int64),
+        ("long_rows", ctypes.c_int64),
+        ("hub_rows", ctypes.c_int64),
+        ("device_bytes", ctypes.c_int64),
+        ("reordered", ctypes.c_int32),
+        ("borrowed", ctypes.c_int32),
+    ]
+
+
+class ChebypropError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        msg = cp_status_str(status)
+        if status == CP_EHIP:
+            msg += f" (hipError_t {cp_last_hip_error()})"
+        super().__init__(f"{where}: {msg} [{status}]")
+
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """Load libchebyprop.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(
+            f"{LIB_PATH} is missing: build it with `python -m paper_2412_10789_amd.build` "
+            "(there is no CPU fallback)"
+        )
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.c_void_p
+    i32, i64, f64, sz = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_size_t
+    sig = {
+        "cp_graph_create": (i32, [i64, i64, P, P, i32, P, ctypes.POINTER(P)]),
+        "cp_graph_destroy": (i32, [P]),
+        "cp_graph_get_stats": (i32, [P, ctypes.POINTER(cp_graph_stats)]),
+        "cp_coeffs": (i32, [i32, f64, i32, ctypes.POINTER(f64)]),
+        "cp_choose_K": (i32, [i32, f64, f64, i32, i32, f64, f64, i32, ctypes.POINTER(i32), ctypes.POINTER(f64)]),
+        "cp_workspace_bytes": (sz, [P, i32, i32]),
+        "cp_power": (i32, [P, ctypes.POINTER(cp_query), i32, P, P, sz, P, ctypes.POINTER(cp_info)]),
+        "cp_power_batch": (i32, [P, i32, ctypes.POINTER(cp_query), i32, P, P, sz, P, ctypes.POINTER(cp_info)]),
+        "cp_status_str": (ctypes.c_char_p, [i32]),
+        "cp_last_hip_error": (i32, []),
+        "cp_version": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+# ---------------------------------------------------------------- raw calls
+
+
+def cp_status_str(status: int) -> str:
+    return load().cp_status_str(status).decode()
+
+
+def cp_last_hip_error() -> int:
+    return int(load().cp_last_hip_error())
+
+
+def cp_version() -> str:
+    return load().cp_version().decode()
+
+
+def _check(status: int, where: str) -> None:
+    if status != CP_OK:
+        raise ChebypropError(status, where)
+
+
+def cp_coeffs(kind: int, param: float, K: int) -> np.ndarray:
+    c = np.zeros(K + 1, dtype=np.float64)
+    _check(load().cp_coeffs(kind, param, K, c.ctypes.data_as(ctypes.POINTER(ctypes.c_double))), "cp_coeffs")
+    return c
+
+
+def cp_choose_K(kind: int, param: float, tol: float, kmode: int = CP_K_CERTIFIED, K_fixed: int = 0,
+                vol: float = 1.0, d_s: float = 1.0, K_max: int = 0) -> tuple[int, float]:
+    K = ctypes.c_int32(0)
+    tail = ctypes.c_double(0.0)
+    _check(load().cp_choose_K(kind, param, tol, kmode, K_fixed, vol, d_s, K_max,
+                              ctypes.byref(K), ctypes.byref(tail)), "cp_choose_K")
+    return int(K.value), float(tail.value)
+
+
+def cp_graph_create(n: int, nnz: int, row_ptr_ptr: int, col_idx_ptr: int, flags: int, stream: int) -> int:
+    out = ctypes.c_void_p()
+    _check(load().cp_graph_create(n, nnz, row_ptr_ptr, col_idx_ptr, flags, stream, ctypes.byref(out)),
+           "cp_graph_create")
+    return out.value
+
+
+def cp_graph_destroy(handle: int) -> None:
+    _check(load().cp_graph_destroy(handle), "cp_graph_destroy")
+
+
+def cp_graph_get_stats(handle: int) -> dict:
+    st = cp_graph_stats()
+    _check(load().cp_graph_get_stats(handle, ctypes.byref(st)), "cp_graph_get_stats")
+    return {f: getattr(st, f) for f, _ in st._fields_}
+
+
+def cp_workspace_bytes(handle: int, nq: int, prec: int) -> int:
+    return int(load().cp_workspace_bytes(handle, nq, prec))
+
+
+def cp_power(handle: int, query: cp_query, prec: int, y_ptr: int, ws_ptr: int, ws_bytes: int,
+             stream: int) -> cp_info:
+    info = cp_info()
+    _check(load().cp_power(handle, ctypes.byref(query), prec, y_ptr, ws_ptr, ws_bytes, stream,
+                           ctypes.byref(info)), "cp_power")
+    return info
+
+
+def cp_power_batch(handle: int, queries, prec: int, Y_ptr: int, ws_ptr: int, ws_bytes: int,
+                   stream: int) -> list:
+    nq = len(queries)
+    arr = (cp_query * nq)(*queries)
+    infos = (cp_info * nq)()
+    _check(load().cp_power_batch(handle, nq, arr, prec, Y_ptr, ws_ptr, ws_bytes, stream, infos),
+           "cp_power_batch")
+    return list(infos)
+
+
+def make_query(kind: str, param: float, source: int, tol: float = 1e-6, kmode: str = "certified",
+               K: int = 0, flags: int = 0) -> cp_query:
+    return cp_query(KINDS[kind], KMODES[kmode], float(param), float(tol), int(source), int(K), int(flags))
+
+
+# ---------------------------------------------------------------- torch wrapper
+
+
+@dataclass
+class Result:
+    y: "object"  # torch tensor on the GPU (caller ids)
+    info: dict
+
+
+class Graph:
+    """A graph resident in HBM (owned by the library)."""
+
+    def __init__(self, row_ptr, col_idx, reorder: bool = False, validate: bool = False, device=None):
+        import torch
+
+        self.torch = torch
+        dev = torch.device(device or "cuda")
+        rp = torch.as_tensor(np.asarray(row_ptr, dtype=np.int64)).to(dev)
+        ci = torch.as_tensor(np.asarray(col_idx, dtype=np.int32)).to(dev)
+        self.n = int(rp.numel() - 1)
+        self.nnz = int(ci.numel())
+        self.device = dev
+        flags = (CP_GRAPH_REORDER if reorder else 0) | (CP_GRAPH_VALIDATE if validate else 0)
+        with torch.cuda.device(dev):
+            stream = torch.cuda.current_stream().cuda_stream
+            self.handle = cp_graph_create(self.n, self.nnz, rp.data_ptr(), ci.data_ptr(), flags, stream)
+        self.stats = cp_graph_get_stats(self.handle)
+        self._ws = {}
+
+    def close(self) -> None:
+        if getattr(self, "handle", None):
+            cp_graph_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # noqa: BLE001
+            pass
+
+    def workspace(self, nq: int, prec: int):
+        nbytes = cp_workspace_bytes(self.handle, nq, prec)
+        key = (nq, prec)
+        ws = self._ws.get(key)
+        if ws is None or ws.numel() < nbytes:
+            ws = self.torch.empty(nbytes, dtype=self.torch.uint8, device=self.device)
+            self._ws = {key: ws}
+        return ws, nbytes
+
+    def out_dtype(self, prec: int):
+        return self.torch.float64 if prec == CP_F64 else self.torch.float32
+
+    def power(self, kind: str, param: float, source: int, tol: float = 1e-6, prec: str = "f32",
+              kmode: str = "certified", K: int = 0, flags: int = 0, y=None, stream=None) -> Result:
+        torch = self.torch
+        p = PRECS[prec]
+        if y is None:
+            y = torch.empty(self.n, dtype=self.out_dtype(p), device=self.device)
+        ws, nbytes = self.workspace(1, p)
+        st = stream if stream is not None else torch.cuda.current_stream(self.device).cuda_stream
+        q = make_query(kind, param, source, tol, kmode, K, flags)
+        info = cp_power(self.handle, q, p, y.data_ptr(), ws.data_ptr(), nbytes, st)
+        return Result(y, info.as_dict())
+
+    def power_batch(self, queries, prec: str = "f32", Y=None, stream=None):
+        torch = self.torch
+        p = PRECS[prec]
+        nq = len(queries)
+        if Y is None:
+            Y = torch.empty((self.n, nq), dtype=self.out_dtype(p), device=self.device)
+        ws, nbytes = self.workspace(nq, p)
+        st = stream if stream is not None else torch.cuda.current_stream(self.device).cuda_stream
+        infos = cp_power_batch(self.handle, queries, p, Y.data_ptr(), ws.data_ptr(), nbytes, st)
+        return Y, [i.as_dict() for i in infos]

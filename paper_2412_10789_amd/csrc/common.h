@@ -1,0 +1,135 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <vector>
+
+#include "chebyprop.h"
+
+namespace cp {
+
+// ---------------------------------------------------------------- work plan
+//
+// The step kernel walks the CSR in "blocks", one workgroup each:
+//   kind 0 (stream): a run of consecutive rows whose arcs fit in one LDS
+//          tile (at most kTileNnz arcs and kTileRows rows);
+//   kind 1 (long):   one row with more than kTileNnz arcs, streamed from
+//          global memory by the whole workgroup;
+//   kind 2 (hub):    one segment of kHubSeg arcs of a row with more than
+//          kHubThreshold arcs; the segments' partial sums are combined in
+//          segment order by whichever workgroup finishes its row last.
+// Blocks are ordered hubs, long rows (longest first), then stream blocks in
+// row order.
+
+constexpr int kThreads = 256;      // workgroup size (4 wave64)
+constexpr int kTileNnz = 2048;     // arcs per stream tile (8 per thread)
+constexpr int kTileRows = 256;     // rows per stream tile (1 per thread)
+constexpr int kPerThread = kTileNnz / kThreads;
+constexpr int64_t kHubThreshold = 16384;
+constexpr int64_t kHubSeg = 8192;
+
+enum BlockKind : int32_t { kStream = 0, kLong = 1, kHub = 2 };
+
+struct BlockDesc {
+  int32_t r0;    // first row
+  int32_t r1;    // one past the last row (stream, long); hub id (hub)
+  int32_t kind;  // BlockKind
+  int32_t aux;   // hub: segment index within the row
+};
+
+struct HubDesc {
+  int32_t row;
+  int32_t nseg;
+  int32_t base;  // index of segment 0 in the partial-sum array
+  int32_t pad;
+};
+
+struct Plan {
+  std::vector<BlockDesc> blocks;
+  std::vector<HubDesc> hubs;
+  int64_t nspecial = 0;  // hub + long blocks at the front
+  int64_t nlong = 0;
+  int64_t hub_segments = 0;
+};
+
+Plan build_plan(const int64_t* row_ptr, int64_t n);
+
+// ------------------------------------------------------------------ kernels
+
+// Chebyshev step over all blocks: for every row v
+//   acc = sum_{u in N(v)} x[u]            (x = D^{-1} r_k)
+//   z[v] = 2 acc / d_v - z[v]             (z: D^{-1} r_{k-1} -> D^{-1} r_{k+1})
+//   yacc[v] += c * z[v]                   (yacc = D^{-1} y)
+struct StepArgs {
+  const int64_t* row_ptr;
+  const int32_t* col_idx;
+  const BlockDesc* blocks;
+  const HubDesc* hubs;
+  int64_t nblocks;
+  int64_t nspecial;
+  const void* x;
+  void* z;
+  void* yacc;
+  double c;
+  void* hub_partial;  // Acc[hub_segments]
+  int32_t* hub_count; // int32[nhubs], zero between steps
+};
+
+hipError_t launch_step(int32_t prec, const StepArgs& a, hipStream_t st);
+
+// Zero-fill `bytes` bytes (multiple of 4) at `p`.
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t st);
+
+// r~_0 = e_s / d_s, r~_1 = D^{-1} P e_s, yacc = c0 r~_0 + c1 r~_1, for one
+// source (s, internal id); buffers already zero.
+struct InitArgs {
+  const int64_t* row_ptr;
+  const int32_t* col_idx;
+  int64_t s;
+  void* r0;
+  void* r1;
+  void* yacc;
+  double c0, c1;
+};
+hipError_t launch_init(int32_t prec, const InitArgs& a, hipStream_t st);
+
+// y_out[perm(v)] = d_v * yacc[v]; optional double sum of y into *mass.
+struct FinalArgs {
+  const int64_t* row_ptr;
+  const int32_t* perm;  // internal -> caller id, or null
+  int64_t n;
+  const void* yacc;
+  void* y_out;
+  double* mass;         // device, or null
+};
+hipError_t launch_finalize(int32_t prec, const FinalArgs& a, hipStream_t st);
+
+// ------------------------------------------------------------- host helpers
+
+cp_status coeffs_impl(int32_t kind, double param, int32_t K, double* c);
+cp_status choose_K_impl(int32_t kind, double param, double tol, int32_t kmode, int32_t K_fixed,
+                        double vol, double d_s, int32_t K_max, int32_t* K_out, double* tail_out);
+
+void set_hip_error(hipError_t e);
+
+constexpr int32_t kDefaultKMax = 4096;
+
+}  // namespace cp
+
+struct cp_graph {
+  int64_t n = 0, nnz = 0, d_max = 0;
+  int device = 0;
+  const int64_t* row_ptr = nullptr;  // internal node order
+  const int32_t* col_idx = nullptr;
+  void* owned_csr = nullptr;         // allocation holding row_ptr/col_idx when owned
+  int32_t* perm = nullptr;           // internal -> caller id (reordered graphs)
+  std::vector<int32_t> ext2int;      // caller id -> internal id (reordered graphs)
+  std::vector<int32_t> degree;       // by caller id
+  cp::BlockDesc* blocks = nullptr;
+  cp::HubDesc* hubs = nullptr;
+  int64_t nblocks = 0, nspecial = 0, nlong = 0, nhubs = 0, hub_segments = 0;
+  int64_t device_bytes = 0;
+  bool reordered = false, borrowed = false;
+};

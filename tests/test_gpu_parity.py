@@ -1,0 +1,209 @@
+"""GPU ChebyPower (HIP library through the C ABI) against the FP64 oracle.
+
+Tolerances: FP64 vectors are compared element by element with the oracle's
+Alg. 3 at the same K to 1e-12 (only summation order differs).  FP32 vectors
+carry a relative rounding of 2^-24 per operation; across K <= 40 steps of a
+recurrence whose iterates have l1 norm up to sqrt(vol/d_s) this gives l1
+deviations of order 1e-7 on these graphs, and the tests allow 2e-6.  The
+contract against the exact vector (l1 <= tol, here 1e-6) is checked with
+the certified K.
+"""
+
+import numpy as np
+import pytest
+
+import synth
+from gpu_util import compare, gpu_graph, oracle_yK, require_gpu
+from oracle import errors as E
+from oracle import propagation as PR
+
+pytestmark = pytest.mark.gpu
+
+
+def _print_case(*a):
+    print("CASE", *a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def torch():
+    return require_gpu()
+
+
+def test_star_example_f64(torch):
+    """Sec. 4.2 star, source v1: Alg. 3 with K = 1..3 against the oracle."""
+    g = synth.star(3)
+    G = gpu_graph(g)
+    for K in (1, 2, 3):
+        _print_case("star", K)
+        r = G.power("ppr", 0.2, 1, prec="f64", kmode="fixed", K=K)
+        ref = oracle_yK(g, 1, "ppr", 0.2, K)
+        np.testing.assert_allclose(r.y.cpu().numpy(), ref, atol=1e-15)
+        assert r.info["K"] == K and r.info["steps"] == K - 1
+
+
+@pytest.mark.parametrize("kind,param", [("ppr", 0.2), ("ppr", 0.05), ("hkpr", 5.0), ("hkpr", 0.7)])
+def test_tiny_graphs_f64(torch, kind, param):
+    import pins
+
+    for g in pins.tiny_graphs():
+        s = int(np.flatnonzero(g.degrees > 0)[2])
+        _print_case("tiny", g.name, kind, param, s)
+        G = gpu_graph(g, validate=True)
+        r = G.power(kind, param, s, tol=1e-12, prec="f64")
+        ref = oracle_yK(g, s, kind, param, r.info["K"])
+        np.testing.assert_allclose(r.y.cpu().numpy(), ref, atol=1e-13, rtol=1e-12)
+
+
+def test_config1_shape_f64(torch):
+    """n=20,000 Chung-Lu, avg degree 10, exponent 2.5, PPR alpha=0.2, FP64,
+    K certified for l1 <= 1e-8 against the exact vector."""
+    g = synth.chung_lu(20_000, 100_000, 2.5, seed=1)
+    P = PR.transition_matrix(g.row_ptr, g.col_idx)
+    G = gpu_graph(g)
+    for s in synth.sources(g, 4, seed=1):
+        _print_case("config1", int(s))
+        r = G.power("ppr", 0.2, int(s), tol=1e-8, prec="f64", flags=1)
+        y = r.y.cpu().numpy()
+        ref_K = oracle_yK(g, s, "ppr", 0.2, r.info["K"], P)
+        exact = PR.ground_truth(P, int(s), "ppr", 0.2)
+        np.testing.assert_allclose(y, ref_K, atol=1e-14, rtol=1e-12)
+        assert E.l1(y, exact) <= 1e-8
+        assert abs(r.info["mass"] - 1.0) < 1e-8
+
+
+@pytest.mark.parametrize("reorder", [False, True])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_powerlaw_tiles_and_long_rows(torch, prec, reorder):
+    """200k-node power-law graph: thousands of stream tiles, a ragged last
+    tile, rows longer than one tile (whole-workgroup rows)."""
+    g = synth.chung_lu(200_000, 2_400_000, 2.1, seed=12)
+    assert g.degrees.max() > 2048, "graph must contain long rows"
+    P = PR.transition_matrix(g.row_ptr, g.col_idx)
+    G = gpu_graph(g, reorder=reorder)
+    assert G.stats["long_rows"] > 0
+    for kind, param in [("ppr", 0.2), ("hkpr", 5.0)]:
+        for s in synth.sources(g, 2, seed=3):
+            _print_case("powerlaw", prec, reorder, kind, int(s))
+            r = G.power(kind, param, int(s), tol=1e-6, prec=prec)
+            y = r.y.cpu().numpy()
+            ref = oracle_yK(g, s, kind, param, r.info["K"], P)
+            m = compare(y, ref)
+            if prec == "f64":
+                assert m["max_abs"] <= 1e-13, m
+            else:
+                assert m["l1"] <= 2e-6, m
+            exact = PR.ground_truth(P, int(s), kind, param)
+            assert E.l1(y, exact) <= 1e-6 + (0 if prec == "f64" else 2e-6)
+
+
+def test_hub_rows_split_f64(torch):
+    """A hub of degree 40,000 (split over several workgroups, combined in
+    segment order) plus a random graph among its leaves."""
+    leaves = 40_000
+    rng_edges = synth.erdos_renyi(2_000, 0.004, seed=5)
+    e = [(0, i) for i in range(1, leaves + 1)]
+    rows = np.repeat(np.arange(rng_edges.n), rng_edges.degrees)
+    e += [(int(a) + 1, int(b) + 1) for a, b in zip(rows, rng_edges.col_idx) if a < b]
+    g = synth.from_edges(leaves + 1, e, name="hub")
+    G = gpu_graph(g)
+    assert G.stats["hub_rows"] == 1
+    P = PR.transition_matrix(g.row_ptr, g.col_idx)
+    for s in (0, 5, leaves):
+        for prec in ("f64", "f32"):
+            _print_case("hub", s, prec)
+            r = G.power("hkpr", 3.0, s, tol=1e-10, prec=prec)
+            ref = oracle_yK(g, s, "hkpr", 3.0, r.info["K"], P)
+            m = compare(r.y.cpu().numpy(), ref)
+            # a 40,000-term row sum: rounding up to d * eps * sum|x| (about 1e-11
+            # in FP64, 1e-6 in FP32 relative to the hub value)
+            assert m["max_abs"] <= (1e-11 if prec == "f64" else 1e-6), m
+
+
+def test_isolated_nodes_and_errors(torch):
+    from paper_2412_10789_amd import chebyprop as cp
+
+    g = synth.from_edges(8, [(0, 1), (1, 2), (2, 0), (4, 5)], name="with isolated")
+    G = gpu_graph(g, validate=True)
+    _print_case("isolated")
+    r = G.power("ppr", 0.3, 0, tol=1e-12, prec="f64")
+    y = r.y.cpu().numpy()
+    assert np.all(y[[3, 6, 7]] == 0.0) and np.all(y[[4, 5]] == 0.0)
+    ref = oracle_yK(g, 0, "ppr", 0.3, r.info["K"])
+    np.testing.assert_allclose(y, ref, atol=1e-15)
+    with pytest.raises(cp.ChebypropError) as ei:
+        G.power("ppr", 0.3, 3)
+    assert ei.value.status == cp.CP_EISOLATED
+    with pytest.raises(cp.ChebypropError) as ei:
+        G.power("ppr", 0.3, 8)
+    assert ei.value.status == cp.CP_ESOURCE
+    with pytest.raises(cp.ChebypropError) as ei:
+        G.power("ppr", 1.5, 0)
+    assert ei.value.status == cp.CP_EINVAL
+    with pytest.raises(cp.ChebypropError) as ei:
+        G.power("ppr", 0.2, 0, kmode="fixed", K=0)
+    assert ei.value.status == cp.CP_EINVAL
+    q = cp.make_query("ppr", 0.2, 0, 1e-6)
+    y = torch.empty(g.n, dtype=torch.float32, device="cuda")
+    with pytest.raises(cp.ChebypropError) as ei:
+        cp.cp_power(G.handle, q, cp.CP_F32, y.data_ptr(), 0, 0, 0)
+    assert ei.value.status == cp.CP_EWORKSPACE
+
+
+def test_validation_rejects_bad_csr(torch):
+    from paper_2412_10789_amd import chebyprop as cp
+
+    rp = np.array([0, 1, 2, 2], np.int64)
+    ci = np.array([1, 2], np.int32)  # 0->1, 1->2: not symmetric
+    with pytest.raises(cp.ChebypropError) as ei:
+        cp.Graph(rp, ci, validate=True)
+    assert ei.value.status == cp.CP_EGRAPH
+    rp = np.array([0, 1, 2], np.int64)
+    ci = np.array([0, 1], np.int32)  # self-loops
+    with pytest.raises(cp.ChebypropError) as ei:
+        cp.Graph(rp, ci, validate=True)
+    assert ei.value.status == cp.CP_EGRAPH
+
+
+def test_bitwise_reproducible_and_timing(torch):
+    g = synth.chung_lu(100_000, 900_000, 2.3, seed=2)
+    G = gpu_graph(g)
+    s = int(synth.sources(g, 1, seed=4)[0])
+    _print_case("repro", s)
+    a = G.power("hkpr", 5.0, s, tol=1e-6, prec="f32").y.clone()
+    b = G.power("hkpr", 5.0, s, tol=1e-6, prec="f32", flags=2)
+    assert torch.equal(a, b.y)
+    assert b.info["elapsed_ms"] > 0 and 0 < b.info["step_ms"] <= b.info["elapsed_ms"]
+
+
+def test_bf16_storage_error_reported(torch):
+    g = synth.chung_lu(100_000, 900_000, 2.3, seed=2)
+    P = PR.transition_matrix(g.row_ptr, g.col_idx)
+    G = gpu_graph(g)
+    s = int(synth.sources(g, 1, seed=4)[0])
+    _print_case("bf16", s)
+    r = G.power("ppr", 0.2, s, tol=1e-6, prec="bf16")
+    ref = oracle_yK(g, s, "ppr", 0.2, r.info["K"], P)
+    m = compare(r.y.cpu().numpy(), ref)
+    print("bf16 storage error vs FP64 oracle:", m)
+    assert m["l1"] < 2e-2
+
+
+@pytest.mark.slow
+def test_config2_full_size_f32(torch):
+    """Chung-Lu n=4M, ~35M edges, exponent 2.3; HKPR t=5, FP32, l1 <= 1e-6
+    against the FP64 oracle for sampled sources (full vectors)."""
+    g = synth.chung_lu(4_000_000, 35_000_000, 2.3, seed=2)
+    P = PR.transition_matrix(g.row_ptr, g.col_idx)
+    for reorder in (False, True):
+        G = gpu_graph(g, reorder=reorder)
+        for s in synth.sources(g, 2, seed=2):
+            _print_case("config2", reorder, int(s))
+            r = G.power("hkpr", 5.0, int(s), tol=1e-6, prec="f32")
+            y = r.y.cpu().numpy()
+            ref = oracle_yK(g, s, "hkpr", 5.0, r.info["K"], P)
+            exact = PR.ground_truth(P, int(s), "hkpr", 5.0, tol=1e-12)
+            m = compare(y, ref)
+            print("config2", reorder, int(s), r.info["K"], m, "vs exact", E.l1(y, exact), flush=True)
+            assert m["l1"] <= 2e-6
+            assert E.l1(y, exact) <= 1e-6
+        G.close()
