@@ -166,6 +166,19 @@ cp_status cp_power(const cp_graph* g, const cp_query* q, int32_t prec, void* y, 
 cp_status cp_power_batch(const cp_graph* g, int32_t nq, const cp_query* q, int32_t prec, void* Y,
                          void* ws, size_t ws_bytes, void* stream, cp_info* infos);
 
+/* Pick the source-tile width (8, 16, 32 or 64 sources per tile) that runs
+ * these nq queries fastest on this graph and remember it for later
+ * cp_power_batch calls with the same nq and precision.  Runs the queries
+ * once per candidate width (Y, ws as for cp_power_batch; Y holds the last
+ * run's result).  Synchronizes `stream`.  bw_out may be NULL. */
+cp_status cp_autotune_batch(cp_graph* g, int32_t nq, const cp_query* q, int32_t prec, void* Y, void* ws,
+                            size_t ws_bytes, void* stream, int32_t* bw_out);
+
+/* Fix the source-tile width used by cp_power_batch for (nq, prec) on this
+ * graph (bw in {8, 16, 32, 64}; 0 forgets the choice and returns to the
+ * built-in default).  Errors: CP_EINVAL. */
+cp_status cp_set_batch_width(cp_graph* g, int32_t nq, int32_t prec, int32_t bw);
+
 const char* cp_status_str(int32_t st);
 int32_t cp_last_hip_error(void);
 const char* cp_version(void);

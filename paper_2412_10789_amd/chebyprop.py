@@ -46,8 +46,8 @@ KMODES = {"certified": CP_K_CERTIFIED, "tail": CP_K_TAIL, "paper": CP_K_PAPER, "
 # every symbol the header declares
 EXPORTED = [
     "cp_graph_create", "cp_graph_destroy", "cp_graph_get_stats", "cp_coeffs", "cp_choose_K",
-    "cp_workspace_bytes", "cp_power", "cp_power_batch", "cp_status_str", "cp_last_hip_error",
-    "cp_version",
+    "cp_workspace_bytes", "cp_power", "cp_power_batch", "cp_autotune_batch", "cp_set_batch_width",
+    "cp_status_str", "cp_last_hip_error", "cp_version",
 ]
 
 
@@ -126,6 +126,8 @@ def load() -> ctypes.CDLL:
         "cp_workspace_bytes": (sz, [P, i32, i32]),
         "cp_power": (i32, [P, ctypes.POINTER(cp_query), i32, P, P, sz, P, ctypes.POINTER(cp_info)]),
         "cp_power_batch": (i32, [P, i32, ctypes.POINTER(cp_query), i32, P, P, sz, P, ctypes.POINTER(cp_info)]),
+        "cp_autotune_batch": (i32, [P, i32, ctypes.POINTER(cp_query), i32, P, P, sz, P, ctypes.POINTER(i32)]),
+        "cp_set_batch_width": (i32, [P, i32, i32, i32]),
         "cp_status_str": (ctypes.c_char_p, [i32]),
         "cp_last_hip_error": (i32, []),
         "cp_version": (ctypes.c_char_p, []),
@@ -212,6 +214,20 @@ def cp_power_batch(handle: int, queries, prec: int, Y_ptr: int, ws_ptr: int, ws_
     return list(infos)
 
 
+def cp_autotune_batch(handle: int, queries, prec: int, Y_ptr: int, ws_ptr: int, ws_bytes: int,
+                      stream: int) -> int:
+    nq = len(queries)
+    arr = (cp_query * nq)(*queries)
+    bw = ctypes.c_int32(0)
+    _check(load().cp_autotune_batch(handle, nq, arr, prec, Y_ptr, ws_ptr, ws_bytes, stream, ctypes.byref(bw)),
+           "cp_autotune_batch")
+    return int(bw.value)
+
+
+def cp_set_batch_width(handle: int, nq: int, prec: int, bw: int) -> None:
+    _check(load().cp_set_batch_width(handle, nq, prec, bw), "cp_set_batch_width")
+
+
 def make_query(kind: str, param: float, source: int, tol: float = 1e-6, kmode: str = "certified",
                K: int = 0, flags: int = 0) -> cp_query:
     return cp_query(KINDS[kind], KMODES[kmode], float(param), float(tol), int(source), int(K), int(flags))
@@ -280,6 +296,18 @@ class Graph:
         q = make_query(kind, param, source, tol, kmode, K, flags)
         info = cp_power(self.handle, q, p, y.data_ptr(), ws.data_ptr(), nbytes, st)
         return Result(y, info.as_dict())
+
+    def set_batch_width(self, nq: int, prec: str, bw: int) -> None:
+        cp_set_batch_width(self.handle, nq, PRECS[prec], bw)
+
+    def autotune_batch(self, queries, prec: str = "f32", stream=None) -> int:
+        torch = self.torch
+        p = PRECS[prec]
+        nq = len(queries)
+        Y = torch.empty((self.n, nq), dtype=self.out_dtype(p), device=self.device)
+        ws, nbytes = self.workspace(nq, p)
+        st = stream if stream is not None else torch.cuda.current_stream(self.device).cuda_stream
+        return cp_autotune_batch(self.handle, queries, p, Y.data_ptr(), ws.data_ptr(), nbytes, st)
 
     def power_batch(self, queries, prec: str = "f32", Y=None, stream=None):
         torch = self.torch

@@ -86,13 +86,13 @@ bool validate_csr(int64_t n, int64_t nnz, const int64_t* rp, const int32_t* ci) 
 
 }  // namespace
 
-Plan build_plan(const int64_t* rp, int64_t n) {
+Plan build_plan(const int64_t* rp, int64_t n, int64_t long_threshold) {
   Plan p;
   std::vector<int32_t> hubs, longs;
   for (int64_t v = 0; v < n; ++v) {
     const int64_t d = rp[v + 1] - rp[v];
     if (d > kHubThreshold) hubs.push_back((int32_t)v);
-    else if (d > kTileNnz) longs.push_back((int32_t)v);
+    else if (d > long_threshold) longs.push_back((int32_t)v);
   }
   auto by_degree = [&](int32_t a, int32_t b) {
     const int64_t da = rp[a + 1] - rp[a], db = rp[b + 1] - rp[b];
@@ -121,7 +121,7 @@ Plan build_plan(const int64_t* rp, int64_t n) {
   };
   for (int64_t v = 0; v < n; ++v) {
     const int64_t d = rp[v + 1] - rp[v];
-    if (d > kTileNnz) { close(v); continue; }
+    if (d > long_threshold) { close(v); continue; }
     if (r0 >= 0 && (nnz + d > kTileNnz || v - r0 == kTileRows)) close(v);
     if (r0 < 0) r0 = v;
     nnz += d;
@@ -144,8 +144,8 @@ WsLayout ws_layout(const cp_graph* g, int32_t nq, int32_t prec) {
   L.rA = off; off += vec;
   L.rB = off; off += vec;
   L.yacc = off; off += yv;
-  L.hub_count = off; off += align256((size_t)std::max<int64_t>(g->nhubs, 1) * 4);
-  L.hub_partial = off; off += align256((size_t)std::max<int64_t>(g->hub_segments, 1) * 8 * nq);
+  L.hub_count = off; off += align256((size_t)std::max<int64_t>(g->single.nhubs, 1) * 4);
+  L.hub_partial = off; off += align256((size_t)std::max<int64_t>(g->single.hub_segments, 1) * 8 * nq);
   L.mass = off; off += align256((1 + 1024) * 8);
   L.total = off;
   return L;
@@ -162,6 +162,62 @@ cp_status check_query(const cp_graph* g, const cp_query* q, int64_t* s_int, int3
   *L = std::sqrt((double)g->nnz / (double)ds);
   return choose_K_impl(q->kind, q->param, q->tol, q->kmode, q->K_fixed, (double)g->nnz, (double)ds,
                        kDefaultKMax, K, tail);
+}
+
+struct BatchLayout {
+  int32_t bw = 0, nq_pad = 0, ntiles = 0;
+  size_t rA = 0, rB = 0, yacc = 0, hub_count = 0, hub_partial = 0, coef = 0, src = 0, slotmap = 0,
+         total = 0;
+};
+
+int32_t round_up(int32_t a, int32_t b) { return (a + b - 1) / b * b; }
+
+BatchLayout batch_layout(const cp_graph* g, int32_t nq, int32_t prec, int32_t bw) {
+  BatchLayout L;
+  L.bw = bw;
+  L.nq_pad = round_up(nq, bw);
+  L.ntiles = L.nq_pad / bw;
+  const size_t vec = align256((size_t)g->n * (size_t)L.nq_pad * storage_bytes(prec));
+  const size_t yv = align256((size_t)g->n * (size_t)L.nq_pad * acc_bytes(prec));
+  size_t off = 0;
+  L.rA = off; off += vec;
+  L.rB = off; off += vec;
+  L.yacc = off; off += yv;
+  L.hub_count = off; off += align256((size_t)std::max<int64_t>(g->batch.nhubs, 1) * L.ntiles * 4);
+  L.hub_partial = off; off += align256((size_t)std::max<int64_t>(g->batch.hub_segments, 1) * L.nq_pad * 8);
+  L.coef = off; off += align256((size_t)(kBatchKCap + 1) * L.nq_pad * 8);
+  L.src = off; off += align256((size_t)L.nq_pad * 8);
+  L.slotmap = off; off += align256((size_t)nq * 4);
+  L.total = off;
+  return L;
+}
+
+const int32_t kBatchWidths[] = {8, 16, 32, 64};
+
+bool width_allowed(int32_t nq, int32_t bw) {
+  int32_t cap = 8;
+  while (cap < nq && cap < 64) cap *= 2;
+  return bw <= cap;
+}
+
+size_t batch_ws_bytes(const cp_graph* g, int32_t nq, int32_t prec) {
+  size_t m = 0;
+  for (int32_t bw : kBatchWidths)
+    if (width_allowed(nq, bw)) m = std::max(m, batch_layout(g, nq, prec, bw).total);
+  return m;
+}
+
+int64_t tune_key(int32_t nq, int32_t prec) { return ((int64_t)nq << 4) | prec; }
+
+int32_t choose_bw(cp_graph* g, int32_t nq, int32_t prec) {
+  {
+    std::lock_guard<std::mutex> lk(g->tune_mu);
+    auto it = g->tuned_bw.find(tune_key(nq, prec));
+    if (it != g->tuned_bw.end()) return it->second;
+  }
+  int32_t bw = 8;
+  while (bw < nq && bw < 32) bw *= 2;
+  return bw;
 }
 
 }  // namespace
@@ -269,28 +325,37 @@ cp_status cp_graph_create(int64_t n, int64_t nnz, const int64_t* row_ptr, const 
       ci.swap(ci2);
       g->reordered = true;
     }
-    const Plan plan = build_plan(rp.data(), n);
-    g->nblocks = (int64_t)plan.blocks.size();
-    g->nspecial = plan.nspecial;
-    g->nlong = plan.nlong;
-    g->nhubs = (int64_t)plan.hubs.size();
-    g->hub_segments = plan.hub_segments;
+    const Plan plans[2] = {build_plan(rp.data(), n, kTileNnz), build_plan(rp.data(), n, kBatchLong)};
 
-    // device copies: [row_ptr | col_idx | perm | blocks | hubs] in one allocation
+    // device copies: [row_ptr | col_idx | perm] in one allocation, plans in another
     const size_t b_rp = borrow ? 0 : align256(sizeof(int64_t) * (n + 1));
     const size_t b_ci = borrow ? 0 : align256(sizeof(int32_t) * std::max<int64_t>(nnz, 1));
     const size_t b_pm = reorder ? align256(sizeof(int32_t) * n) : 0;
-    const size_t b_bl = align256(sizeof(BlockDesc) * std::max<int64_t>(g->nblocks, 1));
-    const size_t b_hb = align256(sizeof(HubDesc) * std::max<int64_t>(g->nhubs, 1));
-    const size_t total = b_rp + b_ci + b_pm + b_bl + b_hb;
+    const size_t total = b_rp + b_ci + b_pm;
     char* base = nullptr;
-    hipError_t e = hipMalloc(&base, total);
-    if (e != hipSuccess) {
-      delete g;
-      return e == hipErrorOutOfMemory ? CP_ENOMEM : (set_hip_error(e), CP_EHIP);
+    if (total) {
+      hipError_t e = hipMalloc(&base, total);
+      if (e != hipSuccess) {
+        delete g;
+        return e == hipErrorOutOfMemory ? CP_ENOMEM : (set_hip_error(e), CP_EHIP);
+      }
+      g->owned_csr = base;
     }
-    g->owned_csr = base;
-    g->device_bytes = (int64_t)total;
+    size_t b_plans = 0;
+    for (const Plan& pl : plans)
+      b_plans += align256(sizeof(BlockDesc) * std::max<size_t>(pl.blocks.size(), 1)) +
+                 align256(sizeof(HubDesc) * std::max<size_t>(pl.hubs.size(), 1));
+    char* pbase = nullptr;
+    {
+      hipError_t e = hipMalloc(&pbase, b_plans);
+      if (e != hipSuccess) {
+        if (base) (void)hipFree(base);
+        delete g;
+        return e == hipErrorOutOfMemory ? CP_ENOMEM : (set_hip_error(e), CP_EHIP);
+      }
+      g->plan_mem = pbase;
+    }
+    g->device_bytes = (int64_t)(total + b_plans);
     char* p = base;
     if (borrow) {
       g->row_ptr = row_ptr;
@@ -313,19 +378,33 @@ cp_status cp_graph_create(int64_t n, int64_t nnz, const int64_t* row_ptr, const 
       g->perm = reinterpret_cast<int32_t*>(p); p += b_pm;
       CP_HIP(hipMemcpyAsync(g->perm, perm.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, st));
     }
-    g->blocks = reinterpret_cast<BlockDesc*>(p); p += b_bl;
-    g->hubs = reinterpret_cast<HubDesc*>(p); p += b_hb;
-    if (g->nblocks)
-      CP_HIP(hipMemcpyAsync(g->blocks, plan.blocks.data(), sizeof(BlockDesc) * g->nblocks,
-                            hipMemcpyHostToDevice, st));
-    if (g->nhubs)
-      CP_HIP(hipMemcpyAsync(g->hubs, plan.hubs.data(), sizeof(HubDesc) * g->nhubs,
-                            hipMemcpyHostToDevice, st));
+    DevPlan* dps[2] = {&g->single, &g->batch};
+    char* q = pbase;
+    for (int i = 0; i < 2; ++i) {
+      const Plan& pl = plans[i];
+      DevPlan& dp = *dps[i];
+      dp.nblocks = (int64_t)pl.blocks.size();
+      dp.nspecial = pl.nspecial;
+      dp.nlong = pl.nlong;
+      dp.nhubs = (int64_t)pl.hubs.size();
+      dp.hub_segments = pl.hub_segments;
+      dp.blocks = reinterpret_cast<BlockDesc*>(q);
+      q += align256(sizeof(BlockDesc) * std::max<size_t>(pl.blocks.size(), 1));
+      dp.hubs = reinterpret_cast<HubDesc*>(q);
+      q += align256(sizeof(HubDesc) * std::max<size_t>(pl.hubs.size(), 1));
+      if (dp.nblocks)
+        CP_HIP(hipMemcpyAsync(dp.blocks, pl.blocks.data(), sizeof(BlockDesc) * dp.nblocks,
+                              hipMemcpyHostToDevice, st));
+      if (dp.nhubs)
+        CP_HIP(hipMemcpyAsync(dp.hubs, pl.hubs.data(), sizeof(HubDesc) * dp.nhubs,
+                              hipMemcpyHostToDevice, st));
+    }
     CP_HIP(hipStreamSynchronize(st));
     *out = g;
     return CP_OK;
   } catch (const std::bad_alloc&) {
     if (g && g->owned_csr) (void)hipFree(g->owned_csr);
+    if (g && g->plan_mem) (void)hipFree(g->plan_mem);
     delete g;
     return CP_ENOMEM;
   }
@@ -333,11 +412,14 @@ cp_status cp_graph_create(int64_t n, int64_t nnz, const int64_t* row_ptr, const 
 
 cp_status cp_graph_destroy(cp_graph* g) {
   if (!g) return CP_EINVAL;
-  if (g->owned_csr) {
-    hipError_t e = hipFree(g->owned_csr);
-    if (e != hipSuccess) { set_hip_error(e); delete g; return CP_EHIP; }
+  hipError_t e = hipSuccess;
+  if (g->owned_csr) e = hipFree(g->owned_csr);
+  if (g->plan_mem) {
+    hipError_t e2 = hipFree(g->plan_mem);
+    if (e == hipSuccess) e = e2;
   }
   delete g;
+  if (e != hipSuccess) { set_hip_error(e); return CP_EHIP; }
   return CP_OK;
 }
 
@@ -346,9 +428,9 @@ cp_status cp_graph_get_stats(const cp_graph* g, cp_graph_stats* out) {
   out->n = g->n;
   out->nnz = g->nnz;
   out->d_max = g->d_max;
-  out->blocks = g->nblocks;
-  out->long_rows = g->nlong;
-  out->hub_rows = g->nhubs;
+  out->blocks = g->single.nblocks;
+  out->long_rows = g->single.nlong;
+  out->hub_rows = g->single.nhubs;
   out->device_bytes = g->device_bytes;
   out->reordered = g->reordered;
   out->borrowed = g->borrowed;
@@ -357,7 +439,8 @@ cp_status cp_graph_get_stats(const cp_graph* g, cp_graph_stats* out) {
 
 size_t cp_workspace_bytes(const cp_graph* g, int32_t nq, int32_t prec) {
   if (!g || nq < 1 || !valid_prec(prec)) return 0;
-  return ws_layout(g, nq, prec).total;
+  if (nq == 1) return std::max(ws_layout(g, 1, prec).total, batch_ws_bytes(g, 1, prec));
+  return batch_ws_bytes(g, nq, prec);
 }
 
 cp_status cp_power(const cp_graph* g, const cp_query* q, int32_t prec, void* y, void* ws,
@@ -410,10 +493,10 @@ cp_status cp_power(const cp_graph* g, const cp_query* q, int32_t prec, void* y, 
   StepArgs sa{};
   sa.row_ptr = g->row_ptr;
   sa.col_idx = g->col_idx;
-  sa.blocks = g->blocks;
-  sa.hubs = g->hubs;
-  sa.nblocks = g->nblocks;
-  sa.nspecial = g->nspecial;
+  sa.blocks = g->single.blocks;
+  sa.hubs = g->single.hubs;
+  sa.nblocks = g->single.nblocks;
+  sa.nspecial = g->single.nspecial;
   sa.yacc = yacc;
   sa.hub_partial = w + W.hub_partial;
   sa.hub_count = reinterpret_cast<int32_t*>(w + W.hub_count);
@@ -464,10 +547,178 @@ cp_status cp_power(const cp_graph* g, const cp_query* q, int32_t prec, void* y, 
   return CP_OK;
 }
 
+}  // extern "C"
+
+namespace cp {
+namespace {
+
+cp_status power_batch_bw(cp_graph* g, int32_t nq, const cp_query* q, int32_t prec, void* Y, void* ws,
+                         size_t ws_bytes, hipStream_t st, cp_info* infos, int32_t bw) {
+  std::vector<int64_t> s_int(nq);
+  std::vector<int32_t> K(nq);
+  std::vector<double> tail(nq), L(nq);
+  for (int32_t j = 0; j < nq; ++j) {
+    cp_status rc = check_query(g, &q[j], &s_int[j], &K[j], &tail[j], &L[j]);
+    if (rc != CP_OK) return rc;
+    if (K[j] > kBatchKCap) return CP_EKMAX;
+  }
+  const BatchLayout W = batch_layout(g, nq, prec, bw);
+  if (!ws || ws_bytes < W.total || (reinterpret_cast<uintptr_t>(ws) & 255)) return CP_EWORKSPACE;
+  // slots in decreasing K (stable), tiles of bw slots
+  std::vector<int32_t> order(nq);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return K[a] > K[b]; });
+  std::vector<int32_t> slot_of_query(nq);
+  for (int32_t i = 0; i < nq; ++i) slot_of_query[order[i]] = i;
+  const int32_t Kmax = K[order[0]];
+  std::vector<double> coef((size_t)(Kmax + 1) * W.nq_pad, 0.0);
+  std::vector<int64_t> src(W.nq_pad, -1);
+  std::vector<double> c;
+  for (int32_t i = 0; i < nq; ++i) {
+    const int32_t j = order[i];
+    c.assign(K[j] + 1, 0.0);
+    cp_status rc = coeffs_impl(q[j].kind, q[j].param, K[j], c.data());
+    if (rc != CP_OK) return rc;
+    for (int32_t k = 0; k <= K[j]; ++k) coef[(size_t)k * W.nq_pad + i] = c[k];
+    src[i] = s_int[j];
+  }
+  std::vector<int32_t> tileK(W.ntiles);
+  for (int32_t t = 0; t < W.ntiles; ++t) tileK[t] = K[order[t * bw]];
+
+  char* w = static_cast<char*>(ws);
+  double* dcoef = reinterpret_cast<double*>(w + W.coef);
+  const bool timing = q[0].flags & CP_Q_TIMING;
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  auto cleanup = [&] {
+    for (hipEvent_t e : ev)
+      if (e) (void)hipEventDestroy(e);
+  };
+#define CP_HIP_B(call)        \
+  do {                        \
+    hipError_t e_ = (call);   \
+    if (e_ != hipSuccess) {   \
+      set_hip_error(e_);      \
+      cleanup();              \
+      return CP_EHIP;         \
+    }                         \
+  } while (0)
+  if (timing)
+    for (auto& e : ev) CP_HIP_B(hipEventCreate(&e));
+  if (timing) CP_HIP_B(hipEventRecord(ev[0], st));
+  CP_HIP_B(launch_zero(w, W.hub_partial, st));
+  CP_HIP_B(launch_upload(dcoef, coef.data(), coef.size() * sizeof(double), st));
+  CP_HIP_B(launch_upload(w + W.src, src.data(), src.size() * sizeof(int64_t), st));
+  CP_HIP_B(launch_upload(w + W.slotmap, slot_of_query.data(), slot_of_query.size() * sizeof(int32_t), st));
+  void* rA = w + W.rA;
+  void* rB = w + W.rB;
+  BatchInitArgs ia{g->row_ptr, g->col_idx, reinterpret_cast<const int64_t*>(w + W.src), g->n, bw,
+                   W.nq_pad, rA, rB, w + W.yacc, dcoef};
+  CP_HIP_B(launch_batch_init(prec, ia, nq, st));
+  BatchStepArgs sa{};
+  sa.row_ptr = g->row_ptr;
+  sa.col_idx = g->col_idx;
+  sa.blocks = g->batch.blocks;
+  sa.hubs = g->batch.hubs;
+  sa.nblocks = g->batch.nblocks;
+  sa.nspecial = g->batch.nspecial;
+  sa.n = g->n;
+  sa.bw = bw;
+  sa.nq_pad = W.nq_pad;
+  sa.yacc = w + W.yacc;
+  sa.hub_partial = w + W.hub_partial;
+  sa.hub_count = reinterpret_cast<int32_t*>(w + W.hub_count);
+  sa.ntiles_total = W.ntiles;
+  if (timing) CP_HIP_B(hipEventRecord(ev[1], st));
+  int64_t launches = 0;
+  for (int32_t k = 1; k < Kmax; ++k) {
+    int32_t active = 0;
+    while (active < W.ntiles && tileK[active] > k) ++active;
+    if (active == 0) break;
+    sa.ntiles = active;
+    sa.x = (k & 1) ? rB : rA;
+    sa.z = (k & 1) ? rA : rB;
+    sa.coef_row = dcoef + (size_t)(k + 1) * W.nq_pad;
+    CP_HIP_B(launch_batch_step(prec, sa, st));
+    ++launches;
+  }
+  if (timing) CP_HIP_B(hipEventRecord(ev[2], st));
+  BatchFinalArgs fa{g->row_ptr, g->perm, reinterpret_cast<const int32_t*>(w + W.slotmap), g->n, bw, nq,
+                    w + W.yacc, Y};
+  CP_HIP_B(launch_batch_finalize(prec, fa, st));
+  if (timing) CP_HIP_B(hipEventRecord(ev[3], st));
+  float ms_all = NAN, ms_steps = NAN;
+  if (timing) {
+    CP_HIP_B(hipStreamSynchronize(st));
+    CP_HIP_B(hipEventElapsedTime(&ms_all, ev[0], ev[3]));
+    CP_HIP_B(hipEventElapsedTime(&ms_steps, ev[1], ev[2]));
+  }
+  if (infos)
+    for (int32_t j = 0; j < nq; ++j) {
+      infos[j].K = K[j];
+      infos[j].steps = (int32_t)launches;
+      infos[j].tail = tail[j];
+      infos[j].tail_bound_l1 = tail[j] * L[j];
+      infos[j].mass = NAN;
+      infos[j].elapsed_ms = ms_all;
+      infos[j].step_ms = ms_steps;
+    }
+  cleanup();
+#undef CP_HIP_B
+  return CP_OK;
+}
+
+}  // namespace
+}  // namespace cp
+
+extern "C" {
+
 cp_status cp_power_batch(const cp_graph* g, int32_t nq, const cp_query* q, int32_t prec, void* Y,
                          void* ws, size_t ws_bytes, void* stream, cp_info* infos) {
-  (void)g; (void)nq; (void)q; (void)prec; (void)Y; (void)ws; (void)ws_bytes; (void)stream; (void)infos;
-  return CP_EINVAL;
+  if (!g || nq < 1 || !q || !Y || !valid_prec(prec)) return CP_EINVAL;
+  cp_graph* gm = const_cast<cp_graph*>(g);  // only the tuning cache is mutable
+  const int32_t bw = choose_bw(gm, nq, prec);
+  if (ws_bytes < batch_ws_bytes(g, nq, prec)) return CP_EWORKSPACE;
+  return power_batch_bw(gm, nq, q, prec, Y, ws, ws_bytes, static_cast<hipStream_t>(stream), infos, bw);
+}
+
+cp_status cp_set_batch_width(cp_graph* g, int32_t nq, int32_t prec, int32_t bw) {
+  if (!g || nq < 1 || !valid_prec(prec)) return CP_EINVAL;
+  std::lock_guard<std::mutex> lk(g->tune_mu);
+  if (bw == 0) {
+    g->tuned_bw.erase(tune_key(nq, prec));
+    return CP_OK;
+  }
+  if (!(bw == 8 || bw == 16 || bw == 32 || bw == 64) || !width_allowed(nq, bw)) return CP_EINVAL;
+  g->tuned_bw[tune_key(nq, prec)] = bw;
+  return CP_OK;
+}
+
+cp_status cp_autotune_batch(cp_graph* g, int32_t nq, const cp_query* q, int32_t prec, void* Y, void* ws,
+                            size_t ws_bytes, void* stream, int32_t* bw_out) {
+  if (!g || nq < 1 || !q || !Y || !valid_prec(prec)) return CP_EINVAL;
+  if (ws_bytes < batch_ws_bytes(g, nq, prec)) return CP_EWORKSPACE;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  std::vector<cp_query> qq(q, q + nq);
+  for (auto& x : qq) x.flags = CP_Q_TIMING;
+  std::vector<cp_info> infos(nq);
+  int32_t best = 0;
+  double best_ms = 1e300;
+  for (int32_t bw : kBatchWidths) {
+    if (!width_allowed(nq, bw)) continue;
+    double ms = 1e300;
+    for (int rep = 0; rep < 2; ++rep) {  // first run warms caches and code objects
+      cp_status rc = power_batch_bw(g, nq, qq.data(), prec, Y, ws, ws_bytes, st, infos.data(), bw);
+      if (rc != CP_OK) return rc;
+      ms = infos[0].elapsed_ms;
+    }
+    if (ms < best_ms) { best_ms = ms; best = bw; }
+  }
+  {
+    std::lock_guard<std::mutex> lk(g->tune_mu);
+    g->tuned_bw[tune_key(nq, prec)] = best;
+  }
+  if (bw_out) *bw_out = best;
+  return CP_OK;
 }
 
 }  // extern "C"

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <map>
+#include <mutex>
 #include <vector>
 
 #include "chebyprop.h"
@@ -29,6 +31,8 @@ constexpr int kTileRows = 256;     // rows per stream tile (1 per thread)
 constexpr int kPerThread = kTileNnz / kThreads;
 constexpr int64_t kHubThreshold = 16384;
 constexpr int64_t kHubSeg = 8192;
+constexpr int64_t kBatchLong = 256;  // batched kernel: rows above this use the whole workgroup
+constexpr int kMaxUploadWords = 960; // 32-bit words per kernel-argument upload launch
 
 enum BlockKind : int32_t { kStream = 0, kLong = 1, kHub = 2 };
 
@@ -54,7 +58,16 @@ struct Plan {
   int64_t hub_segments = 0;
 };
 
-Plan build_plan(const int64_t* row_ptr, int64_t n);
+// long_threshold: rows with more arcs than this leave the stream tiles
+// (kTileNnz for the single-source kernel, kBatchLong for the batched one).
+Plan build_plan(const int64_t* row_ptr, int64_t n, int64_t long_threshold);
+
+// Plan as uploaded to the device.
+struct DevPlan {
+  BlockDesc* blocks = nullptr;
+  HubDesc* hubs = nullptr;
+  int64_t nblocks = 0, nspecial = 0, nlong = 0, nhubs = 0, hub_segments = 0;
+};
 
 // ------------------------------------------------------------------ kernels
 
@@ -106,6 +119,65 @@ struct FinalArgs {
 };
 hipError_t launch_finalize(int32_t prec, const FinalArgs& a, hipStream_t st);
 
+// ----------------------------------------------------------- batched kernels
+//
+// Queries sorted by K (descending) occupy "slots"; slots are grouped into
+// source tiles of width bw.  Tile t owns three tile-major matrices
+// [n][bw]: two recurrence buffers (storage type) and the estimate
+// (accumulator type).  coef is a [(Kmax+1)][nq_pad] table of c_k per slot
+// (zero once k exceeds the slot's own K).
+
+struct BatchStepArgs {
+  const int64_t* row_ptr;
+  const int32_t* col_idx;
+  const BlockDesc* blocks;
+  const HubDesc* hubs;
+  int64_t nblocks;
+  int64_t nspecial;
+  int64_t n;
+  int32_t bw;
+  int32_t ntiles;        // active tiles in this launch (grid.y)
+  int32_t nq_pad;
+  const void* x;         // tile 0 base of x; tile t at + t*n*bw elements
+  void* z;
+  void* yacc;
+  const double* coef_row;  // coef + (k+1)*nq_pad
+  void* hub_partial;     // A[hub_segments][nq_pad]
+  int32_t* hub_count;    // int32[nhubs][ntiles_total]
+  int32_t ntiles_total;
+};
+hipError_t launch_batch_step(int32_t prec, const BatchStepArgs& a, hipStream_t st);
+
+struct BatchInitArgs {
+  const int64_t* row_ptr;
+  const int32_t* col_idx;
+  const int64_t* src;    // [nq_pad] internal source id per slot (-1: unused slot)
+  int64_t n;
+  int32_t bw;
+  int32_t nq_pad;
+  void* r0;
+  void* r1;
+  void* yacc;
+  const double* coef;    // rows 0 and 1 used
+};
+hipError_t launch_batch_init(int32_t prec, const BatchInitArgs& a, int32_t nslots, hipStream_t st);
+
+struct BatchFinalArgs {
+  const int64_t* row_ptr;
+  const int32_t* perm;   // internal -> caller id, or null
+  const int32_t* slot_of_query;  // [nq]
+  int64_t n;
+  int32_t bw;
+  int32_t nq;
+  const void* yacc;
+  void* Y;               // [n][nq] caller ids
+};
+hipError_t launch_batch_finalize(int32_t prec, const BatchFinalArgs& a, hipStream_t st);
+
+// Copy `bytes` (multiple of 4) of host data to device memory through kernel
+// arguments (no host buffer has to outlive the call; capturable in graphs).
+hipError_t launch_upload(void* dst, const void* host, size_t bytes, hipStream_t st);
+
 // ------------------------------------------------------------- host helpers
 
 cp_status coeffs_impl(int32_t kind, double param, int32_t K, double* c);
@@ -115,6 +187,7 @@ cp_status choose_K_impl(int32_t kind, double param, double tol, int32_t kmode, i
 void set_hip_error(hipError_t e);
 
 constexpr int32_t kDefaultKMax = 4096;
+constexpr int32_t kBatchKCap = 1024;  // largest K a batched query may need
 
 }  // namespace cp
 
@@ -127,9 +200,12 @@ struct cp_graph {
   int32_t* perm = nullptr;           // internal -> caller id (reordered graphs)
   std::vector<int32_t> ext2int;      // caller id -> internal id (reordered graphs)
   std::vector<int32_t> degree;       // by caller id
-  cp::BlockDesc* blocks = nullptr;
-  cp::HubDesc* hubs = nullptr;
-  int64_t nblocks = 0, nspecial = 0, nlong = 0, nhubs = 0, hub_segments = 0;
+  cp::DevPlan single;  // plan of the single-source step kernel
+  cp::DevPlan batch;   // plan of the batched step kernel
+  void* plan_mem = nullptr;
   int64_t device_bytes = 0;
   bool reordered = false, borrowed = false;
+  // batched source-tile width chosen by cp_autotune_batch, keyed by (nq, prec)
+  std::map<int64_t, int32_t> tuned_bw;
+  std::mutex tune_mu;
 };

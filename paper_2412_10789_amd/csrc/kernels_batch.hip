@@ -1,0 +1,307 @@
+// Batched ChebyPower kernels: Alg. 3 for many sources at once.
+//
+// The recurrence vectors of bw sources form a tile-major matrix [n][bw]
+// (D^{-1} basis, as in the single-source kernels), so for every arc u -> v
+// one gather reads the bw contiguous values x[u][0..bw) and all bw
+// sources share one pass over the column ids.  A workgroup of 256 threads
+// splits into 256/bw lane groups; each lane owns one source of the tile.
+// Each source carries its own coefficient row, so sources with different
+// truncation steps share the launches (a finished source gets c = 0).
+
+#include <hip/hip_runtime.h>
+
+#include "common.h"
+
+namespace cp {
+namespace {
+
+struct bf16 {
+  uint16_t bits;
+};
+
+template <typename T> struct Acc;
+template <> struct Acc<double> { using type = double; };
+template <> struct Acc<float> { using type = float; };
+template <> struct Acc<bf16> { using type = float; };
+
+__device__ __forceinline__ double to_acc(double v) { return v; }
+__device__ __forceinline__ float to_acc(float v) { return v; }
+__device__ __forceinline__ float to_acc(bf16 v) { return __uint_as_float((uint32_t)v.bits << 16); }
+
+template <typename T> __device__ __forceinline__ T from_acc(typename Acc<T>::type v);
+template <> __device__ __forceinline__ double from_acc<double>(double v) { return v; }
+template <> __device__ __forceinline__ float from_acc<float>(float v) { return v; }
+template <> __device__ __forceinline__ bf16 from_acc<bf16>(float v) {
+  uint32_t u = __float_as_uint(v);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return bf16{(uint16_t)(u >> 16)};
+}
+
+template <typename T> __device__ __forceinline__ T ld_nt(const T* p) { return __builtin_nontemporal_load(p); }
+template <> __device__ __forceinline__ bf16 ld_nt<bf16>(const bf16* p) {
+  return bf16{__builtin_nontemporal_load(&p->bits)};
+}
+template <typename T> __device__ __forceinline__ void st_nt(T* p, T v) { __builtin_nontemporal_store(v, p); }
+template <> __device__ __forceinline__ void st_nt<bf16>(bf16* p, bf16 v) {
+  __builtin_nontemporal_store(v.bits, &p->bits);
+}
+
+__device__ __forceinline__ int64_t logical_block(int64_t w, int64_t nblocks, int64_t nspecial) {
+  if (w < nspecial) return w;
+  const int64_t m = nblocks - nspecial, i = w - nspecial;
+  const int64_t q = m >> 3, r = m & 7, x = i & 7, j = i >> 3;
+  return nspecial + x * q + (x < r ? x : r) + j;
+}
+
+template <typename T, typename A>
+__device__ __forceinline__ void row_update(T* z, A* y, size_t e, A acc, int32_t d, A c) {
+  const A zn = (A(2) * acc) / A(d) - to_acc(ld_nt(z + e));
+  st_nt(z + e, from_acc<T>(zn));
+  st_nt(y + e, ld_nt(y + e) + c * zn);
+}
+
+// Sum over arcs [p0, p1) of x[col[p]][lane]; the workgroup's lane groups
+// take interleaved arcs, partial sums are combined in group order.
+// Result valid in group 0.
+template <typename T, typename A, int BW>
+__device__ __forceinline__ A wg_row_sum(const int32_t* __restrict__ col, const T* __restrict__ x,
+                                        int64_t p0, int64_t p1, int grp, int lane, A (*part)[BW]) {
+  constexpr int G = kThreads / BW;
+  A acc = A(0);
+  int64_t p = p0 + grp;
+  for (; p + 3 * G < p1; p += 4 * G) {
+    const int32_t c0 = col[p], c1 = col[p + G], c2 = col[p + 2 * G], c3 = col[p + 3 * G];
+    const A v0 = to_acc(x[(size_t)c0 * BW + lane]);
+    const A v1 = to_acc(x[(size_t)c1 * BW + lane]);
+    const A v2 = to_acc(x[(size_t)c2 * BW + lane]);
+    const A v3 = to_acc(x[(size_t)c3 * BW + lane]);
+    acc += (v0 + v1) + (v2 + v3);
+  }
+  for (; p < p1; p += G) acc += to_acc(x[(size_t)col[p] * BW + lane]);
+  part[grp][lane] = acc;
+  __syncthreads();
+  A total = A(0);
+  if (grp == 0) {
+    for (int g = 0; g < G; ++g) total += part[g][lane];
+  }
+  return total;
+}
+
+template <typename T, int BW>
+__global__ void __launch_bounds__(kThreads) batch_step_kernel(BatchStepArgs a) {
+  using A = typename Acc<T>::type;
+  constexpr int G = kThreads / BW;
+  __shared__ int32_t cols[kTileNnz];
+  __shared__ int32_t rpl[kTileRows + 1];
+  __shared__ A part[G][BW];
+  __shared__ int32_t last_flag;
+
+  const int tid = threadIdx.x, grp = tid / BW, lane = tid % BW;
+  const int tile = blockIdx.y;
+  const size_t toff = (size_t)tile * (size_t)a.n * BW;
+  const T* __restrict__ x = static_cast<const T*>(a.x) + toff;
+  T* __restrict__ z = static_cast<T*>(a.z) + toff;
+  A* __restrict__ y = static_cast<A*>(a.yacc) + toff;
+  const A c = (A)a.coef_row[tile * BW + lane];
+  const int64_t* __restrict__ rp = a.row_ptr;
+  const int32_t* __restrict__ col = a.col_idx;
+  const int64_t b = logical_block(blockIdx.x, a.nblocks, a.nspecial);
+  const BlockDesc bd = a.blocks[b];
+
+  if (bd.kind == kStream) {
+    const int32_t r0 = bd.r0, nr = bd.r1 - bd.r0;
+    const int64_t p0 = rp[r0];
+    const int32_t cnt = (int32_t)(rp[bd.r1] - p0);
+    for (int j = tid; j <= nr; j += kThreads) rpl[j] = (int32_t)(rp[r0 + j] - p0);
+    for (int i = tid; i < cnt; i += kThreads) cols[i] = ld_nt(col + p0 + i);
+    __syncthreads();
+    // rows of this group: those starting in arc range [grp*cnt/G, (grp+1)*cnt/G)
+    auto first_row_at = [&](int target) {  // smallest j with rpl[j] >= target
+      int lo = 0, hi = nr;
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (rpl[mid] >= target) hi = mid; else lo = mid + 1;
+      }
+      return lo;
+    };
+    const int rlo = grp == 0 ? 0 : first_row_at((grp * cnt + G - 1) / G);
+    const int rhi = grp == G - 1 ? nr : first_row_at(((grp + 1) * cnt + G - 1) / G);
+    for (int r = rlo; r < rhi; ++r) {
+      const int pb = rpl[r], pe = rpl[r + 1];
+      if (pe == pb) continue;
+      A acc = A(0);
+      int p = pb;
+      for (; p + 4 <= pe; p += 4) {
+        const A v0 = to_acc(x[(size_t)cols[p] * BW + lane]);
+        const A v1 = to_acc(x[(size_t)cols[p + 1] * BW + lane]);
+        const A v2 = to_acc(x[(size_t)cols[p + 2] * BW + lane]);
+        const A v3 = to_acc(x[(size_t)cols[p + 3] * BW + lane]);
+        acc += (v0 + v1) + (v2 + v3);
+      }
+      for (; p < pe; ++p) acc += to_acc(x[(size_t)cols[p] * BW + lane]);
+      row_update<T, A>(z, y, (size_t)(r0 + r) * BW + lane, acc, pe - pb, c);
+    }
+    return;
+  }
+
+  if (bd.kind == kLong) {
+    const int64_t v = bd.r0;
+    const int64_t p0 = rp[v], p1 = rp[v + 1];
+    const A total = wg_row_sum<T, A, BW>(col, x, p0, p1, grp, lane, part);
+    if (grp == 0) row_update<T, A>(z, y, (size_t)v * BW + lane, total, (int32_t)(p1 - p0), c);
+    return;
+  }
+
+  // hub segment: partial per (segment, slot); last workgroup of (hub, tile) combines
+  const HubDesc h = a.hubs[bd.r1];
+  const int64_t rb = rp[h.row], re = rp[h.row + 1];
+  const int64_t p0 = rb + (int64_t)bd.aux * kHubSeg;
+  const int64_t p1 = p0 + kHubSeg < re ? p0 + kHubSeg : re;
+  const A total = wg_row_sum<T, A, BW>(col, x, p0, p1, grp, lane, part);
+  A* hp = static_cast<A*>(a.hub_partial);
+  const int slot = tile * BW + lane;
+  if (grp == 0) {
+    __hip_atomic_store(hp + (size_t)(h.base + bd.aux) * a.nq_pad + slot, total, __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+    __threadfence();
+  }
+  __syncthreads();
+  int32_t* counter = a.hub_count + (size_t)bd.r1 * a.ntiles_total + tile;
+  if (tid == 0) {
+    const int32_t prev = __hip_atomic_fetch_add(counter, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    last_flag = prev == h.nseg - 1;
+  }
+  __syncthreads();
+  if (last_flag && grp == 0) {
+    __threadfence();
+    A s = A(0);
+    for (int q = 0; q < h.nseg; ++q)
+      s += __hip_atomic_load(hp + (size_t)(h.base + q) * a.nq_pad + slot, __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+    row_update<T, A>(z, y, (size_t)h.row * BW + lane, s, (int32_t)(re - rb), c);
+    if (lane == 0) __hip_atomic_store(counter, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+// One workgroup per slot: r~_0 = e_s/d_s, r~_1 = D^{-1} P e_s, estimate.
+template <typename T>
+__global__ void __launch_bounds__(kThreads) batch_init_kernel(BatchInitArgs a) {
+  using A = typename Acc<T>::type;
+  const int slot = blockIdx.x;
+  const int64_t s = a.src[slot];
+  if (s < 0) return;
+  const int tile = slot / a.bw, lane = slot % a.bw;
+  const size_t toff = (size_t)tile * (size_t)a.n * a.bw;
+  T* r0 = static_cast<T*>(a.r0) + toff;
+  T* r1 = static_cast<T*>(a.r1) + toff;
+  A* y = static_cast<A*>(a.yacc) + toff;
+  const double c0 = a.coef[slot], c1 = a.coef[a.nq_pad + slot];
+  const int64_t p0 = a.row_ptr[s], ds = a.row_ptr[s + 1] - p0;
+  for (int64_t i = threadIdx.x; i < ds; i += blockDim.x) {
+    const int32_t u = a.col_idx[p0 + i];
+    const int64_t du = a.row_ptr[u + 1] - a.row_ptr[u];
+    const double val = 1.0 / ((double)ds * (double)du);
+    r1[(size_t)u * a.bw + lane] = from_acc<T>((A)val);
+    y[(size_t)u * a.bw + lane] = (A)(c1 * val);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    r0[(size_t)s * a.bw + lane] = from_acc<T>((A)(1.0 / (double)ds));
+    y[(size_t)s * a.bw + lane] = y[(size_t)s * a.bw + lane] + (A)(c0 / (double)ds);
+  }
+}
+
+// Y[perm(v)][q] = d_v * yacc[tile(slot)][v][lane(slot)]
+template <typename A>
+__global__ void __launch_bounds__(kThreads) batch_finalize_kernel(BatchFinalArgs a) {
+  const A* y = static_cast<const A*>(a.yacc);
+  A* out = static_cast<A*>(a.Y);
+  const int64_t total = a.n * a.nq;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) {
+    const int64_t v = i / a.nq;
+    const int q = (int)(i - v * a.nq);
+    const int slot = a.slot_of_query[q];
+    const int tile = slot / a.bw, lane = slot % a.bw;
+    const A val = y[((size_t)tile * a.n + v) * a.bw + lane];
+    const int64_t d = a.row_ptr[v + 1] - a.row_ptr[v];
+    const int64_t vo = a.perm ? a.perm[v] : v;
+    out[vo * a.nq + q] = A(d) * val;
+  }
+}
+
+struct UploadArgs {
+  uint32_t* dst;
+  int32_t count;  // 32-bit words
+  uint32_t vals[kMaxUploadWords];
+};
+
+__global__ void upload_kernel(UploadArgs a) {
+  for (int i = threadIdx.x; i < a.count; i += blockDim.x) a.dst[i] = a.vals[i];
+}
+
+template <typename T>
+hipError_t launch_bs(const BatchStepArgs& a, hipStream_t st) {
+  dim3 grid((unsigned)a.nblocks, (unsigned)a.ntiles), block(kThreads);
+  switch (a.bw) {
+    case 8: hipLaunchKernelGGL((batch_step_kernel<T, 8>), grid, block, 0, st, a); break;
+    case 16: hipLaunchKernelGGL((batch_step_kernel<T, 16>), grid, block, 0, st, a); break;
+    case 32: hipLaunchKernelGGL((batch_step_kernel<T, 32>), grid, block, 0, st, a); break;
+    case 64: hipLaunchKernelGGL((batch_step_kernel<T, 64>), grid, block, 0, st, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_batch_step(int32_t prec, const BatchStepArgs& a, hipStream_t st) {
+  if (a.nblocks <= 0 || a.ntiles <= 0) return hipSuccess;
+  switch (prec) {
+    case CP_F64: return launch_bs<double>(a, st);
+    case CP_F32: return launch_bs<float>(a, st);
+    case CP_BF16: return launch_bs<bf16>(a, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_batch_init(int32_t prec, const BatchInitArgs& a, int32_t nslots, hipStream_t st) {
+  if (nslots <= 0) return hipSuccess;
+  dim3 grid((unsigned)nslots), block(kThreads);
+  switch (prec) {
+    case CP_F64: hipLaunchKernelGGL(batch_init_kernel<double>, grid, block, 0, st, a); break;
+    case CP_F32: hipLaunchKernelGGL(batch_init_kernel<float>, grid, block, 0, st, a); break;
+    case CP_BF16: hipLaunchKernelGGL(batch_init_kernel<bf16>, grid, block, 0, st, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_finalize(int32_t prec, const BatchFinalArgs& a, hipStream_t st) {
+  dim3 grid(2048), block(kThreads);
+  if (prec == CP_F64) hipLaunchKernelGGL(batch_finalize_kernel<double>, grid, block, 0, st, a);
+  else hipLaunchKernelGGL(batch_finalize_kernel<float>, grid, block, 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_upload(void* dst, const void* host, size_t bytes, hipStream_t st) {
+  if (bytes % 4) return hipErrorInvalidValue;
+  uint32_t* d = static_cast<uint32_t*>(dst);
+  const uint32_t* h = static_cast<const uint32_t*>(host);
+  size_t words = bytes / 4;
+  while (words > 0) {
+    UploadArgs u;
+    u.dst = d;
+    u.count = (int32_t)(words < (size_t)kMaxUploadWords ? words : (size_t)kMaxUploadWords);
+    for (int i = 0; i < u.count; ++i) u.vals[i] = h[i];
+    hipLaunchKernelGGL(upload_kernel, dim3(1), dim3(256), 0, st, u);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    d += u.count;
+    h += u.count;
+    words -= (size_t)u.count;
+  }
+  return hipSuccess;
+}
+
+}  // namespace cp

@@ -1,0 +1,133 @@
+"""Batched ChebyPower (cp_power_batch) against the FP64 oracle and against
+single-source runs: every column must be the single-source result of its
+own query (same K), whatever the source-tile width."""
+
+import numpy as np
+import pytest
+
+import synth
+from gpu_util import compare, gpu_graph, oracle_yK, require_gpu
+from oracle import propagation as PR
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    return require_gpu()
+
+
+def _queries(g, nq, seed, tol_choices=(1e-4, 1e-6, 1e-8)):
+    from paper_2412_10789_amd import chebyprop as cp
+
+    srcs = synth.sources(g, nq, seed=seed)
+    tols = synth.tolerance_choice(seed, nq, tol_choices)
+    kinds = [("ppr", 0.2), ("ppr", 0.1), ("hkpr", 5.0), ("hkpr", 3.0)]
+    qs, meta = [], []
+    for i in range(nq):
+        kind, param = kinds[i % len(kinds)]
+        qs.append(cp.make_query(kind, param, int(srcs[i]), float(tols[i])))
+        meta.append((kind, param, int(srcs[i])))
+    return qs, meta
+
+
+@pytest.fixture(scope="module")
+def mid_graph():
+    return synth.chung_lu(150_000, 1_500_000, 2.2, seed=31)
+
+
+@pytest.mark.parametrize("bw", [8, 16, 32, 64])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_batch_columns_match_oracle(torch, mid_graph, bw, prec):
+    g = mid_graph
+    P = PR.transition_matrix(g.row_ptr, g.col_idx)
+    G = gpu_graph(g, reorder=(bw in (16, 64)))
+    nq = 37  # ragged last tile for every width
+    qs, meta = _queries(g, nq, seed=bw)
+    G.set_batch_width(nq, prec, bw)
+    print("CASE batch", prec, bw, flush=True)
+    Y, infos = G.power_batch(qs, prec=prec)
+    Y = Y.cpu().numpy()
+    Ks = [i["K"] for i in infos]
+    assert len(set(Ks)) > 1, "queries must differ in K"
+    for j in range(0, nq, 6):
+        kind, param, s = meta[j]
+        ref = oracle_yK(g, s, kind, param, Ks[j], P)
+        m = compare(Y[:, j], ref)
+        if prec == "f64":
+            assert m["max_abs"] <= 1e-13, (j, m)
+        else:
+            assert m["l1"] <= 2e-6, (j, m)
+
+
+def test_batch_equals_single_source_f64(torch, mid_graph):
+    g = mid_graph
+    G = gpu_graph(g)
+    qs, meta = _queries(g, 12, seed=5)
+    print("CASE batch-vs-single", flush=True)
+    Y, infos = G.power_batch(qs, prec="f64")
+    for j, (kind, param, s) in enumerate(meta):
+        r = G.power(kind, param, s, tol=qs[j].tol, prec="f64")
+        assert r.info["K"] == infos[j]["K"]
+        np.testing.assert_allclose(Y[:, j].cpu().numpy(), r.y.cpu().numpy(), atol=1e-14, rtol=1e-12)
+
+
+def test_batch_hub_split(torch):
+    leaves = 40_000
+    base = synth.erdos_renyi(1_500, 0.005, seed=9)
+    e = [(0, i) for i in range(1, leaves + 1)]
+    rows = np.repeat(np.arange(base.n), base.degrees)
+    e += [(int(a) + 1, int(b) + 1) for a, b in zip(rows, base.col_idx) if a < b]
+    g = synth.from_edges(leaves + 1, e, name="hub")
+    P = PR.transition_matrix(g.row_ptr, g.col_idx)
+    G = gpu_graph(g)
+    from paper_2412_10789_amd import chebyprop as cp
+
+    srcs = [0, 3, 17, leaves, 1200, 5]
+    qs = [cp.make_query("hkpr", 3.0, s, 1e-9) for s in srcs] + [cp.make_query("ppr", 0.2, s, 1e-7) for s in srcs]
+    for bw in (8, 16):
+        G.set_batch_width(len(qs), "f64", bw)
+        print("CASE batch-hub", bw, flush=True)
+        Y, infos = G.power_batch(qs, prec="f64")
+        Y = Y.cpu().numpy()
+        for j, q in enumerate(qs):
+            kind = "hkpr" if q.kind == 1 else "ppr"
+            ref = oracle_yK(g, q.source, kind, q.param, infos[j]["K"], P)
+            assert compare(Y[:, j], ref)["max_abs"] <= 1e-11
+
+
+def test_batch_edge_cases(torch):
+    from paper_2412_10789_amd import chebyprop as cp
+
+    g = synth.chung_lu(5_000, 20_000, 2.5, seed=3)
+    G = gpu_graph(g)
+    s = int(synth.sources(g, 1, seed=1)[0])
+    print("CASE batch-edge", flush=True)
+    # one query, and duplicated sources with different parameters
+    Y1, _ = G.power_batch([cp.make_query("ppr", 0.2, s, 1e-8)], prec="f64")
+    r = G.power("ppr", 0.2, s, tol=1e-8, prec="f64")
+    np.testing.assert_allclose(Y1[:, 0].cpu().numpy(), r.y.cpu().numpy(), atol=1e-15)
+    qs = [cp.make_query("ppr", 0.2, s, 1e-8), cp.make_query("hkpr", 5.0, s, 1e-8),
+          cp.make_query("ppr", 0.2, s, 1e-8)]
+    Y, infos = G.power_batch(qs, prec="f64")
+    np.testing.assert_array_equal(Y[:, 0].cpu().numpy(), Y[:, 2].cpu().numpy())
+    # an invalid query anywhere rejects the whole batch
+    Yb = torch.full((g.n, 3), 7.0, dtype=torch.float64, device="cuda")
+    bad = [qs[0], cp.make_query("ppr", 0.2, g.n + 5, 1e-6), qs[1]]
+    with pytest.raises(cp.ChebypropError) as ei:
+        G.power_batch(bad, prec="f64", Y=Yb)
+    assert ei.value.status == cp.CP_ESOURCE
+    assert bool(torch.all(Yb == 7.0))
+    with pytest.raises(cp.ChebypropError):
+        G.set_batch_width(3, "f32", 12)
+
+
+def test_autotune_picks_a_width(torch, mid_graph):
+    g = mid_graph
+    G = gpu_graph(g)
+    qs, _ = _queries(g, 32, seed=8)
+    print("CASE autotune", flush=True)
+    bw = G.autotune_batch(qs, prec="f32")
+    assert bw in (8, 16, 32)
+    Y, infos = G.power_batch(qs, prec="f32")
+    assert infos[0]["K"] > 0

@@ -1,0 +1,100 @@
+"""Host-side parts of the HIP library, runnable without a GPU: the shared
+library loads and exports every symbol its header declares; coefficients
+and truncation steps agree with the oracle (CPU only)."""
+
+import os
+import re
+
+import numpy as np
+import pytest
+import scipy.special as ss
+
+from oracle import coefficients as C
+from oracle import truncation as T
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def cp():
+    from paper_2412_10789_amd import chebyprop
+
+    chebyprop.load()
+    return chebyprop
+
+
+def _declared():
+    with open(os.path.join(ROOT, "include", "chebyprop.h")) as fh:
+        text = fh.read()
+    return sorted(set(re.findall(r"^\s*(?:cp_status|size_t|const char\*|int32_t)\s+(cp_\w+)\s*\(", text, re.M)))
+
+
+def test_exports_every_declared_symbol(cp):
+    names = _declared()
+    assert len(names) >= 13
+    lib = cp.load()
+    for name in names:
+        assert hasattr(lib, name), name
+    assert sorted(cp.EXPORTED) == names
+
+
+def test_status_strings(cp):
+    for code in range(0, -13, -1):
+        assert cp.cp_status_str(code) not in ("", "unknown status")
+    assert cp.cp_status_str(-99) == "unknown status"
+    assert "gfx950" in cp.cp_version()
+
+
+@pytest.mark.parametrize("alpha", [0.01, 0.1, 0.2, 0.5, 0.9])
+def test_ppr_coefficients_match_oracle(cp, alpha):
+    np.testing.assert_allclose(cp.cp_coeffs(cp.CP_PPR, alpha, 60), C.ppr_chebyshev_coeffs(alpha, 60),
+                               rtol=1e-13, atol=0)
+
+
+@pytest.mark.parametrize("t", [0.3, 1.0, 5.0, 10.0, 40.0])
+def test_hkpr_coefficients_match_oracle_and_library(cp, t):
+    c = cp.cp_coeffs(cp.CP_HKPR, t, 80)
+    np.testing.assert_allclose(c, C.hkpr_chebyshev_coeffs(t, 80), atol=2e-15, rtol=1e-12)
+    ref = np.r_[ss.ive(0, t), 2 * ss.ive(np.arange(1, 81), t)]
+    big = ref > 1e-290
+    np.testing.assert_allclose(c[big], ref[big], rtol=1e-12)
+
+
+@pytest.mark.parametrize("mode,omode", [(0, "certified"), (1, "tail"), (2, "paper")])
+def test_truncation_step_matches_oracle(cp, mode, omode):
+    cases = [("ppr", 0.2), ("ppr", 0.1), ("ppr", 0.02), ("hkpr", 3.0), ("hkpr", 5.0), ("hkpr", 10.0)]
+    for kind, p in cases:
+        for tol in (1e-4, 1e-6, 1e-7, 1e-9):
+            for vol, ds in ((7e7, 8.0), (2e5, 1.0), (1e3, 900.0)):
+                K, tail = cp.cp_choose_K(cp.KINDS[kind], p, tol, mode, 0, vol, ds)
+                Ko = T.choose_K(kind, p, tol, mode=omode, vol=vol, d_s=ds)
+                # the oracle's HKPR tails come from quadrature with ~1e-16 absolute
+                # noise per coefficient (~1e-13 summed); the library's from
+                # Miller's recurrence (relative accuracy).  K may differ only
+                # where the tail sits within that noise of the threshold.
+                noise = 1e-13 if kind == "hkpr" else 1e-16
+                L = np.sqrt(vol / ds) if omode == "certified" else 1.0
+                if K != Ko:
+                    tails = T.chebyshev_tails(kind, p, max(K, Ko) + 1)
+                    assert abs(tails[min(K, Ko)] - tol / L) <= 1e-9 * tol / L + noise, (kind, p, tol, K, Ko)
+                if omode != "paper":
+                    assert abs(tail - T.chebyshev_tails(kind, p, K + 1)[K]) <= 1e-12 * tail + noise
+
+
+def test_argument_errors_without_gpu(cp):
+    with pytest.raises(cp.ChebypropError) as ei:
+        cp.cp_coeffs(cp.CP_PPR, 1.0, 3)
+    assert ei.value.status == cp.CP_EINVAL
+    with pytest.raises(cp.ChebypropError) as ei:
+        cp.cp_choose_K(cp.CP_PPR, 0.2, 1e-6, cp.CP_K_FIXED, 0)
+    assert ei.value.status == cp.CP_EINVAL
+    with pytest.raises(cp.ChebypropError) as ei:
+        cp.cp_choose_K(cp.CP_PPR, 0.2, 1e-6, cp.CP_K_FIXED, 5000, K_max=100)
+    assert ei.value.status == cp.CP_EKMAX
+    with pytest.raises(cp.ChebypropError) as ei:
+        cp.cp_choose_K(cp.CP_HKPR, 5.0, 1.5)
+    assert ei.value.status == cp.CP_EINVAL
+    assert cp.cp_workspace_bytes(0, 1, cp.CP_F32) == 0
+    with pytest.raises(cp.ChebypropError) as ei:
+        cp.cp_graph_create(0, 0, 0, 0, 0, 0)
+    assert ei.value.status == cp.CP_EINVAL
