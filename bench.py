@@ -1,17 +1,23 @@
 #!/usr/bin/env python3
 """ChebyPower benchmark on one MI355X.
 
-Default workload: heat-kernel PageRank (t = 5) on a seeded Chung-Lu graph
-shaped like LiveJournal (n = 4,000,000 target nodes, 35,000,000 undirected
-edges, degree exponent 2.3, int64 offsets / int32 columns), 16 random
-sources run one at a time, FP32 vectors, l1 tolerance 1e-6 with the
-certified truncation step.  One "step" of this benchmark is one pass of the
-whole path (coefficients, K, init, K-1 Chebyshev steps, finalize) for all
-16 sources.
+Main line (the JSON's "value"): heat-kernel PageRank (t = 5) on a seeded
+Chung-Lu graph shaped like LiveJournal (n = 4,000,000 target nodes,
+35,000,000 undirected edges, degree exponent 2.3, int64 offsets / int32
+columns), 16 random sources run one at a time, FP32 vectors, l1 tolerance
+1e-6 with the certified truncation step.  One "step" of this benchmark is
+one pass of the whole path (coefficients, K, init, K-1 Chebyshev steps,
+finalize) for all 16 sources.
 
-Prints one JSON line: GTEPS (CSR arcs traversed per second), the roofline
-of the dominant kernel (the Chebyshev step) against MI355X's 8 TB/s HBM, and
-the FP64 CPU oracle timed on a bounded sample of the same workload.
+Beside it ("batched"): 64 PPR (alpha = 0.2) sources with per-source
+tolerances drawn from {1e-4, 1e-6, 1e-7} in one batch on a Chung-Lu graph
+shaped like Orkut (n = 3,000,000, 117,000,000 edges, exponent 2.2), FP32,
+autotuned source-tile width.
+
+Prints one JSON line: GTEPS (CSR arcs traversed per second, summed over
+sources), the roofline of the dominant kernel (the Chebyshev step) against
+MI355X's 8 TB/s HBM, accuracy against the FP64 oracle, and the FP64 CPU
+oracle timed on a bounded sample of the same workload.
 """
 
 from __future__ import annotations
@@ -32,37 +38,47 @@ METRIC = "GTEPS of Chebyshev steps, % HBM peak; served queries/s + p50/p99 vs pl
 WORKLOADS = {
     # name: (n, m, gamma, seed, kind, param, tol, sources, prec)
     "hkpr-livejournal": (4_000_000, 35_000_000, 2.3, 2, "hkpr", 5.0, 1e-6, 16, "f32"),
-    # small variant for local checks
     "hkpr-small": (200_000, 1_750_000, 2.3, 2, "hkpr", 5.0, 1e-6, 16, "f32"),
 }
+
+BATCH_WORKLOADS = {
+    # name: (n, m, gamma, seed, alpha, sources, tolerance choices, prec)
+    "ppr-batch-orkut": (3_000_000, 117_000_000, 2.2, 3, 0.2, 64, (1e-4, 1e-6, 1e-7), "f32"),
+    "ppr-batch-small": (200_000, 4_000_000, 2.2, 3, 0.2, 64, (1e-4, 1e-6, 1e-7), "f32"),
+}
+
+STORAGE_BYTES = {"f64": 8, "f32": 4, "bf16": 2}
+ACC_BYTES = {"f64": 8, "f32": 4, "bf16": 4}
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def kernel_hash() -> str:
+def kernel_hash(files=("kernels.hip", "kernels_batch.hip", "common.h")) -> str:
     h = hashlib.sha256()
-    for f in ("kernels.hip", "common.h"):
+    for f in files:
         with open(os.path.join(ROOT, "paper_2412_10789_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def step_bytes(n: int, nnz: int, s: int) -> int:
-    """Algorithmic bytes of one Chebyshev step launch: column ids once, row
-    offsets once, and per node one compulsory gather of x, read+write of z,
-    read+write of the estimate."""
-    return 4 * nnz + 8 * (n + 1) + n * 5 * s
+def step_bytes(n: int, nnz: int, prec: str, sources: int = 1) -> int:
+    """Algorithmic bytes of one Chebyshev step launch: column ids and row
+    offsets once, and per node and source one compulsory gather of x,
+    read + write of z, read + write of the estimate."""
+    s, a = STORAGE_BYTES[prec], ACC_BYTES[prec]
+    return 4 * nnz + 8 * (n + 1) + n * sources * (3 * s + 2 * a)
 
 
-def measured_traffic(workload: str, reorder: bool):
+def measured_traffic(key: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary,
+    if it was taken with the current kernel sources (else None)."""
     path = os.path.join(ROOT, "profiles", "step_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         rec = json.load(fh)
-    key = f"{workload}:{'reorder' if reorder else 'native'}"
     e = rec.get(key)
     if not e or e.get("kernel_hash") != kernel_hash():
         return None
@@ -87,49 +103,18 @@ def copy_ceiling(torch, nbytes: int = 1 << 30) -> float:
     return 2 * nbytes / (ms * 1e-3) / 1e9
 
 
-def main() -> int:
-    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="hkpr-livejournal", choices=sorted(WORKLOADS))
-    ap.add_argument("--reorder", default="on", choices=["on", "off"],
-                    help="relabel nodes by degree inside the library (results stay in caller ids)")
-    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
-    ap.add_argument("--copy-probe", action="store_true",
-                    help="also run a plain 1 GiB device copy (counter scaling for rocprofv3 --pmc)")
-    args = ap.parse_args()
-
-    world = int(os.environ.get("WORLD_SIZE", "1"))
-    if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(queries would shard by source across GPUs with the graph replicated; see DESIGN.md)",
-              file=sys.stderr)
-        return 2
-
-    import numpy as np
-    import torch
-
-    import synth
-    from paper_2412_10789_amd import chebyprop as cp
-
-    cp.load()
-    if not torch.cuda.is_available():
-        print("bench.py needs a GPU", file=sys.stderr)
-        return 2
-    torch.cuda.set_device(0)
-
+def run_single(args, torch, cp, synth):
     n_t, m_t, gamma, seed, kind, param, tol, nsrc, prec = WORKLOADS[args.workload]
     t0 = time.time()
     g = synth.chung_lu(n_t, m_t, gamma, seed=seed)
-    log(f"graph: n={g.n} nnz={g.nnz} d_max={g.meta['d_max']} ({time.time() - t0:.1f}s)")
+    log(f"[single] graph: n={g.n} nnz={g.nnz} d_max={g.meta['d_max']} ({time.time() - t0:.1f}s)")
     reorder = args.reorder == "on"
     t0 = time.time()
     G = cp.Graph(g.row_ptr, g.col_idx, reorder=reorder)
-    log(f"graph create (reorder={reorder}): {time.time() - t0:.2f}s, stats={G.stats}")
+    create_s = time.time() - t0
+    log(f"[single] graph create (reorder={reorder}): {create_s:.2f}s, stats={G.stats}")
     srcs = [int(s) for s in synth.sources(g, nsrc, seed=seed)]
-    p = cp.PRECS[prec]
-    Y = torch.empty((nsrc, g.n), dtype=G.out_dtype(p), device="cuda")
+    Y = torch.empty((nsrc, g.n), dtype=G.out_dtype(cp.PRECS[prec]), device="cuda")
     stream = torch.cuda.current_stream().cuda_stream
 
     def one_step(timing: bool):
@@ -142,7 +127,6 @@ def main() -> int:
 
     for _ in range(args.warmup):
         one_step(False)
-    torch.cuda.synchronize()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     infos = []
     torch.cuda.synchronize()
@@ -153,88 +137,190 @@ def main() -> int:
     ev1.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - w0
-    gpu_ms = ev0.elapsed_time(ev1)
-    total_s = max(wall, gpu_ms * 1e-3)
+    total_s = max(wall, ev0.elapsed_time(ev1) * 1e-3)
 
     deg = g.degrees
     arcs = sum((inf["K"] - 1) * g.nnz + int(deg[s]) for inf, s in zip(infos, srcs * args.steps))
     launches = sum(inf["steps"] for inf in infos)
-    step_ms_total = sum(inf["step_ms"] for inf in infos)
-    avg_step_ms = step_ms_total / max(launches, 1)
-    s_bytes = 4 if prec in ("f32", "bf16") else 8
-    if prec == "bf16":
-        s_bytes = 2
-    bpl = step_bytes(g.n, g.nnz, s_bytes)
+    avg_step_ms = sum(inf["step_ms"] for inf in infos) / max(launches, 1)
+    bpl = step_bytes(g.n, g.nnz, prec)
     achieved = bpl / (avg_step_ms * 1e-3) / 1e9
-    value = arcs / total_s / 1e9
-    eff_frac = launches * bpl / total_s / 1e9 / HBM_PEAK_GBPS
     Ks = [inf["K"] for inf in infos[:nsrc]]
-    log(f"K per source: {Ks}; avg step kernel {avg_step_ms * 1e3:.1f} us; wall {wall * 1e3:.1f} ms")
+    log(f"[single] K per source: {Ks}; avg step kernel {avg_step_ms * 1e3:.1f} us; wall {wall * 1e3:.1f} ms")
+    out = dict(
+        value=arcs / total_s / 1e9, total_s=total_s, launches=launches, bpl=bpl,
+        achieved=achieved, avg_step_ms=avg_step_ms, Ks=Ks, g=g, srcs=srcs, Y=Y, reorder=reorder,
+        create_s=create_s, kind=kind, param=param, tol=tol, nsrc=nsrc, prec=prec,
+        workload=f"{args.workload}: HKPR t={param}, {nsrc} sources one at a time, tol {tol} l1 (certified K), "
+                 f"Chung-Lu n={n_t} m={m_t} gamma={gamma} seed={seed}",
+    )
+    G.close()
+    return out
 
+
+def run_batch(args, torch, cp, synth):
+    n_t, m_t, gamma, seed, alpha, nq, tol_choices, prec = BATCH_WORKLOADS[args.batch_workload]
+    t0 = time.time()
+    g = synth.chung_lu(n_t, m_t, gamma, seed=seed)
+    log(f"[batch] graph: n={g.n} nnz={g.nnz} d_max={g.meta['d_max']} ({time.time() - t0:.1f}s)")
+    G = cp.Graph(g.row_ptr, g.col_idx, reorder=args.reorder == "on")
+    srcs = [int(s) for s in synth.sources(g, nq, seed=seed)]
+    tols = [float(t) for t in synth.tolerance_choice(seed, nq, tol_choices)]
+    qs = [cp.make_query("ppr", alpha, s, t) for s, t in zip(srcs, tols)]
+    bw = G.autotune_batch(qs, prec=prec)
+    log(f"[batch] autotuned source-tile width {bw}")
+    qt = [cp.make_query("ppr", alpha, s, t, flags=cp.CP_Q_TIMING) for s, t in zip(srcs, tols)]
+    Yb = torch.empty((g.n, nq), dtype=G.out_dtype(cp.PRECS[prec]), device="cuda")
+    for _ in range(max(1, args.warmup)):
+        G.power_batch(qs, prec=prec, Y=Yb)
+    torch.cuda.synchronize()
+    nb = max(1, args.steps // 2)
+    w0 = time.perf_counter()
+    step_ms = 0.0
+    launches = 0
+    infos = None
+    for _ in range(nb):
+        _, infos = G.power_batch(qt, prec=prec, Y=Yb)
+        step_ms += infos[0]["step_ms"]
+        launches += infos[0]["steps"]
+    torch.cuda.synchronize()
+    total_s = time.perf_counter() - w0
+    Ks = [i["K"] for i in infos]
+    arcs = nb * sum((k - 1) * g.nnz for k in Ks)
+    # algorithmic bytes of each launch: sources still active in it
+    per_batch_bytes = 0
+    for k in range(1, max(Ks)):
+        active = sum(1 for K in Ks if K > k)
+        per_batch_bytes += step_bytes(g.n, g.nnz, prec, active)
+    avg_launch_ms = step_ms / max(launches, 1)
+    achieved = per_batch_bytes * nb / (step_ms * 1e-3) / 1e9
+    out = {
+        "workload": f"{args.batch_workload}: {nq} PPR alpha={alpha} sources in one batch, tol per source from "
+                    f"{list(tol_choices)} (certified K), Chung-Lu n={n_t} m={m_t} gamma={gamma} seed={seed}",
+        "value": round(arcs / total_s / 1e9, 3),
+        "unit": "GTEPS",
+        "ms_per_batch": round(total_s * 1e3 / nb, 3),
+        "n": g.n, "nnz": g.nnz, "source_tile_width": bw, "K_min": min(Ks), "K_max": max(Ks),
+        "roofline": {
+            "bound": "hbm", "kernel": "batch_step_kernel",
+            "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBPS, 4),
+            "traffic": measured_traffic(f"{args.batch_workload}:batch"),
+            "avg_launch_ms": round(avg_launch_ms, 4),
+        },
+    }
+    if not args.no_cpu:
+        from oracle import coefficients as C
+        from oracle import errors as E
+        from oracle import propagation as PR
+
+        j = min(range(nq), key=lambda i: tols[i])  # the tightest tolerance
+        P = PR.transition_matrix(g.row_ptr, g.col_idx)
+        ref = PR.cheby_power(P, srcs[j], C.ppr_chebyshev_coeffs(alpha, Ks[j]), Ks[j])
+        col = Yb[:, j].double().cpu().numpy()
+        out["accuracy_vs_fp64_oracle"] = {"column": j, "tol": tols[j], "K": Ks[j],
+                                          "l1": E.l1(col, ref), "max_abs": E.max_abs(col, ref)}
+    G.close()
+    return out
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="hkpr-livejournal", choices=sorted(WORKLOADS))
+    ap.add_argument("--batch-workload", default="ppr-batch-orkut", choices=sorted(BATCH_WORKLOADS) + ["none"],
+                    help="batched measurement reported beside the main line")
+    ap.add_argument("--reorder", default="on", choices=["on", "off"],
+                    help="relabel nodes by degree inside the library (results stay in caller ids)")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle legs")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="run a plain 1 GiB device copy first (counter scaling for rocprofv3 --pmc)")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(queries would shard by source across GPUs with the graph replicated; see DESIGN.md)",
+              file=sys.stderr)
+        return 2
+
+    import torch
+
+    import synth
+    from paper_2412_10789_amd import chebyprop as cp
+
+    cp.load()
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 2
+    torch.cuda.set_device(0)
+    copy_gbps = copy_ceiling(torch)
+    log(f"device copy ceiling: {copy_gbps:.0f} GB/s")
+
+    S = run_single(args, torch, cp, synth)
     result = {
         "metric": METRIC,
-        "value": round(value, 3),
+        "value": round(S["value"], 3),
         "unit": "GTEPS",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(total_s * 1e3 / args.steps, 4),
+        "ms_per_step": round(S["total_s"] * 1e3 / args.steps, 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if prec == "f32" else prec,
-        "data": "synthetic (seeded Chung-Lu graph shaped like LiveJournal; random sources)",
+        "dtype": S["prec"],
+        "data": "synthetic (seeded Chung-Lu graphs shaped like LiveJournal / Orkut; random sources)",
         "config": {
-            "workload": f"{args.workload}: HKPR t={param}, {nsrc} sources one at a time, tol {tol} l1 "
-                        f"(certified K), Chung-Lu n={n_t} m={m_t} gamma={gamma} seed={seed}",
-            "n": g.n, "nnz": g.nnz, "d_max": int(deg.max()), "sources": nsrc,
-            "K_per_source": Ks, "reorder": reorder, "prec": prec,
-            "parallelism": "single-gpu",
+            "workload": S["workload"],
+            "n": S["g"].n, "nnz": S["g"].nnz, "d_max": int(S["g"].degrees.max()), "sources": S["nsrc"],
+            "K_per_source": S["Ks"], "reorder": S["reorder"], "prec": S["prec"],
+            "graph_create_s": round(S["create_s"], 3), "parallelism": "single-gpu",
         },
-        "hbm_frac_whole_run": round(eff_frac, 4),
+        "hbm_frac_whole_run": round(S["launches"] * S["bpl"] / S["total_s"] / 1e9 / HBM_PEAK_GBPS, 4),
         "roofline": {
             "bound": "hbm",
             "kernel": "step_kernel",
-            "achieved": round(achieved, 1),
+            "achieved": round(S["achieved"], 1),
             "peak": HBM_PEAK_GBPS,
             "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBPS, 4),
-            "traffic": measured_traffic(args.workload, reorder),
-            "bytes_per_launch": bpl,
-            "avg_launch_us": round(avg_step_ms * 1e3, 2),
-            "launches_timed": launches,
+            "frac": round(S["achieved"] / HBM_PEAK_GBPS, 4),
+            "traffic": measured_traffic(f"{args.workload}:{'reorder' if S['reorder'] else 'native'}"),
+            "bytes_per_launch": S["bpl"],
+            "avg_launch_us": round(S["avg_step_ms"] * 1e3, 2),
+            "launches_timed": S["launches"],
         },
+        "copy_ceiling_gbps": round(copy_gbps, 1),
     }
-
-    if args.copy_probe or True:
-        result["copy_ceiling_gbps"] = round(copy_ceiling(torch), 1)
 
     if not args.no_cpu:
         from oracle import coefficients as C
         from oracle import errors as E
         from oracle import propagation as PR
 
-        s = srcs[0]
-        K = Ks[0]
+        g, s, K = S["g"], S["srcs"][0], S["Ks"][0]
         P = PR.transition_matrix(g.row_ptr, g.col_idx)
-        c = C.chebyshev_coeffs(kind, param, K)
+        c = C.chebyshev_coeffs(S["kind"], S["param"], K)
         c0 = time.perf_counter()
         y_ref = PR.cheby_power(P, s, c, K)
         cpu_s = time.perf_counter() - c0
-        cpu_arcs = (K - 1) * g.nnz + int(deg[s])
-        y_gpu = Y[0].double().cpu().numpy()
+        cpu_arcs = (K - 1) * g.nnz + int(g.degrees[s])
+        y_gpu = S["Y"][0].double().cpu().numpy()
         result["cpu_baseline"] = {
             "value": round(cpu_arcs / cpu_s / 1e9, 4),
             "unit": "GTEPS",
             "cores": 1,
             "kind": "oracle",
-            "sample": f"1 of the {nsrc} sources (same graph, same K={K}), FP64 scipy CSR products, "
-                      f"{cpu_s:.1f} s",
+            "sample": f"1 of the {S['nsrc']} sources (same graph, same K={K}): FP64 Alg. 3 with scipy CSR "
+                      f"products, {cpu_s:.1f} s",
         }
-        result["accuracy_vs_fp64_oracle"] = {
-            "source": s, "K": K,
-            "l1": E.l1(y_gpu, y_ref), "max_abs": E.max_abs(y_gpu, y_ref),
-        }
+        result["accuracy_vs_fp64_oracle"] = {"source": s, "K": K, "l1": E.l1(y_gpu, y_ref),
+                                             "max_abs": E.max_abs(y_gpu, y_ref)}
+    del S
+    if args.batch_workload != "none":
+        result["batched"] = run_batch(args, torch, cp, synth)
     print(json.dumps(result), flush=True)
     return 0
 

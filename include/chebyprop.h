@@ -105,6 +105,8 @@ typedef struct {
   double mass;          /* sum_u y(u) (CP_Q_STATS; 1 up to truncation and rounding) */
   double elapsed_ms;    /* whole query on the device (CP_Q_TIMING) */
   double step_ms;       /* sum of the Chebyshev step kernels' durations (CP_Q_TIMING) */
+  double latency_ms;    /* server: submit -> result written (host clock) */
+  double wait_ms;       /* server: submit -> admitted into a resident slot */
 } cp_info;
 
 typedef struct {
@@ -178,6 +180,57 @@ cp_status cp_autotune_batch(cp_graph* g, int32_t nq, const cp_query* q, int32_t 
  * graph (bw in {8, 16, 32, 64}; 0 forgets the choice and returns to the
  * built-in default).  Errors: CP_EINVAL. */
 cp_status cp_set_batch_width(cp_graph* g, int32_t nq, int32_t prec, int32_t bw);
+
+/* ------------------------------------------------------------ query server
+ *
+ * A server keeps the graph and the recurrence state of up to `slots`
+ * queries resident in HBM and advances every admitted query by one
+ * Chebyshev step per batched launch (iteration-level batching: queries join
+ * and leave at step boundaries, each with its own K and coefficients).
+ * Slots are sized by the HBM budget: one slot costs n * (2 * storage + 1 *
+ * accumulator) bytes; queries beyond the resident slots wait in a host
+ * queue of `max_queue` entries.  The server drives the GPU from its own
+ * host thread on its own stream; all calls are thread-safe. */
+typedef struct cp_server cp_server;
+
+typedef struct {
+  int64_t slots;        /* resident query slots */
+  int64_t active;       /* slots holding a running query */
+  int64_t queued;       /* queries waiting for a slot */
+  int64_t completed;    /* queries finished since creation */
+  int64_t cancelled;
+  int64_t ticks;        /* batched step launches */
+  int64_t device_bytes; /* HBM held by the server (state + scratch) */
+  int32_t tile_width;   /* sources per tile in the step kernel */
+  int32_t prec;
+} cp_server_stats;
+
+/* hbm_budget_bytes: HBM the server may use for query state (>= one slot).
+ * max_slots: upper bound on resident queries (0: as many as the budget
+ * allows, at most 1024).  max_queue: waiting-queue capacity.  prec: CP_F32 /
+ * CP_F64 / CP_BF16 for all slots.  Errors: CP_EINVAL, CP_ENOMEM (budget below
+ * one slot or allocation failure), CP_EHIP. */
+cp_status cp_server_create(const cp_graph* g, size_t hbm_budget_bytes, int32_t max_slots, int32_t max_queue,
+                           int32_t prec, cp_server** out);
+/* Queue a query whose result y (device, n elements: float, or double for
+ * CP_F64) will be written to y_out, in caller ids.  y_out must stay valid
+ * until the query is done or cancelled.  Errors: CP_EINVAL, CP_ESOURCE,
+ * CP_EISOLATED, CP_EKMAX (as cp_power), CP_EBUSY (queue full). */
+cp_status cp_server_submit(cp_server* s, const cp_query* q, void* y_out, uint64_t* ticket);
+/* CP_OK and info (may be NULL) when the result is in y_out; CP_EPENDING while
+ * queued or running; CP_ECANCELLED; CP_ENOTFOUND for unknown tickets.  A
+ * ticket is forgotten once poll has returned CP_OK or CP_ECANCELLED. */
+cp_status cp_server_poll(cp_server* s, uint64_t ticket, cp_info* info);
+/* As poll, but blocks until the query is done or cancelled (timeout_ms < 0:
+ * no limit; on timeout returns CP_EPENDING). */
+cp_status cp_server_wait(cp_server* s, uint64_t ticket, int64_t timeout_ms, cp_info* info);
+/* Cancel a queued or running query (its y_out is left partially written or
+ * untouched).  Errors: CP_ENOTFOUND (unknown or already finished). */
+cp_status cp_server_cancel(cp_server* s, uint64_t ticket);
+cp_status cp_server_get_stats(cp_server* s, cp_server_stats* out);
+/* Stop the server thread (queued and running queries are cancelled) and
+ * free its memory. */
+cp_status cp_server_destroy(cp_server* s);
 
 const char* cp_status_str(int32_t st);
 int32_t cp_last_hip_error(void);

@@ -48,6 +48,8 @@ EXPORTED = [
     "cp_graph_create", "cp_graph_destroy", "cp_graph_get_stats", "cp_coeffs", "cp_choose_K",
     "cp_workspace_bytes", "cp_power", "cp_power_batch", "cp_autotune_batch", "cp_set_batch_width",
     "cp_status_str", "cp_last_hip_error", "cp_version",
+    "cp_server_create", "cp_server_submit", "cp_server_poll", "cp_server_wait", "cp_server_cancel",
+    "cp_server_get_stats", "cp_server_destroy",
 ]
 
 
@@ -72,6 +74,8 @@ class cp_info(ctypes.Structure):
         ("mass", ctypes.c_double),
         ("elapsed_ms", ctypes.c_double),
         ("step_ms", ctypes.c_double),
+        ("latency_ms", ctypes.c_double),
+        ("wait_ms", ctypes.c_double),
     ]
 
     def as_dict(self) -> dict:
@@ -89,6 +93,20 @@ class cp_graph_stats(ctypes.Structure):
         ("device_bytes", ctypes.c_int64),
         ("reordered", ctypes.c_int32),
         ("borrowed", ctypes.c_int32),
+    ]
+
+
+class cp_server_stats(ctypes.Structure):
+    _fields_ = [
+        ("slots", ctypes.c_int64),
+        ("active", ctypes.c_int64),
+        ("queued", ctypes.c_int64),
+        ("completed", ctypes.c_int64),
+        ("cancelled", ctypes.c_int64),
+        ("ticks", ctypes.c_int64),
+        ("device_bytes", ctypes.c_int64),
+        ("tile_width", ctypes.c_int32),
+        ("prec", ctypes.c_int32),
     ]
 
 
@@ -114,6 +132,14 @@ def load() -> ctypes.CDLL:
             f"{LIB_PATH} is missing: build it with `python -m paper_2412_10789_amd.build` "
             "(there is no CPU fallback)"
         )
+    # Bind to the HIP runtime PyTorch uses (torch ships its own libamdhip64
+    # with the same soname as ROCm's): streams and device pointers handed
+    # over from torch are only valid in that runtime, so torch is loaded
+    # first and the library's libamdhip64 dependency resolves to it.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(LIB_PATH)
     P = ctypes.c_void_p
     i32, i64, f64, sz = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_size_t
@@ -128,6 +154,13 @@ def load() -> ctypes.CDLL:
         "cp_power_batch": (i32, [P, i32, ctypes.POINTER(cp_query), i32, P, P, sz, P, ctypes.POINTER(cp_info)]),
         "cp_autotune_batch": (i32, [P, i32, ctypes.POINTER(cp_query), i32, P, P, sz, P, ctypes.POINTER(i32)]),
         "cp_set_batch_width": (i32, [P, i32, i32, i32]),
+        "cp_server_create": (i32, [P, sz, i32, i32, i32, ctypes.POINTER(P)]),
+        "cp_server_submit": (i32, [P, ctypes.POINTER(cp_query), P, ctypes.POINTER(ctypes.c_uint64)]),
+        "cp_server_poll": (i32, [P, ctypes.c_uint64, ctypes.POINTER(cp_info)]),
+        "cp_server_wait": (i32, [P, ctypes.c_uint64, i64, ctypes.POINTER(cp_info)]),
+        "cp_server_cancel": (i32, [P, ctypes.c_uint64]),
+        "cp_server_get_stats": (i32, [P, ctypes.POINTER(cp_server_stats)]),
+        "cp_server_destroy": (i32, [P]),
         "cp_status_str": (ctypes.c_char_p, [i32]),
         "cp_last_hip_error": (i32, []),
         "cp_version": (ctypes.c_char_p, []),
@@ -319,3 +352,57 @@ class Graph:
         st = stream if stream is not None else torch.cuda.current_stream(self.device).cuda_stream
         infos = cp_power_batch(self.handle, queries, p, Y.data_ptr(), ws.data_ptr(), nbytes, st)
         return Y, [i.as_dict() for i in infos]
+
+
+# ---------------------------------------------------------------- server
+
+
+class Server:
+    """Query server over a Graph (see cp_server_* in include/chebyprop.h).
+
+    Results land in caller-provided torch tensors; ``submit`` returns a
+    ticket, ``wait``/``poll`` return (status, info dict)."""
+
+    def __init__(self, graph: Graph, hbm_budget_bytes: int, max_slots: int = 0, max_queue: int = 4096,
+                 prec: str = "f32"):
+        self.graph = graph
+        self.prec = PRECS[prec]
+        out = ctypes.c_void_p()
+        _check(load().cp_server_create(graph.handle, int(hbm_budget_bytes), int(max_slots), int(max_queue),
+                                       self.prec, ctypes.byref(out)), "cp_server_create")
+        self.handle = out.value
+
+    def submit(self, query: cp_query, y) -> int:
+        t = ctypes.c_uint64(0)
+        _check(load().cp_server_submit(self.handle, ctypes.byref(query), y.data_ptr(), ctypes.byref(t)),
+               "cp_server_submit")
+        return int(t.value)
+
+    def poll(self, ticket: int):
+        info = cp_info()
+        st = load().cp_server_poll(self.handle, ticket, ctypes.byref(info))
+        return st, (info.as_dict() if st == CP_OK else None)
+
+    def wait(self, ticket: int, timeout_ms: int = -1):
+        info = cp_info()
+        st = load().cp_server_wait(self.handle, ticket, int(timeout_ms), ctypes.byref(info))
+        return st, (info.as_dict() if st == CP_OK else None)
+
+    def cancel(self, ticket: int) -> int:
+        return int(load().cp_server_cancel(self.handle, ticket))
+
+    def stats(self) -> dict:
+        st = cp_server_stats()
+        _check(load().cp_server_get_stats(self.handle, ctypes.byref(st)), "cp_server_get_stats")
+        return {f: getattr(st, f) for f, _ in st._fields_}
+
+    def close(self) -> None:
+        if getattr(self, "handle", None):
+            _check(load().cp_server_destroy(self.handle), "cp_server_destroy")
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # noqa: BLE001
+            pass

@@ -151,6 +151,8 @@ WsLayout ws_layout(const cp_graph* g, int32_t nq, int32_t prec) {
   return L;
 }
 
+}  // namespace
+
 cp_status check_query(const cp_graph* g, const cp_query* q, int64_t* s_int, int32_t* K,
                       double* tail, double* L) {
   if (!q) return CP_EINVAL;
@@ -163,6 +165,8 @@ cp_status check_query(const cp_graph* g, const cp_query* q, int64_t* s_int, int3
   return choose_K_impl(q->kind, q->param, q->tol, q->kmode, q->K_fixed, (double)g->nnz, (double)ds,
                        kDefaultKMax, K, tail);
 }
+
+namespace {
 
 struct BatchLayout {
   int32_t bw = 0, nq_pad = 0, ntiles = 0;
@@ -522,6 +526,8 @@ cp_status cp_power(const cp_graph* g, const cp_query* q, int32_t prec, void* y, 
     info->mass = NAN;
     info->elapsed_ms = NAN;
     info->step_ms = NAN;
+    info->latency_ms = NAN;
+    info->wait_ms = NAN;
   }
   if (stats || timing) {
     CP_HIP_C(hipStreamSynchronize(st));
@@ -661,6 +667,8 @@ cp_status power_batch_bw(cp_graph* g, int32_t nq, const cp_query* q, int32_t pre
       infos[j].mass = NAN;
       infos[j].elapsed_ms = ms_all;
       infos[j].step_ms = ms_steps;
+      infos[j].latency_ms = NAN;
+      infos[j].wait_ms = NAN;
     }
   cleanup();
 #undef CP_HIP_B

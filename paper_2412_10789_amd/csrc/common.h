@@ -174,6 +174,22 @@ struct BatchFinalArgs {
 };
 hipError_t launch_batch_finalize(int32_t prec, const BatchFinalArgs& a, hipStream_t st);
 
+// Server: for finished (or cancelled) slots, write y = D yacc of the slot
+// (caller ids) to its output (if non-null) and zero the slot's columns of
+// all three tile-major buffers, leaving the slot ready for a new query.
+struct SlotFinishArgs {
+  const int64_t* row_ptr;
+  const int32_t* perm;
+  int64_t n;
+  int32_t bw;
+  const int32_t* slots;  // [count]
+  void* const* outs;     // [count] device pointers (null: clear only)
+  void* rA;
+  void* rB;
+  void* yacc;
+};
+hipError_t launch_slot_finish(int32_t prec, const SlotFinishArgs& a, int32_t count, hipStream_t st);
+
 // Copy `bytes` (multiple of 4) of host data to device memory through kernel
 // arguments (no host buffer has to outlive the call; capturable in graphs).
 hipError_t launch_upload(void* dst, const void* host, size_t bytes, hipStream_t st);
@@ -185,6 +201,12 @@ cp_status choose_K_impl(int32_t kind, double param, double tol, int32_t kmode, i
                         double vol, double d_s, int32_t K_max, int32_t* K_out, double* tail_out);
 
 void set_hip_error(hipError_t e);
+
+// Validate a query against a graph: source range and degree, parameter
+// domain, truncation step.  s_int is the source in internal node order, L
+// the certified l1 multiplier sqrt(vol / d_s).
+cp_status check_query(const cp_graph* g, const cp_query* q, int64_t* s_int, int32_t* K,
+                      double* tail, double* L);
 
 constexpr int32_t kDefaultKMax = 4096;
 constexpr int32_t kBatchKCap = 1024;  // largest K a batched query may need

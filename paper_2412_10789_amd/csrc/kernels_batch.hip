@@ -230,6 +230,30 @@ __global__ void __launch_bounds__(kThreads) batch_finalize_kernel(BatchFinalArgs
   }
 }
 
+template <typename T>
+__global__ void __launch_bounds__(kThreads) slot_finish_kernel(SlotFinishArgs a) {
+  using A = typename Acc<T>::type;
+  const int f = blockIdx.y;
+  const int slot = a.slots[f];
+  const int tile = slot / a.bw, lane = slot % a.bw;
+  A* out = static_cast<A*>(a.outs[f]);
+  T* rA = static_cast<T*>(a.rA);
+  T* rB = static_cast<T*>(a.rB);
+  A* y = static_cast<A*>(a.yacc);
+  const T zero = from_acc<T>(A(0));
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < a.n; v += stride) {
+    const size_t e = ((size_t)tile * a.n + v) * a.bw + lane;
+    if (out) {
+      const int64_t d = a.row_ptr[v + 1] - a.row_ptr[v];
+      out[a.perm ? a.perm[v] : v] = A(d) * y[e];
+    }
+    y[e] = A(0);
+    rA[e] = zero;
+    rB[e] = zero;
+  }
+}
+
 struct UploadArgs {
   uint32_t* dst;
   int32_t count;  // 32-bit words
@@ -281,6 +305,18 @@ hipError_t launch_batch_finalize(int32_t prec, const BatchFinalArgs& a, hipStrea
   dim3 grid(2048), block(kThreads);
   if (prec == CP_F64) hipLaunchKernelGGL(batch_finalize_kernel<double>, grid, block, 0, st, a);
   else hipLaunchKernelGGL(batch_finalize_kernel<float>, grid, block, 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_slot_finish(int32_t prec, const SlotFinishArgs& a, int32_t count, hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  dim3 grid(1024, (unsigned)count), block(kThreads);
+  switch (prec) {
+    case CP_F64: hipLaunchKernelGGL(slot_finish_kernel<double>, grid, block, 0, st, a); break;
+    case CP_F32: hipLaunchKernelGGL(slot_finish_kernel<float>, grid, block, 0, st, a); break;
+    case CP_BF16: hipLaunchKernelGGL(slot_finish_kernel<bf16>, grid, block, 0, st, a); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

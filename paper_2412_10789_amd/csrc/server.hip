@@ -1,0 +1,472 @@
+// Query server: resident recurrence state for many queries, advanced by
+// one batched Chebyshev step per launch (iteration-level batching).
+//
+// Slot s of the server owns column (s % bw) of tile (s / bw) in three
+// tile-major matrices [n][bw] (two recurrence buffers and the estimate, the
+// same layout as cp_power_batch).  The two recurrence buffers swap roles
+// after every launch for all slots at once; a query admitted at a step
+// boundary is initialised straight into the current roles (r~_0 into the
+// buffer about to be overwritten, r~_1 into the one about to be gathered),
+// so slots at different k share every launch.  A finished slot is
+// finalised (y = D yacc into the caller's buffer) and its columns zeroed in
+// one pass, ready for the next query.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <mutex>
+#include <new>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "common.h"
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+size_t a256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+enum TicketState { kQueued = 0, kRunning = 1, kDone = 2, kCancelled = 3, kFailed = 4 };
+
+struct Ticket {
+  int state = kQueued;
+  bool cancel_requested = false;
+  cp_query q{};
+  void* y = nullptr;
+  int64_t s_int = 0;
+  int32_t K = 0;
+  double tail = 0, L = 0;
+  std::vector<double> c;
+  int32_t slot = -1;
+  Clock::time_point t_submit, t_admit, t_done;
+};
+
+}  // namespace
+
+struct cp_server {
+  const cp_graph* g = nullptr;
+  int32_t prec = CP_F32, bw = 32, nslots = 0, ntiles = 0;
+  size_t max_queue = 0;
+  hipStream_t st = nullptr;
+  char* dev = nullptr;
+  size_t dev_bytes = 0;
+  // device layout
+  size_t o_rA = 0, o_rB = 0, o_y = 0, o_hcount = 0, o_hpart = 0, o_coef = 0, o_src = 0, o_c01 = 0,
+         o_fslots = 0, o_fouts = 0;
+
+  std::mutex mu;
+  std::condition_variable cv;       // wakes the worker
+  std::condition_variable done_cv;  // wakes waiters
+  bool stop = false;
+  int32_t failed_hip = 0;
+  std::unordered_map<uint64_t, Ticket> tickets;
+  std::deque<uint64_t> queue;
+  std::vector<uint64_t> slot_ticket;  // 0 = free
+  std::vector<int32_t> slot_k;        // current k of the slot's query
+  uint64_t next_ticket = 1;
+  int parity = 0;
+  int64_t completed = 0, cancelled = 0, ticks = 0;
+  std::thread worker;
+
+  void run();
+};
+
+namespace {
+
+size_t storage_bytes(int32_t prec) { return prec == CP_F64 ? 8 : prec == CP_F32 ? 4 : 2; }
+size_t acc_bytes(int32_t prec) { return prec == CP_F64 ? 8 : 4; }
+
+double ms_between(Clock::time_point a, Clock::time_point b) {
+  return std::chrono::duration<double, std::milli>(b - a).count();
+}
+
+void fill_info(const Ticket& t, cp_info* info) {
+  if (!info) return;
+  info->K = t.K;
+  info->steps = t.K - 1;
+  info->tail = t.tail;
+  info->tail_bound_l1 = t.tail * t.L;
+  info->mass = NAN;
+  info->elapsed_ms = NAN;
+  info->step_ms = NAN;
+  info->latency_ms = t.state == kDone ? ms_between(t.t_submit, t.t_done) : NAN;
+  info->wait_ms = t.state >= kRunning ? ms_between(t.t_submit, t.t_admit) : NAN;
+}
+
+}  // namespace
+
+void cp_server::run() {
+  using namespace cp;
+  const size_t nslot = (size_t)nslots;
+  std::vector<double> coef_row(nslot), c01(2 * nslot);
+  std::vector<int64_t> src(nslot);
+  std::vector<int32_t> fin_slots;
+  std::vector<void*> fin_outs;
+  for (;;) {
+    std::vector<int32_t> admitted, stepping, finishing, clearing;
+    std::vector<uint64_t> fin_tickets;
+    {
+      std::unique_lock<std::mutex> lk(mu);
+      cv.wait(lk, [&] {
+        if (stop) return true;
+        if (failed_hip) return false;
+        if (!queue.empty() && std::find(slot_ticket.begin(), slot_ticket.end(), 0) != slot_ticket.end())
+          return true;
+        for (uint64_t t : slot_ticket)
+          if (t) return true;
+        return false;
+      });
+      if (stop) break;
+      // running queries whose cancellation was requested: clear their slots
+      for (int32_t s = 0; s < nslots; ++s) {
+        const uint64_t t = slot_ticket[s];
+        if (t && tickets[t].cancel_requested) {
+          clearing.push_back(s);
+          Ticket& tk = tickets[t];
+          tk.state = kCancelled;
+          tk.slot = -1;
+          slot_ticket[s] = 0;
+          ++cancelled;
+        }
+      }
+      // admit waiting queries into the lowest free slots
+      for (int32_t s = 0; s < nslots && !queue.empty(); ++s) {
+        if (slot_ticket[s]) continue;
+        if (std::find(clearing.begin(), clearing.end(), s) != clearing.end()) continue;
+        const uint64_t t = queue.front();
+        queue.pop_front();
+        Ticket& tk = tickets[t];
+        tk.state = kRunning;
+        tk.slot = s;
+        tk.t_admit = Clock::now();
+        slot_ticket[s] = t;
+        slot_k[s] = 1;
+        admitted.push_back(s);
+      }
+      std::fill(coef_row.begin(), coef_row.end(), 0.0);
+      for (int32_t s = 0; s < nslots; ++s) {
+        const uint64_t t = slot_ticket[s];
+        if (!t) continue;
+        const Ticket& tk = tickets[t];
+        if (slot_k[s] < tk.K) {
+          stepping.push_back(s);
+          coef_row[s] = tk.c[slot_k[s] + 1];
+        }
+      }
+      std::fill(src.begin(), src.end(), -1);
+      for (int32_t s : admitted) {
+        const Ticket& tk = tickets[slot_ticket[s]];
+        src[s] = tk.s_int;
+        c01[s] = tk.c[0];
+        c01[nslot + s] = tk.c[1];
+      }
+      // queries that finish with this launch (or right after init when K == 1)
+      for (int32_t s = 0; s < nslots; ++s) {
+        const uint64_t t = slot_ticket[s];
+        if (!t) continue;
+        const Ticket& tk = tickets[t];
+        const int32_t k_after = slot_k[s] < tk.K ? slot_k[s] + 1 : slot_k[s];
+        if (k_after >= tk.K) {
+          finishing.push_back(s);
+          fin_tickets.push_back(t);
+        }
+      }
+      fin_slots.clear();
+      fin_outs.clear();
+      for (size_t i = 0; i < finishing.size(); ++i) {
+        fin_slots.push_back(finishing[i]);
+        fin_outs.push_back(tickets[fin_tickets[i]].y);
+      }
+      for (int32_t s : clearing) {
+        fin_slots.push_back(s);
+        fin_outs.push_back(nullptr);
+      }
+    }
+
+    // ---- GPU work for this step boundary (no lock held)
+    hipError_t e = hipSuccess;
+    char* w = dev;
+    void* xbuf = w + (parity ? o_rA : o_rB);  // gathered this launch (holds r~_k)
+    void* zbuf = w + (parity ? o_rB : o_rA);  // r~_{k-1}, overwritten with r~_{k+1}
+    auto chk = [&](hipError_t x) {
+      if (e == hipSuccess && x != hipSuccess) e = x;
+    };
+    if (!admitted.empty()) {
+      chk(launch_upload(w + o_src, src.data(), nslot * sizeof(int64_t), st));
+      chk(launch_upload(w + o_c01, c01.data(), 2 * nslot * sizeof(double), st));
+      BatchInitArgs ia{g->row_ptr, g->col_idx, reinterpret_cast<const int64_t*>(w + o_src), g->n, bw, nslots,
+                       zbuf, xbuf, w + o_y, reinterpret_cast<const double*>(w + o_c01)};
+      chk(launch_batch_init(prec, ia, nslots, st));
+    }
+    if (!stepping.empty()) {
+      int32_t tiles = 0;
+      for (int32_t s : stepping) tiles = std::max(tiles, s / bw + 1);
+      chk(launch_upload(w + o_coef, coef_row.data(), nslot * sizeof(double), st));
+      BatchStepArgs sa{};
+      sa.row_ptr = g->row_ptr;
+      sa.col_idx = g->col_idx;
+      sa.blocks = g->batch.blocks;
+      sa.hubs = g->batch.hubs;
+      sa.nblocks = g->batch.nblocks;
+      sa.nspecial = g->batch.nspecial;
+      sa.n = g->n;
+      sa.bw = bw;
+      sa.ntiles = tiles;
+      sa.nq_pad = nslots;
+      sa.x = xbuf;
+      sa.z = zbuf;
+      sa.yacc = w + o_y;
+      sa.coef_row = reinterpret_cast<const double*>(w + o_coef);
+      sa.hub_partial = w + o_hpart;
+      sa.hub_count = reinterpret_cast<int32_t*>(w + o_hcount);
+      sa.ntiles_total = ntiles;
+      chk(launch_batch_step(prec, sa, st));
+    }
+    if (!fin_slots.empty()) {
+      chk(launch_upload(w + o_fslots, fin_slots.data(), fin_slots.size() * sizeof(int32_t), st));
+      chk(launch_upload(w + o_fouts, fin_outs.data(), fin_outs.size() * sizeof(void*), st));
+      SlotFinishArgs fa{g->row_ptr, g->perm, g->n, bw, reinterpret_cast<const int32_t*>(w + o_fslots),
+                        reinterpret_cast<void* const*>(w + o_fouts), w + o_rA, w + o_rB, w + o_y};
+      chk(launch_slot_finish(prec, fa, (int32_t)fin_slots.size(), st));
+    }
+    chk(hipStreamSynchronize(st));
+
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      if (e != hipSuccess) {
+        failed_hip = (int32_t)e;
+        for (auto& kv : tickets)
+          if (kv.second.state == kQueued || kv.second.state == kRunning) kv.second.state = kFailed;
+        queue.clear();
+        std::fill(slot_ticket.begin(), slot_ticket.end(), 0);
+        done_cv.notify_all();
+        continue;
+      }
+      if (!stepping.empty()) {
+        parity ^= 1;
+        ++ticks;
+        for (int32_t s : stepping) ++slot_k[s];
+      }
+      const Clock::time_point now = Clock::now();
+      for (size_t i = 0; i < finishing.size(); ++i) {
+        Ticket& tk = tickets[fin_tickets[i]];
+        tk.state = tk.cancel_requested ? kCancelled : kDone;
+        tk.t_done = now;
+        tk.slot = -1;
+        slot_ticket[finishing[i]] = 0;
+        if (tk.state == kDone) ++completed; else ++cancelled;
+      }
+    }
+    done_cv.notify_all();
+  }
+}
+
+using namespace cp;
+
+extern "C" {
+
+cp_status cp_server_create(const cp_graph* g, size_t hbm_budget_bytes, int32_t max_slots, int32_t max_queue,
+                           int32_t prec, cp_server** out) {
+  if (!g || !out || max_queue < 0 || max_slots < 0 || !(prec == CP_F64 || prec == CP_F32 || prec == CP_BF16))
+    return CP_EINVAL;
+  *out = nullptr;
+  cp_server* s = nullptr;
+  try {
+    s = new cp_server();
+  } catch (const std::bad_alloc&) {
+    return CP_ENOMEM;
+  }
+  s->g = g;
+  s->prec = prec;
+  // one tile row is one 128-byte line per gathered node
+  s->bw = prec == CP_F64 ? 16 : prec == CP_F32 ? 32 : 64;
+  const size_t per_tile = a256((size_t)g->n * s->bw * storage_bytes(prec)) * 2 +
+                          a256((size_t)g->n * s->bw * acc_bytes(prec));
+  int64_t tiles = (int64_t)(hbm_budget_bytes / per_tile);
+  const int32_t cap = max_slots > 0 ? std::min(max_slots, 1024) : 1024;
+  tiles = std::min<int64_t>(tiles, (cap + s->bw - 1) / s->bw);
+  if (tiles < 1) {
+    delete s;
+    return CP_ENOMEM;
+  }
+  s->ntiles = (int32_t)tiles;
+  s->nslots = s->ntiles * s->bw;
+  s->max_queue = (size_t)max_queue;
+  const size_t ns = (size_t)s->nslots;
+  size_t off = 0;
+  s->o_rA = off; off += a256((size_t)g->n * ns * storage_bytes(prec));
+  s->o_rB = off; off += a256((size_t)g->n * ns * storage_bytes(prec));
+  s->o_y = off; off += a256((size_t)g->n * ns * acc_bytes(prec));
+  s->o_hcount = off; off += a256((size_t)std::max<int64_t>(g->batch.nhubs, 1) * s->ntiles * 4);
+  s->o_hpart = off; off += a256((size_t)std::max<int64_t>(g->batch.hub_segments, 1) * ns * 8);
+  s->o_coef = off; off += a256(ns * 8);
+  s->o_src = off; off += a256(ns * 8);
+  s->o_c01 = off; off += a256(2 * ns * 8);
+  s->o_fslots = off; off += a256(ns * 4);
+  s->o_fouts = off; off += a256(ns * 8);
+  s->dev_bytes = off;
+  hipError_t e = hipStreamCreate(&s->st);
+  if (e != hipSuccess) { set_hip_error(e); delete s; return CP_EHIP; }
+  e = hipMalloc(&s->dev, off);
+  if (e != hipSuccess) {
+    (void)hipStreamDestroy(s->st);
+    delete s;
+    if (e == hipErrorOutOfMemory) return CP_ENOMEM;
+    set_hip_error(e);
+    return CP_EHIP;
+  }
+  e = launch_zero(s->dev, s->o_hpart, s->st);  // state buffers and hub counters start at zero
+  if (e == hipSuccess) e = hipStreamSynchronize(s->st);
+  if (e != hipSuccess) {
+    set_hip_error(e);
+    (void)hipFree(s->dev);
+    (void)hipStreamDestroy(s->st);
+    delete s;
+    return CP_EHIP;
+  }
+  s->slot_ticket.assign(ns, 0);
+  s->slot_k.assign(ns, 0);
+  try {
+    s->worker = std::thread([s] { s->run(); });
+  } catch (...) {
+    (void)hipFree(s->dev);
+    (void)hipStreamDestroy(s->st);
+    delete s;
+    return CP_ENOMEM;
+  }
+  *out = s;
+  return CP_OK;
+}
+
+cp_status cp_server_submit(cp_server* s, const cp_query* q, void* y_out, uint64_t* ticket) {
+  if (!s || !q || !y_out || !ticket) return CP_EINVAL;
+  Ticket tk;
+  cp_status rc = check_query(s->g, q, &tk.s_int, &tk.K, &tk.tail, &tk.L);
+  if (rc != CP_OK) return rc;
+  if (tk.K > kBatchKCap) return CP_EKMAX;
+  tk.c.assign(tk.K + 2, 0.0);  // c_{K+1} slot stays 0
+  rc = coeffs_impl(q->kind, q->param, tk.K, tk.c.data());
+  if (rc != CP_OK) return rc;
+  tk.q = *q;
+  tk.y = y_out;
+  tk.t_submit = Clock::now();
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->failed_hip) { set_hip_error((hipError_t)s->failed_hip); return CP_EHIP; }
+    // the queue holds max_queue waiting queries beyond those about to take a free slot
+    const size_t free_slots = (size_t)std::count(s->slot_ticket.begin(), s->slot_ticket.end(), (uint64_t)0);
+    if (s->queue.size() >= s->max_queue + free_slots) return CP_EBUSY;
+    const uint64_t id = s->next_ticket++;
+    s->tickets.emplace(id, std::move(tk));
+    s->queue.push_back(id);
+    *ticket = id;
+  }
+  s->cv.notify_one();
+  return CP_OK;
+}
+
+static cp_status poll_locked(cp_server* s, uint64_t ticket, cp_info* info) {
+  auto it = s->tickets.find(ticket);
+  if (it == s->tickets.end()) return CP_ENOTFOUND;
+  const Ticket& tk = it->second;
+  switch (tk.state) {
+    case kDone:
+      fill_info(tk, info);
+      s->tickets.erase(it);
+      return CP_OK;
+    case kCancelled:
+      s->tickets.erase(it);
+      return CP_ECANCELLED;
+    case kFailed:
+      s->tickets.erase(it);
+      set_hip_error((hipError_t)s->failed_hip);
+      return CP_EHIP;
+    default:
+      return CP_EPENDING;
+  }
+}
+
+cp_status cp_server_poll(cp_server* s, uint64_t ticket, cp_info* info) {
+  if (!s) return CP_EINVAL;
+  std::lock_guard<std::mutex> lk(s->mu);
+  return poll_locked(s, ticket, info);
+}
+
+cp_status cp_server_wait(cp_server* s, uint64_t ticket, int64_t timeout_ms, cp_info* info) {
+  if (!s) return CP_EINVAL;
+  std::unique_lock<std::mutex> lk(s->mu);
+  auto ready = [&] {
+    auto it = s->tickets.find(ticket);
+    return it == s->tickets.end() || it->second.state >= kDone;
+  };
+  if (timeout_ms < 0) s->done_cv.wait(lk, ready);
+  else s->done_cv.wait_for(lk, std::chrono::milliseconds(timeout_ms), ready);
+  return poll_locked(s, ticket, info);
+}
+
+cp_status cp_server_cancel(cp_server* s, uint64_t ticket) {
+  if (!s) return CP_EINVAL;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->tickets.find(ticket);
+    if (it == s->tickets.end() || it->second.state >= kDone) return CP_ENOTFOUND;
+    Ticket& tk = it->second;
+    if (tk.state == kQueued) {
+      s->queue.erase(std::find(s->queue.begin(), s->queue.end(), ticket));
+      tk.state = kCancelled;
+      ++s->cancelled;
+    } else {
+      tk.cancel_requested = true;
+    }
+  }
+  s->cv.notify_one();
+  s->done_cv.notify_all();
+  return CP_OK;
+}
+
+cp_status cp_server_get_stats(cp_server* s, cp_server_stats* out) {
+  if (!s || !out) return CP_EINVAL;
+  std::lock_guard<std::mutex> lk(s->mu);
+  out->slots = s->nslots;
+  out->active = (int64_t)std::count_if(s->slot_ticket.begin(), s->slot_ticket.end(), [](uint64_t t) { return t; });
+  out->queued = (int64_t)s->queue.size();
+  out->completed = s->completed;
+  out->cancelled = s->cancelled;
+  out->ticks = s->ticks;
+  out->device_bytes = (int64_t)s->dev_bytes;
+  out->tile_width = s->bw;
+  out->prec = s->prec;
+  return CP_OK;
+}
+
+cp_status cp_server_destroy(cp_server* s) {
+  if (!s) return CP_EINVAL;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->stop = true;
+  }
+  s->cv.notify_all();
+  if (s->worker.joinable()) s->worker.join();
+  hipError_t e = hipStreamSynchronize(s->st);
+  hipError_t e2 = hipFree(s->dev);
+  hipError_t e3 = hipStreamDestroy(s->st);
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    for (auto& kv : s->tickets)
+      if (kv.second.state < kDone) kv.second.state = kCancelled;
+  }
+  s->done_cv.notify_all();
+  delete s;
+  if (e != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
+    set_hip_error(e != hipSuccess ? e : e2 != hipSuccess ? e2 : e3);
+    return CP_EHIP;
+  }
+  return CP_OK;
+}
+
+}  // extern "C"

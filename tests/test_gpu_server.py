@@ -1,0 +1,125 @@
+"""Query server (iteration-level batching) against single-query runs and the
+oracle; admission, cancellation and error paths."""
+
+import time
+
+import numpy as np
+import pytest
+
+import synth
+from gpu_util import compare, gpu_graph, oracle_yK, require_gpu
+from oracle import propagation as PR
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    return require_gpu()
+
+
+@pytest.fixture(scope="module")
+def graph():
+    return synth.chung_lu(120_000, 1_000_000, 2.3, seed=41)
+
+
+def _mixed_queries(g, n, seed):
+    from paper_2412_10789_amd import chebyprop as cp
+
+    kinds = [("ppr", 0.1), ("ppr", 0.2), ("hkpr", 3.0), ("hkpr", 5.0), ("hkpr", 10.0)]
+    srcs = synth.sources(g, n, seed=seed)
+    tols = synth.tolerance_loguniform(seed, n, 1e-9, 1e-4)
+    return [cp.make_query(*kinds[i % 5], int(srcs[i]), float(tols[i])) for i in range(n)]
+
+
+def test_server_results_equal_single_queries_f64(torch, graph):
+    from paper_2412_10789_amd import chebyprop as cp
+
+    g = graph
+    G = gpu_graph(g, reorder=True)
+    per_tile = 3 * g.n * 16 * 8
+    S = cp.Server(G, hbm_budget_bytes=2 * per_tile + 4096, prec="f64")
+    assert S.stats()["slots"] == 32 and S.stats()["tile_width"] == 16
+    qs = _mixed_queries(g, 70, seed=2)
+    ys = [torch.full((g.n,), -1.0, dtype=torch.float64, device="cuda") for _ in qs]
+    print("CASE server-f64", flush=True)
+    tickets = [S.submit(q, y) for q, y in zip(qs, ys)]
+    infos = []
+    for t in tickets:
+        st, info = S.wait(t, timeout_ms=60_000)
+        assert st == cp.CP_OK, st
+        infos.append(info)
+    torch.cuda.synchronize()
+    for q, y, info in zip(qs, ys, infos):
+        kind = "hkpr" if q.kind == 1 else "ppr"
+        r = G.power(kind, q.param, q.source, tol=q.tol, prec="f64")
+        assert r.info["K"] == info["K"]
+        np.testing.assert_allclose(y.cpu().numpy(), r.y.cpu().numpy(), atol=1e-14, rtol=1e-12)
+        assert info["latency_ms"] >= info["wait_ms"] >= 0
+    st = S.stats()
+    assert st["completed"] == 70 and st["active"] == 0 and st["queued"] == 0
+    S.close()
+
+
+def test_server_f32_against_oracle(torch, graph):
+    from paper_2412_10789_amd import chebyprop as cp
+
+    g = graph
+    P = PR.transition_matrix(g.row_ptr, g.col_idx)
+    G = gpu_graph(g)
+    S = cp.Server(G, hbm_budget_bytes=1 << 30, max_slots=64, prec="f32")
+    qs = _mixed_queries(g, 24, seed=3)
+    ys = [torch.empty(g.n, dtype=torch.float32, device="cuda") for _ in qs]
+    print("CASE server-f32", flush=True)
+    tickets = []
+    for q, y in zip(qs, ys):  # staggered arrivals: queries join running batches
+        tickets.append(S.submit(q, y))
+        time.sleep(0.002)
+    for j, t in enumerate(tickets):
+        st, info = S.wait(t, timeout_ms=60_000)
+        assert st == cp.CP_OK
+        if j % 4 == 0:
+            q = qs[j]
+            kind = "hkpr" if q.kind == 1 else "ppr"
+            ref = oracle_yK(g, q.source, kind, q.param, info["K"], P)
+            assert compare(ys[j].cpu().numpy(), ref)["l1"] <= 2e-6
+    S.close()
+
+
+def test_server_cancel_busy_and_budget(torch, graph):
+    from paper_2412_10789_amd import chebyprop as cp
+
+    g = graph
+    G = gpu_graph(g)
+    with pytest.raises(cp.ChebypropError) as ei:
+        cp.Server(G, hbm_budget_bytes=1000, prec="f32")
+    assert ei.value.status == cp.CP_ENOMEM
+    S = cp.Server(G, hbm_budget_bytes=1 << 40, max_slots=16, max_queue=4, prec="f64")
+    assert S.stats()["slots"] == 16
+    s0 = int(synth.sources(g, 1, seed=9)[0])
+    slow = cp.make_query("ppr", 0.001, s0, 1e-12)  # long-running (K in the hundreds)
+    ys = [torch.empty(g.n, dtype=torch.float64, device="cuda") for _ in range(21)]
+    print("CASE server-cancel", flush=True)
+    tickets = [S.submit(slow, ys[i]) for i in range(20)]
+    with pytest.raises(cp.ChebypropError) as ei:
+        S.submit(slow, ys[20])
+    assert ei.value.status == cp.CP_EBUSY
+    # cancel one queued (the last) and one running (the first) query
+    assert S.cancel(tickets[-1]) == cp.CP_OK
+    t0 = time.time()
+    while S.stats()["active"] == 0 and time.time() - t0 < 10:
+        time.sleep(0.0005)
+    assert S.cancel(tickets[0]) == cp.CP_OK
+    assert S.wait(tickets[-1])[0] == cp.CP_ECANCELLED
+    assert S.wait(tickets[0])[0] == cp.CP_ECANCELLED
+    assert S.cancel(tickets[0]) == cp.CP_ENOTFOUND
+    for t in tickets[1:-1]:
+        st, info = S.wait(t, timeout_ms=120_000)
+        assert st == cp.CP_OK
+    r = G.power("ppr", 0.001, s0, tol=1e-12, prec="f64")
+    np.testing.assert_allclose(ys[1].cpu().numpy(), r.y.cpu().numpy(), atol=1e-14, rtol=1e-12)
+    with pytest.raises(cp.ChebypropError) as ei:
+        S.submit(cp.make_query("ppr", 0.2, g.n + 1, 1e-6), ys[20])
+    assert ei.value.status == cp.CP_ESOURCE
+    assert S.poll(123456789)[0] == cp.CP_ENOTFOUND
+    S.close()
