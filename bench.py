@@ -48,7 +48,7 @@ BATCH_WORKLOADS = {
 }
 
 STORAGE_BYTES = {"f64": 8, "f32": 4, "bf16": 2}
-ACC_BYTES = {"f64": 8, "f32": 4, "bf16": 4}
+ACC_BYTES = {"f64": 8, "f32": 8, "bf16": 4}  # estimate precision (FP32 storage keeps a double estimate)
 
 
 def log(*a):
@@ -224,6 +224,114 @@ def run_batch(args, torch, cp, synth):
     return out
 
 
+SERVE_KINDS = [("ppr", 0.1), ("ppr", 0.2), ("hkpr", 3.0), ("hkpr", 5.0), ("hkpr", 10.0)]
+
+
+def serve_trace(g, synth, seconds: float, rate: float, seed: int = 4):
+    """Seeded Poisson arrivals: exponential gaps, kind uniform over the five
+    GP functions, tolerance log-uniform in [1e-7, 1e-4], uniform sources."""
+    nmax = int(seconds * rate * 2 + 50)
+    u = synth.uniform01(seed ^ 0xA11, nmax)
+    gaps = -np.log1p(-u) / rate
+    t = np.cumsum(gaps)
+    n = int(np.searchsorted(t, seconds))
+    kinds = synth.uniform_ints(seed ^ 0xB22, n, len(SERVE_KINDS))
+    tols = synth.tolerance_loguniform(seed ^ 0xC33, n, 1e-7, 1e-4)
+    srcs = synth.sources(g, n, seed=seed ^ 0xD44)
+    return [(float(t[i]), *SERVE_KINDS[int(kinds[i])], int(srcs[i]), float(tols[i])) for i in range(n)]
+
+
+def _pct(xs, p):
+    return float(np.percentile(np.asarray(xs), p)) if len(xs) else None
+
+
+def run_serve(args, torch, cp, synth, g):
+    """Served query stream: the batched server vs plain one-at-a-time
+    queries on the same arrival trace (same graph, same FP32 precision)."""
+    trace = serve_trace(g, synth, args.serve_seconds, args.serve_rate)
+    G = cp.Graph(g.row_ptr, g.col_idx, reorder=args.reorder == "on")
+    nbuf = 256
+    bufs = [torch.empty(g.n, dtype=torch.float32, device="cuda") for _ in range(nbuf)]
+    # warm both paths (code objects, caches)
+    for (_, kind, param, s, tol) in trace[:4]:
+        G.power(kind, param, s, tol=tol, prec="f32", y=bufs[0])
+    torch.cuda.synchronize()
+
+    # ---- batched server
+    S = cp.Server(G, hbm_budget_bytes=16 << 30, max_slots=512, max_queue=100000, prec="f32")
+    for (_, kind, param, s, tol) in trace[:8]:
+        S.wait(S.submit(cp.make_query(kind, param, s, tol), bufs[1]))
+    tickets = [None] * len(trace)
+    t0 = time.perf_counter()
+    for i, (ta, kind, param, s, tol) in enumerate(trace):
+        dt = ta - (time.perf_counter() - t0)
+        if dt > 0:
+            time.sleep(dt)
+        j = i % nbuf
+        if i >= nbuf:  # the buffer's previous query must be finished before reuse
+            st, info = S.wait(tickets[i - nbuf])
+            tickets[i - nbuf] = (st, info)
+        tickets[i] = S.submit(cp.make_query(kind, param, s, tol), bufs[j])
+    for i in range(max(0, len(trace) - nbuf), len(trace)):
+        if not isinstance(tickets[i], tuple):
+            tickets[i] = S.wait(tickets[i])
+    t_end = time.perf_counter() - t0
+    lat = [info["latency_ms"] for st, info in tickets if st == cp.CP_OK]
+    Ks = [info["K"] for st, info in tickets if st == cp.CP_OK]
+    sstats = S.stats()
+    # accuracy of two served results (rerun into a fresh buffer through the server)
+    acc = None
+    if not args.no_cpu:
+        from oracle import coefficients as C
+        from oracle import errors as E
+        from oracle import propagation as PR
+
+        P = PR.transition_matrix(g.row_ptr, g.col_idx)
+        acc = []
+        for i in (0, len(trace) // 2):
+            _, kind, param, s, tol = trace[i]
+            st, info = S.wait(S.submit(cp.make_query(kind, param, s, tol), bufs[2]))
+            ref = PR.cheby_power(P, s, C.chebyshev_coeffs(kind, param, info["K"]), info["K"])
+            y = bufs[2].double().cpu().numpy()
+            acc.append({"kind": kind, "param": param, "tol": tol, "K": info["K"],
+                        "l1": E.l1(y, ref), "max_abs": E.max_abs(y, ref)})
+    S.close()
+    server = {"completed": len(lat), "qps": round(len(lat) / t_end, 1), "p50_ms": _pct(lat, 50),
+              "p99_ms": _pct(lat, 99), "mean_ms": float(np.mean(lat)) if lat else None,
+              "span_s": round(t_end, 3), "slots": sstats["slots"], "tile_width": sstats["tile_width"],
+              "batched_launches": sstats["ticks"], "mean_K": float(np.mean(Ks)) if Ks else None}
+    log(f"[serve] server: {server}")
+
+    # ---- plain: one query at a time, FIFO, single-source path
+    lat_p = []
+    stream = torch.cuda.current_stream().cuda_stream
+    t0 = time.perf_counter()
+    for (ta, kind, param, s, tol) in trace:
+        now = time.perf_counter() - t0
+        if ta > now:
+            time.sleep(ta - now)
+        G.power(kind, param, s, tol=tol, prec="f32", y=bufs[0], stream=stream)
+        torch.cuda.synchronize()
+        lat_p.append((time.perf_counter() - t0 - ta) * 1e3)
+    t_end_p = time.perf_counter() - t0
+    plain = {"completed": len(lat_p), "qps": round(len(lat_p) / t_end_p, 1), "p50_ms": _pct(lat_p, 50),
+             "p99_ms": _pct(lat_p, 99), "mean_ms": float(np.mean(lat_p)), "span_s": round(t_end_p, 3)}
+    log(f"[serve] plain: {plain}")
+    G.close()
+    out = {
+        "workload": f"Poisson arrivals at {args.serve_rate}/s for {args.serve_seconds} s ({len(trace)} queries): "
+                    f"PPR alpha in {{0.1, 0.2}}, HKPR t in {{3, 5, 10}} uniformly, tol log-uniform [1e-7, 1e-4] "
+                    f"(certified K), FP32 resident state, on the main line's graph",
+        "offered_qps": args.serve_rate,
+        "server": server,
+        "plain": plain,
+        "speedup_qps": round(server["qps"] / plain["qps"], 2) if plain["qps"] else None,
+    }
+    if acc is not None:
+        out["accuracy_vs_fp64_oracle"] = acc
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -232,6 +340,9 @@ def main() -> int:
     ap.add_argument("--workload", default="hkpr-livejournal", choices=sorted(WORKLOADS))
     ap.add_argument("--batch-workload", default="ppr-batch-orkut", choices=sorted(BATCH_WORKLOADS) + ["none"],
                     help="batched measurement reported beside the main line")
+    ap.add_argument("--serve-seconds", type=float, default=3.0,
+                    help="length of the Poisson arrival trace for the served measurement (0: skip)")
+    ap.add_argument("--serve-rate", type=float, default=200.0, help="offered queries per second")
     ap.add_argument("--reorder", default="on", choices=["on", "off"],
                     help="relabel nodes by degree inside the library (results stay in caller ids)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle legs")
@@ -246,6 +357,8 @@ def main() -> int:
               file=sys.stderr)
         return 2
 
+    global np
+    import numpy as np
     import torch
 
     import synth
@@ -318,7 +431,11 @@ def main() -> int:
         }
         result["accuracy_vs_fp64_oracle"] = {"source": s, "K": K, "l1": E.l1(y_gpu, y_ref),
                                              "max_abs": E.max_abs(y_gpu, y_ref)}
+    g_main = S["g"]
     del S
+    if args.serve_seconds > 0:
+        result["served"] = run_serve(args, torch, cp, synth, g_main)
+    del g_main
     if args.batch_workload != "none":
         result["batched"] = run_batch(args, torch, cp, synth)
     print(json.dumps(result), flush=True)

@@ -1,5 +1,10 @@
 // Device kernels of the single-source ChebyPower path (gfx950, wave64).
 //
+// Precision: CP_F64 stores and computes in double; CP_F32 stores the
+// recurrence vectors in float (the gathered bytes) but sums, updates and
+// accumulates the estimate in double; CP_BF16 stores bfloat16 and computes
+// in float.
+//
 // Vectors live in the D^{-1} basis: x = D^{-1} r_k, z = D^{-1} r_{k-1},
 // yacc = D^{-1} y.  Then (P r_k)(v) = sum_{u in N(v)} r_k(u)/d_u is a pure
 // gather-sum of x over row v, and the Chebyshev recurrence of Eq. (6),
@@ -27,7 +32,7 @@ struct bf16 {
 
 template <typename T> struct Acc;
 template <> struct Acc<double> { using type = double; };
-template <> struct Acc<float> { using type = float; };
+template <> struct Acc<float> { using type = double; };  // FP32 storage, FP64 arithmetic
 template <> struct Acc<bf16> { using type = float; };
 
 __device__ __forceinline__ double to_acc(double v) { return v; }
@@ -36,7 +41,7 @@ __device__ __forceinline__ float to_acc(bf16 v) { return __uint_as_float((uint32
 
 template <typename T> __device__ __forceinline__ T from_acc(typename Acc<T>::type v);
 template <> __device__ __forceinline__ double from_acc<double>(double v) { return v; }
-template <> __device__ __forceinline__ float from_acc<float>(float v) { return v; }
+template <> __device__ __forceinline__ float from_acc<float>(double v) { return (float)v; }
 // float -> bfloat16, round to nearest even (finite inputs)
 template <> __device__ __forceinline__ bf16 from_acc<bf16>(float v) {
   uint32_t u = __float_as_uint(v);
@@ -275,17 +280,17 @@ __global__ void __launch_bounds__(kThreads) init_kernel(InitArgs a) {
   }
 }
 
-template <typename A>
+template <typename A, typename O>
 __global__ void __launch_bounds__(kThreads) finalize_kernel(FinalArgs a, double* block_sums) {
   const A* yacc = static_cast<const A*>(a.yacc);
-  A* out = static_cast<A*>(a.y_out);
+  O* out = static_cast<O*>(a.y_out);
   double local = 0.0;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < a.n; v += stride) {
     const int64_t d = a.row_ptr[v + 1] - a.row_ptr[v];
     const A yv = A(d) * yacc[v];
-    out[a.perm ? a.perm[v] : v] = yv;
-    local += (double)yv;
+    out[a.perm ? a.perm[v] : v] = (O)yv;
+    local += (double)(O)yv;
   }
   if (block_sums) {
     __shared__ double ws[kThreads / 64];
@@ -348,9 +353,11 @@ hipError_t launch_init(int32_t prec, const InitArgs& a, hipStream_t st) {
 hipError_t launch_finalize(int32_t prec, const FinalArgs& a, hipStream_t st) {
   double* block_sums = a.mass ? a.mass + 1 : nullptr;  // mass[0] result, mass[1..] scratch
   if (prec == CP_F64)
-    hipLaunchKernelGGL(finalize_kernel<double>, dim3(kFinalBlocks), dim3(kThreads), 0, st, a, block_sums);
+    hipLaunchKernelGGL((finalize_kernel<double, double>), dim3(kFinalBlocks), dim3(kThreads), 0, st, a, block_sums);
+  else if (prec == CP_F32)
+    hipLaunchKernelGGL((finalize_kernel<double, float>), dim3(kFinalBlocks), dim3(kThreads), 0, st, a, block_sums);
   else
-    hipLaunchKernelGGL(finalize_kernel<float>, dim3(kFinalBlocks), dim3(kThreads), 0, st, a, block_sums);
+    hipLaunchKernelGGL((finalize_kernel<float, float>), dim3(kFinalBlocks), dim3(kThreads), 0, st, a, block_sums);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || !a.mass) return e;
   hipLaunchKernelGGL(sum_blocks_kernel, dim3(1), dim3(64), 0, st, block_sums, kFinalBlocks, a.mass);

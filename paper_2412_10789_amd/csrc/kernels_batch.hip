@@ -21,7 +21,10 @@ struct bf16 {
 
 template <typename T> struct Acc;
 template <> struct Acc<double> { using type = double; };
-template <> struct Acc<float> { using type = float; };
+template <> struct Acc<float> { using type = double; };  // FP32 storage, FP64 arithmetic
+
+template <typename T> struct Out { using type = float; };  // result type handed to the caller
+template <> struct Out<double> { using type = double; };
 template <> struct Acc<bf16> { using type = float; };
 
 __device__ __forceinline__ double to_acc(double v) { return v; }
@@ -30,7 +33,7 @@ __device__ __forceinline__ float to_acc(bf16 v) { return __uint_as_float((uint32
 
 template <typename T> __device__ __forceinline__ T from_acc(typename Acc<T>::type v);
 template <> __device__ __forceinline__ double from_acc<double>(double v) { return v; }
-template <> __device__ __forceinline__ float from_acc<float>(float v) { return v; }
+template <> __device__ __forceinline__ float from_acc<float>(double v) { return (float)v; }
 template <> __device__ __forceinline__ bf16 from_acc<bf16>(float v) {
   uint32_t u = __float_as_uint(v);
   u += 0x7FFFu + ((u >> 16) & 1u);
@@ -212,10 +215,10 @@ __global__ void __launch_bounds__(kThreads) batch_init_kernel(BatchInitArgs a) {
 }
 
 // Y[perm(v)][q] = d_v * yacc[tile(slot)][v][lane(slot)]
-template <typename A>
+template <typename A, typename O>
 __global__ void __launch_bounds__(kThreads) batch_finalize_kernel(BatchFinalArgs a) {
   const A* y = static_cast<const A*>(a.yacc);
-  A* out = static_cast<A*>(a.Y);
+  O* out = static_cast<O*>(a.Y);
   const int64_t total = a.n * a.nq;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) {
@@ -226,17 +229,18 @@ __global__ void __launch_bounds__(kThreads) batch_finalize_kernel(BatchFinalArgs
     const A val = y[((size_t)tile * a.n + v) * a.bw + lane];
     const int64_t d = a.row_ptr[v + 1] - a.row_ptr[v];
     const int64_t vo = a.perm ? a.perm[v] : v;
-    out[vo * a.nq + q] = A(d) * val;
+    out[vo * a.nq + q] = (O)(A(d) * val);
   }
 }
 
 template <typename T>
 __global__ void __launch_bounds__(kThreads) slot_finish_kernel(SlotFinishArgs a) {
   using A = typename Acc<T>::type;
+  using O = typename Out<T>::type;
   const int f = blockIdx.y;
   const int slot = a.slots[f];
   const int tile = slot / a.bw, lane = slot % a.bw;
-  A* out = static_cast<A*>(a.outs[f]);
+  O* out = static_cast<O*>(a.outs[f]);
   T* rA = static_cast<T*>(a.rA);
   T* rB = static_cast<T*>(a.rB);
   A* y = static_cast<A*>(a.yacc);
@@ -246,7 +250,7 @@ __global__ void __launch_bounds__(kThreads) slot_finish_kernel(SlotFinishArgs a)
     const size_t e = ((size_t)tile * a.n + v) * a.bw + lane;
     if (out) {
       const int64_t d = a.row_ptr[v + 1] - a.row_ptr[v];
-      out[a.perm ? a.perm[v] : v] = A(d) * y[e];
+      out[a.perm ? a.perm[v] : v] = (O)(A(d) * y[e]);
     }
     y[e] = A(0);
     rA[e] = zero;
@@ -303,8 +307,9 @@ hipError_t launch_batch_init(int32_t prec, const BatchInitArgs& a, int32_t nslot
 
 hipError_t launch_batch_finalize(int32_t prec, const BatchFinalArgs& a, hipStream_t st) {
   dim3 grid(2048), block(kThreads);
-  if (prec == CP_F64) hipLaunchKernelGGL(batch_finalize_kernel<double>, grid, block, 0, st, a);
-  else hipLaunchKernelGGL(batch_finalize_kernel<float>, grid, block, 0, st, a);
+  if (prec == CP_F64) hipLaunchKernelGGL((batch_finalize_kernel<double, double>), grid, block, 0, st, a);
+  else if (prec == CP_F32) hipLaunchKernelGGL((batch_finalize_kernel<double, float>), grid, block, 0, st, a);
+  else hipLaunchKernelGGL((batch_finalize_kernel<float, float>), grid, block, 0, st, a);
   return hipGetLastError();
 }
 

@@ -79,7 +79,7 @@ struct cp_server {
 namespace {
 
 size_t storage_bytes(int32_t prec) { return prec == CP_F64 ? 8 : prec == CP_F32 ? 4 : 2; }
-size_t acc_bytes(int32_t prec) { return prec == CP_F64 ? 8 : 4; }
+size_t acc_bytes(int32_t prec) { return prec == CP_BF16 ? 4 : 8; }
 
 double ms_between(Clock::time_point a, Clock::time_point b) {
   return std::chrono::duration<double, std::milli>(b - a).count();
