@@ -108,11 +108,10 @@ def run_single(args, torch, cp, synth):
     t0 = time.time()
     g = synth.chung_lu(n_t, m_t, gamma, seed=seed)
     log(f"[single] graph: n={g.n} nnz={g.nnz} d_max={g.meta['d_max']} ({time.time() - t0:.1f}s)")
-    reorder = args.reorder == "on"
     t0 = time.time()
-    G = cp.Graph(g.row_ptr, g.col_idx, reorder=reorder)
+    G = cp.Graph(g.row_ptr, g.col_idx, reorder=args.layout == "degree", stripes=args.layout == "stripes")
     create_s = time.time() - t0
-    log(f"[single] graph create (reorder={reorder}): {create_s:.2f}s, stats={G.stats}")
+    log(f"[single] graph create (layout={args.layout}): {create_s:.2f}s, stats={G.stats}")
     srcs = [int(s) for s in synth.sources(g, nsrc, seed=seed)]
     Y = torch.empty((nsrc, g.n), dtype=G.out_dtype(cp.PRECS[prec]), device="cuda")
     stream = torch.cuda.current_stream().cuda_stream
@@ -149,7 +148,7 @@ def run_single(args, torch, cp, synth):
     log(f"[single] K per source: {Ks}; avg step kernel {avg_step_ms * 1e3:.1f} us; wall {wall * 1e3:.1f} ms")
     out = dict(
         value=arcs / total_s / 1e9, total_s=total_s, launches=launches, bpl=bpl,
-        achieved=achieved, avg_step_ms=avg_step_ms, Ks=Ks, g=g, srcs=srcs, Y=Y, reorder=reorder,
+        achieved=achieved, avg_step_ms=avg_step_ms, Ks=Ks, g=g, srcs=srcs, Y=Y, layout=args.layout,
         create_s=create_s, kind=kind, param=param, tol=tol, nsrc=nsrc, prec=prec,
         workload=f"{args.workload}: HKPR t={param}, {nsrc} sources one at a time, tol {tol} l1 (certified K), "
                  f"Chung-Lu n={n_t} m={m_t} gamma={gamma} seed={seed}",
@@ -163,7 +162,7 @@ def run_batch(args, torch, cp, synth):
     t0 = time.time()
     g = synth.chung_lu(n_t, m_t, gamma, seed=seed)
     log(f"[batch] graph: n={g.n} nnz={g.nnz} d_max={g.meta['d_max']} ({time.time() - t0:.1f}s)")
-    G = cp.Graph(g.row_ptr, g.col_idx, reorder=args.reorder == "on")
+    G = cp.Graph(g.row_ptr, g.col_idx, reorder=args.layout != "native")
     srcs = [int(s) for s in synth.sources(g, nq, seed=seed)]
     tols = [float(t) for t in synth.tolerance_choice(seed, nq, tol_choices)]
     qs = [cp.make_query("ppr", alpha, s, t) for s, t in zip(srcs, tols)]
@@ -249,7 +248,7 @@ def run_serve(args, torch, cp, synth, g):
     """Served query stream: the batched server vs plain one-at-a-time
     queries on the same arrival trace (same graph, same FP32 precision)."""
     trace = serve_trace(g, synth, args.serve_seconds, args.serve_rate)
-    G = cp.Graph(g.row_ptr, g.col_idx, reorder=args.reorder == "on")
+    G = cp.Graph(g.row_ptr, g.col_idx, reorder=args.layout != "native", stripes=args.layout == "stripes")
     nbuf = 256
     bufs = [torch.empty(g.n, dtype=torch.float32, device="cuda") for _ in range(nbuf)]
     # warm both paths (code objects, caches)
@@ -343,8 +342,10 @@ def main() -> int:
     ap.add_argument("--serve-seconds", type=float, default=3.0,
                     help="length of the Poisson arrival trace for the served measurement (0: skip)")
     ap.add_argument("--serve-rate", type=float, default=200.0, help="offered queries per second")
-    ap.add_argument("--reorder", default="on", choices=["on", "off"],
-                    help="relabel nodes by degree inside the library (results stay in caller ids)")
+    ap.add_argument("--layout", default="stripes", choices=["stripes", "degree", "native"],
+                    help="graph layout inside the library for single-source queries: XCD column stripes "
+                         "(CP_GRAPH_XCD_STRIPES), degree order (CP_GRAPH_REORDER) or the caller's ids; "
+                         "results are always in caller ids")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle legs")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run a plain 1 GiB device copy first (counter scaling for rocprofv3 --pmc)")
@@ -389,18 +390,18 @@ def main() -> int:
         "config": {
             "workload": S["workload"],
             "n": S["g"].n, "nnz": S["g"].nnz, "d_max": int(S["g"].degrees.max()), "sources": S["nsrc"],
-            "K_per_source": S["Ks"], "reorder": S["reorder"], "prec": S["prec"],
+            "K_per_source": S["Ks"], "layout": S["layout"], "prec": S["prec"],
             "graph_create_s": round(S["create_s"], 3), "parallelism": "single-gpu",
         },
         "hbm_frac_whole_run": round(S["launches"] * S["bpl"] / S["total_s"] / 1e9 / HBM_PEAK_GBPS, 4),
         "roofline": {
             "bound": "hbm",
-            "kernel": "step_kernel",
+            "kernel": "stripe_gather_kernel + stripe_combine_kernel" if S["layout"] == "stripes" else "step_kernel",
             "achieved": round(S["achieved"], 1),
             "peak": HBM_PEAK_GBPS,
             "unit": "GB/s",
             "frac": round(S["achieved"] / HBM_PEAK_GBPS, 4),
-            "traffic": measured_traffic(f"{args.workload}:{'reorder' if S['reorder'] else 'native'}"),
+            "traffic": measured_traffic(f"{args.workload}:{S['layout']}"),
             "bytes_per_launch": S["bpl"],
             "avg_launch_us": round(S["avg_step_ms"] * 1e3, 2),
             "launches_timed": S["launches"],

@@ -82,6 +82,11 @@ typedef enum { CP_K_CERTIFIED = 0, CP_K_TAIL = 1, CP_K_PAPER = 2, CP_K_FIXED = 3
 #define CP_GRAPH_REORDER 0x4  /* relabel nodes internally by decreasing degree
                                  (results are still returned in caller ids) */
 #define CP_GRAPH_HOST 0x8     /* row_ptr / col_idx are host pointers */
+#define CP_GRAPH_XCD_STRIPES 0x10 /* relabel nodes into 8 degree-interleaved column
+                                     stripes and keep one CSR per stripe, so that
+                                     single-source steps gather each stripe on one
+                                     XCD (from its L2); costs a second copy of the
+                                     column ids plus 8 (n+1) int32 offsets */
 
 /* cp_query.flags */
 #define CP_Q_STATS 0x1  /* after the run, synchronize and fill cp_info.mass */
@@ -120,6 +125,7 @@ typedef struct {
   int64_t device_bytes; /* graph bytes held in HBM by the library */
   int32_t reordered;
   int32_t borrowed;
+  int64_t stripe_tiles; /* row tiles of the XCD-striped step (0 if not striped) */
 } cp_graph_stats;
 
 /* Build a graph from symmetric CSR (Sec. 2.1: undirected, A in {0,1}):

@@ -37,6 +37,7 @@ CP_PPR, CP_HKPR = 0, 1
 CP_F64, CP_F32, CP_BF16 = 0, 1, 2
 CP_K_CERTIFIED, CP_K_TAIL, CP_K_PAPER, CP_K_FIXED = 0, 1, 2, 3
 CP_GRAPH_BORROW, CP_GRAPH_VALIDATE, CP_GRAPH_REORDER, CP_GRAPH_HOST = 0x1, 0x2, 0x4, 0x8
+CP_GRAPH_XCD_STRIPES = 0x10
 CP_Q_STATS, CP_Q_TIMING = 0x1, 0x2
 
 KINDS = {"ppr": CP_PPR, "hkpr": CP_HKPR}
@@ -93,6 +94,7 @@ class cp_graph_stats(ctypes.Structure):
         ("device_bytes", ctypes.c_int64),
         ("reordered", ctypes.c_int32),
         ("borrowed", ctypes.c_int32),
+        ("stripe_tiles", ctypes.c_int64),
     ]
 
 
@@ -278,7 +280,8 @@ class Result:
 class Graph:
     """A graph resident in HBM (owned by the library)."""
 
-    def __init__(self, row_ptr, col_idx, reorder: bool = False, validate: bool = False, device=None):
+    def __init__(self, row_ptr, col_idx, reorder: bool = False, validate: bool = False, device=None,
+                 stripes: bool = False):
         import torch
 
         self.torch = torch
@@ -288,7 +291,8 @@ class Graph:
         self.n = int(rp.numel() - 1)
         self.nnz = int(ci.numel())
         self.device = dev
-        flags = (CP_GRAPH_REORDER if reorder else 0) | (CP_GRAPH_VALIDATE if validate else 0)
+        flags = ((CP_GRAPH_REORDER if reorder else 0) | (CP_GRAPH_VALIDATE if validate else 0)
+                 | (CP_GRAPH_XCD_STRIPES if stripes else 0))
         with torch.cuda.device(dev):
             stream = torch.cuda.current_stream().cuda_stream
             self.handle = cp_graph_create(self.n, self.nnz, rp.data_ptr(), ci.data_ptr(), flags, stream)

@@ -86,6 +86,93 @@ bool validate_csr(int64_t n, int64_t nnz, const int64_t* rp, const int32_t* ci) 
 
 }  // namespace
 
+struct StripeLayout {
+  std::vector<int32_t> rp;    // [kStripes][n+1]
+  std::vector<int32_t> cols;  // stripe CSRs concatenated
+  int64_t col_off[kStripes] = {};
+  std::vector<StripeBlock> blocks;  // [tiles][kStripes]
+  int64_t ntiles = 0, nlong = 0;
+};
+
+// Per-stripe CSRs of a graph already relabelled into kStripes contiguous
+// stripes, and the row tiles of the striped step (see common.h).
+void build_stripes(const int64_t* rp, const int32_t* ci, int64_t n, StripeLayout& sl) {
+  int64_t start[kStripes + 1] = {0};
+  for (int j = 0; j < kStripes; ++j) start[j + 1] = start[j] + (n - j + kStripes - 1) / kStripes;
+  // per row, per stripe arc counts (rows are sorted by column)
+  std::vector<int32_t> cnt((size_t)n * kStripes);
+  parallel_rows(n, [&](int64_t b, int64_t e) {
+    for (int64_t v = b; v < e; ++v) {
+      const int32_t* r = ci + rp[v];
+      const int32_t* re = ci + rp[v + 1];
+      const int32_t* lo = r;
+      for (int j = 0; j < kStripes; ++j) {
+        const int32_t* hi = std::lower_bound(lo, re, (int32_t)start[j + 1]);
+        cnt[(size_t)v * kStripes + j] = (int32_t)(hi - lo);
+        lo = hi;
+      }
+    }
+  });
+  sl.rp.assign((size_t)kStripes * (n + 1), 0);
+  int64_t total = 0;
+  for (int j = 0; j < kStripes; ++j) {
+    int32_t* rj = sl.rp.data() + (size_t)j * (n + 1);
+    int64_t acc = 0;
+    for (int64_t v = 0; v < n; ++v) {
+      rj[v] = (int32_t)acc;
+      acc += cnt[(size_t)v * kStripes + j];
+    }
+    rj[n] = (int32_t)acc;
+    sl.col_off[j] = total;
+    total += acc;
+  }
+  sl.cols.resize((size_t)total);
+  parallel_rows(n, [&](int64_t b, int64_t e) {
+    for (int64_t v = b; v < e; ++v) {
+      const int32_t* src = ci + rp[v];
+      for (int j = 0; j < kStripes; ++j) {
+        const int32_t c = cnt[(size_t)v * kStripes + j];
+        int32_t* dst = sl.cols.data() + sl.col_off[j] + sl.rp[(size_t)j * (n + 1) + v];
+        std::copy(src, src + c, dst);
+        src += c;
+      }
+    }
+  });
+  // row tiles: at most kStripeTileRows rows and kStripeTileNnz arcs per stripe
+  int64_t r0 = -1;
+  int64_t acc[kStripes] = {0};
+  auto emit = [&](int64_t a, int64_t b) {  // one tile = kStripes blocks
+    for (int j = 0; j < kStripes; ++j) {
+      const int32_t* rj = sl.rp.data() + (size_t)j * (n + 1);
+      sl.blocks.push_back(StripeBlock{(int32_t)a, (int32_t)(b - a), rj[a], rj[b] - rj[a]});
+    }
+    ++sl.ntiles;
+  };
+  auto close = [&](int64_t r1) {
+    if (r0 >= 0) emit(r0, r1);
+    r0 = -1;
+  };
+  for (int64_t v = 0; v < n; ++v) {
+    const int32_t* c = cnt.data() + (size_t)v * kStripes;
+    const int32_t cmax = *std::max_element(c, c + kStripes);
+    if (cmax > kStripeTileNnz) {
+      close(v);
+      emit(v, v + 1);  // stripes of this row above the tile size stream it whole
+      ++sl.nlong;
+      continue;
+    }
+    bool full = r0 >= 0 && v - r0 == kStripeTileRows;
+    for (int j = 0; j < kStripes && !full; ++j) full = r0 >= 0 && acc[j] + c[j] > kStripeTileNnz;
+    if (full) close(v);
+    if (r0 < 0) {
+      r0 = v;
+      for (int j = 0; j < kStripes; ++j) acc[j] = 0;
+    }
+    for (int j = 0; j < kStripes; ++j) acc[j] += c[j];
+  }
+  close(n);
+}
+
 Plan build_plan(const int64_t* rp, int64_t n, int64_t long_threshold) {
   Plan p;
   std::vector<int32_t> hubs, longs;
@@ -133,7 +220,7 @@ Plan build_plan(const int64_t* rp, int64_t n, int64_t long_threshold) {
 namespace {
 
 struct WsLayout {
-  size_t rA, rB, yacc, hub_count, hub_partial, mass, total;
+  size_t rA, rB, yacc, hub_count, hub_partial, mass, partial, total;
 };
 
 WsLayout ws_layout(const cp_graph* g, int32_t nq, int32_t prec) {
@@ -147,6 +234,8 @@ WsLayout ws_layout(const cp_graph* g, int32_t nq, int32_t prec) {
   L.hub_count = off; off += align256((size_t)std::max<int64_t>(g->single.nhubs, 1) * 4);
   L.hub_partial = off; off += align256((size_t)std::max<int64_t>(g->single.hub_segments, 1) * 8 * nq);
   L.mass = off; off += align256((1 + 1024) * 8);
+  L.partial = off;
+  if (g->striped) off += align256((size_t)kStripes * (size_t)g->n * acc_bytes(prec));
   L.total = off;
   return L;
 }
@@ -270,7 +359,8 @@ cp_status cp_graph_create(int64_t n, int64_t nnz, const int64_t* row_ptr, const 
   *out = nullptr;
   hipStream_t st = static_cast<hipStream_t>(stream);
   const bool host_in = flags & CP_GRAPH_HOST;
-  const bool reorder = flags & CP_GRAPH_REORDER;
+  const bool striped = flags & CP_GRAPH_XCD_STRIPES;
+  const bool reorder = (flags & CP_GRAPH_REORDER) || striped;
   const bool borrow = (flags & CP_GRAPH_BORROW) && !host_in && !reorder;
   cp_graph* g = nullptr;
   try {
@@ -312,6 +402,13 @@ cp_status cp_graph_create(int64_t n, int64_t nnz, const int64_t* row_ptr, const 
       std::iota(perm.begin(), perm.end(), 0);
       std::stable_sort(perm.begin(), perm.end(),
                        [&](int32_t a, int32_t b) { return g->degree[a] > g->degree[b]; });
+      if (striped) {
+        // degree rank r -> stripe r % 8, position r / 8 (stripes contiguous)
+        std::vector<int32_t> by_rank(perm);
+        int64_t start[kStripes + 1] = {0};
+        for (int j = 0; j < kStripes; ++j) start[j + 1] = start[j] + (n - j + kStripes - 1) / kStripes;
+        for (int64_t r = 0; r < n; ++r) perm[start[r % kStripes] + r / kStripes] = by_rank[r];
+      }
       g->ext2int.resize(n);
       for (int64_t i = 0; i < n; ++i) g->ext2int[perm[i]] = (int32_t)i;
       std::vector<int64_t> rp2(n + 1, 0);
@@ -330,6 +427,8 @@ cp_status cp_graph_create(int64_t n, int64_t nnz, const int64_t* row_ptr, const 
       g->reordered = true;
     }
     const Plan plans[2] = {build_plan(rp.data(), n, kTileNnz), build_plan(rp.data(), n, kBatchLong)};
+    StripeLayout sl;
+    if (striped) build_stripes(rp.data(), ci.data(), n, sl);
 
     // device copies: [row_ptr | col_idx | perm] in one allocation, plans in another
     const size_t b_rp = borrow ? 0 : align256(sizeof(int64_t) * (n + 1));
@@ -359,7 +458,37 @@ cp_status cp_graph_create(int64_t n, int64_t nnz, const int64_t* row_ptr, const 
       }
       g->plan_mem = pbase;
     }
-    g->device_bytes = (int64_t)(total + b_plans);
+    size_t b_stripes = 0;
+    if (striped) {
+      b_stripes = align256(sizeof(int32_t) * (size_t)kStripes * (n + 1)) +
+                  align256(sizeof(int32_t) * std::max<size_t>(sl.cols.size(), 1)) +
+                  align256(sizeof(StripeBlock) * std::max<size_t>(sl.blocks.size(), 1));
+      char* sb = nullptr;
+      hipError_t e = hipMalloc(&sb, b_stripes);
+      if (e != hipSuccess) {
+        if (base) (void)hipFree(base);
+        (void)hipFree(pbase);
+        delete g;
+        return e == hipErrorOutOfMemory ? CP_ENOMEM : (set_hip_error(e), CP_EHIP);
+      }
+      g->striped = true;
+      g->s_rp = reinterpret_cast<int32_t*>(sb);
+      sb += align256(sizeof(int32_t) * (size_t)kStripes * (n + 1));
+      g->s_cols = reinterpret_cast<int32_t*>(sb);
+      sb += align256(sizeof(int32_t) * std::max<size_t>(sl.cols.size(), 1));
+      g->s_blocks = reinterpret_cast<StripeBlock*>(sb);
+      g->s_ntiles = sl.ntiles;
+      g->s_nlong = sl.nlong;
+      for (int j = 0; j < kStripes; ++j) g->s_col_off[j] = sl.col_off[j];
+      CP_HIP(hipMemcpyAsync(g->s_rp, sl.rp.data(), sizeof(int32_t) * sl.rp.size(), hipMemcpyHostToDevice, st));
+      if (!sl.cols.empty())
+        CP_HIP(hipMemcpyAsync(g->s_cols, sl.cols.data(), sizeof(int32_t) * sl.cols.size(), hipMemcpyHostToDevice,
+                              st));
+      if (!sl.blocks.empty())
+        CP_HIP(hipMemcpyAsync(g->s_blocks, sl.blocks.data(), sizeof(StripeBlock) * sl.blocks.size(),
+                              hipMemcpyHostToDevice, st));
+    }
+    g->device_bytes = (int64_t)(total + b_plans + b_stripes);
     char* p = base;
     if (borrow) {
       g->row_ptr = row_ptr;
@@ -422,6 +551,10 @@ cp_status cp_graph_destroy(cp_graph* g) {
     hipError_t e2 = hipFree(g->plan_mem);
     if (e == hipSuccess) e = e2;
   }
+  if (g->s_rp) {
+    hipError_t e3 = hipFree(g->s_rp);
+    if (e == hipSuccess) e = e3;
+  }
   delete g;
   if (e != hipSuccess) { set_hip_error(e); return CP_EHIP; }
   return CP_OK;
@@ -438,6 +571,7 @@ cp_status cp_graph_get_stats(const cp_graph* g, cp_graph_stats* out) {
   out->device_bytes = g->device_bytes;
   out->reordered = g->reordered;
   out->borrowed = g->borrowed;
+  out->stripe_tiles = g->s_ntiles;
   return CP_OK;
 }
 
@@ -510,7 +644,22 @@ cp_status cp_power(const cp_graph* g, const cp_query* q, int32_t prec, void* y, 
     sa.z = (k & 1) ? rA : rB;
     sa.c = c[k + 1];
     if (timing) CP_HIP_C(hipEventRecord(ev[2 * k], st));
-    CP_HIP_C(launch_step(prec, sa, st));
+    if (g->striped) {
+      StripeArgs ga{};
+      ga.rp = g->s_rp;
+      ga.cols = g->s_cols;
+      for (int j = 0; j < kStripes; ++j) ga.col_off[j] = g->s_col_off[j];
+      ga.blocks = g->s_blocks;
+      ga.ntiles = g->s_ntiles;
+      ga.n = g->n;
+      ga.x = sa.x;
+      ga.partial = w + W.partial;
+      CP_HIP_C(launch_stripe_gather(prec, ga, st));
+      CombineArgs ca{g->row_ptr, g->n, w + W.partial, sa.z, yacc, sa.c};
+      CP_HIP_C(launch_stripe_combine(prec, ca, st));
+    } else {
+      CP_HIP_C(launch_step(prec, sa, st));
+    }
     if (timing) CP_HIP_C(hipEventRecord(ev[2 * k + 1], st));
   }
   double* mass = stats ? reinterpret_cast<double*>(w + W.mass) : nullptr;

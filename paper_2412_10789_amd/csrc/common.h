@@ -69,6 +69,55 @@ struct DevPlan {
   int64_t nblocks = 0, nspecial = 0, nlong = 0, nhubs = 0, hub_segments = 0;
 };
 
+// ------------------------------------------------------------ XCD stripes
+//
+// With CP_GRAPH_XCD_STRIPES the nodes are relabelled so that degree rank r
+// goes to stripe r % 8, position r / 8: eight contiguous id ranges of equal
+// size and (statistically) equal arc mass, each degree-ordered.  Each
+// stripe's arcs are also stored as a CSR of their own (all rows, columns in
+// that stripe only).  A Chebyshev step then runs as
+//   1. stripe kernel: workgroup w = 8 t + j handles row tile t restricted
+//      to stripe j; workgroups are dispatched round-robin over the 8 XCDs,
+//      so XCD j only ever gathers from stripe j's slice of x and that slice
+//      stays in its L2; each writes the partial row sums of its stripe;
+//   2. combine kernel: the 8 partials of every row are added in stripe
+//      order and the recurrence / estimate update is applied.
+
+constexpr int kStripes = 8;
+constexpr int kStripeTileNnz = 2048;   // arcs per (tile, stripe)
+constexpr int kStripeTileRows = 1024;  // rows per tile
+
+// One workgroup of the striped step: rows [r0, r0 + nr) of the tile,
+// restricted to stripe (block index % 8), whose arcs are cols[p0, p0 + cnt)
+// of that stripe's CSR.  cnt > kStripeTileNnz marks a single long row
+// streamed by the whole workgroup.
+struct StripeBlock {
+  int32_t r0, nr;
+  int32_t p0, cnt;
+};
+
+struct StripeArgs {
+  const int32_t* rp;                // [kStripes][n+1] per-stripe row offsets
+  const int32_t* cols;              // stripe CSRs, concatenated
+  int64_t col_off[kStripes];        // start of stripe j's columns in cols
+  const StripeBlock* blocks;        // [ntiles * kStripes], block index = 8 * tile + stripe
+  int64_t ntiles;
+  int64_t n;
+  const void* x;
+  void* partial;                    // Acc[kStripes][n]
+};
+hipError_t launch_stripe_gather(int32_t prec, const StripeArgs& a, hipStream_t st);
+
+struct CombineArgs {
+  const int64_t* row_ptr;
+  int64_t n;
+  const void* partial;              // Acc[kStripes][n]
+  void* z;
+  void* yacc;
+  double c;
+};
+hipError_t launch_stripe_combine(int32_t prec, const CombineArgs& a, hipStream_t st);
+
 // ------------------------------------------------------------------ kernels
 
 // Chebyshev step over all blocks: for every row v
@@ -222,6 +271,13 @@ struct cp_graph {
   int32_t* perm = nullptr;           // internal -> caller id (reordered graphs)
   std::vector<int32_t> ext2int;      // caller id -> internal id (reordered graphs)
   std::vector<int32_t> degree;       // by caller id
+  // XCD-striped layout (CP_GRAPH_XCD_STRIPES)
+  bool striped = false;
+  int32_t* s_rp = nullptr;          // [8][n+1]
+  int32_t* s_cols = nullptr;        // nnz
+  int64_t s_col_off[cp::kStripes] = {};
+  cp::StripeBlock* s_blocks = nullptr;
+  int64_t s_ntiles = 0, s_nlong = 0;
   cp::DevPlan single;  // plan of the single-source step kernel
   cp::DevPlan batch;   // plan of the batched step kernel
   void* plan_mem = nullptr;

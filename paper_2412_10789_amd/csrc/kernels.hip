@@ -116,6 +116,68 @@ __device__ __forceinline__ A block_gather_sum(const int32_t* __restrict__ col, c
   return total;
 }
 
+// Row sums of an LDS tile: vals[0..cnt) holds the gathered values of the
+// tile's arcs, rpl[0..nr] the tile-relative row offsets (cnt <= kTileNnz).
+// Thread t owns arcs [CH t, CH t + CH); heads are row starts.  (F, V) = (chunk holds
+// a head, sum since the last head) is scanned over threads (wavefront
+// shuffles, then wavefront totals in LDS) to give each thread the partial
+// sum of the row still open at its chunk start; the thread holding a row's
+// last arc writes rowsum[row].  Caller: vals/rpl staged, rowsum zeroed,
+// barrier passed.  Ends with a barrier.
+template <int CH, typename VT, typename A>
+__device__ __forceinline__ void tile_rowsums(const VT* vals, const int32_t* rpl, int nr, int cnt, A* rowsum,
+                                             A* wsum, int32_t* wflag) {
+  const int tid = threadIdx.x;
+  const int start = tid * CH;
+  const int end = start + CH < cnt ? start + CH : cnt;
+  int row = 0;
+  int32_t F = 0;
+  A V = A(0);
+  if (start < cnt) {
+    int lo = 0, hi = nr - 1;  // largest j with rpl[j] <= start
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (rpl[mid] <= start) lo = mid; else hi = mid - 1;
+    }
+    row = lo;
+    int r = row;
+    for (int p = start; p < end; ++p) {
+      while (rpl[r + 1] <= p) ++r;
+      if (rpl[r] == p) { F = 1; V = A(0); }
+      V += (A)vals[p];
+    }
+  }
+  const int lane = tid & 63, wv = tid >> 6;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const A Vp = __shfl_up(V, off, 64);
+    const int32_t Fp = __shfl_up(F, off, 64);
+    if (lane >= off) {
+      if (!F) V = Vp + V;
+      F |= Fp;
+    }
+  }
+  if (lane == 63) { wsum[wv] = V; wflag[wv] = F; }
+  __syncthreads();
+  A Vex = __shfl_up(V, 1, 64);
+  int32_t Fex = __shfl_up(F, 1, 64);
+  if (lane == 0) { Vex = A(0); Fex = 0; }
+  A Cw = A(0);
+  for (int q = 0; q < wv; ++q) Cw = wflag[q] ? wsum[q] : Cw + wsum[q];
+  const A carry = Fex ? Vex : Cw + Vex;
+  if (start < cnt) {
+    int r = row;
+    A acc = carry;
+    for (int p = start; p < end; ++p) {
+      while (rpl[r + 1] <= p) ++r;
+      if (rpl[r] == p) acc = A(0);
+      acc += (A)vals[p];
+      if (p + 1 == rpl[r + 1]) rowsum[r] = acc;
+    }
+  }
+  __syncthreads();
+}
+
 template <typename T>
 __global__ void __launch_bounds__(kThreads) step_kernel(StepArgs a) {
   using A = typename Acc<T>::type;
@@ -159,58 +221,7 @@ __global__ void __launch_bounds__(kThreads) step_kernel(StepArgs a) {
     }
     __syncthreads();
 
-    // Phase 2: segmented sum.  Thread t owns arcs [8t, 8t+8); heads are row
-    // starts.  (F, V) = (chunk holds a head, sum since the last head) is
-    // scanned over threads to give each thread the partial sum of the row
-    // still open at its chunk start.
-    const int start = tid * kPerThread;
-    const int end = start + kPerThread < cnt ? start + kPerThread : cnt;
-    int row = 0;
-    int32_t F = 0;
-    A V = A(0);
-    if (start < cnt) {
-      int lo = 0, hi = nr - 1;  // largest j with rpl[j] <= start
-      while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (rpl[mid] <= start) lo = mid; else hi = mid - 1;
-      }
-      row = lo;
-      int r = row;
-      for (int p = start; p < end; ++p) {
-        while (rpl[r + 1] <= p) ++r;
-        if (rpl[r] == p) { F = 1; V = A(0); }
-        V += vals[p];
-      }
-    }
-    const int lane = tid & 63, wv = tid >> 6;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-      const A Vp = __shfl_up(V, off, 64);
-      const int32_t Fp = __shfl_up(F, off, 64);
-      if (lane >= off) {
-        if (!F) V = Vp + V;
-        F |= Fp;
-      }
-    }
-    if (lane == 63) { wsum[wv] = V; wflag[wv] = F; }
-    __syncthreads();
-    A Vex = __shfl_up(V, 1, 64);
-    int32_t Fex = __shfl_up(F, 1, 64);
-    if (lane == 0) { Vex = A(0); Fex = 0; }
-    A Cw = A(0);
-    for (int q = 0; q < wv; ++q) Cw = wflag[q] ? wsum[q] : Cw + wsum[q];
-    const A carry = Fex ? Vex : Cw + Vex;
-    if (start < cnt) {
-      int r = row;
-      A acc = carry;
-      for (int p = start; p < end; ++p) {
-        while (rpl[r + 1] <= p) ++r;
-        if (rpl[r] == p) acc = A(0);
-        acc += vals[p];
-        if (p + 1 == rpl[r + 1]) rowsum[r] = acc;
-      }
-    }
-    __syncthreads();
+    tile_rowsums<kPerThread, A, A>(vals, rpl, nr, cnt, rowsum, wsum, wflag);
 
     // Phase 3: row-parallel recurrence and accumulation.
     for (int j = tid; j < nr; j += kThreads) {
@@ -246,6 +257,82 @@ __global__ void __launch_bounds__(kThreads) step_kernel(StepArgs a) {
       row_update<T, A>(z, yacc, h.row, s, (int32_t)(re - rb), c);
       __hip_atomic_store(a.hub_count + bd.r1, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
+  }
+}
+
+
+// LDS copy of gathered values: the stored precision (exact), float for bf16.
+template <typename T> struct Lds { using type = T; };
+template <> struct Lds<bf16> { using type = float; };
+
+// One (row tile, stripe) block of an XCD-striped step: partial row sums of
+// the tile's rows over the stripe's columns.  Workgroup w handles tile
+// w / 8 and stripe w % 8, so every workgroup of stripe j runs on XCD j.
+template <typename T>
+__global__ void __launch_bounds__(kThreads) stripe_gather_kernel(StripeArgs a) {
+  using A = typename Acc<T>::type;
+  using L = typename Lds<T>::type;
+  __shared__ L vals[kStripeTileNnz];
+  __shared__ int32_t rpl[kStripeTileRows + 1];
+  __shared__ A rowsum[kStripeTileRows];
+  __shared__ A wsum[kThreads / 64];
+  __shared__ int32_t wflag[kThreads / 64];
+
+  const int tid = threadIdx.x;
+  const int j = (int)(blockIdx.x % kStripes);
+  const StripeBlock sb = a.blocks[blockIdx.x];
+  const int32_t* __restrict__ rpj = a.rp + (size_t)j * (size_t)(a.n + 1);
+  const int32_t* __restrict__ cols = a.cols + a.col_off[j];
+  const T* __restrict__ x = static_cast<const T*>(a.x);
+  A* __restrict__ part = static_cast<A*>(a.partial) + (size_t)j * (size_t)a.n;
+  const int32_t r0 = sb.r0, nr = sb.nr, p0 = sb.p0, cnt = sb.cnt;
+
+  if (cnt <= kStripeTileNnz) {
+    // column ids and row offsets only depend on the descriptor: issue both
+    constexpr int CH = kStripeTileNnz / kThreads;
+    int32_t idx[CH];
+#pragma unroll
+    for (int u = 0; u < CH; ++u) {
+      const int i = tid + u * kThreads;
+      idx[u] = i < cnt ? ld_stream(cols + p0 + i) : -1;
+    }
+    for (int i = tid; i <= nr; i += kThreads) rpl[i] = rpj[r0 + i] - p0;
+    for (int i = tid; i < nr; i += kThreads) rowsum[i] = A(0);
+    L v[CH];
+#pragma unroll
+    for (int u = 0; u < CH; ++u) v[u] = idx[u] >= 0 ? (L)to_acc(x[idx[u]]) : L(0);
+#pragma unroll
+    for (int u = 0; u < CH; ++u) {
+      const int i = tid + u * kThreads;
+      if (i < cnt) vals[i] = v[u];
+    }
+    __syncthreads();
+    tile_rowsums<CH, L, A>(vals, rpl, nr, cnt, rowsum, wsum, wflag);
+    for (int i = tid; i < nr; i += kThreads) st_stream(part + r0 + i, rowsum[i]);
+    return;
+  }
+  // one row whose stripe segment exceeds the LDS tile: whole-workgroup stream
+  const A total = block_gather_sum<T, A>(cols, x, p0, (int64_t)p0 + cnt, wsum);
+  if (tid == 0) st_stream(part + r0, total);
+}
+
+// Combine the 8 stripe partials of every row (in stripe order) and apply the
+// recurrence and estimate update.
+template <typename T>
+__global__ void __launch_bounds__(kThreads) stripe_combine_kernel(CombineArgs a) {
+  using A = typename Acc<T>::type;
+  const A* __restrict__ part = static_cast<const A*>(a.partial);
+  T* __restrict__ z = static_cast<T*>(a.z);
+  A* __restrict__ yacc = static_cast<A*>(a.yacc);
+  const A c = (A)a.c;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < a.n; v += stride) {
+    const int64_t d = a.row_ptr[v + 1] - a.row_ptr[v];
+    if (d == 0) continue;
+    A acc = A(0);
+#pragma unroll
+    for (int j = 0; j < kStripes; ++j) acc += ld_stream(part + (size_t)j * (size_t)a.n + v);
+    row_update<T, A>(z, yacc, v, acc, (int32_t)d, c);
   }
 }
 
@@ -324,6 +411,32 @@ hipError_t launch_step(int32_t prec, const StepArgs& a, hipStream_t st) {
     case CP_F64: hipLaunchKernelGGL(step_kernel<double>, grid, block, 0, st, a); break;
     case CP_F32: hipLaunchKernelGGL(step_kernel<float>, grid, block, 0, st, a); break;
     case CP_BF16: hipLaunchKernelGGL(step_kernel<bf16>, grid, block, 0, st, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_stripe_gather(int32_t prec, const StripeArgs& a, hipStream_t st) {
+  if (a.ntiles <= 0) return hipSuccess;
+  dim3 grid((unsigned)(a.ntiles * kStripes)), block(kThreads);
+  switch (prec) {
+    case CP_F64: hipLaunchKernelGGL(stripe_gather_kernel<double>, grid, block, 0, st, a); break;
+    case CP_F32: hipLaunchKernelGGL(stripe_gather_kernel<float>, grid, block, 0, st, a); break;
+    case CP_BF16: hipLaunchKernelGGL(stripe_gather_kernel<bf16>, grid, block, 0, st, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_stripe_combine(int32_t prec, const CombineArgs& a, hipStream_t st) {
+  int64_t blocks = (a.n + kThreads - 1) / kThreads;
+  if (blocks > 4096) blocks = 4096;
+  if (blocks < 1) blocks = 1;
+  dim3 grid((unsigned)blocks), block(kThreads);
+  switch (prec) {
+    case CP_F64: hipLaunchKernelGGL(stripe_combine_kernel<double>, grid, block, 0, st, a); break;
+    case CP_F32: hipLaunchKernelGGL(stripe_combine_kernel<float>, grid, block, 0, st, a); break;
+    case CP_BF16: hipLaunchKernelGGL(stripe_combine_kernel<bf16>, grid, block, 0, st, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

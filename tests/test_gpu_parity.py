@@ -207,3 +207,43 @@ def test_config2_full_size_f32(torch):
             assert m["l1"] <= 2e-6
             assert E.l1(y, exact) <= 1e-6
         G.close()
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_xcd_striped_layout(torch, prec):
+    """XCD-striped single-source steps (8 column stripes, partial sums
+    combined in stripe order) against the oracle: many row tiles, rows
+    whose stripe segment exceeds one LDS tile, ragged stripes (n % 8 != 0)."""
+    g = synth.chung_lu(150_003, 2_400_000, 2.0, seed=17)
+    P = PR.transition_matrix(g.row_ptr, g.col_idx)
+    G = gpu_graph(g, stripes=True)
+    assert G.stats["stripe_tiles"] > 0 and G.stats["reordered"] == 1
+    for kind, param in [("ppr", 0.2), ("hkpr", 5.0)]:
+        for s in synth.sources(g, 2, seed=7):
+            _print_case("striped", prec, kind, int(s))
+            r = G.power(kind, param, int(s), tol=1e-7, prec=prec)
+            ref = oracle_yK(g, s, kind, param, r.info["K"], P)
+            m = compare(r.y.cpu().numpy(), ref)
+            assert m["max_abs"] <= (1e-13 if prec == "f64" else 1e-8), m
+            assert m["l1"] <= (1e-12 if prec == "f64" else 2e-7), m
+
+
+def test_xcd_striped_hub_and_tiny(torch):
+    from paper_2412_10789_amd import chebyprop as cp  # noqa: F401
+
+    leaves = 40_000
+    e = [(0, i) for i in range(1, leaves + 1)] + [(i, i + 1) for i in range(1, leaves, 3)]
+    g = synth.from_edges(leaves + 1, e, name="hub+chain")
+    P = PR.transition_matrix(g.row_ptr, g.col_idx)
+    G = gpu_graph(g, stripes=True)
+    for s in (0, 7, leaves):
+        _print_case("striped-hub", s)
+        r = G.power("hkpr", 3.0, s, tol=1e-10, prec="f64")
+        ref = oracle_yK(g, s, "hkpr", 3.0, r.info["K"], P)
+        assert compare(r.y.cpu().numpy(), ref)["max_abs"] <= 1e-11
+    for gg in (synth.star(3), synth.path(5), synth.complete(9)):
+        G = gpu_graph(gg, stripes=True)
+        for K in (1, 2, 5):
+            _print_case("striped-tiny", gg.name, K)
+            r = G.power("ppr", 0.2, 1, prec="f64", kmode="fixed", K=K)
+            np.testing.assert_allclose(r.y.cpu().numpy(), oracle_yK(gg, 1, "ppr", 0.2, K), atol=1e-15)
