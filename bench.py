@@ -331,6 +331,70 @@ def run_serve(args, torch, cp, synth, g):
     return out
 
 
+LARGE = (65_000_000, 1_800_000_000, 2.1, 5, 0.2, 8, 1e-6)
+
+
+def run_large(args, torch, cp, synth):
+    """Friendster-sized graph (n = 65M target nodes, 1.8B undirected edges,
+    exponent 2.1): a batch of 8 PPR sources with FP32 and with BF16 storage,
+    one single-source query, and the l1 / max error of each against the
+    plain-C FP64 oracle on one source (full vector)."""
+    n_t, m_t, gamma, seed, alpha, nq, tol = LARGE
+    t0 = time.time()
+    g = synth.chung_lu(n_t, m_t, gamma, seed=seed, tune_passes=0, verbose=True)
+    gen_s = time.time() - t0
+    log(f"[large] graph: n={g.n} nnz={g.nnz} d_max={g.meta['d_max']} ({gen_s:.0f}s)")
+    t0 = time.time()
+    G = cp.Graph(g.row_ptr, g.col_idx, reorder=True)
+    create_s = time.time() - t0
+    log(f"[large] graph create {create_s:.0f}s, device bytes {G.stats['device_bytes']}")
+    srcs = [int(s) for s in synth.sources(g, nq, seed=seed)]
+    qs = [cp.make_query("ppr", alpha, s, tol, flags=cp.CP_Q_TIMING) for s in srcs]
+    out = {"workload": f"large: {nq} PPR alpha={alpha} sources, tol {tol} l1 (certified K), Chung-Lu n={n_t} "
+                       f"m={m_t} gamma={gamma} seed={seed} (one generation pass)",
+           "n": g.n, "nnz": g.nnz, "d_max": int(g.degrees.max()), "generate_s": round(gen_s, 1),
+           "graph_create_s": round(create_s, 1)}
+    cols = {}
+    for prec in ("f32", "bf16"):
+        G.set_batch_width(nq, prec, 8)
+        Yb, infos = G.power_batch(qs, prec=prec)  # warm-up
+        Yb, infos = G.power_batch(qs, prec=prec, Y=Yb)
+        Ks = [i["K"] for i in infos]
+        ms = infos[0]["elapsed_ms"]
+        arcs = sum((k - 1) * g.nnz for k in Ks)
+        out[f"batch_{prec}"] = {"GTEPS": round(arcs / ms / 1e6, 2), "ms_per_batch": round(ms, 1),
+                                "avg_launch_ms": round(infos[0]["step_ms"] / infos[0]["steps"], 3),
+                                "K": Ks, "source_tile_width": 8}
+        cols[prec] = Yb[:, 0].double().cpu().numpy()
+        log(f"[large] batch {prec}: {out[f'batch_{prec}']}")
+        del Yb
+    r = G.power("ppr", alpha, srcs[0], tol=tol, prec="f32", flags=cp.CP_Q_TIMING)
+    out["single_f32"] = {"GTEPS": round((r.info["K"] - 1) * g.nnz / r.info["elapsed_ms"] / 1e6, 2),
+                         "ms": round(r.info["elapsed_ms"], 1), "K": r.info["K"],
+                         "avg_step_ms": round(r.info["step_ms"] / r.info["steps"], 3)}
+    cols["single_f32"] = r.y.double().cpu().numpy()
+    log(f"[large] single: {out['single_f32']}")
+    G.close()
+    if not args.no_cpu:
+        from oracle import coefficients as C
+        from oracle import errors as E
+        from oracle import native as NO
+
+        NO.set_verbose(True)
+        K = out["batch_f32"]["K"][0]
+        t0 = time.perf_counter()
+        ref = NO.cheby_power(g.row_ptr, g.col_idx, srcs[0], C.ppr_chebyshev_coeffs(alpha, K), K)
+        cpu_s = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": round((K - 1) * g.nnz / cpu_s / 1e9, 4), "unit": "GTEPS",
+                               "cores": NO.threads(), "kind": "oracle",
+                               "sample": f"1 of the {nq} sources, same K={K}: plain-C FP64 Alg. 3 with an OpenMP "
+                                         f"node loop, {cpu_s:.0f} s"}
+        out["accuracy_vs_fp64_oracle"] = {k: {"l1": E.l1(v, ref), "max_abs": E.max_abs(v, ref)}
+                                          for k, v in cols.items()}
+        log(f"[large] accuracy {out['accuracy_vs_fp64_oracle']}")
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -349,6 +413,8 @@ def main() -> int:
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle legs")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run a plain 1 GiB device copy first (counter scaling for rocprofv3 --pmc)")
+    ap.add_argument("--large", action="store_true",
+                    help="run only the Friendster-sized measurement (n=65M, 1.8B edges; minutes, ~60 GB host RAM)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -370,6 +436,10 @@ def main() -> int:
         print("bench.py needs a GPU", file=sys.stderr)
         return 2
     torch.cuda.set_device(0)
+    if args.large:
+        res = {"metric": METRIC, "n_gpus": 1, "large": run_large(args, torch, cp, synth)}
+        print(json.dumps(res), flush=True)
+        return 0
     copy_gbps = copy_ceiling(torch)
     log(f"device copy ceiling: {copy_gbps:.0f} GB/s")
 

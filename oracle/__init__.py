@@ -23,6 +23,8 @@ Modules
   dense         dense definitions for tiny graphs: inverse (Def. 3),
                 matrix exponential (Def. 4), eigen route (Lemma 1 proof)
   errors        error measures (Def. 5) and the PPR residual certificate
+  native        the same Alg. 3 / Alg. 1 in plain C with an OpenMP node
+                loop (oracle/c/chebypower.c), for graphs with billions of arcs
 """
 
 from . import coefficients, dense, errors, propagation, truncation  # noqa: F401

@@ -1,0 +1,116 @@
+/* FP64 CPU reference of ChebyPower (Alg. 3) and PwMethod (Alg. 1) in plain C.
+ *
+ * TEST INFRASTRUCTURE ONLY: this is part of the oracle the GPU library is
+ * checked against (large graphs, where the Python oracle is too slow).  It
+ * shares no code with the library.  Plain loops in the paper's order; the
+ * only parallelism is an OpenMP split of the node loop of each step, which
+ * does not change any sum (every output element is summed serially over
+ * its row, in CSR order).
+ *
+ *   (P r)(v) = sum_{u in N(v)} r(u) / d_u          P = A D^{-1}  (Sec. 2.1)
+ *   Alg. 3:  y = c_0 e_s; r_0 = e_s; r_1 = P e_s;
+ *            for k = 1 .. K-1: y += c_k r_k; r_{k+1} = 2 P r_k - r_{k-1};
+ *            y += c_K r_K.
+ *   Alg. 1:  y = 0; r = e_s; for k = 0 .. N-1: y += zeta_k r; r = P r.
+ */
+#include <stdint.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+static int g_verbose = 0;
+void oracle_set_verbose(int v) { g_verbose = v; }
+
+static void apply_P(int64_t n, const int64_t* rp, const int32_t* ci, const double* inv_d, const double* r,
+                    double* out) {
+#pragma omp parallel for schedule(dynamic, 4096)
+  for (int64_t v = 0; v < n; ++v) {
+    double acc = 0.0;
+    for (int64_t q = rp[v]; q < rp[v + 1]; ++q) acc += r[ci[q]] * inv_d[ci[q]];
+    out[v] = acc;
+  }
+}
+
+static double* inverse_degrees(int64_t n, const int64_t* rp) {
+  double* inv_d = (double*)malloc(sizeof(double) * (size_t)n);
+  if (!inv_d) return NULL;
+#pragma omp parallel for
+  for (int64_t v = 0; v < n; ++v) {
+    const int64_t d = rp[v + 1] - rp[v];
+    inv_d[v] = d > 0 ? 1.0 / (double)d : 0.0;
+  }
+  return inv_d;
+}
+
+/* Returns 0 on success, -1 on bad arguments, -2 on allocation failure. */
+int oracle_chebypower(int64_t n, const int64_t* rp, const int32_t* ci, int64_t s, const double* c, int32_t K,
+                      double* y) {
+  if (n < 1 || s < 0 || s >= n || K < 1 || !rp || !ci || !c || !y) return -1;
+  double* inv_d = inverse_degrees(n, rp);
+  double* r_prev = (double*)calloc((size_t)n, sizeof(double));
+  double* r_cur = (double*)calloc((size_t)n, sizeof(double));
+  double* r_next = (double*)malloc(sizeof(double) * (size_t)n);
+  if (!inv_d || !r_prev || !r_cur || !r_next) {
+    free(inv_d); free(r_prev); free(r_cur); free(r_next);
+    return -2;
+  }
+  memset(y, 0, sizeof(double) * (size_t)n);
+  y[s] = c[0];            /* y = c_0 e_s */
+  r_prev[s] = 1.0;        /* r_0 = e_s   */
+  apply_P(n, rp, ci, inv_d, r_prev, r_cur); /* r_1 = P e_s */
+  for (int32_t k = 1; k < K; ++k) {
+    const double ck = c[k];
+#pragma omp parallel for
+    for (int64_t v = 0; v < n; ++v) y[v] += ck * r_cur[v];
+    apply_P(n, rp, ci, inv_d, r_cur, r_next);
+#pragma omp parallel for
+    for (int64_t v = 0; v < n; ++v) r_next[v] = 2.0 * r_next[v] - r_prev[v];
+    double* t = r_prev;
+    r_prev = r_cur;
+    r_cur = r_next;
+    r_next = t;
+    if (g_verbose) {
+      fprintf(stderr, "[oracle] Alg. 3 step %d/%d\n", k, K - 1);
+      fflush(stderr);
+    }
+  }
+  const double cK = c[K];
+#pragma omp parallel for
+  for (int64_t v = 0; v < n; ++v) y[v] += cK * r_cur[v];
+  free(inv_d); free(r_prev); free(r_cur); free(r_next);
+  return 0;
+}
+
+int oracle_pwmethod(int64_t n, const int64_t* rp, const int32_t* ci, int64_t s, const double* zeta, int32_t N,
+                    double* y) {
+  if (n < 1 || s < 0 || s >= n || N < 1 || !rp || !ci || !zeta || !y) return -1;
+  double* inv_d = inverse_degrees(n, rp);
+  double* r = (double*)calloc((size_t)n, sizeof(double));
+  double* r2 = (double*)malloc(sizeof(double) * (size_t)n);
+  if (!inv_d || !r || !r2) {
+    free(inv_d); free(r); free(r2);
+    return -2;
+  }
+  memset(y, 0, sizeof(double) * (size_t)n);
+  r[s] = 1.0;
+  for (int32_t k = 0; k < N; ++k) {
+    const double zk = zeta[k];
+#pragma omp parallel for
+    for (int64_t v = 0; v < n; ++v) y[v] += zk * r[v];
+    apply_P(n, rp, ci, inv_d, r, r2);
+    double* t = r;
+    r = r2;
+    r2 = t;
+  }
+  free(inv_d); free(r); free(r2);
+  return 0;
+}
+
+int oracle_threads(void) {
+#ifdef _OPENMP
+  extern int omp_get_max_threads(void);
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}

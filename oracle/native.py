@@ -1,0 +1,78 @@
+"""ctypes access to the plain-C FP64 oracle (oracle/c/chebypower.c).
+
+TEST INFRASTRUCTURE ONLY (see oracle/__init__.py).  Same Alg. 3 / Alg. 1 as
+oracle.propagation, for graphs where the scipy version is too slow; it is
+pinned against the Python oracle by tests/test_oracle_native.py.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "c", "chebypower.c")
+_LIB = os.path.join(_HERE, "c", "liboracle.so")
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.run(["gcc", "-O2", "-fopenmp", "-shared", "-fPIC", _SRC, "-o", tmp], check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=False)
+        lib = ctypes.CDLL(_LIB)
+        P = ctypes.c_void_p
+        for fn in ("oracle_chebypower", "oracle_pwmethod"):
+            f = getattr(lib, fn)
+            f.argtypes = [ctypes.c_int64, P, P, ctypes.c_int64, P, ctypes.c_int32, P]
+            f.restype = ctypes.c_int
+        lib.oracle_threads.restype = ctypes.c_int
+        lib.oracle_set_verbose.argtypes = [ctypes.c_int]
+        lib.oracle_set_verbose.restype = None
+        _lib = lib
+    return _lib
+
+
+def set_verbose(on: bool) -> None:
+    """Print one line per step to stderr (long runs on large graphs)."""
+    _load().oracle_set_verbose(1 if on else 0)
+
+
+def threads() -> int:
+    return int(_load().oracle_threads())
+
+
+def _call(name, row_ptr, col_idx, s, coeffs, K):
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
+    ci = np.ascontiguousarray(col_idx, dtype=np.int32)
+    c = np.ascontiguousarray(coeffs, dtype=np.float64)
+    n = rp.shape[0] - 1
+    y = np.empty(n, dtype=np.float64)
+    rc = getattr(_load(), name)(n, rp.ctypes.data, ci.ctypes.data, int(s), c.ctypes.data, int(K), y.ctypes.data)
+    if rc != 0:
+        raise RuntimeError(f"{name} failed with {rc}")
+    return y
+
+
+def cheby_power(row_ptr, col_idx, s: int, c, K: int) -> np.ndarray:
+    """Alg. 3 with coefficients c_0..c_K (FP64)."""
+    if len(c) < K + 1:
+        raise ValueError("need c_0..c_K")
+    return _call("oracle_chebypower", row_ptr, col_idx, s, c, K)
+
+
+def power_method(row_ptr, col_idx, s: int, zeta, N: int) -> np.ndarray:
+    """Alg. 1 with Taylor coefficients zeta_0..zeta_{N-1} (FP64)."""
+    return _call("oracle_pwmethod", row_ptr, col_idx, s, zeta, N)

@@ -46,7 +46,7 @@ class _Params(ctypes.Structure):
         ("relabel", ctypes.c_int32),
         ("threads", ctypes.c_int32),
         ("tune_passes", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("verbose", ctypes.c_int32),
     ]
 
 
@@ -171,10 +171,11 @@ def chung_lu(
     relabel: str = "random",
     threads: int = 0,
     tune_passes: int = 3,
+    verbose: bool = False,
 ) -> CSRGraph:
     """Seeded Chung-Lu power-law graph with about ``m`` undirected edges."""
     lib = _load()
-    p = _Params(n, m, gamma, seed & _MASK, {"none": 0, "random": 1}[relabel], threads, tune_passes, 0)
+    p = _Params(n, m, gamma, seed & _MASK, {"none": 0, "random": 1}[relabel], threads, tune_passes, int(verbose))
     out = ctypes.POINTER(_Graph)()
     rc = lib.synth_chunglu(ctypes.byref(p), ctypes.byref(out))
     if rc != 0:

@@ -25,6 +25,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <cstdio>
 #include <cmath>
 #include <cstdint>
 #include <cstdlib>
@@ -172,7 +173,10 @@ struct RawCSR {
 
 // Draw M pairs, symmetrize, dedup.  Returns false on allocation failure.
 bool build_simple_graph(const Alias& al, int64_t n, uint64_t seed, int64_t M,
-                        int nt, RawCSR* out) {
+                        int nt, RawCSR* out, bool verbose) {
+  auto stage = [&](const char* what) {
+    if (verbose) { fprintf(stderr, "[synth]   %s\n", what); fflush(stderr); }
+  };
   std::vector<std::atomic<uint32_t>> deg(n);
   for (auto& d : deg) d.store(0, std::memory_order_relaxed);
   parallel_ranges(M, nt, [&](int, int64_t b, int64_t e) {
@@ -183,6 +187,7 @@ bool build_simple_graph(const Alias& al, int64_t n, uint64_t seed, int64_t M,
         deg[y].fetch_add(1, std::memory_order_relaxed);
       }
   });
+  stage("degrees counted");
   std::vector<int64_t> off(n + 1, 0);
   for (int64_t i = 0; i < n; ++i) off[i + 1] = off[i] + deg[i].load(std::memory_order_relaxed);
   const int64_t total = off[n];
@@ -198,6 +203,7 @@ bool build_simple_graph(const Alias& al, int64_t n, uint64_t seed, int64_t M,
         adj[cur[y].fetch_add(1, std::memory_order_relaxed)] = x;
       }
   });
+  stage("arcs scattered");
   // Sort and dedup each row (slot order from the scatter is nondeterministic,
   // the sorted unique row is not).
   std::vector<int64_t> ulen(n, 0);
@@ -209,6 +215,7 @@ bool build_simple_graph(const Alias& al, int64_t n, uint64_t seed, int64_t M,
       ulen[i] = std::unique(r, r + len) - r;
     }
   });
+  stage("rows sorted and deduplicated");
   // Compact in row order (left moves only, so sequential memmove is safe).
   out->off.assign(n + 1, 0);
   for (int64_t i = 0; i < n; ++i) {
@@ -233,7 +240,7 @@ typedef struct {
   int32_t relabel;      // 0: weight order (heaviest first), 1: seeded random permutation
   int32_t threads;      // 0: all hardware threads, capped at 16
   int32_t tune_passes;  // extra M-correction passes (0: single pass with M = m_target)
-  int32_t reserved;
+  int32_t verbose;      // 1: one progress line per stage on stderr
 } synth_cl_params;
 
 typedef struct {
@@ -271,7 +278,8 @@ int synth_chunglu(const synth_cl_params* p, synth_graph** out) {
     int64_t M = p->m_target;
     int64_t prevM = 0, prevm = 0;
     for (int pass = 0;; ++pass) {
-      if (!build_simple_graph(al, n, p->seed, M, nt, &g)) return -2;
+      if (p->verbose) { fprintf(stderr, "[synth] pass %d: drawing %lld pairs\n", pass, (long long)M); fflush(stderr); }
+      if (!build_simple_graph(al, n, p->seed, M, nt, &g, p->verbose != 0)) return -2;
       int64_t m = g.off[n] / 2;
       double rel = (double)m / (double)p->m_target - 1.0;
       if (pass >= p->tune_passes || std::fabs(rel) < 0.005) break;
@@ -287,6 +295,7 @@ int synth_chunglu(const synth_cl_params* p, synth_graph** out) {
       M = std::max<int64_t>(1, nextM);
     }
 
+    if (p->verbose) { fprintf(stderr, "[synth] relabelling %lld nodes\n", (long long)n); fflush(stderr); }
     // Drop isolated nodes and relabel.
     std::vector<int32_t> kept;
     kept.reserve(n);

@@ -1,0 +1,52 @@
+"""The plain-C oracle against the pinned Python oracle and the paper's
+worked example (CPU only)."""
+
+import numpy as np
+import pytest
+
+import synth
+from conftest import load_golden
+from oracle import coefficients as C
+from oracle import native as NO
+from oracle import propagation as PR
+from oracle import truncation as T
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _built():
+    NO.build(force=False)
+
+
+def test_star_example():
+    """Sec. 4.2: with c = e_k, Alg. 3 returns T_k(P) e_{v1}."""
+    gold = load_golden("star_example.txt")
+    g = synth.star(3)
+    for k, key in [(1, "T1"), (2, "T2"), (3, "T3")]:
+        c = np.zeros(k + 1)
+        c[k] = 1.0
+        np.testing.assert_allclose(NO.cheby_power(g.row_ptr, g.col_idx, 1, c, k), gold[key], atol=1e-15)
+
+
+@pytest.mark.parametrize("kind,param", [("ppr", 0.2), ("ppr", 0.05), ("hkpr", 5.0)])
+def test_matches_python_oracle(kind, param):
+    g = synth.chung_lu(30_000, 200_000, 2.2, seed=6)
+    P = PR.transition_matrix(g.row_ptr, g.col_idx)
+    for s in synth.sources(g, 2, seed=1):
+        K = T.choose_K(kind, param, 1e-9, vol=g.nnz, d_s=g.degrees[s])
+        c = C.chebyshev_coeffs(kind, param, K)
+        a = NO.cheby_power(g.row_ptr, g.col_idx, int(s), c, K)
+        b = PR.cheby_power(P, int(s), c, K)
+        np.testing.assert_allclose(a, b, atol=1e-15, rtol=1e-12)
+        N = T.pwmethod_steps(kind, param, 1e-10)
+        z = C.taylor_coeffs(kind, param, N)
+        np.testing.assert_allclose(NO.power_method(g.row_ptr, g.col_idx, int(s), z, N),
+                                   PR.power_method(P, int(s), z, N), atol=1e-15, rtol=1e-12)
+
+
+def test_isolated_nodes_and_mass():
+    g = synth.from_edges(6, [(0, 1), (1, 2), (2, 0)], name="triangle+isolated")
+    c = C.ppr_chebyshev_coeffs(0.3, 40)
+    y = NO.cheby_power(g.row_ptr, g.col_idx, 0, c, 40)
+    assert np.all(y[3:] == 0.0) and abs(y.sum() - 1.0) < 1e-12
+    with pytest.raises(RuntimeError):
+        NO.cheby_power(g.row_ptr, g.col_idx, 9, c, 40)
