@@ -318,6 +318,23 @@ int32_t choose_bw(cp_graph* g, int32_t nq, int32_t prec) {
 
 using namespace cp;
 
+namespace {
+
+// Free every device allocation a (possibly partially built) graph holds.
+hipError_t release_graph(cp_graph* g) {
+  if (!g) return hipSuccess;
+  hipError_t e = hipSuccess;
+  for (void* p : {g->owned_csr, g->plan_mem, static_cast<void*>(g->s_rp)}) {
+    if (!p) continue;
+    const hipError_t x = hipFree(p);
+    if (e == hipSuccess) e = x;
+  }
+  delete g;
+  return e;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* cp_version(void) { return "chebyprop 0.1 (gfx950)"; }
@@ -363,11 +380,20 @@ cp_status cp_graph_create(int64_t n, int64_t nnz, const int64_t* row_ptr, const 
   const bool reorder = (flags & CP_GRAPH_REORDER) || striped;
   const bool borrow = (flags & CP_GRAPH_BORROW) && !host_in && !reorder;
   cp_graph* g = nullptr;
+#define CP_HIP_G(call)      \
+  do {                      \
+    hipError_t e_ = (call); \
+    if (e_ != hipSuccess) { \
+      set_hip_error(e_);    \
+      (void)release_graph(g); \
+      return CP_EHIP;       \
+    }                       \
+  } while (0)
   try {
     g = new cp_graph();
     g->n = n;
     g->nnz = nnz;
-    CP_HIP(hipGetDevice(&g->device));
+    CP_HIP_G(hipGetDevice(&g->device));
     // host copies of the CSR (row offsets always; columns when needed)
     std::vector<int64_t> rp(n + 1);
     std::vector<int32_t> ci;
@@ -375,18 +401,18 @@ cp_status cp_graph_create(int64_t n, int64_t nnz, const int64_t* row_ptr, const 
     if (host_in) {
       std::memcpy(rp.data(), row_ptr, sizeof(int64_t) * (n + 1));
     } else {
-      CP_HIP(hipMemcpyAsync(rp.data(), row_ptr, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToHost, st));
+      CP_HIP_G(hipMemcpyAsync(rp.data(), row_ptr, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToHost, st));
     }
     if (need_cols) {
       ci.resize(nnz);
       if (host_in) std::memcpy(ci.data(), col_idx, sizeof(int32_t) * nnz);
       else if (nnz)
-        CP_HIP(hipMemcpyAsync(ci.data(), col_idx, sizeof(int32_t) * nnz, hipMemcpyDeviceToHost, st));
+        CP_HIP_G(hipMemcpyAsync(ci.data(), col_idx, sizeof(int32_t) * nnz, hipMemcpyDeviceToHost, st));
     }
-    CP_HIP(hipStreamSynchronize(st));
-    if (rp[0] != 0 || rp[n] != nnz) { delete g; return CP_EINVAL; }
+    CP_HIP_G(hipStreamSynchronize(st));
+    if (rp[0] != 0 || rp[n] != nnz) { (void)release_graph(g); return CP_EINVAL; }
     if ((flags & CP_GRAPH_VALIDATE) && !validate_csr(n, nnz, rp.data(), ci.data())) {
-      delete g;
+      (void)release_graph(g);
       return CP_EGRAPH;
     }
     g->degree.resize(n);
@@ -439,7 +465,7 @@ cp_status cp_graph_create(int64_t n, int64_t nnz, const int64_t* row_ptr, const 
     if (total) {
       hipError_t e = hipMalloc(&base, total);
       if (e != hipSuccess) {
-        delete g;
+        (void)release_graph(g);
         return e == hipErrorOutOfMemory ? CP_ENOMEM : (set_hip_error(e), CP_EHIP);
       }
       g->owned_csr = base;
@@ -452,8 +478,7 @@ cp_status cp_graph_create(int64_t n, int64_t nnz, const int64_t* row_ptr, const 
     {
       hipError_t e = hipMalloc(&pbase, b_plans);
       if (e != hipSuccess) {
-        if (base) (void)hipFree(base);
-        delete g;
+        (void)release_graph(g);
         return e == hipErrorOutOfMemory ? CP_ENOMEM : (set_hip_error(e), CP_EHIP);
       }
       g->plan_mem = pbase;
@@ -466,9 +491,7 @@ cp_status cp_graph_create(int64_t n, int64_t nnz, const int64_t* row_ptr, const 
       char* sb = nullptr;
       hipError_t e = hipMalloc(&sb, b_stripes);
       if (e != hipSuccess) {
-        if (base) (void)hipFree(base);
-        (void)hipFree(pbase);
-        delete g;
+        (void)release_graph(g);
         return e == hipErrorOutOfMemory ? CP_ENOMEM : (set_hip_error(e), CP_EHIP);
       }
       g->striped = true;
@@ -480,12 +503,12 @@ cp_status cp_graph_create(int64_t n, int64_t nnz, const int64_t* row_ptr, const 
       g->s_ntiles = sl.ntiles;
       g->s_nlong = sl.nlong;
       for (int j = 0; j < kStripes; ++j) g->s_col_off[j] = sl.col_off[j];
-      CP_HIP(hipMemcpyAsync(g->s_rp, sl.rp.data(), sizeof(int32_t) * sl.rp.size(), hipMemcpyHostToDevice, st));
+      CP_HIP_G(hipMemcpyAsync(g->s_rp, sl.rp.data(), sizeof(int32_t) * sl.rp.size(), hipMemcpyHostToDevice, st));
       if (!sl.cols.empty())
-        CP_HIP(hipMemcpyAsync(g->s_cols, sl.cols.data(), sizeof(int32_t) * sl.cols.size(), hipMemcpyHostToDevice,
+        CP_HIP_G(hipMemcpyAsync(g->s_cols, sl.cols.data(), sizeof(int32_t) * sl.cols.size(), hipMemcpyHostToDevice,
                               st));
       if (!sl.blocks.empty())
-        CP_HIP(hipMemcpyAsync(g->s_blocks, sl.blocks.data(), sizeof(StripeBlock) * sl.blocks.size(),
+        CP_HIP_G(hipMemcpyAsync(g->s_blocks, sl.blocks.data(), sizeof(StripeBlock) * sl.blocks.size(),
                               hipMemcpyHostToDevice, st));
     }
     g->device_bytes = (int64_t)(total + b_plans + b_stripes);
@@ -497,19 +520,19 @@ cp_status cp_graph_create(int64_t n, int64_t nnz, const int64_t* row_ptr, const 
     } else {
       int64_t* drp = reinterpret_cast<int64_t*>(p); p += b_rp;
       int32_t* dci = reinterpret_cast<int32_t*>(p); p += b_ci;
-      CP_HIP(hipMemcpyAsync(drp, rp.data(), sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice, st));
+      CP_HIP_G(hipMemcpyAsync(drp, rp.data(), sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice, st));
       if (nnz) {
         if (need_cols)
-          CP_HIP(hipMemcpyAsync(dci, ci.data(), sizeof(int32_t) * nnz, hipMemcpyHostToDevice, st));
+          CP_HIP_G(hipMemcpyAsync(dci, ci.data(), sizeof(int32_t) * nnz, hipMemcpyHostToDevice, st));
         else
-          CP_HIP(hipMemcpyAsync(dci, col_idx, sizeof(int32_t) * nnz, hipMemcpyDeviceToDevice, st));
+          CP_HIP_G(hipMemcpyAsync(dci, col_idx, sizeof(int32_t) * nnz, hipMemcpyDeviceToDevice, st));
       }
       g->row_ptr = drp;
       g->col_idx = dci;
     }
     if (reorder) {
       g->perm = reinterpret_cast<int32_t*>(p); p += b_pm;
-      CP_HIP(hipMemcpyAsync(g->perm, perm.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, st));
+      CP_HIP_G(hipMemcpyAsync(g->perm, perm.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, st));
     }
     DevPlan* dps[2] = {&g->single, &g->batch};
     char* q = pbase;
@@ -526,36 +549,25 @@ cp_status cp_graph_create(int64_t n, int64_t nnz, const int64_t* row_ptr, const 
       dp.hubs = reinterpret_cast<HubDesc*>(q);
       q += align256(sizeof(HubDesc) * std::max<size_t>(pl.hubs.size(), 1));
       if (dp.nblocks)
-        CP_HIP(hipMemcpyAsync(dp.blocks, pl.blocks.data(), sizeof(BlockDesc) * dp.nblocks,
+        CP_HIP_G(hipMemcpyAsync(dp.blocks, pl.blocks.data(), sizeof(BlockDesc) * dp.nblocks,
                               hipMemcpyHostToDevice, st));
       if (dp.nhubs)
-        CP_HIP(hipMemcpyAsync(dp.hubs, pl.hubs.data(), sizeof(HubDesc) * dp.nhubs,
+        CP_HIP_G(hipMemcpyAsync(dp.hubs, pl.hubs.data(), sizeof(HubDesc) * dp.nhubs,
                               hipMemcpyHostToDevice, st));
     }
-    CP_HIP(hipStreamSynchronize(st));
+    CP_HIP_G(hipStreamSynchronize(st));
     *out = g;
     return CP_OK;
   } catch (const std::bad_alloc&) {
-    if (g && g->owned_csr) (void)hipFree(g->owned_csr);
-    if (g && g->plan_mem) (void)hipFree(g->plan_mem);
-    delete g;
+    (void)release_graph(g);
     return CP_ENOMEM;
   }
+#undef CP_HIP_G
 }
 
 cp_status cp_graph_destroy(cp_graph* g) {
   if (!g) return CP_EINVAL;
-  hipError_t e = hipSuccess;
-  if (g->owned_csr) e = hipFree(g->owned_csr);
-  if (g->plan_mem) {
-    hipError_t e2 = hipFree(g->plan_mem);
-    if (e == hipSuccess) e = e2;
-  }
-  if (g->s_rp) {
-    hipError_t e3 = hipFree(g->s_rp);
-    if (e == hipSuccess) e = e3;
-  }
-  delete g;
+  const hipError_t e = release_graph(g);
   if (e != hipSuccess) { set_hip_error(e); return CP_EHIP; }
   return CP_OK;
 }
