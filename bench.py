@@ -249,7 +249,7 @@ def run_serve(args, torch, cp, synth, g):
     queries on the same arrival trace (same graph, same FP32 precision)."""
     trace = serve_trace(g, synth, args.serve_seconds, args.serve_rate)
     G = cp.Graph(g.row_ptr, g.col_idx, reorder=args.layout != "native", stripes=args.layout == "stripes")
-    nbuf = 256
+    nbuf = 512  # one result buffer per server slot
     bufs = [torch.empty(g.n, dtype=torch.float32, device="cuda") for _ in range(nbuf)]
     # warm both paths (code objects, caches)
     for (_, kind, param, s, tol) in trace[:4]:
@@ -260,24 +260,38 @@ def run_serve(args, torch, cp, synth, g):
     S = cp.Server(G, hbm_budget_bytes=16 << 30, max_slots=512, max_queue=100000, prec="f32")
     for (_, kind, param, s, tol) in trace[:8]:
         S.wait(S.submit(cp.make_query(kind, param, s, tol), bufs[1]))
-    tickets = [None] * len(trace)
-    t0 = time.perf_counter()
-    for i, (ta, kind, param, s, tol) in enumerate(trace):
-        dt = ta - (time.perf_counter() - t0)
-        if dt > 0:
-            time.sleep(dt)
-        j = i % nbuf
-        if i >= nbuf:  # the buffer's previous query must be finished before reuse
-            st, info = S.wait(tickets[i - nbuf])
-            tickets[i - nbuf] = (st, info)
-        tickets[i] = S.submit(cp.make_query(kind, param, s, tol), bufs[j])
-    for i in range(max(0, len(trace) - nbuf), len(trace)):
-        if not isinstance(tickets[i], tuple):
-            tickets[i] = S.wait(tickets[i])
-    t_end = time.perf_counter() - t0
+
+    def replay(tr):
+        """Submit at the trace's arrival times; results land in a ring of
+        buffers (a buffer is reused once its previous query is done)."""
+        tickets = [None] * len(tr)
+        t0 = time.perf_counter()
+        for i, (ta, kind, param, s, tol) in enumerate(tr):
+            dt = ta - (time.perf_counter() - t0)
+            if dt > 0:
+                time.sleep(dt)
+            if i >= nbuf:
+                tickets[i - nbuf] = S.wait(tickets[i - nbuf])
+            tickets[i] = S.submit(cp.make_query(kind, param, s, tol), bufs[i % nbuf])
+        for i in range(max(0, len(tr) - nbuf), len(tr)):
+            if not isinstance(tickets[i], tuple):
+                tickets[i] = S.wait(tickets[i])
+        return tickets, time.perf_counter() - t0
+
+    ticks0 = S.stats()["ticks"]
+    tickets, t_end = replay(trace)
     lat = [info["latency_ms"] for st, info in tickets if st == cp.CP_OK]
     Ks = [info["K"] for st, info in tickets if st == cp.CP_OK]
     sstats = S.stats()
+    sat = None
+    if args.saturation_rate > 0:
+        burst = serve_trace(g, synth, 1.0, args.saturation_rate, seed=7)
+        bt, b_end = replay(burst)
+        blat = [info["latency_ms"] for st, info in bt if st == cp.CP_OK]
+        sat = {"offered_qps": args.saturation_rate, "queries": len(burst), "completed": len(blat),
+               "qps": round(len(blat) / b_end, 1), "p50_ms": _pct(blat, 50), "p99_ms": _pct(blat, 99),
+               "span_s": round(b_end, 3), "latency_from": "submission (a submit waits for a free result buffer)"}
+        log(f"[serve] saturation burst: {sat}")
     # accuracy of two served results (rerun into a fresh buffer through the server)
     acc = None
     if not args.no_cpu:
@@ -298,7 +312,7 @@ def run_serve(args, torch, cp, synth, g):
     server = {"completed": len(lat), "qps": round(len(lat) / t_end, 1), "p50_ms": _pct(lat, 50),
               "p99_ms": _pct(lat, 99), "mean_ms": float(np.mean(lat)) if lat else None,
               "span_s": round(t_end, 3), "slots": sstats["slots"], "tile_width": sstats["tile_width"],
-              "batched_launches": sstats["ticks"], "mean_K": float(np.mean(Ks)) if Ks else None}
+              "batched_launches": sstats["ticks"] - ticks0, "mean_K": float(np.mean(Ks)) if Ks else None}
     log(f"[serve] server: {server}")
 
     # ---- plain: one query at a time, FIFO, single-source path
@@ -326,6 +340,9 @@ def run_serve(args, torch, cp, synth, g):
         "plain": plain,
         "speedup_qps": round(server["qps"] / plain["qps"], 2) if plain["qps"] else None,
     }
+    if sat is not None:
+        out["server_saturation"] = sat
+        out["capacity_vs_plain"] = round(sat["qps"] / plain["qps"], 2) if plain["qps"] else None
     if acc is not None:
         out["accuracy_vs_fp64_oracle"] = acc
     return out
@@ -406,6 +423,8 @@ def main() -> int:
     ap.add_argument("--serve-seconds", type=float, default=3.0,
                     help="length of the Poisson arrival trace for the served measurement (0: skip)")
     ap.add_argument("--serve-rate", type=float, default=200.0, help="offered queries per second")
+    ap.add_argument("--saturation-rate", type=float, default=2000.0,
+                    help="offered rate of a 1-second burst that measures the server's capacity (0: skip)")
     ap.add_argument("--layout", default="stripes", choices=["stripes", "degree", "native"],
                     help="graph layout inside the library for single-source queries: XCD column stripes "
                          "(CP_GRAPH_XCD_STRIPES), degree order (CP_GRAPH_REORDER) or the caller's ids; "
@@ -419,8 +438,8 @@ def main() -> int:
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(queries would shard by source across GPUs with the graph replicated; see DESIGN.md)",
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
+              "(queries would shard by source across GPUs, with the graph replicated on each)",
               file=sys.stderr)
         return 2
 

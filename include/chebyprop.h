@@ -86,7 +86,9 @@ typedef enum { CP_K_CERTIFIED = 0, CP_K_TAIL = 1, CP_K_PAPER = 2, CP_K_FIXED = 3
                                      stripes and keep one CSR per stripe, so that
                                      single-source steps gather each stripe on one
                                      XCD (from its L2); costs a second copy of the
-                                     column ids plus 8 (n+1) int32 offsets */
+                                     column ids plus 8 (n+1) int32 offsets, so
+                                     each stripe must hold fewer than 2^31 arcs
+                                     (CP_EINVAL otherwise) */
 
 /* cp_query.flags */
 #define CP_Q_STATS 0x1  /* after the run, synchronize and fill cp_info.mass */

@@ -23,7 +23,7 @@ HIPCC_FLAGS = [
     f"--offload-arch={ARCH}",
     "-fPIC",
     "-shared",
-    # packed FP32 instructions stay off (hardware notes)
+    # packed FP32 instructions stay off: plain scalar FP32 code is generated instead
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall",
     "-Wno-unused-result",

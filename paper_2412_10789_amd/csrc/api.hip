@@ -95,8 +95,9 @@ struct StripeLayout {
 };
 
 // Per-stripe CSRs of a graph already relabelled into kStripes contiguous
-// stripes, and the row tiles of the striped step (see common.h).
-void build_stripes(const int64_t* rp, const int32_t* ci, int64_t n, StripeLayout& sl) {
+// stripes, and the row tiles of the striped step (see common.h).  Stripe
+// offsets are int32: returns false when one stripe holds 2^31 arcs or more.
+bool build_stripes(const int64_t* rp, const int32_t* ci, int64_t n, StripeLayout& sl) {
   int64_t start[kStripes + 1] = {0};
   for (int j = 0; j < kStripes; ++j) start[j + 1] = start[j] + (n - j + kStripes - 1) / kStripes;
   // per row, per stripe arc counts (rows are sorted by column)
@@ -113,6 +114,11 @@ void build_stripes(const int64_t* rp, const int32_t* ci, int64_t n, StripeLayout
       }
     }
   });
+  for (int j = 0; j < kStripes; ++j) {
+    int64_t arcs = 0;
+    for (int64_t v = 0; v < n; ++v) arcs += cnt[(size_t)v * kStripes + j];
+    if (arcs > INT32_MAX) return false;
+  }
   sl.rp.assign((size_t)kStripes * (n + 1), 0);
   int64_t total = 0;
   for (int j = 0; j < kStripes; ++j) {
@@ -171,6 +177,7 @@ void build_stripes(const int64_t* rp, const int32_t* ci, int64_t n, StripeLayout
     for (int j = 0; j < kStripes; ++j) acc[j] += c[j];
   }
   close(n);
+  return true;
 }
 
 Plan build_plan(const int64_t* rp, int64_t n, int64_t long_threshold) {
@@ -454,7 +461,10 @@ cp_status cp_graph_create(int64_t n, int64_t nnz, const int64_t* row_ptr, const 
     }
     const Plan plans[2] = {build_plan(rp.data(), n, kTileNnz), build_plan(rp.data(), n, kBatchLong)};
     StripeLayout sl;
-    if (striped) build_stripes(rp.data(), ci.data(), n, sl);
+    if (striped && !build_stripes(rp.data(), ci.data(), n, sl)) {
+      (void)release_graph(g);
+      return CP_EINVAL;
+    }
 
     // device copies: [row_ptr | col_idx | perm] in one allocation, plans in another
     const size_t b_rp = borrow ? 0 : align256(sizeof(int64_t) * (n + 1));

@@ -85,7 +85,7 @@ struct DevPlan {
 
 constexpr int kStripes = 8;
 constexpr int kStripeTileNnz = 2048;   // arcs per (tile, stripe)
-constexpr int kStripeTileRows = 1024;  // rows per tile
+constexpr int kStripeTileRows = 1000;  // rows per tile (keeps 8 workgroups per CU in LDS)
 
 // One workgroup of the striped step: rows [r0, r0 + nr) of the tile,
 // restricted to stripe (block index % 8), whose arcs are cols[p0, p0 + cnt)
