@@ -94,6 +94,15 @@ typedef enum { CP_K_CERTIFIED = 0, CP_K_TAIL = 1, CP_K_PAPER = 2, CP_K_FIXED = 3
 #define CP_Q_STATS 0x1  /* after the run, synchronize and fill cp_info.mass */
 #define CP_Q_TIMING 0x2 /* time the run and each Chebyshev step with HIP events
                            (synchronizes; fills elapsed_ms, step_ms) */
+#define CP_Q_PWMETHOD 0x4 /* evaluate with PwMethod (Alg. 1) instead of
+                             ChebyPower: y = sum_{k<N} zeta_k P^k e_s with the
+                             Taylor weights of Def. 3 / Def. 4.  N (reported
+                             in cp_info.K) is the smallest N whose exact l1
+                             tail sum_{k>=N} zeta_k is <= tol for every kmode
+                             but CP_K_FIXED (N = K_fixed); that tail is also
+                             the exact l1 truncation error (tail_bound_l1).
+                             Runs max(N - 2, 0) full power steps after the
+                             init, on the same kernels as Alg. 3. */
 
 typedef struct cp_graph cp_graph;
 
@@ -104,14 +113,15 @@ typedef struct {
   double tol;      /* l1 tolerance in (0,1); unused for CP_K_FIXED */
   int64_t source;  /* s, in the caller's node ids */
   int32_t K_fixed; /* K for CP_K_FIXED */
-  int32_t flags;   /* CP_Q_* */
+  int32_t flags;   /* CP_Q_* (any other bit: CP_EINVAL) */
 } cp_query;
 
 typedef struct {
-  int32_t K;            /* truncation step used (number of P-products) */
-  int32_t steps;        /* Chebyshev step launches (K - 1) */
-  double tail;          /* sum_{k>K} |c_k| */
-  double tail_bound_l1; /* sqrt(vol/d_s) * tail: bound on the l1 truncation error */
+  int32_t K;            /* truncation step used: K of Alg. 3, or N of Alg. 1 */
+  int32_t steps;        /* full step launches for this query: K - 1 (Alg. 3), max(N - 2, 0) (Alg. 1) */
+  double tail;          /* sum_{k>K} |c_k|, or sum_{k>=N} zeta_k */
+  double tail_bound_l1; /* bound on the l1 truncation error: sqrt(vol/d_s) * tail
+                           (Alg. 3, CP_K_CERTIFIED reading), tail (Alg. 1, exact) */
   double mass;          /* sum_u y(u) (CP_Q_STATS; 1 up to truncation and rounding) */
   double elapsed_ms;    /* whole query on the device (CP_Q_TIMING) */
   double step_ms;       /* sum of the Chebyshev step kernels' durations (CP_Q_TIMING) */
@@ -157,11 +167,23 @@ cp_status cp_coeffs(int32_t kind, double param, int32_t K, double* c_out);
 cp_status cp_choose_K(int32_t kind, double param, double tol, int32_t kmode, int32_t K_fixed,
                       double vol, double d_s, int32_t K_max, int32_t* K_out, double* tail_out);
 
+/* Taylor weights zeta_0..zeta_{N-1} of PwMethod into host zeta_out[N], FP64
+ * (Def. 3: zeta_k = alpha (1 - alpha)^k; Def. 4: zeta_k = e^{-t} t^k / k!).
+ * Pure host code.  Errors: CP_EINVAL. */
+cp_status cp_taylor(int32_t kind, double param, int32_t N, double* zeta_out);
+
+/* PwMethod's number of terms N for a tolerance: the smallest N >= 1 with
+ * sum_{k>=N} zeta_k <= tol (every P^k e_s is a probability vector, so this
+ * tail is the exact l1 error), or N_fixed for CP_K_FIXED.  Writes N and the
+ * tail.  Pure host code.  Errors: CP_EINVAL, CP_EKMAX (N > N_max). */
+cp_status cp_choose_N(int32_t kind, double param, double tol, int32_t kmode, int32_t N_fixed, int32_t N_max,
+                      int32_t* N_out, double* tail_out);
+
 /* Device workspace needed by cp_power (nq = 1) or cp_power_batch (nq
  * queries) at precision `prec`.  Returns 0 for invalid arguments. */
 size_t cp_workspace_bytes(const cp_graph* g, int32_t nq, int32_t prec);
 
-/* One query (Alg. 3): y = sum_{k<=K} c_k T_k(P) e_s.
+/* One query (Alg. 3): y = sum_{k<=K} c_k T_k(P) e_s (Alg. 1 with CP_Q_PWMETHOD).
  *   y     device, n elements (double for CP_F64, float otherwise), caller ids
  *   ws    device workspace of at least cp_workspace_bytes(g, 1, prec) bytes,
  *         256-byte aligned; contents are scratch

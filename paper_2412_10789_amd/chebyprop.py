@@ -38,15 +38,17 @@ CP_F64, CP_F32, CP_BF16 = 0, 1, 2
 CP_K_CERTIFIED, CP_K_TAIL, CP_K_PAPER, CP_K_FIXED = 0, 1, 2, 3
 CP_GRAPH_BORROW, CP_GRAPH_VALIDATE, CP_GRAPH_REORDER, CP_GRAPH_HOST = 0x1, 0x2, 0x4, 0x8
 CP_GRAPH_XCD_STRIPES = 0x10
-CP_Q_STATS, CP_Q_TIMING = 0x1, 0x2
+CP_Q_STATS, CP_Q_TIMING, CP_Q_PWMETHOD = 0x1, 0x2, 0x4
 
 KINDS = {"ppr": CP_PPR, "hkpr": CP_HKPR}
 PRECS = {"f64": CP_F64, "f32": CP_F32, "bf16": CP_BF16}
 KMODES = {"certified": CP_K_CERTIFIED, "tail": CP_K_TAIL, "paper": CP_K_PAPER, "fixed": CP_K_FIXED}
+METHODS = {"cheby": 0, "power": CP_Q_PWMETHOD}  # Alg. 3 (ChebyPower) or Alg. 1 (PwMethod)
 
 # every symbol the header declares
 EXPORTED = [
     "cp_graph_create", "cp_graph_destroy", "cp_graph_get_stats", "cp_coeffs", "cp_choose_K",
+    "cp_taylor", "cp_choose_N",
     "cp_workspace_bytes", "cp_power", "cp_power_batch", "cp_autotune_batch", "cp_set_batch_width",
     "cp_status_str", "cp_last_hip_error", "cp_version",
     "cp_server_create", "cp_server_submit", "cp_server_poll", "cp_server_wait", "cp_server_cancel",
@@ -151,6 +153,8 @@ def load() -> ctypes.CDLL:
         "cp_graph_get_stats": (i32, [P, ctypes.POINTER(cp_graph_stats)]),
         "cp_coeffs": (i32, [i32, f64, i32, ctypes.POINTER(f64)]),
         "cp_choose_K": (i32, [i32, f64, f64, i32, i32, f64, f64, i32, ctypes.POINTER(i32), ctypes.POINTER(f64)]),
+        "cp_taylor": (i32, [i32, f64, i32, ctypes.POINTER(f64)]),
+        "cp_choose_N": (i32, [i32, f64, f64, i32, i32, i32, ctypes.POINTER(i32), ctypes.POINTER(f64)]),
         "cp_workspace_bytes": (sz, [P, i32, i32]),
         "cp_power": (i32, [P, ctypes.POINTER(cp_query), i32, P, P, sz, P, ctypes.POINTER(cp_info)]),
         "cp_power_batch": (i32, [P, i32, ctypes.POINTER(cp_query), i32, P, P, sz, P, ctypes.POINTER(cp_info)]),
@@ -210,6 +214,21 @@ def cp_choose_K(kind: int, param: float, tol: float, kmode: int = CP_K_CERTIFIED
     return int(K.value), float(tail.value)
 
 
+def cp_taylor(kind: int, param: float, N: int) -> np.ndarray:
+    z = np.zeros(N, dtype=np.float64)
+    _check(load().cp_taylor(kind, param, N, z.ctypes.data_as(ctypes.POINTER(ctypes.c_double))), "cp_taylor")
+    return z
+
+
+def cp_choose_N(kind: int, param: float, tol: float, kmode: int = CP_K_CERTIFIED, N_fixed: int = 0,
+                N_max: int = 0) -> tuple[int, float]:
+    N = ctypes.c_int32(0)
+    tail = ctypes.c_double(0.0)
+    _check(load().cp_choose_N(kind, param, tol, kmode, N_fixed, N_max, ctypes.byref(N), ctypes.byref(tail)),
+           "cp_choose_N")
+    return int(N.value), float(tail.value)
+
+
 def cp_graph_create(n: int, nnz: int, row_ptr_ptr: int, col_idx_ptr: int, flags: int, stream: int) -> int:
     out = ctypes.c_void_p()
     _check(load().cp_graph_create(n, nnz, row_ptr_ptr, col_idx_ptr, flags, stream, ctypes.byref(out)),
@@ -264,8 +283,9 @@ def cp_set_batch_width(handle: int, nq: int, prec: int, bw: int) -> None:
 
 
 def make_query(kind: str, param: float, source: int, tol: float = 1e-6, kmode: str = "certified",
-               K: int = 0, flags: int = 0) -> cp_query:
-    return cp_query(KINDS[kind], KMODES[kmode], float(param), float(tol), int(source), int(K), int(flags))
+               K: int = 0, flags: int = 0, method: str = "cheby") -> cp_query:
+    return cp_query(KINDS[kind], KMODES[kmode], float(param), float(tol), int(source), int(K),
+                    int(flags) | METHODS[method])
 
 
 # ---------------------------------------------------------------- torch wrapper
@@ -323,14 +343,15 @@ class Graph:
         return self.torch.float64 if prec == CP_F64 else self.torch.float32
 
     def power(self, kind: str, param: float, source: int, tol: float = 1e-6, prec: str = "f32",
-              kmode: str = "certified", K: int = 0, flags: int = 0, y=None, stream=None) -> Result:
+              kmode: str = "certified", K: int = 0, flags: int = 0, y=None, stream=None,
+              method: str = "cheby") -> Result:
         torch = self.torch
         p = PRECS[prec]
         if y is None:
             y = torch.empty(self.n, dtype=self.out_dtype(p), device=self.device)
         ws, nbytes = self.workspace(1, p)
         st = stream if stream is not None else torch.cuda.current_stream(self.device).cuda_stream
-        q = make_query(kind, param, source, tol, kmode, K, flags)
+        q = make_query(kind, param, source, tol, kmode, K, flags, method)
         info = cp_power(self.handle, q, p, y.data_ptr(), ws.data_ptr(), nbytes, st)
         return Result(y, info.as_dict())
 

@@ -249,24 +249,40 @@ WsLayout ws_layout(const cp_graph* g, int32_t nq, int32_t prec) {
 
 }  // namespace
 
-cp_status check_query(const cp_graph* g, const cp_query* q, int64_t* s_int, int32_t* K,
-                      double* tail, double* L) {
-  if (!q) return CP_EINVAL;
+cp_status plan_query(const cp_graph* g, const cp_query* q, int32_t K_max, QueryPlan* p) {
+  if (!q || !p) return CP_EINVAL;
   if (q->kind != CP_PPR && q->kind != CP_HKPR) return CP_EINVAL;
+  if (q->flags & ~(CP_Q_STATS | CP_Q_TIMING | CP_Q_PWMETHOD)) return CP_EINVAL;
   if (q->source < 0 || q->source >= g->n) return CP_ESOURCE;
   const int32_t ds = g->degree[q->source];
   if (ds == 0) return CP_EISOLATED;
-  *s_int = g->reordered ? g->ext2int[q->source] : q->source;
-  *L = std::sqrt((double)g->nnz / (double)ds);
-  return choose_K_impl(q->kind, q->param, q->tol, q->kmode, q->K_fixed, (double)g->nnz, (double)ds,
-                       kDefaultKMax, K, tail);
+  p->s_int = g->reordered ? g->ext2int[q->source] : q->source;
+  cp_status rc;
+  if (q->flags & CP_Q_PWMETHOD) {
+    // N terms zeta_0..zeta_{N-1}; the highest index N - 1 must fit K_max
+    rc = choose_N_impl(q->kind, q->param, q->tol, q->kmode, q->K_fixed, K_max + 1, &p->K, &p->tail);
+    if (rc != CP_OK) return rc;
+    p->top = std::max(p->K - 1, 1);
+    p->L = 1.0;
+    p->rec = 1.0;
+    p->c.assign((size_t)p->top + 1, 0.0);
+    return taylor_impl(q->kind, q->param, p->K, p->c.data());
+  }
+  rc = choose_K_impl(q->kind, q->param, q->tol, q->kmode, q->K_fixed, (double)g->nnz, (double)ds, K_max,
+                     &p->K, &p->tail);
+  if (rc != CP_OK) return rc;
+  p->top = p->K;
+  p->L = std::sqrt((double)g->nnz / (double)ds);
+  p->rec = 2.0;
+  p->c.assign((size_t)p->K + 1, 0.0);
+  return coeffs_impl(q->kind, q->param, p->K, p->c.data());
 }
 
 namespace {
 
 struct BatchLayout {
   int32_t bw = 0, nq_pad = 0, ntiles = 0;
-  size_t rA = 0, rB = 0, yacc = 0, hub_count = 0, hub_partial = 0, coef = 0, src = 0, slotmap = 0,
+  size_t rA = 0, rB = 0, yacc = 0, hub_count = 0, hub_partial = 0, coef = 0, src = 0, rec = 0, slotmap = 0,
          total = 0;
 };
 
@@ -287,6 +303,7 @@ BatchLayout batch_layout(const cp_graph* g, int32_t nq, int32_t prec, int32_t bw
   L.hub_partial = off; off += align256((size_t)std::max<int64_t>(g->batch.hub_segments, 1) * L.nq_pad * 8);
   L.coef = off; off += align256((size_t)(kBatchKCap + 1) * L.nq_pad * 8);
   L.src = off; off += align256((size_t)L.nq_pad * 8);
+  L.rec = off; off += align256((size_t)L.nq_pad * 8);
   L.slotmap = off; off += align256((size_t)nq * 4);
   L.total = off;
   return L;
@@ -374,6 +391,15 @@ cp_status cp_coeffs(int32_t kind, double param, int32_t K, double* c_out) {
 cp_status cp_choose_K(int32_t kind, double param, double tol, int32_t kmode, int32_t K_fixed,
                       double vol, double d_s, int32_t K_max, int32_t* K_out, double* tail_out) {
   return choose_K_impl(kind, param, tol, kmode, K_fixed, vol, d_s, K_max, K_out, tail_out);
+}
+
+cp_status cp_taylor(int32_t kind, double param, int32_t N, double* zeta_out) {
+  return taylor_impl(kind, param, N, zeta_out);
+}
+
+cp_status cp_choose_N(int32_t kind, double param, double tol, int32_t kmode, int32_t N_fixed, int32_t N_max,
+                      int32_t* N_out, double* tail_out) {
+  return choose_N_impl(kind, param, tol, kmode, N_fixed, N_max, N_out, tail_out);
 }
 
 cp_status cp_graph_create(int64_t n, int64_t nnz, const int64_t* row_ptr, const int32_t* col_idx,
@@ -606,16 +632,15 @@ size_t cp_workspace_bytes(const cp_graph* g, int32_t nq, int32_t prec) {
 cp_status cp_power(const cp_graph* g, const cp_query* q, int32_t prec, void* y, void* ws,
                    size_t ws_bytes, void* stream, cp_info* info) {
   if (!g || !q || !y || !valid_prec(prec)) return CP_EINVAL;
-  int64_t s = 0;
-  int32_t K = 0;
-  double tail = 0, L = 1;
-  cp_status rc = check_query(g, q, &s, &K, &tail, &L);
+  QueryPlan qp;
+  cp_status rc = plan_query(g, q, kDefaultKMax, &qp);
   if (rc != CP_OK) return rc;
   const WsLayout W = ws_layout(g, 1, prec);
   if (!ws || ws_bytes < W.total || (reinterpret_cast<uintptr_t>(ws) & 255)) return CP_EWORKSPACE;
-  std::vector<double> c(K + 1);
-  rc = coeffs_impl(q->kind, q->param, K, c.data());
-  if (rc != CP_OK) return rc;
+  const int64_t s = qp.s_int;
+  const int32_t top = qp.top;
+  const std::vector<double>& c = qp.c;
+  const bool power = q->flags & CP_Q_PWMETHOD;
 
   hipStream_t st = static_cast<hipStream_t>(stream);
   char* w = static_cast<char*>(ws);
@@ -629,7 +654,7 @@ cp_status cp_power(const cp_graph* g, const cp_query* q, int32_t prec, void* y, 
     for (hipEvent_t e : ev) (void)hipEventDestroy(e);
   };
   if (timing) {
-    ev.resize(2 + 2 * (size_t)std::max(K - 1, 0));
+    ev.resize(2 + 2 * (size_t)std::max(top - 1, 0));
     for (auto& e : ev) {
       hipError_t he = hipEventCreate(&e);
       if (he != hipSuccess) { set_hip_error(he); cleanup(); return CP_EHIP; }
@@ -660,8 +685,8 @@ cp_status cp_power(const cp_graph* g, const cp_query* q, int32_t prec, void* y, 
   sa.yacc = yacc;
   sa.hub_partial = w + W.hub_partial;
   sa.hub_count = reinterpret_cast<int32_t*>(w + W.hub_count);
-  for (int32_t k = 1; k < K; ++k) {
-    // x = r~_k, z = r~_{k-1} -> r~_{k+1}
+  for (int32_t k = 1; k < top; ++k) {
+    // x = r~_k, z = r~_{k-1} -> r~_{k+1} (Alg. 1: z <- r~_{k+1})
     sa.x = (k & 1) ? rB : rA;
     sa.z = (k & 1) ? rA : rB;
     sa.c = c[k + 1];
@@ -678,9 +703,9 @@ cp_status cp_power(const cp_graph* g, const cp_query* q, int32_t prec, void* y, 
       ga.partial = w + W.partial;
       CP_HIP_C(launch_stripe_gather(prec, ga, st));
       CombineArgs ca{g->row_ptr, g->n, w + W.partial, sa.z, yacc, sa.c};
-      CP_HIP_C(launch_stripe_combine(prec, ca, st));
+      CP_HIP_C(launch_stripe_combine(prec, ca, power, st));
     } else {
-      CP_HIP_C(launch_step(prec, sa, st));
+      CP_HIP_C(launch_step(prec, sa, power, st));
     }
     if (timing) CP_HIP_C(hipEventRecord(ev[2 * k + 1], st));
   }
@@ -690,10 +715,10 @@ cp_status cp_power(const cp_graph* g, const cp_query* q, int32_t prec, void* y, 
   if (timing) CP_HIP_C(hipEventRecord(ev[1], st));
 
   if (info) {
-    info->K = K;
-    info->steps = K - 1;
-    info->tail = tail;
-    info->tail_bound_l1 = tail * L;
+    info->K = qp.K;
+    info->steps = top - 1;
+    info->tail = qp.tail;
+    info->tail_bound_l1 = qp.tail * qp.L;
     info->mass = NAN;
     info->elapsed_ms = NAN;
     info->step_ms = NAN;
@@ -712,7 +737,7 @@ cp_status cp_power(const cp_graph* g, const cp_query* q, int32_t prec, void* y, 
       CP_HIP_C(hipEventElapsedTime(&ms, ev[0], ev[1]));
       info->elapsed_ms = ms;
       double sum = 0;
-      for (int32_t k = 1; k < K; ++k) {
+      for (int32_t k = 1; k < top; ++k) {
         CP_HIP_C(hipEventElapsedTime(&ms, ev[2 * k], ev[2 * k + 1]));
         sum += ms;
       }
@@ -731,36 +756,31 @@ namespace {
 
 cp_status power_batch_bw(cp_graph* g, int32_t nq, const cp_query* q, int32_t prec, void* Y, void* ws,
                          size_t ws_bytes, hipStream_t st, cp_info* infos, int32_t bw) {
-  std::vector<int64_t> s_int(nq);
-  std::vector<int32_t> K(nq);
-  std::vector<double> tail(nq), L(nq);
+  std::vector<QueryPlan> P(nq);
   for (int32_t j = 0; j < nq; ++j) {
-    cp_status rc = check_query(g, &q[j], &s_int[j], &K[j], &tail[j], &L[j]);
+    cp_status rc = plan_query(g, &q[j], kBatchKCap, &P[j]);
     if (rc != CP_OK) return rc;
-    if (K[j] > kBatchKCap) return CP_EKMAX;
   }
   const BatchLayout W = batch_layout(g, nq, prec, bw);
   if (!ws || ws_bytes < W.total || (reinterpret_cast<uintptr_t>(ws) & 255)) return CP_EWORKSPACE;
-  // slots in decreasing K (stable), tiles of bw slots
+  // slots in decreasing number of steps (stable), tiles of bw slots
   std::vector<int32_t> order(nq);
   std::iota(order.begin(), order.end(), 0);
-  std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return K[a] > K[b]; });
+  std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return P[a].top > P[b].top; });
   std::vector<int32_t> slot_of_query(nq);
   for (int32_t i = 0; i < nq; ++i) slot_of_query[order[i]] = i;
-  const int32_t Kmax = K[order[0]];
+  const int32_t Kmax = P[order[0]].top;
   std::vector<double> coef((size_t)(Kmax + 1) * W.nq_pad, 0.0);
   std::vector<int64_t> src(W.nq_pad, -1);
-  std::vector<double> c;
+  std::vector<double> rec(W.nq_pad, 2.0);
   for (int32_t i = 0; i < nq; ++i) {
-    const int32_t j = order[i];
-    c.assign(K[j] + 1, 0.0);
-    cp_status rc = coeffs_impl(q[j].kind, q[j].param, K[j], c.data());
-    if (rc != CP_OK) return rc;
-    for (int32_t k = 0; k <= K[j]; ++k) coef[(size_t)k * W.nq_pad + i] = c[k];
-    src[i] = s_int[j];
+    const QueryPlan& p = P[order[i]];
+    for (int32_t k = 0; k <= p.top; ++k) coef[(size_t)k * W.nq_pad + i] = p.c[k];
+    src[i] = p.s_int;
+    rec[i] = p.rec;
   }
   std::vector<int32_t> tileK(W.ntiles);
-  for (int32_t t = 0; t < W.ntiles; ++t) tileK[t] = K[order[t * bw]];
+  for (int32_t t = 0; t < W.ntiles; ++t) tileK[t] = P[order[t * bw]].top;
 
   char* w = static_cast<char*>(ws);
   double* dcoef = reinterpret_cast<double*>(w + W.coef);
@@ -786,6 +806,7 @@ cp_status power_batch_bw(cp_graph* g, int32_t nq, const cp_query* q, int32_t pre
   CP_HIP_B(launch_upload(dcoef, coef.data(), coef.size() * sizeof(double), st));
   CP_HIP_B(launch_upload(w + W.src, src.data(), src.size() * sizeof(int64_t), st));
   CP_HIP_B(launch_upload(w + W.slotmap, slot_of_query.data(), slot_of_query.size() * sizeof(int32_t), st));
+  CP_HIP_B(launch_upload(w + W.rec, rec.data(), rec.size() * sizeof(double), st));
   void* rA = w + W.rA;
   void* rB = w + W.rB;
   BatchInitArgs ia{g->row_ptr, g->col_idx, reinterpret_cast<const int64_t*>(w + W.src), g->n, bw,
@@ -802,11 +823,11 @@ cp_status power_batch_bw(cp_graph* g, int32_t nq, const cp_query* q, int32_t pre
   sa.bw = bw;
   sa.nq_pad = W.nq_pad;
   sa.yacc = w + W.yacc;
+  sa.rec = reinterpret_cast<const double*>(w + W.rec);
   sa.hub_partial = w + W.hub_partial;
   sa.hub_count = reinterpret_cast<int32_t*>(w + W.hub_count);
   sa.ntiles_total = W.ntiles;
   if (timing) CP_HIP_B(hipEventRecord(ev[1], st));
-  int64_t launches = 0;
   for (int32_t k = 1; k < Kmax; ++k) {
     int32_t active = 0;
     while (active < W.ntiles && tileK[active] > k) ++active;
@@ -816,7 +837,6 @@ cp_status power_batch_bw(cp_graph* g, int32_t nq, const cp_query* q, int32_t pre
     sa.z = (k & 1) ? rA : rB;
     sa.coef_row = dcoef + (size_t)(k + 1) * W.nq_pad;
     CP_HIP_B(launch_batch_step(prec, sa, st));
-    ++launches;
   }
   if (timing) CP_HIP_B(hipEventRecord(ev[2], st));
   BatchFinalArgs fa{g->row_ptr, g->perm, reinterpret_cast<const int32_t*>(w + W.slotmap), g->n, bw, nq,
@@ -831,10 +851,10 @@ cp_status power_batch_bw(cp_graph* g, int32_t nq, const cp_query* q, int32_t pre
   }
   if (infos)
     for (int32_t j = 0; j < nq; ++j) {
-      infos[j].K = K[j];
-      infos[j].steps = (int32_t)launches;
-      infos[j].tail = tail[j];
-      infos[j].tail_bound_l1 = tail[j] * L[j];
+      infos[j].K = P[j].K;
+      infos[j].steps = P[j].top - 1;
+      infos[j].tail = P[j].tail;
+      infos[j].tail_bound_l1 = P[j].tail * P[j].L;
       infos[j].mass = NAN;
       infos[j].elapsed_ms = ms_all;
       infos[j].step_ms = ms_steps;

@@ -13,6 +13,12 @@
 //                  recurrence keeps every order accurate to a few ulps
 //                  relative, so tiny tail coefficients are reliable.
 //  K selection: see cp_kmode in chebyprop.h.
+//
+//  Taylor weights of PwMethod (Def. 3, Def. 4, Alg. 1): PPR zeta_k =
+//  alpha (1 - alpha)^k, HKPR zeta_k = e^{-t} t^k / k! (evaluated through
+//  logarithms).  Every P^k e_s is a probability vector, so the l1 error
+//  of N terms is exactly the tail sum_{k>=N} zeta_k: (1 - alpha)^N for PPR,
+//  the Poisson(t) upper tail for HKPR (summed term by term from the far end).
 
 #include <algorithm>
 #include <cmath>
@@ -139,6 +145,73 @@ cp_status choose_K_impl(int32_t kind, double param, double tol, int32_t kmode, i
   }
   *K_out = K;
   if (tail_out) *tail_out = tail(K);
+  return CP_OK;
+}
+
+namespace {
+
+double hkpr_taylor_term(double t, int64_t k) {
+  return std::exp(-t + (double)k * std::log(t) - std::lgamma((double)k + 1.0));
+}
+
+}  // namespace
+
+cp_status taylor_impl(int32_t kind, double param, int32_t N, double* zeta) {
+  if (!zeta || N < 0 || !valid_kind_param(kind, param)) return CP_EINVAL;
+  if (kind == CP_PPR) {
+    double q = 1.0;
+    for (int32_t k = 0; k < N; ++k) {
+      zeta[k] = param * q;
+      q *= 1.0 - param;
+    }
+    return CP_OK;
+  }
+  for (int32_t k = 0; k < N; ++k) zeta[k] = hkpr_taylor_term(param, k);
+  return CP_OK;
+}
+
+cp_status choose_N_impl(int32_t kind, double param, double tol, int32_t kmode, int32_t N_fixed,
+                        int32_t N_max, int32_t* N_out, double* tail_out) {
+  if (!N_out || !valid_kind_param(kind, param)) return CP_EINVAL;
+  if (N_max <= 0) N_max = kDefaultKMax;
+  const bool ppr = kind == CP_PPR;
+  if (kmode != CP_K_FIXED && !(tol > 0.0 && tol < 1.0)) return CP_EINVAL;
+  if (kmode != CP_K_FIXED && kmode != CP_K_CERTIFIED && kmode != CP_K_TAIL && kmode != CP_K_PAPER)
+    return CP_EINVAL;
+  // HKPR: suffix sums S[N] = sum_{k>=N} zeta_k up to a horizon past which the
+  // Poisson mass is below 1e-30 of the total
+  std::vector<double> S;
+  if (!ppr) {
+    const double t = param;
+    if (t - 12.0 * std::sqrt(t) > (double)N_max) return CP_EKMAX;  // tail(N_max) is ~1
+    const int64_t H = (int64_t)std::ceil(std::max((double)N_max, t + 12.0 * std::sqrt(t))) + 64;
+    S.assign((size_t)H + 2, 0.0);
+    for (int64_t k = H; k >= 0; --k) S[(size_t)k] = S[(size_t)k + 1] + hkpr_taylor_term(t, k);
+  }
+  auto tail = [&](int32_t N) -> double {
+    return ppr ? std::pow(1.0 - param, (double)N) : S[(size_t)N];
+  };
+  int32_t N = 0;
+  if (kmode == CP_K_FIXED) {
+    if (N_fixed < 1) return CP_EINVAL;
+    if (N_fixed > N_max) return CP_EKMAX;
+    N = N_fixed;
+  } else if (ppr) {
+    const double guess = std::ceil(std::log(tol) / std::log(1.0 - param));
+    if (!(guess <= (double)N_max + 1.0)) return CP_EKMAX;
+    N = std::max<int32_t>(1, (int32_t)guess);
+    while (N > 1 && tail(N - 1) <= tol) --N;
+    while (tail(N) > tol) {
+      if (++N > N_max) return CP_EKMAX;
+    }
+  } else {
+    N = 1;
+    while (tail(N) > tol) {
+      if (++N > N_max) return CP_EKMAX;
+    }
+  }
+  *N_out = N;
+  if (tail_out) *tail_out = tail(N);
   return CP_OK;
 }
 

@@ -116,7 +116,8 @@ struct CombineArgs {
   void* yacc;
   double c;
 };
-hipError_t launch_stripe_combine(int32_t prec, const CombineArgs& a, hipStream_t st);
+// power: the power step of Alg. 1 (z[v] = acc / d_v) instead of Eq. 6.
+hipError_t launch_stripe_combine(int32_t prec, const CombineArgs& a, bool power, hipStream_t st);
 
 // ------------------------------------------------------------------ kernels
 
@@ -124,6 +125,8 @@ hipError_t launch_stripe_combine(int32_t prec, const CombineArgs& a, hipStream_t
 //   acc = sum_{u in N(v)} x[u]            (x = D^{-1} r_k)
 //   z[v] = 2 acc / d_v - z[v]             (z: D^{-1} r_{k-1} -> D^{-1} r_{k+1})
 //   yacc[v] += c * z[v]                   (yacc = D^{-1} y)
+// With power = true the step is that of Alg. 1: z[v] = acc / d_v (z is
+// only written).
 struct StepArgs {
   const int64_t* row_ptr;
   const int32_t* col_idx;
@@ -139,7 +142,7 @@ struct StepArgs {
   int32_t* hub_count; // int32[nhubs], zero between steps
 };
 
-hipError_t launch_step(int32_t prec, const StepArgs& a, hipStream_t st);
+hipError_t launch_step(int32_t prec, const StepArgs& a, bool power, hipStream_t st);
 
 // Zero-fill `bytes` bytes (multiple of 4) at `p`.
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t st);
@@ -191,6 +194,7 @@ struct BatchStepArgs {
   void* z;
   void* yacc;
   const double* coef_row;  // coef + (k+1)*nq_pad
+  const double* rec;     // [nq_pad] per slot: 2 (Chebyshev step, Eq. 6) or 1 (power step, Alg. 1)
   void* hub_partial;     // A[hub_segments][nq_pad]
   int32_t* hub_count;    // int32[nhubs][ntiles_total]
   int32_t ntiles_total;
@@ -251,11 +255,26 @@ cp_status choose_K_impl(int32_t kind, double param, double tol, int32_t kmode, i
 
 void set_hip_error(hipError_t e);
 
-// Validate a query against a graph: source range and degree, parameter
-// domain, truncation step.  s_int is the source in internal node order, L
-// the certified l1 multiplier sqrt(vol / d_s).
-cp_status check_query(const cp_graph* g, const cp_query* q, int64_t* s_int, int32_t* K,
-                      double* tail, double* L);
+// Validate a query against a graph (source range and degree, parameter
+// domain, flags, truncation step) and plan it: everything a query needs
+// before launch.  s_int is the source in internal node order, L the l1
+// multiplier of the tail bound (sqrt(vol / d_s) for Alg. 3).  Alg. 3: c = c_0..c_K, top = K.
+// Alg. 1 (CP_Q_PWMETHOD): c = zeta_0..zeta_{N-1} (zero-padded to two
+// entries), top = max(N - 1, 1), L = 1.  Both run the same launch sequence:
+// init gives r_0, r_1 and c_0 r_0 + c_1 r_1, then top - 1 steps add
+// c_{k+1} r_{k+1}.
+struct QueryPlan {
+  int64_t s_int = 0;
+  int32_t K = 0;      // reported truncation step: K (Alg. 3) or N (Alg. 1)
+  int32_t top = 0;    // highest coefficient index
+  double tail = 0, L = 1;
+  double rec = 2.0;   // step factor: 2 (Eq. 6) or 1 (Alg. 1)
+  std::vector<double> c;
+};
+cp_status plan_query(const cp_graph* g, const cp_query* q, int32_t K_max, QueryPlan* p);
+cp_status taylor_impl(int32_t kind, double param, int32_t N, double* zeta);
+cp_status choose_N_impl(int32_t kind, double param, double tol, int32_t kmode, int32_t N_fixed,
+                        int32_t N_max, int32_t* N_out, double* tail_out);
 
 constexpr int32_t kDefaultKMax = 4096;
 constexpr int32_t kBatchKCap = 1024;  // largest K a batched query may need

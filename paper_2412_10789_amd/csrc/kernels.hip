@@ -78,10 +78,13 @@ __device__ __forceinline__ int64_t logical_block(int64_t w, int64_t nblocks, int
   return nspecial + x * q + (x < r ? x : r) + j;
 }
 
-// z(v) <- 2 acc / d - z(v);  yacc(v) += c z_new
-template <typename T, typename A>
+// Chebyshev step (Eq. 6): z(v) <- 2 acc / d - z(v);  power step (Alg. 1):
+// z(v) <- acc / d.  Then yacc(v) += c z_new.
+template <typename T, typename A, bool PW>
 __device__ __forceinline__ void row_update(T* z, A* yacc, int64_t v, A acc, int32_t d, A c) {
-  const A zn = (A(2) * acc) / A(d) - to_acc(ld_stream(z + v));
+  A zn;
+  if constexpr (PW) zn = acc / A(d);
+  else zn = (A(2) * acc) / A(d) - to_acc(ld_stream(z + v));
   st_stream(z + v, from_acc<T>(zn));
   st_stream(yacc + v, ld_stream(yacc + v) + c * zn);
 }
@@ -178,7 +181,7 @@ __device__ __forceinline__ void tile_rowsums(const VT* vals, const int32_t* rpl,
   __syncthreads();
 }
 
-template <typename T>
+template <typename T, bool PW>
 __global__ void __launch_bounds__(kThreads) step_kernel(StepArgs a) {
   using A = typename Acc<T>::type;
   __shared__ A vals[kTileNnz];
@@ -226,7 +229,7 @@ __global__ void __launch_bounds__(kThreads) step_kernel(StepArgs a) {
     // Phase 3: row-parallel recurrence and accumulation.
     for (int j = tid; j < nr; j += kThreads) {
       const int32_t d = rpl[j + 1] - rpl[j];
-      if (d > 0) row_update<T, A>(z, yacc, (int64_t)r0 + j, rowsum[j], d, c);
+      if (d > 0) row_update<T, A, PW>(z, yacc, (int64_t)r0 + j, rowsum[j], d, c);
     }
     return;
   }
@@ -235,7 +238,7 @@ __global__ void __launch_bounds__(kThreads) step_kernel(StepArgs a) {
     const int64_t v = bd.r0;
     const int64_t p0 = rp[v], p1 = rp[v + 1];
     const A total = block_gather_sum<T, A>(col, x, p0, p1, wsum);
-    if (tid == 0) row_update<T, A>(z, yacc, v, total, (int32_t)(p1 - p0), c);
+    if (tid == 0) row_update<T, A, PW>(z, yacc, v, total, (int32_t)(p1 - p0), c);
     return;
   }
 
@@ -254,7 +257,7 @@ __global__ void __launch_bounds__(kThreads) step_kernel(StepArgs a) {
       A s = A(0);
       for (int q = 0; q < h.nseg; ++q)
         s += __hip_atomic_load(part + h.base + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      row_update<T, A>(z, yacc, h.row, s, (int32_t)(re - rb), c);
+      row_update<T, A, PW>(z, yacc, h.row, s, (int32_t)(re - rb), c);
       __hip_atomic_store(a.hub_count + bd.r1, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
   }
@@ -318,7 +321,7 @@ __global__ void __launch_bounds__(kThreads) stripe_gather_kernel(StripeArgs a) {
 
 // Combine the 8 stripe partials of every row (in stripe order) and apply the
 // recurrence and estimate update.
-template <typename T>
+template <typename T, bool PW>
 __global__ void __launch_bounds__(kThreads) stripe_combine_kernel(CombineArgs a) {
   using A = typename Acc<T>::type;
   const A* __restrict__ part = static_cast<const A*>(a.partial);
@@ -332,7 +335,7 @@ __global__ void __launch_bounds__(kThreads) stripe_combine_kernel(CombineArgs a)
     A acc = A(0);
 #pragma unroll
     for (int j = 0; j < kStripes; ++j) acc += ld_stream(part + (size_t)j * (size_t)a.n + v);
-    row_update<T, A>(z, yacc, v, acc, (int32_t)d, c);
+    row_update<T, A, PW>(z, yacc, v, acc, (int32_t)d, c);
   }
 }
 
@@ -404,16 +407,21 @@ constexpr int kFinalBlocks = 1024;
 
 }  // namespace
 
-hipError_t launch_step(int32_t prec, const StepArgs& a, hipStream_t st) {
-  if (a.nblocks <= 0) return hipSuccess;
+template <bool PW>
+hipError_t launch_step_t(int32_t prec, const StepArgs& a, hipStream_t st) {
   dim3 grid((unsigned)a.nblocks), block(kThreads);
   switch (prec) {
-    case CP_F64: hipLaunchKernelGGL(step_kernel<double>, grid, block, 0, st, a); break;
-    case CP_F32: hipLaunchKernelGGL(step_kernel<float>, grid, block, 0, st, a); break;
-    case CP_BF16: hipLaunchKernelGGL(step_kernel<bf16>, grid, block, 0, st, a); break;
+    case CP_F64: hipLaunchKernelGGL((step_kernel<double, PW>), grid, block, 0, st, a); break;
+    case CP_F32: hipLaunchKernelGGL((step_kernel<float, PW>), grid, block, 0, st, a); break;
+    case CP_BF16: hipLaunchKernelGGL((step_kernel<bf16, PW>), grid, block, 0, st, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+hipError_t launch_step(int32_t prec, const StepArgs& a, bool power, hipStream_t st) {
+  if (a.nblocks <= 0) return hipSuccess;
+  return power ? launch_step_t<true>(prec, a, st) : launch_step_t<false>(prec, a, st);
 }
 
 hipError_t launch_stripe_gather(int32_t prec, const StripeArgs& a, hipStream_t st) {
@@ -428,18 +436,23 @@ hipError_t launch_stripe_gather(int32_t prec, const StripeArgs& a, hipStream_t s
   return hipGetLastError();
 }
 
-hipError_t launch_stripe_combine(int32_t prec, const CombineArgs& a, hipStream_t st) {
+template <bool PW>
+hipError_t launch_stripe_combine_t(int32_t prec, const CombineArgs& a, hipStream_t st) {
   int64_t blocks = (a.n + kThreads - 1) / kThreads;
   if (blocks > 4096) blocks = 4096;
   if (blocks < 1) blocks = 1;
   dim3 grid((unsigned)blocks), block(kThreads);
   switch (prec) {
-    case CP_F64: hipLaunchKernelGGL(stripe_combine_kernel<double>, grid, block, 0, st, a); break;
-    case CP_F32: hipLaunchKernelGGL(stripe_combine_kernel<float>, grid, block, 0, st, a); break;
-    case CP_BF16: hipLaunchKernelGGL(stripe_combine_kernel<bf16>, grid, block, 0, st, a); break;
+    case CP_F64: hipLaunchKernelGGL((stripe_combine_kernel<double, PW>), grid, block, 0, st, a); break;
+    case CP_F32: hipLaunchKernelGGL((stripe_combine_kernel<float, PW>), grid, block, 0, st, a); break;
+    case CP_BF16: hipLaunchKernelGGL((stripe_combine_kernel<bf16, PW>), grid, block, 0, st, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+hipError_t launch_stripe_combine(int32_t prec, const CombineArgs& a, bool power, hipStream_t st) {
+  return power ? launch_stripe_combine_t<true>(prec, a, st) : launch_stripe_combine_t<false>(prec, a, st);
 }
 
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t st) {

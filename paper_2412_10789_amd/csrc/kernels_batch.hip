@@ -56,9 +56,11 @@ __device__ __forceinline__ int64_t logical_block(int64_t w, int64_t nblocks, int
   return nspecial + x * q + (x < r ? x : r) + j;
 }
 
+// zn = u acc / d - (u - 1) z: u = 2 is the Chebyshev step (Eq. 6), u = 1
+// the power step of Alg. 1 (the old value is read but weighted by zero).
 template <typename T, typename A>
-__device__ __forceinline__ void row_update(T* z, A* y, size_t e, A acc, int32_t d, A c) {
-  const A zn = (A(2) * acc) / A(d) - to_acc(ld_nt(z + e));
+__device__ __forceinline__ void row_update(T* z, A* y, size_t e, A acc, int32_t d, A c, A u) {
+  const A zn = (u * acc) / A(d) - (u - A(1)) * to_acc(ld_nt(z + e));
   st_nt(z + e, from_acc<T>(zn));
   st_nt(y + e, ld_nt(y + e) + c * zn);
 }
@@ -106,6 +108,7 @@ __global__ void __launch_bounds__(kThreads) batch_step_kernel(BatchStepArgs a) {
   T* __restrict__ z = static_cast<T*>(a.z) + toff;
   A* __restrict__ y = static_cast<A*>(a.yacc) + toff;
   const A c = (A)a.coef_row[tile * BW + lane];
+  const A u = (A)a.rec[tile * BW + lane];
   const int64_t* __restrict__ rp = a.row_ptr;
   const int32_t* __restrict__ col = a.col_idx;
   const int64_t b = logical_block(blockIdx.x, a.nblocks, a.nspecial);
@@ -142,7 +145,7 @@ __global__ void __launch_bounds__(kThreads) batch_step_kernel(BatchStepArgs a) {
         acc += (v0 + v1) + (v2 + v3);
       }
       for (; p < pe; ++p) acc += to_acc(x[(size_t)cols[p] * BW + lane]);
-      row_update<T, A>(z, y, (size_t)(r0 + r) * BW + lane, acc, pe - pb, c);
+      row_update<T, A>(z, y, (size_t)(r0 + r) * BW + lane, acc, pe - pb, c, u);
     }
     return;
   }
@@ -151,7 +154,7 @@ __global__ void __launch_bounds__(kThreads) batch_step_kernel(BatchStepArgs a) {
     const int64_t v = bd.r0;
     const int64_t p0 = rp[v], p1 = rp[v + 1];
     const A total = wg_row_sum<T, A, BW>(col, x, p0, p1, grp, lane, part);
-    if (grp == 0) row_update<T, A>(z, y, (size_t)v * BW + lane, total, (int32_t)(p1 - p0), c);
+    if (grp == 0) row_update<T, A>(z, y, (size_t)v * BW + lane, total, (int32_t)(p1 - p0), c, u);
     return;
   }
 
@@ -181,7 +184,7 @@ __global__ void __launch_bounds__(kThreads) batch_step_kernel(BatchStepArgs a) {
     for (int q = 0; q < h.nseg; ++q)
       s += __hip_atomic_load(hp + (size_t)(h.base + q) * a.nq_pad + slot, __ATOMIC_RELAXED,
                              __HIP_MEMORY_SCOPE_AGENT);
-    row_update<T, A>(z, y, (size_t)h.row * BW + lane, s, (int32_t)(re - rb), c);
+    row_update<T, A>(z, y, (size_t)h.row * BW + lane, s, (int32_t)(re - rb), c, u);
     if (lane == 0) __hip_atomic_store(counter, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 }

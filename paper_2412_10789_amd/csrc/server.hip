@@ -38,10 +38,7 @@ struct Ticket {
   bool cancel_requested = false;
   cp_query q{};
   void* y = nullptr;
-  int64_t s_int = 0;
-  int32_t K = 0;
-  double tail = 0, L = 0;
-  std::vector<double> c;
+  cp::QueryPlan plan;  // source, coefficients, steps (top), step factor
   int32_t slot = -1;
   Clock::time_point t_submit, t_admit, t_done;
 };
@@ -57,7 +54,8 @@ struct cp_server {
   size_t dev_bytes = 0;
   // device layout
   size_t o_rA = 0, o_rB = 0, o_y = 0, o_hcount = 0, o_hpart = 0, o_coef = 0, o_src = 0, o_c01 = 0,
-         o_fslots = 0, o_fouts = 0;
+         o_rec = 0, o_fslots = 0, o_fouts = 0;
+  std::vector<double> rec;  // host copy of the per-slot step factor
 
   std::mutex mu;
   std::condition_variable cv;       // wakes the worker
@@ -87,10 +85,10 @@ double ms_between(Clock::time_point a, Clock::time_point b) {
 
 void fill_info(const Ticket& t, cp_info* info) {
   if (!info) return;
-  info->K = t.K;
-  info->steps = t.K - 1;
-  info->tail = t.tail;
-  info->tail_bound_l1 = t.tail * t.L;
+  info->K = t.plan.K;
+  info->steps = t.plan.top - 1;
+  info->tail = t.plan.tail;
+  info->tail_bound_l1 = t.plan.tail * t.plan.L;
   info->mass = NAN;
   info->elapsed_ms = NAN;
   info->step_ms = NAN;
@@ -153,25 +151,26 @@ void cp_server::run() {
         const uint64_t t = slot_ticket[s];
         if (!t) continue;
         const Ticket& tk = tickets[t];
-        if (slot_k[s] < tk.K) {
+        if (slot_k[s] < tk.plan.top) {
           stepping.push_back(s);
-          coef_row[s] = tk.c[slot_k[s] + 1];
+          coef_row[s] = tk.plan.c[slot_k[s] + 1];
         }
       }
       std::fill(src.begin(), src.end(), -1);
       for (int32_t s : admitted) {
         const Ticket& tk = tickets[slot_ticket[s]];
-        src[s] = tk.s_int;
-        c01[s] = tk.c[0];
-        c01[nslot + s] = tk.c[1];
+        src[s] = tk.plan.s_int;
+        c01[s] = tk.plan.c[0];
+        c01[nslot + s] = tk.plan.c[1];
+        rec[s] = tk.plan.rec;
       }
       // queries that finish with this launch (or right after init when K == 1)
       for (int32_t s = 0; s < nslots; ++s) {
         const uint64_t t = slot_ticket[s];
         if (!t) continue;
         const Ticket& tk = tickets[t];
-        const int32_t k_after = slot_k[s] < tk.K ? slot_k[s] + 1 : slot_k[s];
-        if (k_after >= tk.K) {
+        const int32_t k_after = slot_k[s] < tk.plan.top ? slot_k[s] + 1 : slot_k[s];
+        if (k_after >= tk.plan.top) {
           finishing.push_back(s);
           fin_tickets.push_back(t);
         }
@@ -199,6 +198,7 @@ void cp_server::run() {
     if (!admitted.empty()) {
       chk(launch_upload(w + o_src, src.data(), nslot * sizeof(int64_t), st));
       chk(launch_upload(w + o_c01, c01.data(), 2 * nslot * sizeof(double), st));
+      chk(launch_upload(w + o_rec, rec.data(), nslot * sizeof(double), st));
       BatchInitArgs ia{g->row_ptr, g->col_idx, reinterpret_cast<const int64_t*>(w + o_src), g->n, bw, nslots,
                        zbuf, xbuf, w + o_y, reinterpret_cast<const double*>(w + o_c01)};
       chk(launch_batch_init(prec, ia, nslots, st));
@@ -222,6 +222,7 @@ void cp_server::run() {
       sa.z = zbuf;
       sa.yacc = w + o_y;
       sa.coef_row = reinterpret_cast<const double*>(w + o_coef);
+      sa.rec = reinterpret_cast<const double*>(w + o_rec);
       sa.hub_partial = w + o_hpart;
       sa.hub_count = reinterpret_cast<int32_t*>(w + o_hcount);
       sa.ntiles_total = ntiles;
@@ -307,6 +308,7 @@ cp_status cp_server_create(const cp_graph* g, size_t hbm_budget_bytes, int32_t m
   s->o_coef = off; off += a256(ns * 8);
   s->o_src = off; off += a256(ns * 8);
   s->o_c01 = off; off += a256(2 * ns * 8);
+  s->o_rec = off; off += a256(ns * 8);
   s->o_fslots = off; off += a256(ns * 4);
   s->o_fouts = off; off += a256(ns * 8);
   s->dev_bytes = off;
@@ -321,6 +323,8 @@ cp_status cp_server_create(const cp_graph* g, size_t hbm_budget_bytes, int32_t m
     return CP_EHIP;
   }
   e = launch_zero(s->dev, s->o_hpart, s->st);  // state buffers and hub counters start at zero
+  s->rec.assign(ns, 2.0);
+  if (e == hipSuccess) e = launch_upload(s->dev + s->o_rec, s->rec.data(), ns * sizeof(double), s->st);
   if (e == hipSuccess) e = hipStreamSynchronize(s->st);
   if (e != hipSuccess) {
     set_hip_error(e);
@@ -346,11 +350,7 @@ cp_status cp_server_create(const cp_graph* g, size_t hbm_budget_bytes, int32_t m
 cp_status cp_server_submit(cp_server* s, const cp_query* q, void* y_out, uint64_t* ticket) {
   if (!s || !q || !y_out || !ticket) return CP_EINVAL;
   Ticket tk;
-  cp_status rc = check_query(s->g, q, &tk.s_int, &tk.K, &tk.tail, &tk.L);
-  if (rc != CP_OK) return rc;
-  if (tk.K > kBatchKCap) return CP_EKMAX;
-  tk.c.assign(tk.K + 2, 0.0);  // c_{K+1} slot stays 0
-  rc = coeffs_impl(q->kind, q->param, tk.K, tk.c.data());
+  cp_status rc = plan_query(s->g, q, kBatchKCap, &tk.plan);
   if (rc != CP_OK) return rc;
   tk.q = *q;
   tk.y = y_out;

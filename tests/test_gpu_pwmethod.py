@@ -1,0 +1,171 @@
+"""PwMethod (Alg. 1) on the GPU (CP_Q_PWMETHOD through the C ABI) against the
+oracle's Alg. 1 at the same N, and the exact-error identity: every P^k e_s
+is a probability vector, so the l1 distance to f(P) e_s equals the Taylor
+tail sum_{k>=N} zeta_k up to rounding.  Also batched and served queries
+that mix Alg. 1 and Alg. 3 in the same launches."""
+
+import numpy as np
+import pytest
+
+import synth
+from gpu_util import compare, gpu_graph, oracle_yK, require_gpu
+from oracle import coefficients as C
+from oracle import errors as E
+from oracle import propagation as PR
+from oracle import truncation as T
+
+pytestmark = pytest.mark.gpu
+
+
+def _case(*a):
+    print("CASE", *a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def torch():
+    return require_gpu()
+
+
+def oracle_pw(g, s, kind, param, N, P=None):
+    if P is None:
+        P = PR.transition_matrix(g.row_ptr, g.col_idx)
+    return PR.power_method(P, int(s), C.taylor_coeffs(kind, param, N), N)
+
+
+def test_small_N_on_tiny_graphs(torch):
+    """N = 1, 2, 3 (no full step), 4 and 9 terms on textbook graphs."""
+    import pins
+
+    for g in [synth.star(3), synth.path(6)] + list(pins.tiny_graphs())[:3]:
+        G = gpu_graph(g)
+        s = int(np.flatnonzero(g.degrees > 0)[1])
+        for kind, param in (("ppr", 0.3), ("hkpr", 2.0)):
+            for N in (1, 2, 3, 4, 9):
+                _case("pw-tiny", g.name, kind, N)
+                r = G.power(kind, param, s, prec="f64", kmode="fixed", K=N, method="power")
+                assert r.info["K"] == N and r.info["steps"] == max(N - 2, 0)
+                np.testing.assert_allclose(r.y.cpu().numpy(), oracle_pw(g, s, kind, param, N), atol=1e-15)
+
+
+@pytest.mark.parametrize("layout", ["native", "degree", "stripes"])
+def test_config1_exact_error_identity_f64(torch, layout):
+    """n=20,000 Chung-Lu: GPU Alg. 1 equals the oracle's Alg. 1 at the same N,
+    and its l1 error against f(P) e_s equals the Taylor tail."""
+    g = synth.chung_lu(20_000, 100_000, 2.5, seed=1)
+    P = PR.transition_matrix(g.row_ptr, g.col_idx)
+    G = gpu_graph(g, reorder=layout == "degree", stripes=layout == "stripes")
+    for kind, param, tol in (("ppr", 0.2, 1e-8), ("hkpr", 5.0, 1e-9)):
+        exact_by_src = {}
+        for s in synth.sources(g, 2, seed=3):
+            s = int(s)
+            _case("pw-config1", layout, kind, s)
+            r = G.power(kind, param, s, tol=tol, prec="f64", method="power", flags=1)
+            N = r.info["K"]
+            assert N == T.pwmethod_steps(kind, param, tol)
+            y = r.y.cpu().numpy()
+            np.testing.assert_allclose(y, oracle_pw(g, s, kind, param, N, P), atol=1e-15, rtol=1e-12)
+            exact = exact_by_src.setdefault(s, PR.ground_truth(P, s, kind, param))
+            tail = T.taylor_tail(kind, param, N)
+            assert abs(r.info["tail"] - tail) <= 1e-12 * tail
+            assert r.info["tail_bound_l1"] == r.info["tail"]
+            assert abs(E.l1(y, exact) - tail) <= 1e-12 + 1e-9 * tail, (E.l1(y, exact), tail)
+            assert abs(r.info["mass"] - (1.0 - tail)) < 1e-12
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16"])
+def test_powerlaw_reduced_storage(torch, prec):
+    """200k-node power-law graph with rows longer than a tile: FP32 storage
+    (double arithmetic) to the FP32 bound, BF16 reported within its bound."""
+    g = synth.chung_lu(200_000, 2_400_000, 2.1, seed=12)
+    P = PR.transition_matrix(g.row_ptr, g.col_idx)
+    for stripes in (False, True):
+        G = gpu_graph(g, stripes=stripes)
+        s = int(synth.sources(g, 1, seed=4)[0])
+        _case("pw-powerlaw", prec, stripes)
+        r = G.power("ppr", 0.15, s, tol=1e-6, prec=prec, method="power")
+        ref = oracle_pw(g, s, "ppr", 0.15, r.info["K"], P)
+        m = compare(r.y.cpu().numpy(), ref)
+        # storage rounding (2^-24 FP32, 2^-9 BF16 relative) enters every
+        # stored iterate of l1 norm 1 and is carried by later terms: at most
+        # about eps * sum_k k zeta_k = eps (1 - alpha) / alpha
+        assert m["l1"] <= (5e-7 if prec == "f32" else 2e-2), m
+
+
+def test_hub_rows_f64(torch):
+    leaves = 40_000
+    e = [(0, i) for i in range(1, leaves + 1)] + [(i, i + 1) for i in range(1, leaves, 3)]
+    g = synth.from_edges(leaves + 1, e, name="hub+chain")
+    P = PR.transition_matrix(g.row_ptr, g.col_idx)
+    for stripes in (False, True):
+        G = gpu_graph(g, stripes=stripes)
+        assert stripes or G.stats["hub_rows"] == 1
+        for s in (0, 7):
+            _case("pw-hub", stripes, s)
+            r = G.power("hkpr", 3.0, s, tol=1e-10, prec="f64", method="power")
+            ref = oracle_pw(g, s, "hkpr", 3.0, r.info["K"], P)
+            assert compare(r.y.cpu().numpy(), ref)["max_abs"] <= 1e-11
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_batch_mixes_algorithms(torch, prec):
+    """One cp_power_batch call holding Alg. 1 and Alg. 3 queries in the same
+    tiles: every column against the oracle of its own algorithm, and (FP64)
+    against the single-source run of the same query."""
+    from paper_2412_10789_amd import chebyprop as cp
+
+    g = synth.chung_lu(150_000, 1_500_000, 2.2, seed=31)
+    P = PR.transition_matrix(g.row_ptr, g.col_idx)
+    G = gpu_graph(g)
+    nq = 21
+    srcs = synth.sources(g, nq, seed=8)
+    kinds = [("ppr", 0.2), ("hkpr", 5.0), ("ppr", 0.1)]
+    qs, meta = [], []
+    for i in range(nq):
+        kind, param = kinds[i % 3]
+        method = "power" if i % 2 else "cheby"
+        qs.append(cp.make_query(kind, param, int(srcs[i]), 1e-7, method=method))
+        meta.append((kind, param, int(srcs[i]), method))
+    _case("pw-batch", prec)
+    Y, infos = G.power_batch(qs, prec=prec)
+    Y = Y.cpu().numpy()
+    for j, (kind, param, s, method) in enumerate(meta):
+        K = infos[j]["K"]
+        ref = oracle_pw(g, s, kind, param, K, P) if method == "power" else oracle_yK(g, s, kind, param, K, P)
+        m = compare(Y[:, j], ref)
+        assert m["max_abs"] <= 1e-13 if prec == "f64" else m["l1"] <= 2e-6, (j, method, m)
+        if prec == "f64" and j < 6:
+            r = G.power(kind, param, s, tol=1e-7, prec="f64", method=method)
+            assert r.info["K"] == K and r.info["steps"] == infos[j]["steps"]
+            np.testing.assert_allclose(Y[:, j], r.y.cpu().numpy(), atol=1e-14, rtol=1e-12)
+
+
+def test_server_mixes_algorithms(torch):
+    from paper_2412_10789_amd import chebyprop as cp
+
+    g = synth.chung_lu(120_000, 1_000_000, 2.3, seed=41)
+    G = gpu_graph(g, reorder=True)
+    S = cp.Server(G, hbm_budget_bytes=4 << 30, max_slots=32, prec="f64")
+    srcs = synth.sources(g, 40, seed=9)
+    qs = [cp.make_query("ppr" if i % 3 else "hkpr", 0.2 if i % 3 else 4.0, int(srcs[i]), 1e-8,
+                        method="power" if i % 2 else "cheby") for i in range(40)]
+    ys = [torch.full((g.n,), -1.0, dtype=torch.float64, device="cuda") for _ in qs]
+    _case("pw-server")
+    tickets = [S.submit(q, y) for q, y in zip(qs, ys)]
+    for i, t in enumerate(tickets):
+        st, info = S.wait(t, timeout_ms=60_000)
+        assert st == cp.CP_OK, st
+        q = qs[i]
+        method = "power" if q.flags & cp.CP_Q_PWMETHOD else "cheby"
+        r = G.power("hkpr" if q.kind == 1 else "ppr", q.param, q.source, tol=q.tol, prec="f64", method=method)
+        assert r.info["K"] == info["K"]
+        np.testing.assert_allclose(ys[i].cpu().numpy(), r.y.cpu().numpy(), atol=1e-14, rtol=1e-12)
+    S.close()
+
+
+def test_rejects_unknown_query_flags(torch):
+    from paper_2412_10789_amd import chebyprop as cp
+
+    G = gpu_graph(synth.star(3))
+    with pytest.raises(cp.ChebypropError) as ei:
+        G.power("ppr", 0.2, 1, flags=0x40)
+    assert ei.value.status == cp.CP_EINVAL

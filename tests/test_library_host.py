@@ -98,3 +98,45 @@ def test_argument_errors_without_gpu(cp):
     with pytest.raises(cp.ChebypropError) as ei:
         cp.cp_graph_create(0, 0, 0, 0, 0, 0)
     assert ei.value.status == cp.CP_EINVAL
+
+
+@pytest.mark.parametrize("kind,param", [("ppr", 0.01), ("ppr", 0.2), ("ppr", 0.9), ("hkpr", 0.5), ("hkpr", 5.0),
+                                        ("hkpr", 40.0)])
+def test_taylor_weights_match_oracle(cp, kind, param):
+    """Def. 3 / Def. 4 weights of PwMethod (Alg. 1)."""
+    z = cp.cp_taylor(cp.KINDS[kind], param, 300)
+    ref = C.taylor_coeffs(kind, param, 300)
+    big = ref > 1e-290
+    np.testing.assert_allclose(z[big], ref[big], rtol=1e-12)
+    assert np.all(z[~big] < 1e-280)
+    assert cp.cp_taylor(cp.KINDS[kind], param, 0).size == 0
+
+
+def test_pwmethod_terms_match_oracle(cp):
+    for kind, p in [("ppr", 0.2), ("ppr", 0.1), ("ppr", 0.01), ("hkpr", 0.3), ("hkpr", 3.0), ("hkpr", 10.0),
+                    ("hkpr", 60.0)]:
+        for tol in (0.5, 1e-4, 1e-6, 1e-9, 1e-12):
+            for mode in (cp.CP_K_CERTIFIED, cp.CP_K_TAIL, cp.CP_K_PAPER):
+                N, tail = cp.cp_choose_N(cp.KINDS[kind], p, tol, mode)
+                No = T.pwmethod_steps(kind, p, tol)
+                if N != No:  # only where the tail sits on the threshold to rounding
+                    assert abs(T.taylor_tail(kind, p, min(N, No)) - tol) <= 1e-12 * tol, (kind, p, tol, N, No)
+                assert abs(tail - T.taylor_tail(kind, p, N)) <= 1e-12 * tail + 1e-300
+                assert tail <= tol and (N == 1 or T.taylor_tail(kind, p, N - 1) > tol * (1 - 1e-12))
+
+
+def test_pwmethod_term_errors(cp):
+    N, tail = cp.cp_choose_N(cp.CP_PPR, 0.2, 0.0, cp.CP_K_FIXED, 7)
+    assert N == 7 and abs(tail - 0.8**7) < 1e-15
+    for args, status in [((cp.CP_PPR, 0.2, 1e-6, cp.CP_K_FIXED, 0), cp.CP_EINVAL),
+                         ((cp.CP_PPR, 0.2, 1e-6, cp.CP_K_FIXED, 500, 100), cp.CP_EKMAX),
+                         ((cp.CP_PPR, 0.001, 1e-9, cp.CP_K_CERTIFIED, 0, 1000), cp.CP_EKMAX),
+                         ((cp.CP_HKPR, 5000.0, 1e-6, cp.CP_K_CERTIFIED, 0, 4096), cp.CP_EKMAX),
+                         ((cp.CP_HKPR, 5.0, 1.0), cp.CP_EINVAL),
+                         ((cp.CP_PPR, 1.0, 1e-6), cp.CP_EINVAL)]:
+        with pytest.raises(cp.ChebypropError) as ei:
+            cp.cp_choose_N(*args)
+        assert ei.value.status == status, args
+    with pytest.raises(cp.ChebypropError) as ei:
+        cp.cp_taylor(cp.CP_HKPR, -1.0, 3)
+    assert ei.value.status == cp.CP_EINVAL
