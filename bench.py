@@ -85,6 +85,17 @@ def measured_traffic(key: str):
     return e.get("bytes_per_launch")
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def copy_ceiling(torch, nbytes: int = 1 << 30) -> float:
     a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
     b = torch.empty_like(a)
@@ -412,6 +423,64 @@ def run_large(args, torch, cp, synth):
     return out
 
 
+KVN_CASES = [("ppr", 0.2), ("ppr", 0.05), ("ppr", 0.01), ("hkpr", 5.0), ("hkpr", 20.0)]
+
+
+def run_kvn(args, torch, cp, synth, g):
+    """ChebyPower (Alg. 3) against PwMethod (Alg. 1) on the main line's graph
+    at the same l1 guarantee: K from the certified Chebyshev tail, N from the
+    exact Taylor tail, both in FP64 so neither is limited by storage
+    rounding.  Reports K, N and the device time of each query."""
+    tol, nsrc = args.kvn_tol, 2
+    G = cp.Graph(g.row_ptr, g.col_idx, reorder=args.layout == "degree", stripes=args.layout == "stripes")
+    srcs = [int(s) for s in synth.sources(g, nsrc, seed=11)]
+    y = torch.empty(g.n, dtype=torch.float64, device="cuda")
+    G.power("ppr", 0.2, srcs[0], tol=tol, prec="f64", y=y)  # warm-up
+    G.power("ppr", 0.2, srcs[0], tol=tol, prec="f64", y=y, method="power")
+    rows = []
+    for kind, param in KVN_CASES:
+        row = {"kind": kind, "param": param, "tol": tol}
+        for method in ("cheby", "power"):
+            ms, steps, K, bound = [], 0, [], []
+            for s in srcs:
+                r = G.power(kind, param, s, tol=tol, prec="f64", y=y, method=method, flags=cp.CP_Q_TIMING)
+                ms.append(r.info["elapsed_ms"])
+                K.append(r.info["K"])
+                bound.append(r.info["tail_bound_l1"])
+            key = "K" if method == "cheby" else "N"
+            row[key] = K
+            row[f"ms_{method}"] = round(float(np.mean(ms)), 3)
+            row[f"l1_bound_{method}"] = max(bound)
+        row["N_over_K"] = round(float(np.mean(row["N"]) / np.mean(row["K"])), 2)
+        row["speedup"] = round(row["ms_power"] / row["ms_cheby"], 2)
+        rows.append(row)
+        log(f"[kvn] {row}")
+    out = {"workload": f"{nsrc} sources, tol {tol} l1, FP64, on the main line's graph ({args.layout} layout): "
+                       f"ChebyPower with the certified K vs PwMethod with the exact-tail N",
+           "rows": rows}
+    if not args.no_cpu:
+        from oracle import coefficients as C
+        from oracle import errors as E
+        from oracle import native as NO
+        from oracle import truncation as T
+
+        kind, param, s = "ppr", 0.2, srcs[0]
+        Nref = T.pwmethod_steps(kind, param, 1e-15)
+        t0 = time.perf_counter()
+        ref = NO.power_method(g.row_ptr, g.col_idx, s, C.taylor_coeffs(kind, param, Nref), Nref)
+        ref_s = time.perf_counter() - t0
+        acc = {"source": s, "kind": kind, "param": param,
+               "reference": f"plain-C FP64 PwMethod with tail 1e-15 (N={Nref}, {ref_s:.1f} s)"}
+        for method in ("cheby", "power"):
+            r = G.power(kind, param, s, tol=tol, prec="f64", y=y, method=method)
+            v = y.cpu().numpy()
+            acc[method] = {"K": r.info["K"], "l1": E.l1(v, ref), "l1_bound": r.info["tail_bound_l1"]}
+        out["accuracy_vs_fp64_oracle"] = acc
+        log(f"[kvn] accuracy {acc}")
+    G.close()
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -429,6 +498,8 @@ def main() -> int:
                     help="graph layout inside the library for single-source queries: XCD column stripes "
                          "(CP_GRAPH_XCD_STRIPES), degree order (CP_GRAPH_REORDER) or the caller's ids; "
                          "results are always in caller ids")
+    ap.add_argument("--kvn-tol", type=float, default=1e-6,
+                    help="l1 tolerance of the ChebyPower-vs-PwMethod comparison (0: skip it)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle legs")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run a plain 1 GiB device copy first (counter scaling for rocprofv3 --pmc)")
@@ -521,8 +592,22 @@ def main() -> int:
         }
         result["accuracy_vs_fp64_oracle"] = {"source": s, "K": K, "l1": E.l1(y_gpu, y_ref),
                                              "max_abs": E.max_abs(y_gpu, y_ref)}
+        # the same sample on every host thread: the plain-C oracle (OpenMP node loop)
+        from oracle import native as NO
+
+        c0 = time.perf_counter()
+        y_c = NO.cheby_power(g.row_ptr, g.col_idx, s, c, K)
+        cpu_s = time.perf_counter() - c0
+        result["cpu_baseline_threads"] = {
+            "value": round(cpu_arcs / cpu_s / 1e9, 4), "unit": "GTEPS", "cores": NO.threads(), "kind": "oracle",
+            "sample": f"the same source and K: plain-C FP64 Alg. 3, {cpu_s:.2f} s",
+            "agrees_with_scipy_oracle_l1": E.l1(y_c, y_ref),
+            "host": {"nproc": os.cpu_count(), "cpu_model": cpu_model()},
+        }
     g_main = S["g"]
     del S
+    if args.kvn_tol > 0:
+        result["cheby_vs_power"] = run_kvn(args, torch, cp, synth, g_main)
     if args.serve_seconds > 0:
         result["served"] = run_serve(args, torch, cp, synth, g_main)
     del g_main
