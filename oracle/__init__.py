@@ -21,10 +21,13 @@ Modules
   propagation   P = A D^{-1}; ChebyPower (Algorithm 3); PwMethod
                 (Algorithm 1); Chebyshev vectors T_k(P) e_s (Eq. 6)
   dense         dense definitions for tiny graphs: inverse (Def. 3),
-                matrix exponential (Def. 4), eigen route (Lemma 1 proof)
+                matrix exponential (Def. 4), eigen route (Lemma 1 proof),
+                f(D^{-a} A D^{-b}) X (Def. 8)
   errors        error measures (Def. 5) and the PPR residual certificate
+  generalized   Z = f(D^{-a} A D^{-b}) X (Def. 8) through Thm. 5: the series
+                of Alg. 3 / Alg. 1 on D^{a} X, scaled by D^{-a}
   native        the same Alg. 3 / Alg. 1 in plain C with an OpenMP node
                 loop (oracle/c/chebypower.c), for graphs with billions of arcs
 """
 
-from . import coefficients, dense, errors, propagation, truncation  # noqa: F401
+from . import coefficients, dense, errors, generalized, propagation, truncation  # noqa: F401

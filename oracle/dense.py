@@ -71,3 +71,17 @@ def chebyshev_matrix_eigen(A: np.ndarray, k: int) -> np.ndarray:
     lam, U, dh = _sym_eig(A)
     Tk = np.cos(k * np.arccos(lam))
     return (dh[:, None] * (U * Tk[None, :]) @ U.T) / dh[None, :]
+
+
+def generalized_definition(A: np.ndarray, X: np.ndarray, a: float, kind: str, param: float) -> np.ndarray:
+    """Def. 8 written out: M = D^{-a} A D^{-(1-a)}, then f(M) X with f from
+    Def. 3 (alpha (I - (1 - alpha) M)^{-1}) or Def. 4 (e^{-t (I - M)})."""
+    n = A.shape[0]
+    d = A.sum(axis=0)
+    if np.any(d == 0):
+        raise ValueError("dense routes need a graph without isolated nodes")
+    M = (d ** (-a))[:, None] * A * (d ** (a - 1.0))[None, :]
+    X = np.asarray(X, dtype=np.float64)
+    if kind == "ppr":
+        return param * np.linalg.solve(np.eye(n) - (1.0 - param) * M, X)
+    return sla.expm(-param * (np.eye(n) - M)) @ X

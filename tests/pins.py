@@ -20,6 +20,7 @@ from conftest import load_golden
 from oracle import coefficients as C
 from oracle import dense as D
 from oracle import errors as E
+from oracle import generalized as GG
 from oracle import propagation as PR
 from oracle import truncation as T
 
@@ -272,6 +273,72 @@ def pin_convergence_rate():
         assert abs(slope - math.log(beta)) < 0.05 * abs(math.log(beta)), (alpha, slope, math.log(beta))
 
 
+# ---------------------------------------------------------------- Def. 8 / Thm. 5
+
+
+def _features(n, k, seed):
+    return (synth.uniform01(seed, n * k) - 0.5).reshape(n, k)
+
+
+def pin_generalized_definition():
+    """Z = f(D^{-a} A D^{-b}) X, b = 1 - a, formed densely from Def. 8, against
+    Thm. 5's route (the series of Alg. 3 and of Alg. 1 on D^{a} X, then
+    D^{-a}) for several a, on graphs without degree-0 nodes."""
+    for g in tiny_graphs()[:4]:
+        A = D.adjacency(g.row_ptr, g.col_idx)
+        X = _features(g.n, 3, seed=g.n)
+        for kind, p, K in [("ppr", 0.2, 60), ("hkpr", 3.0, 40)]:
+            N = T.pwmethod_steps(kind, p, 1e-15)
+            for a in (0.0, 0.3, 0.5, 1.0):
+                ref = D.generalized_definition(A, X, a, kind, p)
+                Zc = GG.generalized_gp(g.row_ptr, g.col_idx, X, a, kind, p, K, method="cheby")
+                Zp = GG.generalized_gp(g.row_ptr, g.col_idx, X, a, kind, p, N, method="power")
+                assert np.max(np.abs(Zc - ref)) < 1e-11, (g.name, kind, a, np.max(np.abs(Zc - ref)))
+                assert np.max(np.abs(Zp - ref)) < 1e-11, (g.name, kind, a, np.max(np.abs(Zp - ref)))
+
+
+def pin_generalized_symmetric_half():
+    """a = 1/2: f(D^{-1/2} A D^{-1/2}) is a symmetric matrix, so Z for X = I
+    is symmetric (and not for a = 0 on an irregular graph)."""
+    g = synth.barbell_with_tail(5, 4)
+    X = np.eye(g.n)
+    Z = GG.generalized_gp(g.row_ptr, g.col_idx, X, 0.5, "ppr", 0.15, 80)
+    assert np.max(np.abs(Z - Z.T)) < 1e-12
+    Z0 = GG.generalized_gp(g.row_ptr, g.col_idx, X, 0.0, "ppr", 0.15, 80)
+    assert np.max(np.abs(Z0 - Z0.T)) > 1e-3
+
+
+def pin_generalized_single_source():
+    """X = e_s: Thm. 5 reduces to the single-source form d_s^{a} D^{-a} f(P) e_s,
+    and for a = 0 to Alg. 3 itself."""
+    g = synth.erdos_renyi(40, 0.15, seed=3)
+    P = PR.transition_matrix(g.row_ptr, g.col_idx)
+    s = _connected_node(g, 5)
+    for kind, p, K in [("ppr", 0.1, 30), ("hkpr", 5.0, 25)]:
+        y = PR.cheby_power(P, s, C.chebyshev_coeffs(kind, p, K), K)
+        for a in (0.0, 0.5, 0.8):
+            Z = GG.generalized_gp(g.row_ptr, g.col_idx, PR.one_hot(g.n, s), a, kind, p, K)[:, 0]
+            np.testing.assert_allclose(Z, GG.single_source_generalized(g.row_ptr, g.col_idx, s, a, y),
+                                       rtol=1e-12, atol=1e-15)
+            if a == 0.0:
+                np.testing.assert_allclose(Z, y, rtol=0, atol=0)
+
+
+def pin_generalized_degree_zero_reading():
+    """Degree-0 nodes (reading: outside the propagation) get Z = 0, and the
+    other rows equal Def. 8 on the graph without them."""
+    core = synth.erdos_renyi(30, 0.2, seed=4)
+    assert np.all(core.degrees > 0)
+    n = core.n + 2
+    rows = np.repeat(np.arange(core.n), core.degrees)
+    g = synth.from_edges(n, [(int(u), int(v)) for u, v in zip(rows, core.col_idx) if u < v], name="core+2")
+    X = _features(n, 2, seed=9)
+    Z = GG.generalized_gp(g.row_ptr, g.col_idx, X, 0.5, "hkpr", 2.0, 40)
+    assert np.all(Z[core.n:] == 0.0)
+    ref = D.generalized_definition(D.adjacency(core.row_ptr, core.col_idx), X[: core.n], 0.5, "hkpr", 2.0)
+    assert np.max(np.abs(Z[: core.n] - ref)) < 1e-11
+
+
 ALL_PINS = [
     pin_star_example,
     pin_chebyshev_vectors_eigen,
@@ -289,6 +356,10 @@ ALL_PINS = [
     pin_pwmethod_exact_tail,
     pin_certified_bound_and_certificate,
     pin_convergence_rate,
+    pin_generalized_definition,
+    pin_generalized_symmetric_half,
+    pin_generalized_single_source,
+    pin_generalized_degree_zero_reading,
 ]
 
 

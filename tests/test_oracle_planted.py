@@ -56,6 +56,16 @@ def _power_method_extra_step(P, s, zeta, N):
     return PR.__dict__["_orig_power_method"](P, s, np.r_[zeta, 0.0][: N + 1] if len(zeta) > N else np.r_[zeta, zeta[-1:]], N + 1)
 
 
+def _powers_swapped(degrees, a):
+    da, dma = PR.__dict__["_orig_degree_powers"](degrees, a)
+    return dma, da
+
+
+def _start_not_rescaled(degrees, a):
+    _, dma = PR.__dict__["_orig_degree_powers"](degrees, a)
+    return np.where(np.asarray(degrees) > 0, 1.0, 0.0), dma
+
+
 MISTAKES = {
     "recurrence sign": ("propagation", "_chebyshev_step", _wrong_sign_step),
     "recurrence factor 2": ("propagation", "_chebyshev_step", _missing_factor_two_step),
@@ -66,6 +76,8 @@ MISTAKES = {
     "last term c_K r_K dropped": ("propagation", "cheby_power", _cheby_power_drop_last),
     "coefficient/term off by one": ("propagation", "cheby_power", _cheby_power_off_by_one),
     "PwMethod extra term": ("propagation", "power_method", _power_method_extra_step),
+    "Thm. 5 scalings swapped": ("generalized", "degree_powers", _powers_swapped),
+    "Thm. 5 start vector not rescaled": ("generalized", "degree_powers", _start_not_rescaled),
 }
 
 
