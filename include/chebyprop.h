@@ -114,6 +114,10 @@ typedef struct {
   int64_t source;  /* s, in the caller's node ids */
   int32_t K_fixed; /* K for CP_K_FIXED */
   int32_t flags;   /* CP_Q_* (any other bit: CP_EINVAL) */
+  double a;        /* output space, 0 <= a <= 1 (Def. 8 with b = 1 - a): the
+                      result is z = f(D^{-a} A D^{-b}) e_s = d_s^a D^{-a} f(P) e_s
+                      (the single-source form of Thm. 5).  0 gives y = f(P) e_s,
+                      1/2 gives f(A~) e_s for A~ = D^{-1/2} A D^{-1/2}. */
 } cp_query;
 
 typedef struct {
@@ -200,6 +204,28 @@ cp_status cp_power(const cp_graph* g, const cp_query* q, int32_t prec, void* y, 
  * Errors as cp_power; no output is written if any query is invalid. */
 cp_status cp_power_batch(const cp_graph* g, int32_t nq, const cp_query* q, int32_t prec, void* Y,
                          void* ws, size_t ws_bytes, void* stream, cp_info* infos);
+
+/* Generalized graph propagation of a feature matrix (Def. 8, Thm. 5):
+ * Z = f(D^{-a} A D^{-b}) X with b = 1 - a, computed as Z = D^{-a} y^ where y^
+ * is the K-term series of Alg. 3 (or N terms of Alg. 1 with CP_Q_PWMETHOD)
+ * started from D^{a} x_j, for the k columns of X together (batched steps,
+ * k columns in source tiles).
+ *   q     kind, param, a, K_fixed, flags (CP_Q_PWMETHOD, CP_Q_TIMING) and
+ *         the truncation rule: CP_K_FIXED, CP_K_TAIL (tail(K) <= tol) or
+ *         CP_K_PAPER; CP_K_CERTIFIED needs norms of X and gives CP_EINVAL;
+ *         source is ignored
+ *   X, Z  device [n][k] row-major in caller ids, double for CP_F64 and float
+ *         otherwise; Z may be X (X is read once, before Z is written)
+ *   ws    device workspace of cp_workspace_bytes(g, k, prec) bytes (256-byte
+ *         aligned); the source-tile width follows cp_set_batch_width /
+ *         cp_autotune_batch for nq = k
+ *   info  host, may be NULL: K (or N), steps (full step launches, K), tail;
+ *         tail_bound_l1 is NaN (it depends on X)
+ * Reading: a node of degree 0 is outside the propagation; its row of X is
+ * ignored and its row of Z is 0.  Errors: CP_EINVAL, CP_EKMAX (K > 1024),
+ * CP_EWORKSPACE, CP_EHIP. */
+cp_status cp_propagate(const cp_graph* g, const cp_query* q, int32_t k, int32_t prec, const void* X, void* Z,
+                       void* ws, size_t ws_bytes, void* stream, cp_info* info);
 
 /* Pick the source-tile width (8, 16, 32 or 64 sources per tile) that runs
  * these nq queries fastest on this graph and remember it for later

@@ -49,7 +49,7 @@ METHODS = {"cheby": 0, "power": CP_Q_PWMETHOD}  # Alg. 3 (ChebyPower) or Alg. 1 
 EXPORTED = [
     "cp_graph_create", "cp_graph_destroy", "cp_graph_get_stats", "cp_coeffs", "cp_choose_K",
     "cp_taylor", "cp_choose_N",
-    "cp_workspace_bytes", "cp_power", "cp_power_batch", "cp_autotune_batch", "cp_set_batch_width",
+    "cp_workspace_bytes", "cp_power", "cp_power_batch", "cp_propagate", "cp_autotune_batch", "cp_set_batch_width",
     "cp_status_str", "cp_last_hip_error", "cp_version",
     "cp_server_create", "cp_server_submit", "cp_server_poll", "cp_server_wait", "cp_server_cancel",
     "cp_server_get_stats", "cp_server_destroy",
@@ -65,6 +65,7 @@ class cp_query(ctypes.Structure):
         ("source", ctypes.c_int64),
         ("K_fixed", ctypes.c_int32),
         ("flags", ctypes.c_int32),
+        ("a", ctypes.c_double),
     ]
 
 
@@ -158,6 +159,7 @@ def load() -> ctypes.CDLL:
         "cp_workspace_bytes": (sz, [P, i32, i32]),
         "cp_power": (i32, [P, ctypes.POINTER(cp_query), i32, P, P, sz, P, ctypes.POINTER(cp_info)]),
         "cp_power_batch": (i32, [P, i32, ctypes.POINTER(cp_query), i32, P, P, sz, P, ctypes.POINTER(cp_info)]),
+        "cp_propagate": (i32, [P, ctypes.POINTER(cp_query), i32, i32, P, P, P, sz, P, ctypes.POINTER(cp_info)]),
         "cp_autotune_batch": (i32, [P, i32, ctypes.POINTER(cp_query), i32, P, P, sz, P, ctypes.POINTER(i32)]),
         "cp_set_batch_width": (i32, [P, i32, i32, i32]),
         "cp_server_create": (i32, [P, sz, i32, i32, i32, ctypes.POINTER(P)]),
@@ -268,6 +270,14 @@ def cp_power_batch(handle: int, queries, prec: int, Y_ptr: int, ws_ptr: int, ws_
     return list(infos)
 
 
+def cp_propagate(handle: int, query: cp_query, k: int, prec: int, X_ptr: int, Z_ptr: int, ws_ptr: int,
+                 ws_bytes: int, stream: int) -> cp_info:
+    info = cp_info()
+    _check(load().cp_propagate(handle, ctypes.byref(query), k, prec, X_ptr, Z_ptr, ws_ptr, ws_bytes, stream,
+                               ctypes.byref(info)), "cp_propagate")
+    return info
+
+
 def cp_autotune_batch(handle: int, queries, prec: int, Y_ptr: int, ws_ptr: int, ws_bytes: int,
                       stream: int) -> int:
     nq = len(queries)
@@ -283,9 +293,9 @@ def cp_set_batch_width(handle: int, nq: int, prec: int, bw: int) -> None:
 
 
 def make_query(kind: str, param: float, source: int, tol: float = 1e-6, kmode: str = "certified",
-               K: int = 0, flags: int = 0, method: str = "cheby") -> cp_query:
+               K: int = 0, flags: int = 0, method: str = "cheby", a: float = 0.0) -> cp_query:
     return cp_query(KINDS[kind], KMODES[kmode], float(param), float(tol), int(source), int(K),
-                    int(flags) | METHODS[method])
+                    int(flags) | METHODS[method], float(a))
 
 
 # ---------------------------------------------------------------- torch wrapper
@@ -344,14 +354,14 @@ class Graph:
 
     def power(self, kind: str, param: float, source: int, tol: float = 1e-6, prec: str = "f32",
               kmode: str = "certified", K: int = 0, flags: int = 0, y=None, stream=None,
-              method: str = "cheby") -> Result:
+              method: str = "cheby", a: float = 0.0) -> Result:
         torch = self.torch
         p = PRECS[prec]
         if y is None:
             y = torch.empty(self.n, dtype=self.out_dtype(p), device=self.device)
         ws, nbytes = self.workspace(1, p)
         st = stream if stream is not None else torch.cuda.current_stream(self.device).cuda_stream
-        q = make_query(kind, param, source, tol, kmode, K, flags, method)
+        q = make_query(kind, param, source, tol, kmode, K, flags, method, a)
         info = cp_power(self.handle, q, p, y.data_ptr(), ws.data_ptr(), nbytes, st)
         return Result(y, info.as_dict())
 
@@ -377,6 +387,23 @@ class Graph:
         st = stream if stream is not None else torch.cuda.current_stream(self.device).cuda_stream
         infos = cp_power_batch(self.handle, queries, p, Y.data_ptr(), ws.data_ptr(), nbytes, st)
         return Y, [i.as_dict() for i in infos]
+
+    def propagate(self, X, kind: str, param: float, a: float = 0.0, tol: float = 1e-6, kmode: str = "tail",
+                  K: int = 0, prec: str = "f32", method: str = "cheby", flags: int = 0, Z=None, stream=None):
+        """Z = f(D^{-a} A D^{-b}) X (b = 1 - a) for a device matrix X [n][k]
+        (float64 for f64, float32 otherwise; caller ids)."""
+        torch = self.torch
+        p = PRECS[prec]
+        if X.dim() != 2 or X.shape[0] != self.n or X.dtype != self.out_dtype(p) or not X.is_contiguous():
+            raise ValueError("X must be a contiguous [n, k] tensor of the precision's output type")
+        k = int(X.shape[1])
+        if Z is None:
+            Z = torch.empty_like(X)
+        ws, nbytes = self.workspace(k, p)
+        st = stream if stream is not None else torch.cuda.current_stream(self.device).cuda_stream
+        q = make_query(kind, param, 0, tol, kmode, K, flags, method, a)
+        info = cp_propagate(self.handle, q, k, p, X.data_ptr(), Z.data_ptr(), ws.data_ptr(), nbytes, st)
+        return Z, info.as_dict()
 
 
 # ---------------------------------------------------------------- server

@@ -253,10 +253,13 @@ cp_status plan_query(const cp_graph* g, const cp_query* q, int32_t K_max, QueryP
   if (!q || !p) return CP_EINVAL;
   if (q->kind != CP_PPR && q->kind != CP_HKPR) return CP_EINVAL;
   if (q->flags & ~(CP_Q_STATS | CP_Q_TIMING | CP_Q_PWMETHOD)) return CP_EINVAL;
+  if (!(q->a >= 0.0 && q->a <= 1.0)) return CP_EINVAL;
   if (q->source < 0 || q->source >= g->n) return CP_ESOURCE;
   const int32_t ds = g->degree[q->source];
   if (ds == 0) return CP_EISOLATED;
   p->s_int = g->reordered ? g->ext2int[q->source] : q->source;
+  p->oexp = 1.0 - q->a;
+  p->oscale = q->a == 0.0 ? 1.0 : std::pow((double)ds, q->a);
   cp_status rc;
   if (q->flags & CP_Q_PWMETHOD) {
     // N terms zeta_0..zeta_{N-1}; the highest index N - 1 must fit K_max
@@ -276,6 +279,14 @@ cp_status plan_query(const cp_graph* g, const cp_query* q, int32_t K_max, QueryP
   p->rec = 2.0;
   p->c.assign((size_t)p->K + 1, 0.0);
   return coeffs_impl(q->kind, q->param, p->K, p->c.data());
+}
+
+// Host image of the slot parameters (see kSlotParams): step factor 2,
+// output exponent 1, output scale 1, ones.
+std::vector<double> slot_params(int32_t nslots) {
+  std::vector<double> sp((size_t)kSlotParams * nslots, 1.0);
+  std::fill(sp.begin(), sp.begin() + nslots, 2.0);
+  return sp;
 }
 
 namespace {
@@ -303,7 +314,7 @@ BatchLayout batch_layout(const cp_graph* g, int32_t nq, int32_t prec, int32_t bw
   L.hub_partial = off; off += align256((size_t)std::max<int64_t>(g->batch.hub_segments, 1) * L.nq_pad * 8);
   L.coef = off; off += align256((size_t)(kBatchKCap + 1) * L.nq_pad * 8);
   L.src = off; off += align256((size_t)L.nq_pad * 8);
-  L.rec = off; off += align256((size_t)L.nq_pad * 8);
+  L.rec = off; off += align256((size_t)kSlotParams * L.nq_pad * 8);
   L.slotmap = off; off += align256((size_t)nq * 4);
   L.total = off;
   return L;
@@ -710,7 +721,7 @@ cp_status cp_power(const cp_graph* g, const cp_query* q, int32_t prec, void* y, 
     if (timing) CP_HIP_C(hipEventRecord(ev[2 * k + 1], st));
   }
   double* mass = stats ? reinterpret_cast<double*>(w + W.mass) : nullptr;
-  FinalArgs fa{g->row_ptr, g->perm, g->n, yacc, y, mass};
+  FinalArgs fa{g->row_ptr, g->perm, g->n, yacc, y, mass, qp.oexp, qp.oscale};
   CP_HIP_C(launch_finalize(prec, fa, st));
   if (timing) CP_HIP_C(hipEventRecord(ev[1], st));
 
@@ -772,12 +783,14 @@ cp_status power_batch_bw(cp_graph* g, int32_t nq, const cp_query* q, int32_t pre
   const int32_t Kmax = P[order[0]].top;
   std::vector<double> coef((size_t)(Kmax + 1) * W.nq_pad, 0.0);
   std::vector<int64_t> src(W.nq_pad, -1);
-  std::vector<double> rec(W.nq_pad, 2.0);
+  std::vector<double> sp = slot_params(W.nq_pad);
   for (int32_t i = 0; i < nq; ++i) {
     const QueryPlan& p = P[order[i]];
     for (int32_t k = 0; k <= p.top; ++k) coef[(size_t)k * W.nq_pad + i] = p.c[k];
     src[i] = p.s_int;
-    rec[i] = p.rec;
+    sp[i] = p.rec;
+    sp[(size_t)W.nq_pad + i] = p.oexp;
+    sp[2 * (size_t)W.nq_pad + i] = p.oscale;
   }
   std::vector<int32_t> tileK(W.ntiles);
   for (int32_t t = 0; t < W.ntiles; ++t) tileK[t] = P[order[t * bw]].top;
@@ -806,7 +819,7 @@ cp_status power_batch_bw(cp_graph* g, int32_t nq, const cp_query* q, int32_t pre
   CP_HIP_B(launch_upload(dcoef, coef.data(), coef.size() * sizeof(double), st));
   CP_HIP_B(launch_upload(w + W.src, src.data(), src.size() * sizeof(int64_t), st));
   CP_HIP_B(launch_upload(w + W.slotmap, slot_of_query.data(), slot_of_query.size() * sizeof(int32_t), st));
-  CP_HIP_B(launch_upload(w + W.rec, rec.data(), rec.size() * sizeof(double), st));
+  CP_HIP_B(launch_upload(w + W.rec, sp.data(), sp.size() * sizeof(double), st));
   void* rA = w + W.rA;
   void* rB = w + W.rB;
   BatchInitArgs ia{g->row_ptr, g->col_idx, reinterpret_cast<const int64_t*>(w + W.src), g->n, bw,
@@ -839,8 +852,9 @@ cp_status power_batch_bw(cp_graph* g, int32_t nq, const cp_query* q, int32_t pre
     CP_HIP_B(launch_batch_step(prec, sa, st));
   }
   if (timing) CP_HIP_B(hipEventRecord(ev[2], st));
+  const double* dsp = reinterpret_cast<const double*>(w + W.rec);
   BatchFinalArgs fa{g->row_ptr, g->perm, reinterpret_cast<const int32_t*>(w + W.slotmap), g->n, bw, nq,
-                    w + W.yacc, Y};
+                    w + W.yacc, Y, dsp + W.nq_pad, dsp + 2 * (size_t)W.nq_pad};
   CP_HIP_B(launch_batch_finalize(prec, fa, st));
   if (timing) CP_HIP_B(hipEventRecord(ev[3], st));
   float ms_all = NAN, ms_steps = NAN;
@@ -878,6 +892,136 @@ cp_status cp_power_batch(const cp_graph* g, int32_t nq, const cp_query* q, int32
   const int32_t bw = choose_bw(gm, nq, prec);
   if (ws_bytes < batch_ws_bytes(g, nq, prec)) return CP_EWORKSPACE;
   return power_batch_bw(gm, nq, q, prec, Y, ws, ws_bytes, static_cast<hipStream_t>(stream), infos, bw);
+}
+
+cp_status cp_propagate(const cp_graph* g, const cp_query* q, int32_t k, int32_t prec, const void* X, void* Z,
+                       void* ws, size_t ws_bytes, void* stream, cp_info* info) {
+  if (!g || !q || k < 1 || !X || !Z || !valid_prec(prec)) return CP_EINVAL;
+  if (q->kind != CP_PPR && q->kind != CP_HKPR) return CP_EINVAL;
+  if (q->flags & ~(CP_Q_TIMING | CP_Q_PWMETHOD)) return CP_EINVAL;
+  if (!(q->a >= 0.0 && q->a <= 1.0)) return CP_EINVAL;
+  if (q->kmode == CP_K_CERTIFIED) return CP_EINVAL;  // the certified rule needs norms of X
+  const bool power = q->flags & CP_Q_PWMETHOD;
+  int32_t K = 0, top = 0;
+  double tail = 0;
+  std::vector<double> c;
+  cp_status rc;
+  if (power) {
+    rc = choose_N_impl(q->kind, q->param, q->tol, q->kmode, q->K_fixed, kBatchKCap + 1, &K, &tail);
+    if (rc != CP_OK) return rc;
+    top = std::max(K - 1, 1);
+    c.assign((size_t)top + 1, 0.0);
+    rc = taylor_impl(q->kind, q->param, K, c.data());
+  } else {
+    rc = choose_K_impl(q->kind, q->param, q->tol, q->kmode, q->K_fixed, (double)g->nnz, 1.0, kBatchKCap, &K,
+                       &tail);
+    if (rc != CP_OK) return rc;
+    top = K;
+    c.assign((size_t)K + 1, 0.0);
+    rc = coeffs_impl(q->kind, q->param, K, c.data());
+  }
+  if (rc != CP_OK) return rc;
+  cp_graph* gm = const_cast<cp_graph*>(g);  // only the tuning cache is mutable
+  const int32_t bw = choose_bw(gm, k, prec);
+  if (!ws || ws_bytes < batch_ws_bytes(g, k, prec) || (reinterpret_cast<uintptr_t>(ws) & 255))
+    return CP_EWORKSPACE;
+  const BatchLayout W = batch_layout(g, k, prec, bw);
+  const size_t np = (size_t)W.nq_pad;
+  std::vector<double> coef((size_t)(top + 1) * np, 0.0);
+  for (int32_t kk = 0; kk <= top; ++kk)
+    for (int32_t j = 0; j < k; ++j) coef[kk * np + j] = c[kk];
+  std::vector<double> sp = slot_params(W.nq_pad);
+  for (int32_t j = 0; j < k; ++j) {
+    sp[j] = power ? 1.0 : 2.0;
+    sp[np + j] = 1.0 - q->a;
+  }
+  std::vector<int32_t> slotmap(k);
+  std::iota(slotmap.begin(), slotmap.end(), 0);
+
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  char* w = static_cast<char*>(ws);
+  double* dcoef = reinterpret_cast<double*>(w + W.coef);
+  const double* dsp = reinterpret_cast<const double*>(w + W.rec);
+  const bool timing = q->flags & CP_Q_TIMING;
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  auto cleanup = [&] {
+    for (hipEvent_t e : ev)
+      if (e) (void)hipEventDestroy(e);
+  };
+#define CP_HIP_P(call)        \
+  do {                        \
+    hipError_t e_ = (call);   \
+    if (e_ != hipSuccess) {   \
+      set_hip_error(e_);      \
+      cleanup();              \
+      return CP_EHIP;         \
+    }                         \
+  } while (0)
+  if (timing)
+    for (auto& e : ev) CP_HIP_P(hipEventCreate(&e));
+  if (timing) CP_HIP_P(hipEventRecord(ev[0], st));
+  CP_HIP_P(launch_zero(w, W.hub_partial, st));
+  CP_HIP_P(launch_upload(dcoef, coef.data(), coef.size() * sizeof(double), st));
+  CP_HIP_P(launch_upload(w + W.slotmap, slotmap.data(), slotmap.size() * sizeof(int32_t), st));
+  CP_HIP_P(launch_upload(w + W.rec, sp.data(), sp.size() * sizeof(double), st));
+  void* rA = w + W.rA;
+  void* rB = w + W.rB;
+  DenseInitArgs ia{g->row_ptr, g->perm, g->n, bw, k, X, q->a, c[0], rA, w + W.yacc};
+  CP_HIP_P(launch_dense_init(prec, ia, st));
+  BatchStepArgs sa{};
+  sa.row_ptr = g->row_ptr;
+  sa.col_idx = g->col_idx;
+  sa.blocks = g->batch.blocks;
+  sa.hubs = g->batch.hubs;
+  sa.nblocks = g->batch.nblocks;
+  sa.nspecial = g->batch.nspecial;
+  sa.n = g->n;
+  sa.bw = bw;
+  sa.nq_pad = W.nq_pad;
+  sa.ntiles = W.ntiles;
+  sa.yacc = w + W.yacc;
+  sa.hub_partial = w + W.hub_partial;
+  sa.hub_count = reinterpret_cast<int32_t*>(w + W.hub_count);
+  sa.ntiles_total = W.ntiles;
+  if (timing) CP_HIP_P(hipEventRecord(ev[1], st));
+  // r~_1 = D^{-1} P r_0: a power step from r~_0 into the zeroed second buffer
+  sa.x = rA;
+  sa.z = rB;
+  sa.coef_row = dcoef + np;
+  sa.rec = dsp + 3 * np;
+  CP_HIP_P(launch_batch_step(prec, sa, st));
+  sa.rec = dsp;
+  for (int32_t kk = 1; kk < top; ++kk) {
+    sa.x = (kk & 1) ? rB : rA;
+    sa.z = (kk & 1) ? rA : rB;
+    sa.coef_row = dcoef + (size_t)(kk + 1) * np;
+    CP_HIP_P(launch_batch_step(prec, sa, st));
+  }
+  if (timing) CP_HIP_P(hipEventRecord(ev[2], st));
+  BatchFinalArgs fa{g->row_ptr, g->perm, reinterpret_cast<const int32_t*>(w + W.slotmap), g->n, bw, k,
+                    w + W.yacc, Z, dsp + np, dsp + 2 * np};
+  CP_HIP_P(launch_batch_finalize(prec, fa, st));
+  if (timing) CP_HIP_P(hipEventRecord(ev[3], st));
+  float ms_all = NAN, ms_steps = NAN;
+  if (timing) {
+    CP_HIP_P(hipStreamSynchronize(st));
+    CP_HIP_P(hipEventElapsedTime(&ms_all, ev[0], ev[3]));
+    CP_HIP_P(hipEventElapsedTime(&ms_steps, ev[1], ev[2]));
+  }
+  if (info) {
+    info->K = K;
+    info->steps = top;
+    info->tail = tail;
+    info->tail_bound_l1 = NAN;
+    info->mass = NAN;
+    info->elapsed_ms = ms_all;
+    info->step_ms = ms_steps;
+    info->latency_ms = NAN;
+    info->wait_ms = NAN;
+  }
+  cleanup();
+#undef CP_HIP_P
+  return CP_OK;
 }
 
 cp_status cp_set_batch_width(cp_graph* g, int32_t nq, int32_t prec, int32_t bw) {

@@ -160,7 +160,9 @@ struct InitArgs {
 };
 hipError_t launch_init(int32_t prec, const InitArgs& a, hipStream_t st);
 
-// y_out[perm(v)] = d_v * yacc[v]; optional double sum of y into *mass.
+// y_out[perm(v)] = oscale * d_v^oexp * yacc[v] (d_v yacc[v] is y = f(P) e_s;
+// oexp = 1 - a, oscale = d_s^a give the generalized output of Def. 8);
+// optional double sum of the output into *mass.
 struct FinalArgs {
   const int64_t* row_ptr;
   const int32_t* perm;  // internal -> caller id, or null
@@ -168,6 +170,7 @@ struct FinalArgs {
   const void* yacc;
   void* y_out;
   double* mass;         // device, or null
+  double oexp, oscale;
 };
 hipError_t launch_finalize(int32_t prec, const FinalArgs& a, hipStream_t st);
 
@@ -195,6 +198,7 @@ struct BatchStepArgs {
   void* yacc;
   const double* coef_row;  // coef + (k+1)*nq_pad
   const double* rec;     // [nq_pad] per slot: 2 (Chebyshev step, Eq. 6) or 1 (power step, Alg. 1)
+                         // (row 0 of the slot parameters, see kSlotParams)
   void* hub_partial;     // A[hub_segments][nq_pad]
   int32_t* hub_count;    // int32[nhubs][ntiles_total]
   int32_t ntiles_total;
@@ -224,7 +228,32 @@ struct BatchFinalArgs {
   int32_t nq;
   const void* yacc;
   void* Y;               // [n][nq] caller ids
+  const double* oexp;    // [slots] output exponent 1 - a
+  const double* oscale;  // [slots] output scale (d_s^a, or 1)
 };
+
+// Per-slot parameters of batched and served queries, [kSlotParams][slots]
+// doubles: step factor (2 or 1), output exponent 1 - a, output scale, and a
+// row of ones (the step factor of the first step of a dense start).
+constexpr int kSlotParams = 4;
+std::vector<double> slot_params(int32_t nslots);  // host image with the defaults
+
+// Dense start vectors (Thm. 5): column j of the caller's X [n][k] (caller
+// ids) becomes slot j with r~_0(v) = d_v^{a-1} X[perm(v)][j] (0 where d_v = 0)
+// and yacc = c0 r~_0.
+struct DenseInitArgs {
+  const int64_t* row_ptr;
+  const int32_t* perm;   // internal -> caller id, or null
+  int64_t n;
+  int32_t bw;
+  int32_t k;
+  const void* X;         // double for CP_F64, float otherwise
+  double a;
+  double c0;
+  void* r0;
+  void* yacc;
+};
+hipError_t launch_dense_init(int32_t prec, const DenseInitArgs& a, hipStream_t st);
 hipError_t launch_batch_finalize(int32_t prec, const BatchFinalArgs& a, hipStream_t st);
 
 // Server: for finished (or cancelled) slots, write y = D yacc of the slot
@@ -240,6 +269,8 @@ struct SlotFinishArgs {
   void* rA;
   void* rB;
   void* yacc;
+  const double* oexp;    // [slots]
+  const double* oscale;  // [slots]
 };
 hipError_t launch_slot_finish(int32_t prec, const SlotFinishArgs& a, int32_t count, hipStream_t st);
 
@@ -269,6 +300,8 @@ struct QueryPlan {
   int32_t top = 0;    // highest coefficient index
   double tail = 0, L = 1;
   double rec = 2.0;   // step factor: 2 (Eq. 6) or 1 (Alg. 1)
+  double oexp = 1.0;  // output d_v^oexp yacc(v) scaled by oscale (Def. 8: 1 - a, d_s^a)
+  double oscale = 1.0;
   std::vector<double> c;
 };
 cp_status plan_query(const cp_graph* g, const cp_query* q, int32_t K_max, QueryPlan* p);

@@ -378,7 +378,8 @@ __global__ void __launch_bounds__(kThreads) finalize_kernel(FinalArgs a, double*
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < a.n; v += stride) {
     const int64_t d = a.row_ptr[v + 1] - a.row_ptr[v];
-    const A yv = A(d) * yacc[v];
+    const A yv = a.oexp == 1.0 && a.oscale == 1.0 ? A(d) * yacc[v]
+                                                  : (A)(a.oscale * pow((double)d, a.oexp) * (double)yacc[v]);
     out[a.perm ? a.perm[v] : v] = (O)yv;
     local += (double)(O)yv;
   }

@@ -217,7 +217,15 @@ __global__ void __launch_bounds__(kThreads) batch_init_kernel(BatchInitArgs a) {
   }
 }
 
-// Y[perm(v)][q] = d_v * yacc[tile(slot)][v][lane(slot)]
+// Output of one slot at row v: y = d_v yacc, or oscale d_v^oexp yacc for
+// the generalized output of Def. 8 (exact d_v yacc when oexp = 1, oscale = 1).
+template <typename A>
+__device__ __forceinline__ A slot_output(A yv, int64_t d, double oexp, double oscale) {
+  if (oexp == 1.0 && oscale == 1.0) return A(d) * yv;
+  return (A)(oscale * pow((double)d, oexp) * (double)yv);
+}
+
+// Y[perm(v)][q] = output of yacc[tile(slot)][v][lane(slot)]
 template <typename A, typename O>
 __global__ void __launch_bounds__(kThreads) batch_finalize_kernel(BatchFinalArgs a) {
   const A* y = static_cast<const A*>(a.yacc);
@@ -232,7 +240,7 @@ __global__ void __launch_bounds__(kThreads) batch_finalize_kernel(BatchFinalArgs
     const A val = y[((size_t)tile * a.n + v) * a.bw + lane];
     const int64_t d = a.row_ptr[v + 1] - a.row_ptr[v];
     const int64_t vo = a.perm ? a.perm[v] : v;
-    out[vo * a.nq + q] = (O)(A(d) * val);
+    out[vo * a.nq + q] = (O)slot_output<A>(val, d, a.oexp[slot], a.oscale[slot]);
   }
 }
 
@@ -244,6 +252,7 @@ __global__ void __launch_bounds__(kThreads) slot_finish_kernel(SlotFinishArgs a)
   const int slot = a.slots[f];
   const int tile = slot / a.bw, lane = slot % a.bw;
   O* out = static_cast<O*>(a.outs[f]);
+  const double oexp = a.oexp[slot], oscale = a.oscale[slot];
   T* rA = static_cast<T*>(a.rA);
   T* rB = static_cast<T*>(a.rB);
   A* y = static_cast<A*>(a.yacc);
@@ -253,11 +262,34 @@ __global__ void __launch_bounds__(kThreads) slot_finish_kernel(SlotFinishArgs a)
     const size_t e = ((size_t)tile * a.n + v) * a.bw + lane;
     if (out) {
       const int64_t d = a.row_ptr[v + 1] - a.row_ptr[v];
-      out[a.perm ? a.perm[v] : v] = (O)(A(d) * y[e]);
+      out[a.perm ? a.perm[v] : v] = (O)slot_output<A>(y[e], d, oexp, oscale);
     }
     y[e] = A(0);
     rA[e] = zero;
     rB[e] = zero;
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kThreads) dense_init_kernel(DenseInitArgs a) {
+  using A = typename Acc<T>::type;
+  using O = typename Out<T>::type;
+  const O* X = static_cast<const O*>(a.X);
+  T* r0 = static_cast<T*>(a.r0);
+  A* y = static_cast<A*>(a.yacc);
+  const int64_t total = a.n * a.k;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) {
+    const int64_t v = i / a.k;
+    const int j = (int)(i - v * a.k);
+    const int64_t d = a.row_ptr[v + 1] - a.row_ptr[v];
+    double f = 0.0;  // d^{a-1}: the D^{a} rescaling in the D^{-1} basis
+    if (d > 0) f = a.a == 0.0 ? 1.0 / (double)d : a.a == 1.0 ? 1.0 : pow((double)d, a.a - 1.0);
+    const int64_t vo = a.perm ? a.perm[v] : v;
+    const double x = f * (double)X[vo * a.k + j];
+    const size_t e = ((size_t)(j / a.bw) * a.n + v) * a.bw + (j % a.bw);
+    r0[e] = from_acc<T>((A)x);
+    y[e] = (A)(a.c0 * x);
   }
 }
 
@@ -313,6 +345,18 @@ hipError_t launch_batch_finalize(int32_t prec, const BatchFinalArgs& a, hipStrea
   if (prec == CP_F64) hipLaunchKernelGGL((batch_finalize_kernel<double, double>), grid, block, 0, st, a);
   else if (prec == CP_F32) hipLaunchKernelGGL((batch_finalize_kernel<double, float>), grid, block, 0, st, a);
   else hipLaunchKernelGGL((batch_finalize_kernel<float, float>), grid, block, 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_dense_init(int32_t prec, const DenseInitArgs& a, hipStream_t st) {
+  if (a.n * a.k <= 0) return hipSuccess;
+  dim3 grid(2048), block(kThreads);
+  switch (prec) {
+    case CP_F64: hipLaunchKernelGGL(dense_init_kernel<double>, grid, block, 0, st, a); break;
+    case CP_F32: hipLaunchKernelGGL(dense_init_kernel<float>, grid, block, 0, st, a); break;
+    case CP_BF16: hipLaunchKernelGGL(dense_init_kernel<bf16>, grid, block, 0, st, a); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

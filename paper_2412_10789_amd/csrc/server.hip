@@ -55,7 +55,7 @@ struct cp_server {
   // device layout
   size_t o_rA = 0, o_rB = 0, o_y = 0, o_hcount = 0, o_hpart = 0, o_coef = 0, o_src = 0, o_c01 = 0,
          o_rec = 0, o_fslots = 0, o_fouts = 0;
-  std::vector<double> rec;  // host copy of the per-slot step factor
+  std::vector<double> sp;  // host image of the slot parameters [kSlotParams][slots]
 
   std::mutex mu;
   std::condition_variable cv;       // wakes the worker
@@ -162,7 +162,9 @@ void cp_server::run() {
         src[s] = tk.plan.s_int;
         c01[s] = tk.plan.c[0];
         c01[nslot + s] = tk.plan.c[1];
-        rec[s] = tk.plan.rec;
+        sp[s] = tk.plan.rec;
+        sp[nslot + s] = tk.plan.oexp;
+        sp[2 * nslot + s] = tk.plan.oscale;
       }
       // queries that finish with this launch (or right after init when K == 1)
       for (int32_t s = 0; s < nslots; ++s) {
@@ -198,7 +200,7 @@ void cp_server::run() {
     if (!admitted.empty()) {
       chk(launch_upload(w + o_src, src.data(), nslot * sizeof(int64_t), st));
       chk(launch_upload(w + o_c01, c01.data(), 2 * nslot * sizeof(double), st));
-      chk(launch_upload(w + o_rec, rec.data(), nslot * sizeof(double), st));
+      chk(launch_upload(w + o_rec, sp.data(), 3 * nslot * sizeof(double), st));
       BatchInitArgs ia{g->row_ptr, g->col_idx, reinterpret_cast<const int64_t*>(w + o_src), g->n, bw, nslots,
                        zbuf, xbuf, w + o_y, reinterpret_cast<const double*>(w + o_c01)};
       chk(launch_batch_init(prec, ia, nslots, st));
@@ -231,8 +233,10 @@ void cp_server::run() {
     if (!fin_slots.empty()) {
       chk(launch_upload(w + o_fslots, fin_slots.data(), fin_slots.size() * sizeof(int32_t), st));
       chk(launch_upload(w + o_fouts, fin_outs.data(), fin_outs.size() * sizeof(void*), st));
+      const double* dsp = reinterpret_cast<const double*>(w + o_rec);
       SlotFinishArgs fa{g->row_ptr, g->perm, g->n, bw, reinterpret_cast<const int32_t*>(w + o_fslots),
-                        reinterpret_cast<void* const*>(w + o_fouts), w + o_rA, w + o_rB, w + o_y};
+                        reinterpret_cast<void* const*>(w + o_fouts), w + o_rA, w + o_rB, w + o_y,
+                        dsp + nslot, dsp + 2 * nslot};
       chk(launch_slot_finish(prec, fa, (int32_t)fin_slots.size(), st));
     }
     chk(hipStreamSynchronize(st));
@@ -308,7 +312,7 @@ cp_status cp_server_create(const cp_graph* g, size_t hbm_budget_bytes, int32_t m
   s->o_coef = off; off += a256(ns * 8);
   s->o_src = off; off += a256(ns * 8);
   s->o_c01 = off; off += a256(2 * ns * 8);
-  s->o_rec = off; off += a256(ns * 8);
+  s->o_rec = off; off += a256(kSlotParams * ns * 8);
   s->o_fslots = off; off += a256(ns * 4);
   s->o_fouts = off; off += a256(ns * 8);
   s->dev_bytes = off;
@@ -323,8 +327,8 @@ cp_status cp_server_create(const cp_graph* g, size_t hbm_budget_bytes, int32_t m
     return CP_EHIP;
   }
   e = launch_zero(s->dev, s->o_hpart, s->st);  // state buffers and hub counters start at zero
-  s->rec.assign(ns, 2.0);
-  if (e == hipSuccess) e = launch_upload(s->dev + s->o_rec, s->rec.data(), ns * sizeof(double), s->st);
+  s->sp = slot_params(s->nslots);
+  if (e == hipSuccess) e = launch_upload(s->dev + s->o_rec, s->sp.data(), s->sp.size() * sizeof(double), s->st);
   if (e == hipSuccess) e = hipStreamSynchronize(s->st);
   if (e != hipSuccess) {
     set_hip_error(e);
