@@ -481,6 +481,56 @@ def run_kvn(args, torch, cp, synth, g):
     return out
 
 
+def run_propagate(args, torch, cp, synth, g):
+    """Feature-matrix propagation (Def. 8 through Thm. 5) on the main line's
+    graph: Z = f(D^{-1/2} A D^{-1/2}) X for X [n x k] FP32, PPR alpha = 0.1,
+    K from the Thm. 2 tail at 1e-6 (the certified rule needs norms of X)."""
+    k, alpha, tol, a = args.propagate_cols, 0.1, 1e-6, 0.5
+    G = cp.Graph(g.row_ptr, g.col_idx, reorder=True)
+    X = (torch.rand((g.n, k), generator=torch.Generator().manual_seed(5), dtype=torch.float32) - 0.5).cuda()
+    Z = torch.empty_like(X)
+    G.propagate(X, "ppr", alpha, a=a, tol=tol, prec="f32", Z=Z)  # warm-up (default width)
+    best = None
+    for w in (16, 32, 64):  # same tile widths as the batched kernel; keep the fastest
+        if w > max(8, k):  # widths above the column count are not allowed
+            continue
+        G.set_batch_width(k, "f32", w)
+        _, info = G.propagate(X, "ppr", alpha, a=a, tol=tol, prec="f32", Z=Z, flags=cp.CP_Q_TIMING)
+        if best is None or info["elapsed_ms"] < best[1]:
+            best = (w, info["elapsed_ms"])
+    bw = best[0]
+    G.set_batch_width(k, "f32", bw)
+    reps, ms, steps = 3, 0.0, 0
+    for _ in range(reps):
+        _, info = G.propagate(X, "ppr", alpha, a=a, tol=tol, prec="f32", Z=Z, flags=cp.CP_Q_TIMING)
+        ms += info["elapsed_ms"]
+        step_ms = info["step_ms"]
+        steps = info["steps"]
+    ms /= reps
+    K = info["K"]
+    bpl = step_bytes(g.n, g.nnz, "f32", k)
+    out = {"workload": f"Z = f(D^-1/2 A D^-1/2) X, X [n x {k}] FP32, PPR alpha={alpha}, K={K} (Thm. 2 tail "
+                       f"{tol}), degree-ordered layout, on the main line's graph",
+           "GTEPS": round(g.nnz * steps * k / (ms * 1e-3) / 1e9, 2), "ms": round(ms, 2), "K": K,
+           "source_tile_width": bw,
+           "roofline": {"bound": "hbm", "kernel": "batch_step_kernel", "achieved":
+                        round(bpl / (step_ms / steps * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                        "frac": round(bpl / (step_ms / steps * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
+                        "avg_launch_ms": round(step_ms / steps, 3)}}
+    if not args.no_cpu:
+        from oracle import errors as E
+        from oracle import generalized as GG
+
+        j = 0
+        Xc = X[:, j:j + 1].double().cpu().numpy()
+        ref = GG.generalized_gp(g.row_ptr, g.col_idx, Xc, a, "ppr", alpha, K)[:, 0]
+        zj = Z[:, j].double().cpu().numpy()
+        out["accuracy_vs_fp64_oracle"] = {"column": j, "rel_l1": E.l1(zj, ref) / float(np.abs(ref).sum())}
+    log(f"[propagate] {out}")
+    G.close()
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -500,6 +550,8 @@ def main() -> int:
                          "results are always in caller ids")
     ap.add_argument("--kvn-tol", type=float, default=1e-6,
                     help="l1 tolerance of the ChebyPower-vs-PwMethod comparison (0: skip it)")
+    ap.add_argument("--propagate-cols", type=int, default=64,
+                    help="columns of the feature-matrix propagation measurement (0: skip it)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle legs")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run a plain 1 GiB device copy first (counter scaling for rocprofv3 --pmc)")
@@ -608,6 +660,8 @@ def main() -> int:
     del S
     if args.kvn_tol > 0:
         result["cheby_vs_power"] = run_kvn(args, torch, cp, synth, g_main)
+    if args.propagate_cols > 0:
+        result["propagate"] = run_propagate(args, torch, cp, synth, g_main)
     if args.serve_seconds > 0:
         result["served"] = run_serve(args, torch, cp, synth, g_main)
     del g_main
