@@ -22,6 +22,7 @@ from oracle import dense as D
 from oracle import errors as E
 from oracle import generalized as GG
 from oracle import propagation as PR
+from oracle import push as PU
 from oracle import truncation as T
 
 GP_CASES = [("ppr", 0.2), ("ppr", 0.05), ("ppr", 0.5), ("hkpr", 0.7), ("hkpr", 5.0), ("hkpr", 12.0)]
@@ -339,6 +340,125 @@ def pin_generalized_degree_zero_reading():
     assert np.max(np.abs(Z[: core.n] - ref)) < 1e-11
 
 
+# ---------------------------------------------------------------- Sec. 4 (ChebyPush)
+
+
+def pin_chebypush_worked_example():
+    """Sec. 4.2 illustrative example (tests/golden/star_example.txt): star with
+    centre v0, source v1, c = e_3 (f = T_3), eps_k = 1/3; the state after
+    each iteration's pushes and the final r_cur = [5/3, 0, 0, 0].  Only the
+    squared, inclusive threshold reproduces the printed steps."""
+    gold = load_golden("star_example.txt")
+    g = synth.star(3)
+    c = np.array([0.0, 0.0, 0.0, 1.0])
+    y, tr = PU.cheby_push(g.row_ptr, g.col_idx, 1, c, 3, np.full(4, 1.0 / 3.0), rule="squared_inclusive",
+                          trace=True)
+    assert [list(S) for S in tr["sets"]] == [[0], [2, 3]]
+    np.testing.assert_allclose(tr["states"][0][0], gold["push_k1_r_cur_after"], atol=1e-15)
+    np.testing.assert_allclose(tr["states"][0][1], gold["push_k1_r_new_after"], atol=1e-15)
+    np.testing.assert_allclose(tr["states"][1][0], gold["push_k2_r_cur_after"], atol=1e-15)
+    np.testing.assert_allclose(tr["states"][1][1], gold["push_k2_r_new_after"], atol=1e-15)
+    np.testing.assert_allclose(tr["r_cur"], gold["chebypush_T3_threshold_1_3"], atol=1e-15)
+    np.testing.assert_allclose(y, 0.0, atol=0)  # c_1 = c_2 = 0 and Alg. 4 never adds c_K
+
+
+def _push_cases():
+    for g in tiny_graphs()[:4]:
+        s = _connected_node(g, 2)
+        for kind, p, K in (("ppr", 0.2, 12), ("hkpr", 3.0, 10)):
+            for eps_a in (3e-2, 1e-3):
+                for rule in ("linear", "squared_inclusive"):
+                    yield g, s, kind, p, K, eps_a, rule
+
+
+def pin_push_form_is_subset_recurrence():
+    """Lemma 6: after iteration k of the push form, r_cur = r^_{k+1} of Def. 7
+    (formed from the same sets) and r_new = -r^_k|S_k + r^_k|(V - S_k)."""
+    for g, s, kind, p, K, eps_a, rule in _push_cases():
+        c = C.chebyshev_coeffs(kind, p, K)
+        _, tr = PU.cheby_push(g.row_ptr, g.col_idx, s, c, K, eps_a, rule=rule, trace=True)
+        r_hat = PU.subset_recurrence(g.row_ptr, g.col_idx, s, tr["sets"])
+        for k, ((rc, rn), S) in enumerate(zip(tr["states"], tr["sets"]), start=1):
+            on = np.zeros(g.n, dtype=bool)
+            on[S] = True
+            np.testing.assert_allclose(rn, r_hat[k + 1], atol=1e-14)
+            np.testing.assert_allclose(rc, np.where(on, -r_hat[k], r_hat[k]), atol=1e-14)
+        assert any(len(S) < np.count_nonzero(r_hat[k + 1]) for k, S in enumerate(tr["sets"])) or eps_a < 1e-2
+
+
+def pin_subset_recurrence_deviation_identity():
+    """Lemma 5: r_k = r^_k + 2 sum_{l=1}^{k-1} T_{k-l}(P) delta_l, with the
+    exact T_j(P) formed on A~'s spectrum (Def. 6, Lemma 1 proof)."""
+    for g, s, kind, p, K, eps_a, rule in _push_cases():
+        if rule != "linear":
+            continue
+        A = D.adjacency(g.row_ptr, g.col_idx)
+        c = C.chebyshev_coeffs(kind, p, K)
+        _, tr = PU.cheby_push(g.row_ptr, g.col_idx, s, c, K, eps_a, trace=True)
+        r_hat = PU.subset_recurrence(g.row_ptr, g.col_idx, s, tr["sets"])
+        P = PR.transition_matrix(g.row_ptr, g.col_idx)
+        r = PR.chebyshev_vectors(P, s, len(r_hat) - 1)
+        Tm = [D.chebyshev_matrix_eigen(A, j) for j in range(len(r_hat))]
+        delta = [None]
+        for l, S in enumerate(tr["sets"], start=1):
+            off = np.ones(g.n, dtype=bool)
+            off[S] = False
+            delta.append(np.where(off, r_hat[l], 0.0))
+        for k in range(2, len(r_hat)):
+            rhs = r_hat[k] + 2.0 * sum(Tm[k - l] @ delta[l] for l in range(1, k))
+            np.testing.assert_allclose(rhs, r[k], atol=1e-11, err_msg=f"{g.name} {kind} k={k}")
+
+
+def pin_chebypush_without_threshold():
+    """eps_a = 0 pushes every node with a non-zero residual, so the subset
+    recurrence is the exact one (Def. 7 with S_k = V) and Alg. 4 returns the
+    first K terms c_0..c_{K-1} of Alg. 3 (its loop stops before c_K)."""
+    for g in tiny_graphs():
+        P = PR.transition_matrix(g.row_ptr, g.col_idx)
+        s = _connected_node(g, 1)
+        for kind, p in (("ppr", 0.2), ("hkpr", 5.0)):
+            K = 9
+            c = C.chebyshev_coeffs(kind, p, K)
+            y = PU.cheby_push(g.row_ptr, g.col_idx, s, c, K, 0.0)
+            ref = PR.cheby_power(P, s, c[:K], K - 1)
+            np.testing.assert_allclose(y, ref, atol=1e-14, err_msg=g.name)
+
+
+def pin_chebypush_degree_normalized_error():
+    """Thm. 4: max_u |y(u) - y^(u)| / d_u < eps_a with K from Thm. 2's tail at
+    eps_a / 2 (the theorem rests on the stability assumption of Sec. 4.3,
+    which these graphs satisfy closely enough)."""
+    for g in tiny_graphs():
+        P = PR.transition_matrix(g.row_ptr, g.col_idx)
+        s = _connected_node(g, 2)
+        for kind, p in (("ppr", 0.2), ("hkpr", 5.0)):
+            exact = PR.ground_truth(P, s, kind, p)
+            for eps_a in (1e-2, 1e-4, 1e-6):
+                K = T.choose_K(kind, p, eps_a / 2, mode="tail")
+                y = PU.cheby_push(g.row_ptr, g.col_idx, s, C.chebyshev_coeffs(kind, p, K), K, eps_a)
+                err = PU.degree_normalized_error(exact, y, g.degrees)
+                assert err < eps_a, (g.name, kind, eps_a, err)
+
+
+def pin_chebypush_locality():
+    """Lemma 7's locality bound, iteration by iteration: vol(S_k) eps_k is at
+    most the selected residual mass, sum_{u in S_k} |r^_k(u)| with Alg. 4's
+    test and sum_{u in S_k} r^_k(u)^2 with the squared one."""
+    graphs = tiny_graphs() + [synth.chung_lu(20_000, 100_000, 2.5, seed=1)]
+    for g in graphs:
+        s = _connected_node(g, 2)
+        for kind, p in (("ppr", 0.2), ("hkpr", 5.0)):
+            for eps_a in (1e-2, 1e-4):
+                K = T.choose_K(kind, p, eps_a / 2, mode="tail")
+                c = C.chebyshev_coeffs(kind, p, K)
+                for rule in ("linear", "squared_inclusive"):
+                    _, tr = PU.cheby_push(g.row_ptr, g.col_idx, s, c, K, eps_a, rule=rule, trace=True)
+                    r_hat = PU.subset_recurrence(g.row_ptr, g.col_idx, s, tr["sets"])
+                    for k, S in enumerate(tr["sets"], start=1):
+                        mass = np.abs(r_hat[k][S]) if rule == "linear" else r_hat[k][S] ** 2
+                        assert g.degrees[S].sum() * tr["eps"][k] <= mass.sum() * (1 + 1e-12), (g.name, k, rule)
+
+
 ALL_PINS = [
     pin_star_example,
     pin_chebyshev_vectors_eigen,
@@ -360,6 +480,12 @@ ALL_PINS = [
     pin_generalized_symmetric_half,
     pin_generalized_single_source,
     pin_generalized_degree_zero_reading,
+    pin_chebypush_worked_example,
+    pin_push_form_is_subset_recurrence,
+    pin_subset_recurrence_deviation_identity,
+    pin_chebypush_without_threshold,
+    pin_chebypush_degree_normalized_error,
+    pin_chebypush_locality,
 ]
 
 

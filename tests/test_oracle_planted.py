@@ -66,6 +66,32 @@ def _start_not_rescaled(degrees, a):
     return np.where(np.asarray(degrees) > 0, 1.0, 0.0), dma
 
 
+def _push_without_sign_flip(r, d, eps, rule="linear"):
+    # select as usual, but make the caller's sign flip a no-op by returning
+    # the set of nodes whose residual is already zero (nothing flips)
+    S = PR.__dict__["_orig_selected"](r, d, eps, rule)
+    return S & (r == 0.0)
+
+
+def _threshold_without_degree(r, d, eps, rule="linear"):
+    return PR.__dict__["_orig_selected"](r, np.ones_like(d), eps, rule)
+
+
+def _push_form_drops_compensation(row_ptr, col_idx, s, sets):
+    # Def. 7 without the + r^_{k-1}|(V - S_{k-1}) term
+    r = PR.__dict__["_orig_subset_recurrence"](row_ptr, col_idx, s, [])
+    P = PR.transition_matrix(row_ptr, col_idx)
+    n = P.shape[0]
+    masks = [np.ones(n, dtype=bool)]
+    for S in sets:
+        m = np.zeros(n, dtype=bool)
+        m[np.asarray(S, dtype=np.int64)] = True
+        masks.append(m)
+    for k in range(1, len(sets) + 1):
+        r.append(2.0 * (P @ np.where(masks[k], r[k], 0.0)) - np.where(masks[k - 1], r[k - 1], 0.0))
+    return r
+
+
 MISTAKES = {
     "recurrence sign": ("propagation", "_chebyshev_step", _wrong_sign_step),
     "recurrence factor 2": ("propagation", "_chebyshev_step", _missing_factor_two_step),
@@ -78,6 +104,9 @@ MISTAKES = {
     "PwMethod extra term": ("propagation", "power_method", _power_method_extra_step),
     "Thm. 5 scalings swapped": ("generalized", "degree_powers", _powers_swapped),
     "Thm. 5 start vector not rescaled": ("generalized", "degree_powers", _start_not_rescaled),
+    "ChebyPush pushes nothing": ("push", "selected", _push_without_sign_flip),
+    "ChebyPush threshold without degree": ("push", "selected", _threshold_without_degree),
+    "Def. 7 without compensation": ("push", "subset_recurrence", _push_form_drops_compensation),
 }
 
 
