@@ -131,6 +131,9 @@ typedef struct {
   double step_ms;       /* sum of the Chebyshev step kernels' durations (CP_Q_TIMING) */
   double latency_ms;    /* server: submit -> result written (host clock) */
   double wait_ms;       /* server: submit -> admitted into a resident slot */
+  int64_t pushes;       /* cp_push: push operations (sum of |S_k|); 0 for the other paths */
+  int64_t arcs;         /* arcs the full steps processed: steps * nnz, or for cp_push the
+                           sum of vol(S_k) (with CP_Q_STATS / CP_Q_TIMING, else -1) */
 } cp_info;
 
 typedef struct {
@@ -226,6 +229,29 @@ cp_status cp_power_batch(const cp_graph* g, int32_t nq, const cp_query* q, int32
  * CP_EWORKSPACE, CP_EHIP. */
 cp_status cp_propagate(const cp_graph* g, const cp_query* q, int32_t k, int32_t prec, const void* X, void* Z,
                        void* ws, size_t ws_bytes, void* stream, cp_info* info);
+
+/* ChebyPush (Alg. 4, Sec. 4.2): the subset Chebyshev recurrence of Def. 7
+ * in push form, touching only the nodes whose residual passes the step
+ * threshold eps_k = eps_a / (4 K sum_{l=k}^{K} |c_l|), tested as
+ * |r(u)| > eps_k d_u (Alg. 4's test; the paper's prose squares r).  Output
+ * y^ = c_0 e_s + sum_{k<K} c_k r^_k|S_k, in FP64, in the space chosen by
+ * q->a (y^ scaled by d_s^a D^{-a}).  Thm. 4 bounds the degree-normalised
+ * error max_u |y(u) - y^(u)| / d_u by eps_a when K meets Thm. 2's tail at
+ * eps_a / 2 (under the paper's stability assumption).
+ *   q      as cp_power (kind, param, source, K rule, a; CP_Q_STATS,
+ *          CP_Q_TIMING); CP_Q_PWMETHOD gives CP_EINVAL
+ *   eps_a  >= 0 (0 pushes every non-zero residual: the first K terms of
+ *          Alg. 3)
+ *   y      device, n doubles, caller ids
+ *   ws     device workspace of cp_push_workspace_bytes(g) bytes, 256-byte
+ *          aligned
+ *   info   pushes and arcs need CP_Q_STATS or CP_Q_TIMING (synchronizes)
+ * Work per iteration is proportional to the candidate nodes and vol(S_k),
+ * not to n.  Residual updates use FP64 atomic adds, so results agree run to
+ * run up to rounding.  Errors as cp_power. */
+size_t cp_push_workspace_bytes(const cp_graph* g);
+cp_status cp_push(const cp_graph* g, const cp_query* q, double eps_a, double* y, void* ws, size_t ws_bytes,
+                  void* stream, cp_info* info);
 
 /* Pick the source-tile width (8, 16, 32 or 64 sources per tile) that runs
  * these nq queries fastest on this graph and remember it for later

@@ -69,9 +69,15 @@ def cheby_push(row_ptr, col_idx, s: int, c: np.ndarray, K: int, eps, rule: str =
     r_cur = P @ PR.one_hot(n, s)
     r_new = -PR.one_hot(n, s)
     sets, states = [], []
+    margin = np.inf  # smallest relative distance of a residual to its threshold (diagnostic)
     k = 1
     while k < K:
         S = selected(r_cur, d, eps_k[k], rule)
+        if trace and eps_k[k] > 0:
+            live = (r_cur != 0.0) & (d > 0)
+            if np.any(live):
+                t = eps_k[k] * d[live]
+                margin = min(margin, float(np.min(np.abs(np.abs(r_cur[live]) - t) / t)))
         y = y + c[k] * np.where(S, r_cur, 0.0)
         r_new = r_new + 2.0 * (P @ np.where(S, r_cur, 0.0))
         r_cur = np.where(S, -r_cur, r_cur)
@@ -81,7 +87,7 @@ def cheby_push(row_ptr, col_idx, s: int, c: np.ndarray, K: int, eps, rule: str =
         r_cur, r_new = r_new, r_cur
         k += 1
     if trace:
-        return y, {"sets": sets, "states": states, "r_cur": r_cur, "eps": eps_k}
+        return y, {"sets": sets, "states": states, "r_cur": r_cur, "eps": eps_k, "margin": margin}
     return y
 
 

@@ -735,6 +735,8 @@ cp_status cp_power(const cp_graph* g, const cp_query* q, int32_t prec, void* y, 
     info->step_ms = NAN;
     info->latency_ms = NAN;
     info->wait_ms = NAN;
+    info->pushes = 0;
+    info->arcs = (int64_t)(top - 1) * g->nnz;
   }
   if (stats || timing) {
     CP_HIP_C(hipStreamSynchronize(st));
@@ -874,6 +876,8 @@ cp_status power_batch_bw(cp_graph* g, int32_t nq, const cp_query* q, int32_t pre
       infos[j].step_ms = ms_steps;
       infos[j].latency_ms = NAN;
       infos[j].wait_ms = NAN;
+      infos[j].pushes = 0;
+      infos[j].arcs = (int64_t)(P[j].top - 1) * g->nnz;
     }
   cleanup();
 #undef CP_HIP_B
@@ -1018,6 +1022,8 @@ cp_status cp_propagate(const cp_graph* g, const cp_query* q, int32_t k, int32_t 
     info->step_ms = ms_steps;
     info->latency_ms = NAN;
     info->wait_ms = NAN;
+    info->pushes = 0;
+    info->arcs = (int64_t)top * g->nnz;
   }
   cleanup();
 #undef CP_HIP_P

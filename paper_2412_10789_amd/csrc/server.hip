@@ -94,6 +94,8 @@ void fill_info(const Ticket& t, cp_info* info) {
   info->step_ms = NAN;
   info->latency_ms = t.state == kDone ? ms_between(t.t_submit, t.t_done) : NAN;
   info->wait_ms = t.state >= kRunning ? ms_between(t.t_submit, t.t_admit) : NAN;
+  info->pushes = 0;
+  info->arcs = 0;
 }
 
 }  // namespace
