@@ -531,6 +531,43 @@ def run_propagate(args, torch, cp, synth, g):
     return out
 
 
+def run_push(args, torch, cp, synth, g):
+    """ChebyPush (Alg. 4) against ChebyPower (Alg. 3) on the main line's graph:
+    K from Thm. 2's tail at eps_a / 2 (Thm. 4's setting), both FP64; the
+    push's work (sum of vol(S_k)) against the global iteration's (K - 1) nnz,
+    device time of each, and the degree-normalised distance between them."""
+    G = cp.Graph(g.row_ptr, g.col_idx, reorder=args.layout == "degree", stripes=args.layout == "stripes")
+    srcs = [int(s) for s in synth.sources(g, 2, seed=13)]
+    deg = torch.tensor(g.degrees, dtype=torch.float64, device="cuda")
+    G.push("hkpr", 5.0, srcs[0], 1e-6, tol=5e-7, kmode="tail")  # warm-up
+    rows = []
+    for kind, param in (("hkpr", 5.0), ("ppr", 0.2)):
+        for eps_a in args.push_eps:
+            row = {"kind": kind, "param": param, "eps_a": eps_a}
+            ms_p, ms_c, arcs, pushes, dn = [], [], [], [], []
+            for s in srcs:
+                rp = G.push(kind, param, s, eps_a, tol=eps_a / 2, kmode="tail", flags=cp.CP_Q_TIMING)
+                rc = G.power(kind, param, s, tol=eps_a / 2, kmode="tail", prec="f64", flags=cp.CP_Q_TIMING)
+                K = rp.info["K"]
+                ms_p.append(rp.info["elapsed_ms"])
+                ms_c.append(rc.info["elapsed_ms"])
+                arcs.append(rp.info["arcs"])
+                pushes.append(rp.info["pushes"])
+                live = deg > 0
+                dn.append(float(((rp.y - rc.y).abs()[live] / deg[live]).max()))
+            row.update(K=K, ms_push=round(float(np.mean(ms_p)), 3), ms_power_f64=round(float(np.mean(ms_c)), 3),
+                       speedup=round(float(np.mean(ms_c)) / float(np.mean(ms_p)), 2),
+                       push_arcs=int(np.mean(arcs)), power_arcs=(K - 1) * g.nnz, pushes=int(np.mean(pushes)),
+                       work_fraction=round(float(np.mean(arcs)) / ((K - 1) * g.nnz), 4),
+                       deg_norm_vs_power=max(dn))
+            rows.append(row)
+            log(f"[push] {row}")
+    G.close()
+    return {"workload": "ChebyPush vs ChebyPower, 2 sources, FP64, K from the Thm. 2 tail at eps_a / 2, "
+                        f"on the main line's graph ({args.layout} layout); deg_norm_vs_power = max_u |y_push - "
+                        "y_power| / d_u (Thm. 4 bounds the push's own error by eps_a)", "rows": rows}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -552,6 +589,8 @@ def main() -> int:
                     help="l1 tolerance of the ChebyPower-vs-PwMethod comparison (0: skip it)")
     ap.add_argument("--propagate-cols", type=int, default=64,
                     help="columns of the feature-matrix propagation measurement (0: skip it)")
+    ap.add_argument("--push-eps", type=float, nargs="*", default=[1e-5, 1e-6, 1e-7, 1e-8],
+                    help="eps_a values of the ChebyPush measurement (none: skip it)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle legs")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run a plain 1 GiB device copy first (counter scaling for rocprofv3 --pmc)")
@@ -662,6 +701,8 @@ def main() -> int:
         result["cheby_vs_power"] = run_kvn(args, torch, cp, synth, g_main)
     if args.propagate_cols > 0:
         result["propagate"] = run_propagate(args, torch, cp, synth, g_main)
+    if args.push_eps:
+        result["push"] = run_push(args, torch, cp, synth, g_main)
     if args.serve_seconds > 0:
         result["served"] = run_serve(args, torch, cp, synth, g_main)
     del g_main

@@ -1,23 +1,31 @@
 // ChebyPush (Alg. 4, Sec. 4.2) on the GPU: the subset Chebyshev recurrence
-// of Def. 7 in its push form.  Residuals stay in the paper's space (FP64):
-// r_cur starts as P e_s, r_new as -e_s, and iteration k
-//   1. selects S_k = {u : |r_cur(u)| > eps_k d_u} among the nodes where
-//      r_cur can be non-zero (a candidate list), adds c_k r_cur(u) to y(u),
-//      records (u, 2 r_cur(u) / d_u) and flips the sign of r_cur(u);
-//   2. scatters every recorded value to the neighbours of its node in
-//      r_new (FP64 atomic adds), appending each node r_new reaches for the
-//      first time to r_new's candidate list;
-//   3. swaps the two vectors (and their lists) on the host.
-// Work per iteration is O(|candidates| + vol(S_k)), independent of n.  The
-// candidate list of a vector is a superset of its support: a node stays
-// listed once reached.  The atomic adds make the last bits of r_new depend
-// on arrival order, so results are reproducible up to rounding and a node
-// whose residual sits on the threshold to rounding may be selected in one
-// run and not in another.
+// of Def. 7 in its push form, computed without floating-point atomics.
+// Residuals stay in the paper's space (FP64): r_cur starts as P e_s, r_new
+// as -e_s, and iteration k
+//   1. select (one pass over the nodes): every u with |r_cur(u)| > eps_k d_u
+//      adds c_k r_cur(u) to y(u), stores its push value pv(u) = 2 r_cur(u)
+//      / d_u, flips the sign of r_cur(u) and is stamped sel(u) = k; the push
+//      values of the previous iteration are cleared in the same pass;
+//   2. the stamped nodes are listed in node order (S_k) and their arcs mark
+//      every neighbour with mark(v) = k (plain stores);
+//   3. the marked rows are listed in node order, short and long rows apart;
+//   4. pull: every marked row adds sum_{u in N(v)} pv(u) to r_new(v), summed
+//      in CSR order (a long row: one workgroup, thread-strided partial sums
+//      combined in a fixed order);
+//   5. the host swaps r_cur and r_new.
+// Step 4 is r_new += 2 P (r_cur|S_k) restricted to the rows it changes, so
+// the iteration is exactly the push form of Sec. 4.2.  When more than
+// n / kDenseDiv nodes are pushed, steps 2-3 are skipped and every row is
+// pulled (rows with no pushed neighbour add an exact zero).  Nothing depends on
+// timing, so results are bitwise reproducible run to run.  The arcs of the
+// pushed nodes are visited twice (marks, then the pulls of their
+// neighbours' rows), both at gather speed; the listing passes cost O(n) per
+// iteration in coalesced reads.
 
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <limits>
 #include <vector>
 
 #include "common.h"
@@ -25,146 +33,254 @@
 namespace cp {
 namespace {
 
-constexpr int kPushBlocks = 1024;
-constexpr int kChunk = kThreads;  // selected entries expanded together by one workgroup
+constexpr int kRangeBlocks = 1024;  // fixed node ranges of the listing passes
+constexpr int kEdgeBlocks = 1024;
+constexpr int kChunk = kThreads;    // selected nodes expanded together by one workgroup
+constexpr int32_t kShortRow = 32;   // rows up to this degree are pulled by one thread
 
 struct PushLayout {
-  size_t ra, rb, y, la, lb, fa, fb, su, sw, counts, sums, total;
+  size_t r[2], y, pv, deg, sel, mark, slist, tshort, tlong, ashort, along, bcount, counts, sums, total;
 };
 
-// counts region (int64 words): [0] list count of buffer a, [1] of buffer b,
-// [2] pushes, [3] arcs, [4 ...] selected count of iteration k
-constexpr int kCountsFixed = 4;
+// counts (int64): [0] |S_k|, [1] short marked rows, [2] long marked rows,
+// [3] pushes (sum of |S_k|), [4] arcs (sum of vol(S_k)), [5] dense flag of
+// the current iteration, [6] / [7] all short / long rows
+constexpr int kCounts = 8;
+// An iteration with more than n / kDenseDiv pushed nodes pulls every row
+// (no marks, no row lists): the marks would cost about as much as a full
+// gather over the graph.
+constexpr int64_t kDenseDiv = 8;
 
 PushLayout push_layout(const cp_graph* g) {
   auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
   const size_t n = (size_t)g->n;
   PushLayout L{};
   size_t off = 0;
-  L.ra = off; off += al(n * 8);
-  L.rb = off; off += al(n * 8);
+  for (int i = 0; i < 2; ++i) { L.r[i] = off; off += al(n * 8); }
   L.y = off; off += al(n * 8);
-  L.la = off; off += al(n * 4);
-  L.lb = off; off += al(n * 4);
-  L.fa = off; off += al(n * 4);
-  L.fb = off; off += al(n * 4);
-  L.su = off; off += al(n * 4);
-  L.sw = off; off += al(n * 8);
-  L.counts = off; off += al((size_t)(kCountsFixed + kDefaultKMax + 1) * 8);
-  L.sums = off; off += al((size_t)(1 + kPushBlocks) * 8);
+  L.pv = off; off += al(n * 8);
+  L.deg = off; off += al(n * 4);
+  L.sel = off; off += al(n * 4);
+  L.mark = off; off += al(n * 4);
+  L.slist = off; off += al(n * 4);
+  L.tshort = off; off += al(n * 4);
+  L.tlong = off; off += al(n * 4);
+  L.ashort = off; off += al(n * 4);
+  L.along = off; off += al(n * 4);
+  L.bcount = off; off += al((size_t)3 * kRangeBlocks * 4);
+  L.counts = off; off += al((size_t)kCounts * 8);
+  L.sums = off; off += al((size_t)(1 + kRangeBlocks) * 8);
   L.total = off;
   return L;
 }
 
-struct PushInitArgs {
+// Node range [lo, hi) of listing block blockIdx.x (grid of kRangeBlocks).
+__device__ __forceinline__ void block_range(int64_t n, int64_t& lo, int64_t& hi) {
+  const int64_t span = (n + kRangeBlocks - 1) / kRangeBlocks;
+  lo = (int64_t)blockIdx.x * span;
+  hi = lo + span < n ? lo + span : n;
+}
+
+__device__ __forceinline__ int block_sum_int(int v, int* red) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  int t = 0;
+  for (int q = 0; q < kThreads / 64; ++q) t += red[q];
+  __syncthreads();
+  return t;
+}
+
+// Ordered compaction step of a block: among this round's kThreads
+// candidates (one per thread, in thread order) the takers get consecutive
+// positions after `base`, which advances by their number.  All threads
+// call it; returns the taker's position or -1.
+__device__ __forceinline__ int64_t block_place(bool take, int* wcnt, int64_t& base) {
+  const unsigned long long mask = __ballot(take);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane == 0) wcnt[wv] = __popcll(mask);
+  __syncthreads();
+  int before = 0, total = 0;
+  for (int q = 0; q < kThreads / 64; ++q) {
+    if (q < wv) before += wcnt[q];
+    total += wcnt[q];
+  }
+  __syncthreads();
+  const int64_t pos = base + before + __popcll(mask & ((1ull << lane) - 1ull));
+  base += total;
+  return take ? pos : -1;
+}
+
+struct DegreeArgs {
+  const int64_t* row_ptr;
+  int64_t n;
+  int32_t* deg;
+};
+
+__global__ void __launch_bounds__(kThreads) push_degree_kernel(DegreeArgs a) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < a.n; v += stride)
+    a.deg[v] = (int32_t)(a.row_ptr[v + 1] - a.row_ptr[v]);
+}
+
+struct SeedArgs {
   const int64_t* row_ptr;
   const int32_t* col_idx;
   int64_t s;
   double c0;
-  double* ra;  // r_cur = P e_s
-  double* rb;  // r_new = -e_s
+  double* r_cur;  // P e_s
+  double* r_new;  // -e_s
   double* y;
-  int32_t* la;
-  int32_t* lb;
-  int32_t* fa;
-  int32_t* fb;
-  long long* counts;
 };
 
-__global__ void __launch_bounds__(kThreads) push_init_kernel(PushInitArgs a) {
+__global__ void __launch_bounds__(kThreads) push_seed_kernel(SeedArgs a) {
   const int64_t p0 = a.row_ptr[a.s], ds = a.row_ptr[a.s + 1] - p0;
   const double w = 1.0 / (double)ds;
-  for (int64_t i = threadIdx.x; i < ds; i += blockDim.x) {
-    const int32_t v = a.col_idx[p0 + i];
-    a.ra[v] = w;
-    a.la[i] = v;
-    a.fa[v] = 1;
-  }
+  for (int64_t i = threadIdx.x; i < ds; i += blockDim.x) a.r_cur[a.col_idx[p0 + i]] = w;
   if (threadIdx.x == 0) {
-    a.rb[a.s] = -1.0;
-    a.lb[0] = (int32_t)a.s;
-    a.fb[a.s] = 1;
+    a.r_new[a.s] = -1.0;
     a.y[a.s] = a.c0;
-    a.counts[0] = ds;
-    a.counts[1] = 1;
   }
 }
 
-struct PushSelectArgs {
-  const int64_t* row_ptr;
-  const int32_t* list;    // candidates of r_cur
-  const long long* count;  // their number
-  double* r;              // r_cur
+struct SelectArgs {
+  int64_t n;
+  const int32_t* deg;
+  double* r;  // r_cur
   double* y;
-  int32_t* su;
-  double* sw;
-  long long* scount;      // selected count of this iteration
-  long long* pushes;
+  double* pv;
+  int32_t* sel;
+  int32_t k;
   double eps, c;
+  int32_t* bcount;  // per range block: selected nodes
 };
 
-__global__ void __launch_bounds__(kThreads) push_select_kernel(PushSelectArgs a) {
-  const long long m = *a.count;
-  const int lane = threadIdx.x & 63;
-  const long long stride = (long long)gridDim.x * blockDim.x;
-  // every lane of a wave runs the same number of iterations (ballots stay full)
-  for (long long base = (long long)blockIdx.x * blockDim.x; base < m; base += stride) {
-    const long long i = base + threadIdx.x;
-    int32_t u = 0;
-    double val = 0.0, d = 0.0;
-    bool sel = false;
-    if (i < m) {
-      u = a.list[i];
-      val = a.r[u];
-      d = (double)(a.row_ptr[u + 1] - a.row_ptr[u]);
-      sel = d > 0.0 && fabs(val) > a.eps * d;
+__global__ void __launch_bounds__(kThreads) push_select_kernel(SelectArgs a) {
+  __shared__ int red[kThreads / 64];
+  int64_t lo, hi;
+  block_range(a.n, lo, hi);
+  int cnt = 0;
+  for (int64_t v = lo + threadIdx.x; v < hi; v += kThreads) {
+    const double val = a.r[v];
+    const int32_t d = a.deg[v];
+    if (d > 0 && fabs(val) > a.eps * (double)d) {
+      a.y[v] += a.c * val;
+      a.pv[v] = 2.0 * val / (double)d;
+      a.r[v] = -val;
+      a.sel[v] = a.k;
+      ++cnt;
+    } else if (a.k > 1 && a.sel[v] == a.k - 1) {
+      a.pv[v] = 0.0;  // pushed in the previous iteration only
     }
-    const unsigned long long mask = __ballot(sel);
-    if (mask == 0ull) continue;
-    const int leader = __ffsll((long long)mask) - 1;
-    long long slot0 = 0;
-    if (lane == leader) {
-      slot0 = atomicAdd((unsigned long long*)a.scount, (unsigned long long)__popcll(mask));
-      atomicAdd((unsigned long long*)a.pushes, (unsigned long long)__popcll(mask));
-    }
-    slot0 = __shfl(slot0, leader);
-    if (sel) {
-      const long long j = slot0 + __popcll(mask & ((1ull << lane) - 1ull));
-      a.y[u] += a.c * val;
-      a.su[j] = u;
-      a.sw[j] = 2.0 * val / d;
-      a.r[u] = -val;
-    }
+  }
+  const int t = block_sum_int(cnt, red);
+  if (threadIdx.x == 0) a.bcount[blockIdx.x] = t;
+}
+
+// Lists of the nodes stamped k, in node order.  With split_long, rows
+// longer than kShortRow go to list1, the others to list0.
+struct ListArgs {
+  int64_t n;
+  const int32_t* stamp;
+  const int32_t* deg;
+  int32_t k;
+  int32_t split_long;
+  int32_t* bcount0;  // per range block counts (written by the count pass)
+  int32_t* bcount1;
+  int32_t* list0;
+  int32_t* list1;
+  long long* count0;
+  long long* count1;
+  long long* dense;  // S pass: set when the iteration goes dense; row passes: skip when set
+  int32_t all_rows;  // list every row with an edge (the stamp is not read)
+};
+
+__device__ __forceinline__ bool listed(const ListArgs& a, int64_t v) {
+  return a.all_rows ? a.deg[v] > 0 : a.stamp[v] == a.k;
+}
+
+__global__ void __launch_bounds__(kThreads) push_count_kernel(ListArgs a) {
+  __shared__ int red[kThreads / 64];
+  if (!a.all_rows && *a.dense) return;
+  int64_t lo, hi;
+  block_range(a.n, lo, hi);
+  int c0 = 0, c1 = 0;
+  for (int64_t v = lo + threadIdx.x; v < hi; v += kThreads) {
+    if (!listed(a, v)) continue;
+    if (a.split_long && a.deg[v] > kShortRow) ++c1; else ++c0;
+  }
+  const int t0 = block_sum_int(c0, red);
+  const int t1 = block_sum_int(c1, red);
+  if (threadIdx.x == 0) {
+    a.bcount0[blockIdx.x] = t0;
+    a.bcount1[blockIdx.x] = t1;
   }
 }
 
-struct PushScatterArgs {
+__global__ void __launch_bounds__(kThreads) push_list_kernel(ListArgs a) {
+  __shared__ int wcnt[kThreads / 64];
+  __shared__ int red[kThreads / 64];
+  __shared__ long long off[2];
+  if (a.split_long && !a.all_rows && *a.dense) return;
+  // block offsets: the counts of the blocks before this one (block-wide sums)
+  int p0 = 0, p1 = 0;
+  for (int b = threadIdx.x; b < (int)blockIdx.x; b += kThreads) {
+    p0 += a.bcount0[b];
+    if (a.split_long) p1 += a.bcount1[b];
+  }
+  const int o0 = block_sum_int(p0, red);
+  const int o1 = block_sum_int(p1, red);
+  if (threadIdx.x == 0) {
+    off[0] = o0;
+    off[1] = o1;
+    if (blockIdx.x == gridDim.x - 1) {
+      const long long total0 = (long long)o0 + a.bcount0[blockIdx.x];
+      *a.count0 = total0;
+      if (a.split_long) *a.count1 = (long long)o1 + a.bcount1[blockIdx.x];
+      else if (!a.all_rows) *a.dense = total0 * kDenseDiv > a.n ? 1 : 0;
+    }
+  }
+  __syncthreads();
+  int64_t lo, hi;
+  block_range(a.n, lo, hi);
+  int64_t b0 = off[0], b1 = off[1];
+  for (int64_t v0 = lo; v0 < hi; v0 += kThreads) {  // rounds are uniform across the block
+    const int64_t v = v0 + threadIdx.x;
+    const bool hit = v < hi && listed(a, v);
+    const bool longrow = hit && a.split_long && a.deg[v] > kShortRow;
+    const int64_t p0 = block_place(hit && !longrow, wcnt, b0);
+    const int64_t p1 = block_place(longrow, wcnt, b1);
+    if (p0 >= 0) a.list0[p0] = (int32_t)v;
+    if (p1 >= 0) a.list1[p1] = (int32_t)v;
+  }
+}
+
+struct MarkArgs {
   const int64_t* row_ptr;
   const int32_t* col_idx;
-  const int32_t* su;
-  const double* sw;
+  const int32_t* slist;
   const long long* scount;
-  double* r;          // r_new
-  int32_t* list;      // candidates of r_new
-  int32_t* flag;
-  long long* count;
+  int32_t* mark;
+  int32_t k;
+  long long* pushes;
   long long* arcs;
+  const long long* dense;  // count arcs only, no marks
 };
 
-__global__ void __launch_bounds__(kThreads) push_scatter_kernel(PushScatterArgs a) {
+__global__ void __launch_bounds__(kThreads) push_mark_kernel(MarkArgs a) {
   __shared__ long long pre[kChunk];  // inclusive prefix sum of the chunk's degrees
   __shared__ int64_t off[kChunk];
-  __shared__ double wv[kChunk];
   const long long m = *a.scount;
   const int tid = threadIdx.x;
+  if (blockIdx.x == 0 && tid == 0) atomicAdd((unsigned long long*)a.pushes, (unsigned long long)m);
   for (long long chunk = blockIdx.x; chunk * kChunk < m; chunk += gridDim.x) {
     const long long i = chunk * kChunk + tid;
     long long d = 0;
     if (i < m) {
-      const int32_t u = a.su[i];
+      const int32_t u = a.slist[i];
       off[tid] = a.row_ptr[u];
       d = a.row_ptr[u + 1] - off[tid];
-      wv[tid] = a.sw[i];
     }
     pre[tid] = d;
     __syncthreads();
@@ -176,20 +292,88 @@ __global__ void __launch_bounds__(kThreads) push_scatter_kernel(PushScatterArgs 
     }
     const long long total = pre[kChunk - 1];
     if (tid == 0) atomicAdd((unsigned long long*)a.arcs, (unsigned long long)total);
-    for (long long e = tid; e < total; e += kChunk) {
+    const long long todo = *a.dense ? 0 : total;
+    for (long long e = tid; e < todo; e += kChunk) {
       int lo = 0, hi = kChunk - 1;  // first entry whose inclusive prefix exceeds e
       while (lo < hi) {
         const int mid = (lo + hi) >> 1;
         if (pre[mid] > e) hi = mid; else lo = mid + 1;
       }
       const long long before = lo ? pre[lo - 1] : 0;
-      const int32_t v = a.col_idx[off[lo] + (e - before)];
-      unsafeAtomicAdd(a.r + v, wv[lo]);
-      if (__hip_atomic_load(a.flag + v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0 &&
-          atomicCAS(a.flag + v, 0, 1) == 0) {
-        const long long p = (long long)atomicAdd((unsigned long long*)a.count, 1ull);
-        a.list[p] = v;
-      }
+      a.mark[a.col_idx[off[lo] + (e - before)]] = a.k;
+    }
+    __syncthreads();
+  }
+}
+
+struct PullArgs {
+  const int64_t* row_ptr;
+  const int32_t* col_idx;
+  const double* pv;
+  double* r;  // r_new
+  const int32_t* list;       // marked rows of the class
+  const long long* count;
+  const int32_t* all_list;   // every row of the class (dense iterations)
+  const long long* all_count;
+  const long long* dense;
+};
+
+// Short rows: one thread per row, arcs summed in CSR order (four loads in
+// flight, added in order).
+__global__ void __launch_bounds__(kThreads) push_pull_short_kernel(PullArgs a) {
+  const bool dense = *a.dense;
+  const int32_t* list = dense ? a.all_list : a.list;
+  const long long m = dense ? *a.all_count : *a.count;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += stride) {
+    const int32_t v = list[i];
+    const int64_t pe = a.row_ptr[v + 1];
+    int64_t p = a.row_ptr[v];
+    double acc = 0.0;
+    for (; p + 4 <= pe; p += 4) {
+      const double x0 = a.pv[a.col_idx[p]], x1 = a.pv[a.col_idx[p + 1]];
+      const double x2 = a.pv[a.col_idx[p + 2]], x3 = a.pv[a.col_idx[p + 3]];
+      acc += x0;
+      acc += x1;
+      acc += x2;
+      acc += x3;
+    }
+    for (; p < pe; ++p) acc += a.pv[a.col_idx[p]];
+    a.r[v] += acc;
+  }
+}
+
+// Long rows: one workgroup per row; thread t sums arcs t, t + 256, ... in
+// order (four loads in flight), then a fixed wave butterfly and an ordered
+// sum of the four wave totals.
+__global__ void __launch_bounds__(kThreads) push_pull_long_kernel(PullArgs a) {
+  __shared__ double wsum[kThreads / 64];
+  const bool dense = *a.dense;
+  const int32_t* list = dense ? a.all_list : a.list;
+  const long long m = dense ? *a.all_count : *a.count;
+  const int tid = threadIdx.x;
+  for (long long i = blockIdx.x; i < m; i += gridDim.x) {
+    const int32_t v = list[i];
+    const int64_t pb = a.row_ptr[v], pe = a.row_ptr[v + 1];
+    double acc = 0.0;
+    int64_t p = pb + tid;
+    for (; p + 3 * kThreads < pe; p += 4 * kThreads) {
+      const double x0 = a.pv[a.col_idx[p]], x1 = a.pv[a.col_idx[p + kThreads]];
+      const double x2 = a.pv[a.col_idx[p + 2 * kThreads]], x3 = a.pv[a.col_idx[p + 3 * kThreads]];
+      acc += x0;
+      acc += x1;
+      acc += x2;
+      acc += x3;
+    }
+    for (; p < pe; p += kThreads) acc += a.pv[a.col_idx[p]];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    if ((tid & 63) == 0) wsum[tid >> 6] = acc;
+    __syncthreads();
+    if (tid == 0) {
+      double t = 0.0;
+      for (int q = 0; q < kThreads / 64; ++q) t += wsum[q];
+      a.r[v] += t;
     }
     __syncthreads();
   }
@@ -257,13 +441,14 @@ cp_status cp_push(const cp_graph* g, const cp_query* q, double eps_a, double* y,
   if (!ws || ws_bytes < L.total || (reinterpret_cast<uintptr_t>(ws) & 255)) return CP_EWORKSPACE;
   const int32_t K = qp.K;
   const std::vector<double>& c = qp.c;
-  // eps_k = eps_a / (4 K sum_{l=k}^{K} |c_l|), Alg. 4
+  // eps_k = eps_a / (4 K sum_{l=k}^{K} |c_l|), Alg. 4 (a zero tail: nothing
+  // left to weight, so nothing is pushed)
   std::vector<double> eps(K + 1, 0.0);
   {
     double tail = 0.0;
     for (int32_t l = K; l >= 1; --l) {
       tail += std::fabs(c[l]);
-      eps[l] = tail > 0.0 ? eps_a / (4.0 * K * tail) : 0.0;
+      eps[l] = tail > 0.0 ? eps_a / (4.0 * K * tail) : std::numeric_limits<double>::infinity();
     }
   }
   hipStream_t st = static_cast<hipStream_t>(stream);
@@ -288,38 +473,71 @@ cp_status cp_push(const cp_graph* g, const cp_query* q, double eps_a, double* y,
     for (auto& e : ev) CP_HIP_U(hipEventCreate(&e));
   if (timing) CP_HIP_U(hipEventRecord(ev[0], st));
   CP_HIP_U(launch_zero(w, L.sums, st));
-  long long* counts = reinterpret_cast<long long*>(w + L.counts);
-  double* rbuf[2] = {reinterpret_cast<double*>(w + L.ra), reinterpret_cast<double*>(w + L.rb)};
-  int32_t* lbuf[2] = {reinterpret_cast<int32_t*>(w + L.la), reinterpret_cast<int32_t*>(w + L.lb)};
-  int32_t* fbuf[2] = {reinterpret_cast<int32_t*>(w + L.fa), reinterpret_cast<int32_t*>(w + L.fb)};
+  double* rbuf[2] = {reinterpret_cast<double*>(w + L.r[0]), reinterpret_cast<double*>(w + L.r[1])};
   double* yv = reinterpret_cast<double*>(w + L.y);
-  PushInitArgs ia{g->row_ptr, g->col_idx, qp.s_int, c[0], rbuf[0], rbuf[1], yv,
-                  lbuf[0], lbuf[1], fbuf[0], fbuf[1], counts};
-  hipLaunchKernelGGL(push_init_kernel, dim3(1), dim3(kThreads), 0, st, ia);
+  double* pv = reinterpret_cast<double*>(w + L.pv);
+  int32_t* deg = reinterpret_cast<int32_t*>(w + L.deg);
+  int32_t* sel = reinterpret_cast<int32_t*>(w + L.sel);
+  int32_t* mark = reinterpret_cast<int32_t*>(w + L.mark);
+  int32_t* slist = reinterpret_cast<int32_t*>(w + L.slist);
+  int32_t* tshort = reinterpret_cast<int32_t*>(w + L.tshort);
+  int32_t* tlong = reinterpret_cast<int32_t*>(w + L.tlong);
+  int32_t* ashort = reinterpret_cast<int32_t*>(w + L.ashort);
+  int32_t* along = reinterpret_cast<int32_t*>(w + L.along);
+  int32_t* bc = reinterpret_cast<int32_t*>(w + L.bcount);
+  long long* counts = reinterpret_cast<long long*>(w + L.counts);
+  const dim3 rb(kRangeBlocks), eb(kEdgeBlocks), tb(kThreads);
+  hipLaunchKernelGGL(push_degree_kernel, rb, tb, 0, st, DegreeArgs{g->row_ptr, g->n, deg});
+  CP_HIP_U(hipGetLastError());
+  {  // every row with an edge, short and long apart (pulled by dense iterations)
+    const ListArgs la{g->n, nullptr, deg, 0, 1, bc + kRangeBlocks, bc + 2 * kRangeBlocks, ashort, along,
+                      counts + 6, counts + 7, counts + 5, 1};
+    hipLaunchKernelGGL(push_count_kernel, rb, tb, 0, st, la);
+    CP_HIP_U(hipGetLastError());
+    hipLaunchKernelGGL(push_list_kernel, rb, tb, 0, st, la);
+    CP_HIP_U(hipGetLastError());
+  }
+  hipLaunchKernelGGL(push_seed_kernel, dim3(1), tb, 0, st,
+                     SeedArgs{g->row_ptr, g->col_idx, qp.s_int, c[0], rbuf[0], rbuf[1], yv});
   CP_HIP_U(hipGetLastError());
   if (timing) CP_HIP_U(hipEventRecord(ev[1], st));
-  int cur = 0;
+  int cur = 0;  // rbuf[cur] is r_cur
   for (int32_t k = 1; k < K; ++k) {
     const int nxt = cur ^ 1;
-    PushSelectArgs sa{g->row_ptr, lbuf[cur], counts + cur, rbuf[cur], yv,
-                      reinterpret_cast<int32_t*>(w + L.su), reinterpret_cast<double*>(w + L.sw),
-                      counts + kCountsFixed + k, counts + 2, eps[k], c[k]};
-    hipLaunchKernelGGL(push_select_kernel, dim3(kPushBlocks), dim3(kThreads), 0, st, sa);
+    hipLaunchKernelGGL(push_select_kernel, rb, tb, 0, st,
+                       SelectArgs{g->n, deg, rbuf[cur], yv, pv, sel, k, eps[k], c[k], bc});
     CP_HIP_U(hipGetLastError());
-    PushScatterArgs xa{g->row_ptr, g->col_idx, reinterpret_cast<const int32_t*>(w + L.su),
-                       reinterpret_cast<const double*>(w + L.sw), counts + kCountsFixed + k, rbuf[nxt],
-                       lbuf[nxt], fbuf[nxt], counts + nxt, counts + 3};
-    hipLaunchKernelGGL(push_scatter_kernel, dim3(kPushBlocks), dim3(kThreads), 0, st, xa);
+    const ListArgs ls{g->n, sel, deg, k, 0, bc, bc + kRangeBlocks, slist, slist, counts + 0, counts + 0,
+                      counts + 5, 0};
+    hipLaunchKernelGGL(push_list_kernel, rb, tb, 0, st, ls);
+    CP_HIP_U(hipGetLastError());
+    hipLaunchKernelGGL(push_mark_kernel, eb, tb, 0, st,
+                       MarkArgs{g->row_ptr, g->col_idx, slist, counts + 0, mark, k, counts + 3, counts + 4,
+                                counts + 5});
+    CP_HIP_U(hipGetLastError());
+    const ListArgs lt{g->n, mark, deg, k, 1, bc + kRangeBlocks, bc + 2 * kRangeBlocks, tshort, tlong,
+                      counts + 1, counts + 2, counts + 5, 0};
+    hipLaunchKernelGGL(push_count_kernel, rb, tb, 0, st, lt);
+    CP_HIP_U(hipGetLastError());
+    hipLaunchKernelGGL(push_list_kernel, rb, tb, 0, st, lt);
+    CP_HIP_U(hipGetLastError());
+    hipLaunchKernelGGL(push_pull_short_kernel, eb, tb, 0, st,
+                       PullArgs{g->row_ptr, g->col_idx, pv, rbuf[nxt], tshort, counts + 1, ashort, counts + 6,
+                                counts + 5});
+    CP_HIP_U(hipGetLastError());
+    hipLaunchKernelGGL(push_pull_long_kernel, eb, tb, 0, st,
+                       PullArgs{g->row_ptr, g->col_idx, pv, rbuf[nxt], tlong, counts + 2, along, counts + 7,
+                                counts + 5});
     CP_HIP_U(hipGetLastError());
     cur = nxt;
   }
   if (timing) CP_HIP_U(hipEventRecord(ev[2], st));
   double* sums = reinterpret_cast<double*>(w + L.sums);
   PushFinalArgs fa{g->row_ptr, g->perm, g->n, yv, y, -q->a, qp.oscale, stats ? sums : nullptr};
-  hipLaunchKernelGGL(push_final_kernel, dim3(kPushBlocks), dim3(kThreads), 0, st, fa);
+  hipLaunchKernelGGL(push_final_kernel, rb, tb, 0, st, fa);
   CP_HIP_U(hipGetLastError());
   if (stats) {
-    hipLaunchKernelGGL(push_sum_kernel, dim3(1), dim3(64), 0, st, sums, kPushBlocks);
+    hipLaunchKernelGGL(push_sum_kernel, dim3(1), dim3(64), 0, st, sums, kRangeBlocks);
     CP_HIP_U(hipGetLastError());
   }
   if (timing) CP_HIP_U(hipEventRecord(ev[3], st));
@@ -338,11 +556,11 @@ cp_status cp_push(const cp_graph* g, const cp_query* q, double eps_a, double* y,
   }
   if (stats || timing) {
     CP_HIP_U(hipStreamSynchronize(st));
-    long long host[kCountsFixed] = {0, 0, 0, 0};
+    long long host[kCounts] = {0};
     CP_HIP_U(hipMemcpy(host, counts, sizeof(host), hipMemcpyDeviceToHost));
     if (info) {
-      info->pushes = host[2];
-      info->arcs = host[3];
+      info->pushes = host[3];
+      info->arcs = host[4];
       if (stats) {
         double m = 0;
         CP_HIP_U(hipMemcpy(&m, sums, sizeof(double), hipMemcpyDeviceToHost));
