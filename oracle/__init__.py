@@ -26,10 +26,12 @@ Modules
   errors        error measures (Def. 5) and the PPR residual certificate
   push          ChebyPush (Alg. 4) and the subset Chebyshev recurrence
                 (Def. 7), with the two threshold readings of Sec. 4
+  bidirectional ChebyPush + alpha-random walks for SSPPR (Alg. 5), walks
+                drawn from SplitMix64 counters
   generalized   Z = f(D^{-a} A D^{-b}) X (Def. 8) through Thm. 5: the series
                 of Alg. 3 / Alg. 1 on D^{a} X, scaled by D^{-a}
   native        the same Alg. 3 / Alg. 1 in plain C with an OpenMP node
                 loop (oracle/c/chebypower.c), for graphs with billions of arcs
 """
 
-from . import coefficients, dense, errors, generalized, propagation, push, truncation  # noqa: F401
+from . import bidirectional, coefficients, dense, errors, generalized, propagation, push, truncation  # noqa: F401,E501

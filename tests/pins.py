@@ -17,6 +17,7 @@ import scipy.special as ss
 
 import synth
 from conftest import load_golden
+from oracle import bidirectional as BI
 from oracle import coefficients as C
 from oracle import dense as D
 from oracle import errors as E
@@ -459,6 +460,77 @@ def pin_chebypush_locality():
                         assert g.degrees[S].sum() * tr["eps"][k] <= mass.sum() * (1 + 1e-12), (g.name, k, rule)
 
 
+# ---------------------------------------------------------------- Sec. 5.2 (ChebyPush + walks)
+
+
+def pin_splitmix64_published_outputs():
+    """The walk generator is SplitMix64: its first outputs from state 0 equal
+    the published reference values (tests/golden/splitmix64_seed0.txt)."""
+    import os
+    from conftest import HERE
+
+    with open(os.path.join(HERE, "golden", "splitmix64_seed0.txt")) as fh:
+        line = [ln for ln in fh if ln.startswith("outputs:")][0]
+    want = [int(x.strip(), 16) for x in line.split(":", 1)[1].split(",")]
+    assert [BI.splitmix64(0, i) for i in range(len(want))] == want
+
+
+def _ppr_matrix(g, alpha):
+    A = D.adjacency(g.row_ptr, g.col_idx)
+    P = D.random_walk_matrix(A)
+    return alpha * np.linalg.inv(np.eye(g.n) - (1.0 - alpha) * P)  # column v is pi_v
+
+
+def pin_residual_invariant():
+    """Lemma 9: after the push phase, pi_s = pi^ + sum_v r(v) pi_v, with the
+    residual r = e_s - alpha^{-1} [I - (1 - alpha) P] pi^ and the exact pi_v."""
+    for g in tiny_graphs()[:4]:
+        s = _connected_node(g, 1)
+        alpha = 0.2
+        Pi = _ppr_matrix(g, alpha)
+        for eps_a in (1e-2, 1e-4):
+            K = 12
+            pi_hat = PU.cheby_push(g.row_ptr, g.col_idx, s, C.ppr_chebyshev_coeffs(alpha, K), K, eps_a)
+            r = BI.residual(g.row_ptr, g.col_idx, s, alpha, pi_hat)
+            np.testing.assert_allclose(pi_hat + Pi @ r, Pi[:, s], atol=1e-12, err_msg=g.name)
+            assert np.max(np.abs(r)) > 1e-6  # the push left mass to the walks
+
+
+def pin_alpha_walk_end_distribution():
+    """An alpha-random walk from v ends at u with probability pi_v(u) (the
+    walk reading of Def. 3): 40,000 seeded walks against the exact vector,
+    every node within 5 binomial standard deviations."""
+    g = synth.barbell_with_tail(5, 4)
+    alpha = 0.25
+    Pi = _ppr_matrix(g, alpha)
+    v = 3
+    M = 40_000
+    key = BI.splitmix64(123, v)
+    ends = np.bincount([BI.walk_terminal(g.row_ptr, g.col_idx, key, j, v, alpha) for j in range(M)],
+                       minlength=g.n)
+    p = Pi[:, v]
+    sd = np.sqrt(p * (1 - p) / M) + 1e-12
+    assert np.all(np.abs(ends / M - p) <= 5 * sd + 1e-9), np.max(np.abs(ends / M - p) / sd)
+
+
+def pin_push_rw_accuracy():
+    """Alg. 5 end to end, with a threshold large enough that the walks carry
+    most of the mass: |pi^(u) - pi_s(u)| < eps_r pi_s(u) wherever
+    pi_s(u) > delta (the guarantee holds with high probability; seeded)."""
+    g = synth.erdos_renyi(60, 0.12, seed=8)
+    s = _connected_node(g, 2)
+    alpha, eps_r = 0.2, 0.3
+    delta = 1.0 / g.n
+    Pi = _ppr_matrix(g, alpha)
+    pi_hat, tr = BI.push_rw(g.row_ptr, g.col_idx, s, alpha, 4, eps_r, delta, seed=7, trace=True, r_max=1e-2)
+    walked = float(np.sum(np.abs(tr["residual"])))
+    assert walked > 0.5  # most of the mass went through the walks
+    big = Pi[:, s] > delta
+    rel = np.abs(pi_hat[big] - Pi[big, s]) / Pi[big, s]
+    assert np.max(rel) < eps_r, np.max(rel)
+    assert np.max(rel) > 1e-6  # not exact: the walks are sampled
+
+
 ALL_PINS = [
     pin_star_example,
     pin_chebyshev_vectors_eigen,
@@ -486,6 +558,10 @@ ALL_PINS = [
     pin_chebypush_without_threshold,
     pin_chebypush_degree_normalized_error,
     pin_chebypush_locality,
+    pin_splitmix64_published_outputs,
+    pin_residual_invariant,
+    pin_alpha_walk_end_distribution,
+    pin_push_rw_accuracy,
 ]
 
 

@@ -92,6 +92,14 @@ def _push_form_drops_compensation(row_ptr, col_idx, s, sets):
     return r
 
 
+def _walk_stops_with_wrong_probability(row_ptr, col_idx, key, j, start, alpha):
+    return PR.__dict__["_orig_walk_terminal"](row_ptr, col_idx, key, j, start, 1.0 - alpha)
+
+
+def _residual_sign_flipped(row_ptr, col_idx, s, alpha, pi_hat):
+    return -PR.__dict__["_orig_residual"](row_ptr, col_idx, s, alpha, pi_hat)
+
+
 MISTAKES = {
     "recurrence sign": ("propagation", "_chebyshev_step", _wrong_sign_step),
     "recurrence factor 2": ("propagation", "_chebyshev_step", _missing_factor_two_step),
@@ -107,6 +115,8 @@ MISTAKES = {
     "ChebyPush pushes nothing": ("push", "selected", _push_without_sign_flip),
     "ChebyPush threshold without degree": ("push", "selected", _threshold_without_degree),
     "Def. 7 without compensation": ("push", "subset_recurrence", _push_form_drops_compensation),
+    "walk stops with probability 1 - alpha": ("bidirectional", "walk_terminal", _walk_stops_with_wrong_probability),
+    "residual sign flipped": ("bidirectional", "residual", _residual_sign_flipped),
 }
 
 
