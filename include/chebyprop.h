@@ -134,6 +134,8 @@ typedef struct {
   int64_t pushes;       /* cp_push: push operations (sum of |S_k|); 0 for the other paths */
   int64_t arcs;         /* arcs the full steps processed: steps * nnz, or for cp_push the
                            sum of vol(S_k) (with CP_Q_STATS / CP_Q_TIMING, else -1) */
+  int64_t walks;        /* cp_push_rw: random walks run (CP_Q_STATS / CP_Q_TIMING, else -1); 0 otherwise */
+  int64_t walk_steps;   /* cp_push_rw: moves made by those walks */
 } cp_info;
 
 typedef struct {
@@ -252,6 +254,33 @@ cp_status cp_propagate(const cp_graph* g, const cp_query* q, int32_t k, int32_t 
 size_t cp_push_workspace_bytes(const cp_graph* g);
 cp_status cp_push(const cp_graph* g, const cp_query* q, double eps_a, double* y, void* ws, size_t ws_bytes,
                   void* stream, cp_info* info);
+
+/* ChebyPush + random walks for SSPPR (Alg. 5, Sec. 5.2).  With
+ * W = 2 (2 eps_r / 3 + 2) ln(n) / (eps_r^2 delta) and r_max = sqrt(alpha) / W
+ * (or the caller's r_max > 0), ChebyPush runs with threshold r_max, then
+ * every node with a non-zero residual r = e_s - alpha^{-1} [I - (1 - alpha)
+ * P] pi^ starts ceil(|r(v)| W) alpha-random walks, each adding r(v) / W_v at
+ * its end node.  The guarantee is Alg. 5's: |pi^(u) - pi_s(u)| < eps_r
+ * pi_s(u) wherever pi_s(u) > delta, with high probability.
+ *   q      CP_PPR only (param = alpha), source, a (output space),
+ *          CP_Q_STATS / CP_Q_TIMING; K by q->kmode with r_max as the
+ *          tolerance (CP_K_PAPER gives the analysis' K = ln(1/r_max) /
+ *          sqrt(alpha)) or K_fixed
+ *   seed   walk j from node v draws SplitMix64 (Steele, Lea & Flood, 2014)
+ *          outputs j * 2^32 + 2 t and j * 2^32 + 2 t + 1 of the stream
+ *          whose seed is output v (caller id) of the stream of `seed`:
+ *          step t stops when (x >> 11) 2^-53 < alpha, else moves to neighbour
+ *          (x' d) >> 64 of the current row in the graph's internal CSR
+ *          order (the caller's order unless the graph was reordered)
+ *   y      device, n doubles, caller ids
+ *   ws     device workspace of cp_push_rw_workspace_bytes(g) bytes
+ *   info   walks and walk_steps as for pushes; step_ms times the push phase
+ * End-node contributions use FP64 atomic adds: results agree run to run up
+ * to rounding.  Errors: CP_EINVAL (not PPR, eps_r, delta or r_max out of
+ * range), otherwise as cp_push. */
+size_t cp_push_rw_workspace_bytes(const cp_graph* g);
+cp_status cp_push_rw(const cp_graph* g, const cp_query* q, double eps_r, double delta, double r_max,
+                     uint64_t seed, double* y, void* ws, size_t ws_bytes, void* stream, cp_info* info);
 
 /* Pick the source-tile width (8, 16, 32 or 64 sources per tile) that runs
  * these nq queries fastest on this graph and remember it for later

@@ -59,18 +59,23 @@ def residual(row_ptr, col_idx, s: int, alpha: float, pi_hat: np.ndarray) -> np.n
     return PR.one_hot(n, s) - (pi_hat - (1.0 - alpha) * (P @ pi_hat)) / alpha
 
 
-def walk_terminal(row_ptr, col_idx, key: int, j: int, start: int, alpha: float) -> int:
-    """End node of the alpha-random walk j of stream ``key`` from ``start``."""
+def walk(row_ptr, col_idx, key: int, j: int, start: int, alpha: float) -> tuple[int, int]:
+    """The alpha-random walk j of stream ``key`` from ``start``: (end node,
+    number of moves)."""
     cur = int(start)
     base = j << 32
     for t in range(MAX_STEPS):
         x = splitmix64(key, base + 2 * t)
         if (x >> 11) * 2.0**-53 < alpha:
-            return cur
+            return cur, t
         p0, p1 = int(row_ptr[cur]), int(row_ptr[cur + 1])
         x2 = splitmix64(key, base + 2 * t + 1)
         cur = int(col_idx[p0 + ((x2 * (p1 - p0)) >> 64)])
-    return cur
+    return cur, MAX_STEPS
+
+
+def walk_terminal(row_ptr, col_idx, key: int, j: int, start: int, alpha: float) -> int:
+    return walk(row_ptr, col_idx, key, j, start, alpha)[0]
 
 
 def push_rw(row_ptr, col_idx, s: int, alpha: float, K: int, eps_r: float, delta: float, seed: int,
@@ -89,17 +94,23 @@ def push_rw(row_ptr, col_idx, s: int, alpha: float, K: int, eps_r: float, delta:
     pi_hat = pi_push.copy()
     counts = np.zeros(n, dtype=np.int64)
     ends = {}
+    steps = 0
+    ceil_margin = np.inf  # distance of |r(v)| W to the integers (diagnostic)
     for v in np.flatnonzero(r != 0.0):
-        Wv = int(math.ceil(abs(r[v]) * W))
+        x = abs(r[v]) * W
+        ceil_margin = min(ceil_margin, x - math.floor(x) if x != math.floor(x) else 0.0,
+                          math.ceil(x) - x if x != math.ceil(x) else 0.0)
+        Wv = int(math.ceil(x))
         counts[v] = Wv
         key = splitmix64(seed, int(v))
         share = r[v] / Wv
         ends[int(v)] = []
         for j in range(Wv):
-            u = walk_terminal(row_ptr, col_idx, key, j, v, alpha)
+            u, t = walk(row_ptr, col_idx, key, j, v, alpha)
+            steps += t
             pi_hat[u] += share
             ends[int(v)].append(u)
     if trace:
         return pi_hat, {"pi_push": pi_push, "residual": r, "walks": counts, "ends": ends, "W": W,
-                        "r_max": r_max}
+                        "r_max": r_max, "steps": steps, "ceil_margin": ceil_margin}
     return pi_hat

@@ -49,7 +49,8 @@ METHODS = {"cheby": 0, "power": CP_Q_PWMETHOD}  # Alg. 3 (ChebyPower) or Alg. 1 
 EXPORTED = [
     "cp_graph_create", "cp_graph_destroy", "cp_graph_get_stats", "cp_coeffs", "cp_choose_K",
     "cp_taylor", "cp_choose_N",
-    "cp_workspace_bytes", "cp_power", "cp_power_batch", "cp_propagate", "cp_push", "cp_push_workspace_bytes", "cp_autotune_batch", "cp_set_batch_width",
+    "cp_workspace_bytes", "cp_power", "cp_power_batch", "cp_propagate", "cp_push", "cp_push_workspace_bytes",
+    "cp_push_rw", "cp_push_rw_workspace_bytes", "cp_autotune_batch", "cp_set_batch_width",
     "cp_status_str", "cp_last_hip_error", "cp_version",
     "cp_server_create", "cp_server_submit", "cp_server_poll", "cp_server_wait", "cp_server_cancel",
     "cp_server_get_stats", "cp_server_destroy",
@@ -82,6 +83,8 @@ class cp_info(ctypes.Structure):
         ("wait_ms", ctypes.c_double),
         ("pushes", ctypes.c_int64),
         ("arcs", ctypes.c_int64),
+        ("walks", ctypes.c_int64),
+        ("walk_steps", ctypes.c_int64),
     ]
 
     def as_dict(self) -> dict:
@@ -163,6 +166,9 @@ def load() -> ctypes.CDLL:
         "cp_power_batch": (i32, [P, i32, ctypes.POINTER(cp_query), i32, P, P, sz, P, ctypes.POINTER(cp_info)]),
         "cp_push": (i32, [P, ctypes.POINTER(cp_query), f64, P, P, sz, P, ctypes.POINTER(cp_info)]),
         "cp_push_workspace_bytes": (sz, [P]),
+        "cp_push_rw": (i32, [P, ctypes.POINTER(cp_query), f64, f64, f64, ctypes.c_uint64, P, P, sz, P,
+                             ctypes.POINTER(cp_info)]),
+        "cp_push_rw_workspace_bytes": (sz, [P]),
         "cp_propagate": (i32, [P, ctypes.POINTER(cp_query), i32, i32, P, P, P, sz, P, ctypes.POINTER(cp_info)]),
         "cp_autotune_batch": (i32, [P, i32, ctypes.POINTER(cp_query), i32, P, P, sz, P, ctypes.POINTER(i32)]),
         "cp_set_batch_width": (i32, [P, i32, i32, i32]),
@@ -284,6 +290,19 @@ def cp_push(handle: int, query: cp_query, eps_a: float, y_ptr: int, ws_ptr: int,
 
 def cp_push_workspace_bytes(handle: int) -> int:
     return int(load().cp_push_workspace_bytes(handle))
+
+
+def cp_push_rw(handle: int, query: cp_query, eps_r: float, delta: float, r_max: float, seed: int, y_ptr: int,
+               ws_ptr: int, ws_bytes: int, stream: int) -> cp_info:
+    info = cp_info()
+    _check(load().cp_push_rw(handle, ctypes.byref(query), float(eps_r), float(delta), float(r_max),
+                             int(seed) & ((1 << 64) - 1), y_ptr, ws_ptr, ws_bytes, stream, ctypes.byref(info)),
+           "cp_push_rw")
+    return info
+
+
+def cp_push_rw_workspace_bytes(handle: int) -> int:
+    return int(load().cp_push_rw_workspace_bytes(handle))
 
 
 def cp_propagate(handle: int, query: cp_query, k: int, prec: int, X_ptr: int, Z_ptr: int, ws_ptr: int,
@@ -418,6 +437,21 @@ class Graph:
         st = stream if stream is not None else torch.cuda.current_stream(self.device).cuda_stream
         q = make_query(kind, param, source, tol, kmode, K, flags, "cheby", a)
         info = cp_push(self.handle, q, eps_a, y.data_ptr(), ws.data_ptr(), nbytes, st)
+        return Result(y, info.as_dict())
+
+    def push_rw(self, alpha: float, source: int, eps_r: float, delta: float, seed: int, r_max: float = 0.0,
+                kmode: str = "paper", K: int = 0, a: float = 0.0, flags: int = 0, y=None, stream=None) -> Result:
+        """ChebyPush + random walks for SSPPR (Alg. 5): FP64 result in caller ids."""
+        torch = self.torch
+        if y is None:
+            y = torch.empty(self.n, dtype=torch.float64, device=self.device)
+        nbytes = cp_push_rw_workspace_bytes(self.handle)
+        ws = self._push_ws
+        if ws is None or ws.numel() < nbytes:
+            ws = self._push_ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        st = stream if stream is not None else torch.cuda.current_stream(self.device).cuda_stream
+        q = make_query("ppr", alpha, source, 0.5, kmode, K, flags, "cheby", a)
+        info = cp_push_rw(self.handle, q, eps_r, delta, r_max, seed, y.data_ptr(), ws.data_ptr(), nbytes, st)
         return Result(y, info.as_dict())
 
     def propagate(self, X, kind: str, param: float, a: float = 0.0, tol: float = 1e-6, kmode: str = "tail",

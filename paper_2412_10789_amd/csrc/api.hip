@@ -737,6 +737,8 @@ cp_status cp_power(const cp_graph* g, const cp_query* q, int32_t prec, void* y, 
     info->wait_ms = NAN;
     info->pushes = 0;
     info->arcs = (int64_t)(top - 1) * g->nnz;
+    info->walks = 0;
+    info->walk_steps = 0;
   }
   if (stats || timing) {
     CP_HIP_C(hipStreamSynchronize(st));
@@ -878,6 +880,8 @@ cp_status power_batch_bw(cp_graph* g, int32_t nq, const cp_query* q, int32_t pre
       infos[j].wait_ms = NAN;
       infos[j].pushes = 0;
       infos[j].arcs = (int64_t)(P[j].top - 1) * g->nnz;
+      infos[j].walks = 0;
+      infos[j].walk_steps = 0;
     }
   cleanup();
 #undef CP_HIP_B
@@ -1024,6 +1028,8 @@ cp_status cp_propagate(const cp_graph* g, const cp_query* q, int32_t k, int32_t 
     info->wait_ms = NAN;
     info->pushes = 0;
     info->arcs = (int64_t)top * g->nnz;
+    info->walks = 0;
+    info->walk_steps = 0;
   }
   cleanup();
 #undef CP_HIP_P

@@ -421,24 +421,223 @@ __global__ void push_sum_kernel(double* sums, int nb) {
   }
 }
 
-}  // namespace
-}  // namespace cp
+__global__ void rw_zero_counts_kernel(long long* c) {
+  if (threadIdx.x < 8) c[threadIdx.x] = 0;
+}
 
-using namespace cp;
+__global__ void rw_force_dense_kernel(long long* flag) {
+  if (threadIdx.x == 0) *flag = 1;
+}
 
-extern "C" {
+// ---------------------------------------------------------------- Alg. 5
 
-size_t cp_push_workspace_bytes(const cp_graph* g) { return g ? push_layout(g).total : 0; }
+// SplitMix64 (Steele, Lea & Flood, 2014): output c (0-based) of the stream
+// whose state starts at `seed`.
+__device__ __forceinline__ uint64_t splitmix64(uint64_t seed, uint64_t c) {
+  uint64_t z = seed + (c + 1ull) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
 
-cp_status cp_push(const cp_graph* g, const cp_query* q, double eps_a, double* y, void* ws, size_t ws_bytes,
-                  void* stream, cp_info* info) {
-  if (!g || !q || !y || !(eps_a >= 0.0 && std::isfinite(eps_a))) return CP_EINVAL;
-  if (q->flags & CP_Q_PWMETHOD) return CP_EINVAL;
-  QueryPlan qp;
-  cp_status rc = plan_query(g, q, kDefaultKMax, &qp);
-  if (rc != CP_OK) return rc;
-  const PushLayout L = push_layout(g);
-  if (!ws || ws_bytes < L.total || (reinterpret_cast<uintptr_t>(ws) & 255)) return CP_EWORKSPACE;
+constexpr int64_t kMaxWalkSteps = 1ll << 20;
+
+// pv(u) = pi^(u) / d_u written as (1 / d_u) * pi^(u), the entry of P times
+// pi^, for every node (the pull kernels then form P pi^).
+struct ScaleArgs {
+  int64_t n;
+  const int32_t* deg;
+  const double* y;
+  double* pv;
+  double* acc;  // zeroed: receives P pi^
+};
+
+__global__ void __launch_bounds__(kThreads) rw_scale_kernel(ScaleArgs a) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < a.n; v += stride) {
+    const int32_t d = a.deg[v];
+    a.pv[v] = d > 0 ? (1.0 / (double)d) * a.y[v] : 0.0;
+    a.acc[v] = 0.0;
+  }
+}
+
+// r(v) = [v = s] - (pi^(v) - (1 - alpha) (P pi^)(v)) / alpha, the walk count
+// W_v = ceil(|r(v)| W) and its per-block sums (nodes, walks).
+struct ResidualArgs {
+  int64_t n;
+  int64_t s;
+  double alpha, W;
+  const double* y;
+  const double* acc;
+  double* res;
+  long long* wv;
+  int32_t* bnodes;
+  long long* bwalks;
+};
+
+__global__ void __launch_bounds__(kThreads) rw_residual_kernel(ResidualArgs a) {
+  __shared__ int red[kThreads / 64];
+  __shared__ long long redl[kThreads / 64];
+  int64_t lo, hi;
+  block_range(a.n, lo, hi);
+  int nodes = 0;
+  long long walks = 0;
+  for (int64_t v = lo + threadIdx.x; v < hi; v += kThreads) {
+    const double r = (v == a.s ? 1.0 : 0.0) - (a.y[v] - (1.0 - a.alpha) * a.acc[v]) / a.alpha;
+    a.res[v] = r;
+    long long c = 0;
+    if (r != 0.0) {
+      c = (long long)ceil(fabs(r) * a.W);
+      ++nodes;
+    }
+    a.wv[v] = c;
+    walks += c;
+  }
+  const int tn = block_sum_int(nodes, red);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) walks += __shfl_xor(walks, o, 64);
+  if ((threadIdx.x & 63) == 0) redl[threadIdx.x >> 6] = walks;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    long long t = 0;
+    for (int q = 0; q < kThreads / 64; ++q) t += redl[q];
+    a.bnodes[blockIdx.x] = tn;
+    a.bwalks[blockIdx.x] = t;
+  }
+}
+
+// Start nodes in node order with the exclusive prefix of their walk counts.
+struct WalkListArgs {
+  int64_t n;
+  const long long* wv;
+  const int32_t* bnodes;
+  const long long* bwalks;
+  int32_t* starts;
+  long long* first;   // first walk index of each start node
+  long long* nstart;  // number of start nodes
+  long long* nwalks;  // total walks
+};
+
+__global__ void __launch_bounds__(kThreads) rw_list_kernel(WalkListArgs a) {
+  __shared__ int wcnt[kThreads / 64];
+  __shared__ int red[kThreads / 64];
+  __shared__ long long redl[kThreads / 64];
+  __shared__ long long wscan[kThreads];
+  int p0 = 0;
+  long long q0 = 0;
+  for (int b = threadIdx.x; b < (int)blockIdx.x; b += kThreads) {
+    p0 += a.bnodes[b];
+    q0 += a.bwalks[b];
+  }
+  const int node_off = block_sum_int(p0, red);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) q0 += __shfl_xor(q0, o, 64);
+  if ((threadIdx.x & 63) == 0) redl[threadIdx.x >> 6] = q0;
+  __syncthreads();
+  long long walk_off = 0;
+  for (int q = 0; q < kThreads / 64; ++q) walk_off += redl[q];
+  __syncthreads();
+  if (threadIdx.x == 0 && blockIdx.x == gridDim.x - 1) {
+    *a.nstart = (long long)node_off + a.bnodes[blockIdx.x];
+    *a.nwalks = walk_off + a.bwalks[blockIdx.x];
+  }
+  int64_t lo, hi;
+  block_range(a.n, lo, hi);
+  int64_t base = node_off;
+  for (int64_t v0 = lo; v0 < hi; v0 += kThreads) {  // rounds are uniform across the block
+    const int64_t v = v0 + threadIdx.x;
+    const long long c = v < hi ? a.wv[v] : 0;
+    // inclusive scan of the round's walk counts in thread order
+    wscan[threadIdx.x] = c;
+    __syncthreads();
+    for (int step = 1; step < kThreads; step <<= 1) {
+      const long long add = threadIdx.x >= step ? wscan[threadIdx.x - step] : 0;
+      __syncthreads();
+      wscan[threadIdx.x] += add;
+      __syncthreads();
+    }
+    const long long incl = wscan[threadIdx.x], round_total = wscan[kThreads - 1];
+    const int64_t pos = block_place(c > 0, wcnt, base);
+    if (pos >= 0) {
+      a.starts[pos] = (int32_t)v;
+      a.first[pos] = walk_off + incl - c;
+    }
+    walk_off += round_total;
+    __syncthreads();
+  }
+}
+
+struct WalkArgs {
+  const int64_t* row_ptr;
+  const int32_t* col_idx;
+  const int32_t* perm;    // internal -> caller id (the walk streams are keyed by caller id), or null
+  const int32_t* starts;
+  const long long* first;
+  const long long* nstart;
+  const long long* nwalks;
+  const long long* wv;
+  const double* res;
+  double alpha;
+  uint64_t seed;
+  double* y;
+  long long* steps;
+};
+
+__global__ void __launch_bounds__(kThreads) rw_walk_kernel(WalkArgs a) {
+  const long long T = *a.nwalks, S = *a.nstart;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  long long my_steps = 0;
+  for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < T; t += stride) {
+    long long lo = 0, hi = S - 1;  // last start whose first walk is <= t
+    while (lo < hi) {
+      const long long mid = (lo + hi + 1) >> 1;
+      if (a.first[mid] <= t) lo = mid; else hi = mid - 1;
+    }
+    const int32_t v = a.starts[lo];
+    const uint64_t j = (uint64_t)(t - a.first[lo]);
+    const uint64_t key = splitmix64(a.seed, (uint64_t)(a.perm ? a.perm[v] : v));
+    int32_t cur = v;
+    for (int64_t step = 0; step < kMaxWalkSteps; ++step) {
+      const uint64_t x = splitmix64(key, (j << 32) + 2ull * (uint64_t)step);
+      if ((double)(x >> 11) * 0x1.0p-53 < a.alpha) break;
+      const int64_t p0 = a.row_ptr[cur], d = a.row_ptr[cur + 1] - p0;
+      const uint64_t x2 = splitmix64(key, (j << 32) + 2ull * (uint64_t)step + 1ull);
+      cur = a.col_idx[p0 + (int64_t)__umul64hi(x2, (uint64_t)d)];
+      ++my_steps;
+    }
+    unsafeAtomicAdd(a.y + cur, a.res[v] / (double)a.wv[v]);
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) my_steps += __shfl_xor(my_steps, o, 64);
+  if ((threadIdx.x & 63) == 0 && my_steps) atomicAdd((unsigned long long*)a.steps, (unsigned long long)my_steps);
+}
+
+struct RwLayout {
+  PushLayout push;
+  size_t res, wv, starts, first, bnodes, bwalks, counts, total;
+};
+
+RwLayout rw_layout(const cp_graph* g) {
+  auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+  const size_t n = (size_t)g->n;
+  RwLayout L{};
+  L.push = push_layout(g);
+  size_t off = L.push.total;
+  L.res = off; off += al(n * 8);
+  L.wv = off; off += al(n * 8);
+  L.starts = off; off += al(n * 4);
+  L.first = off; off += al(n * 8);
+  L.bnodes = off; off += al((size_t)kRangeBlocks * 4);
+  L.bwalks = off; off += al((size_t)kRangeBlocks * 8);
+  L.counts = off; off += al(8 * 8);  // [0] start nodes, [1] walks, [2] walk steps
+  L.total = off;
+  return L;
+}
+
+// The push phase of Alg. 4 into the workspace: y (internal order, paper
+// space) and the push counters.  Launches only; errors as hipError_t.
+hipError_t push_phase(const cp_graph* g, const QueryPlan& qp, double eps_a, char* w, const PushLayout& L,
+                      hipStream_t st) {
   const int32_t K = qp.K;
   const std::vector<double>& c = qp.c;
   // eps_k = eps_a / (4 K sum_{l=k}^{K} |c_l|), Alg. 4 (a zero tail: nothing
@@ -451,28 +650,8 @@ cp_status cp_push(const cp_graph* g, const cp_query* q, double eps_a, double* y,
       eps[l] = tail > 0.0 ? eps_a / (4.0 * K * tail) : std::numeric_limits<double>::infinity();
     }
   }
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  char* w = static_cast<char*>(ws);
-  const bool stats = q->flags & CP_Q_STATS;
-  const bool timing = q->flags & CP_Q_TIMING;
-  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
-  auto cleanup = [&] {
-    for (hipEvent_t e : ev)
-      if (e) (void)hipEventDestroy(e);
-  };
-#define CP_HIP_U(call)        \
-  do {                        \
-    hipError_t e_ = (call);   \
-    if (e_ != hipSuccess) {   \
-      set_hip_error(e_);      \
-      cleanup();              \
-      return CP_EHIP;         \
-    }                         \
-  } while (0)
-  if (timing)
-    for (auto& e : ev) CP_HIP_U(hipEventCreate(&e));
-  if (timing) CP_HIP_U(hipEventRecord(ev[0], st));
-  CP_HIP_U(launch_zero(w, L.sums, st));
+  hipError_t e = launch_zero(w, L.sums, st);
+  if (e != hipSuccess) return e;
   double* rbuf[2] = {reinterpret_cast<double*>(w + L.r[0]), reinterpret_cast<double*>(w + L.r[1])};
   double* yv = reinterpret_cast<double*>(w + L.y);
   double* pv = reinterpret_cast<double*>(w + L.pv);
@@ -487,63 +666,115 @@ cp_status cp_push(const cp_graph* g, const cp_query* q, double eps_a, double* y,
   int32_t* bc = reinterpret_cast<int32_t*>(w + L.bcount);
   long long* counts = reinterpret_cast<long long*>(w + L.counts);
   const dim3 rb(kRangeBlocks), eb(kEdgeBlocks), tb(kThreads);
-  hipLaunchKernelGGL(push_degree_kernel, rb, tb, 0, st, DegreeArgs{g->row_ptr, g->n, deg});
-  CP_HIP_U(hipGetLastError());
+#define CP_LAUNCH(...)                       \
+  do {                                       \
+    hipLaunchKernelGGL(__VA_ARGS__);         \
+    const hipError_t e_ = hipGetLastError(); \
+    if (e_ != hipSuccess) return e_;         \
+  } while (0)
+  CP_LAUNCH(push_degree_kernel, rb, tb, 0, st, DegreeArgs{g->row_ptr, g->n, deg});
   {  // every row with an edge, short and long apart (pulled by dense iterations)
     const ListArgs la{g->n, nullptr, deg, 0, 1, bc + kRangeBlocks, bc + 2 * kRangeBlocks, ashort, along,
                       counts + 6, counts + 7, counts + 5, 1};
-    hipLaunchKernelGGL(push_count_kernel, rb, tb, 0, st, la);
-    CP_HIP_U(hipGetLastError());
-    hipLaunchKernelGGL(push_list_kernel, rb, tb, 0, st, la);
-    CP_HIP_U(hipGetLastError());
+    CP_LAUNCH(push_count_kernel, rb, tb, 0, st, la);
+    CP_LAUNCH(push_list_kernel, rb, tb, 0, st, la);
   }
-  hipLaunchKernelGGL(push_seed_kernel, dim3(1), tb, 0, st,
-                     SeedArgs{g->row_ptr, g->col_idx, qp.s_int, c[0], rbuf[0], rbuf[1], yv});
-  CP_HIP_U(hipGetLastError());
-  if (timing) CP_HIP_U(hipEventRecord(ev[1], st));
+  CP_LAUNCH(push_seed_kernel, dim3(1), tb, 0, st,
+            SeedArgs{g->row_ptr, g->col_idx, qp.s_int, c[0], rbuf[0], rbuf[1], yv});
   int cur = 0;  // rbuf[cur] is r_cur
   for (int32_t k = 1; k < K; ++k) {
     const int nxt = cur ^ 1;
-    hipLaunchKernelGGL(push_select_kernel, rb, tb, 0, st,
-                       SelectArgs{g->n, deg, rbuf[cur], yv, pv, sel, k, eps[k], c[k], bc});
-    CP_HIP_U(hipGetLastError());
+    CP_LAUNCH(push_select_kernel, rb, tb, 0, st, SelectArgs{g->n, deg, rbuf[cur], yv, pv, sel, k, eps[k], c[k], bc});
     const ListArgs ls{g->n, sel, deg, k, 0, bc, bc + kRangeBlocks, slist, slist, counts + 0, counts + 0,
                       counts + 5, 0};
-    hipLaunchKernelGGL(push_list_kernel, rb, tb, 0, st, ls);
-    CP_HIP_U(hipGetLastError());
-    hipLaunchKernelGGL(push_mark_kernel, eb, tb, 0, st,
-                       MarkArgs{g->row_ptr, g->col_idx, slist, counts + 0, mark, k, counts + 3, counts + 4,
-                                counts + 5});
-    CP_HIP_U(hipGetLastError());
+    CP_LAUNCH(push_list_kernel, rb, tb, 0, st, ls);
+    CP_LAUNCH(push_mark_kernel, eb, tb, 0, st,
+              MarkArgs{g->row_ptr, g->col_idx, slist, counts + 0, mark, k, counts + 3, counts + 4, counts + 5});
     const ListArgs lt{g->n, mark, deg, k, 1, bc + kRangeBlocks, bc + 2 * kRangeBlocks, tshort, tlong,
                       counts + 1, counts + 2, counts + 5, 0};
-    hipLaunchKernelGGL(push_count_kernel, rb, tb, 0, st, lt);
-    CP_HIP_U(hipGetLastError());
-    hipLaunchKernelGGL(push_list_kernel, rb, tb, 0, st, lt);
-    CP_HIP_U(hipGetLastError());
-    hipLaunchKernelGGL(push_pull_short_kernel, eb, tb, 0, st,
-                       PullArgs{g->row_ptr, g->col_idx, pv, rbuf[nxt], tshort, counts + 1, ashort, counts + 6,
-                                counts + 5});
-    CP_HIP_U(hipGetLastError());
-    hipLaunchKernelGGL(push_pull_long_kernel, eb, tb, 0, st,
-                       PullArgs{g->row_ptr, g->col_idx, pv, rbuf[nxt], tlong, counts + 2, along, counts + 7,
-                                counts + 5});
-    CP_HIP_U(hipGetLastError());
+    CP_LAUNCH(push_count_kernel, rb, tb, 0, st, lt);
+    CP_LAUNCH(push_list_kernel, rb, tb, 0, st, lt);
+    CP_LAUNCH(push_pull_short_kernel, eb, tb, 0, st,
+              PullArgs{g->row_ptr, g->col_idx, pv, rbuf[nxt], tshort, counts + 1, ashort, counts + 6, counts + 5});
+    CP_LAUNCH(push_pull_long_kernel, eb, tb, 0, st,
+              PullArgs{g->row_ptr, g->col_idx, pv, rbuf[nxt], tlong, counts + 2, along, counts + 7, counts + 5});
     cur = nxt;
   }
-  if (timing) CP_HIP_U(hipEventRecord(ev[2], st));
+  return hipSuccess;
+}
+
+// Alg. 5's second phase on top of push_phase's y: the residual (one pull
+// over every row), the walk list, the walks.
+hipError_t rw_phase(const cp_graph* g, const QueryPlan& qp, double alpha, double W, uint64_t seed, char* w,
+                    const RwLayout& L, hipStream_t st) {
+  const PushLayout& P = L.push;
+  double* yv = reinterpret_cast<double*>(w + P.y);
+  double* pv = reinterpret_cast<double*>(w + P.pv);
+  double* acc = reinterpret_cast<double*>(w + P.r[0]);
+  int32_t* deg = reinterpret_cast<int32_t*>(w + P.deg);
+  long long* pc = reinterpret_cast<long long*>(w + P.counts);
+  long long* rc = reinterpret_cast<long long*>(w + L.counts);
+  const dim3 rb(kRangeBlocks), eb(kEdgeBlocks), tb(kThreads);
+  CP_LAUNCH(rw_zero_counts_kernel, dim3(1), dim3(64), 0, st, rc);
+  CP_LAUNCH(rw_scale_kernel, rb, tb, 0, st, ScaleArgs{g->n, deg, yv, pv, acc});
+  CP_LAUNCH(rw_force_dense_kernel, dim3(1), dim3(64), 0, st, pc + 5);
+  CP_LAUNCH(push_pull_short_kernel, eb, tb, 0, st,
+            PullArgs{g->row_ptr, g->col_idx, pv, acc, nullptr, nullptr,
+                     reinterpret_cast<const int32_t*>(w + P.ashort), pc + 6, pc + 5});
+  CP_LAUNCH(push_pull_long_kernel, eb, tb, 0, st,
+            PullArgs{g->row_ptr, g->col_idx, pv, acc, nullptr, nullptr,
+                     reinterpret_cast<const int32_t*>(w + P.along), pc + 7, pc + 5});
+  double* res = reinterpret_cast<double*>(w + L.res);
+  long long* wv = reinterpret_cast<long long*>(w + L.wv);
+  int32_t* bnodes = reinterpret_cast<int32_t*>(w + L.bnodes);
+  long long* bwalks = reinterpret_cast<long long*>(w + L.bwalks);
+  CP_LAUNCH(rw_residual_kernel, rb, tb, 0, st,
+            ResidualArgs{g->n, qp.s_int, alpha, W, yv, acc, res, wv, bnodes, bwalks});
+  int32_t* starts = reinterpret_cast<int32_t*>(w + L.starts);
+  long long* first = reinterpret_cast<long long*>(w + L.first);
+  CP_LAUNCH(rw_list_kernel, rb, tb, 0, st, WalkListArgs{g->n, wv, bnodes, bwalks, starts, first, rc + 0, rc + 1});
+  CP_LAUNCH(rw_walk_kernel, dim3(4096), tb, 0, st,
+            WalkArgs{g->row_ptr, g->col_idx, g->perm, starts, first, rc + 0, rc + 1, wv, res, alpha, seed, yv,
+                     rc + 2});
+  return hipSuccess;
+}
+#undef CP_LAUNCH
+
+}  // namespace
+}  // namespace cp
+
+using namespace cp;
+
+extern "C" {
+
+size_t cp_push_workspace_bytes(const cp_graph* g) { return g ? push_layout(g).total : 0; }
+
+size_t cp_push_rw_workspace_bytes(const cp_graph* g) { return g ? rw_layout(g).total : 0; }
+
+}  // extern "C"
+
+namespace {
+
+// Shared tail of cp_push and cp_push_rw: output in caller ids (and the
+// Def. 8 space), optional mass, counters, timing.
+cp_status push_finish(const cp_graph* g, const cp_query* q, const QueryPlan& qp, char* w, const PushLayout& L,
+                      const long long* rw_counts, double* y, hipStream_t st, hipEvent_t* ev, cp_info* info) {
+  const bool stats = q->flags & CP_Q_STATS;
+  const bool timing = q->flags & CP_Q_TIMING;
   double* sums = reinterpret_cast<double*>(w + L.sums);
+  const double* yv = reinterpret_cast<const double*>(w + L.y);
   PushFinalArgs fa{g->row_ptr, g->perm, g->n, yv, y, -q->a, qp.oscale, stats ? sums : nullptr};
-  hipLaunchKernelGGL(push_final_kernel, rb, tb, 0, st, fa);
-  CP_HIP_U(hipGetLastError());
-  if (stats) {
+  hipLaunchKernelGGL(push_final_kernel, dim3(kRangeBlocks), dim3(kThreads), 0, st, fa);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess && stats) {
     hipLaunchKernelGGL(push_sum_kernel, dim3(1), dim3(64), 0, st, sums, kRangeBlocks);
-    CP_HIP_U(hipGetLastError());
+    e = hipGetLastError();
   }
-  if (timing) CP_HIP_U(hipEventRecord(ev[3], st));
+  if (e == hipSuccess && timing) e = hipEventRecord(ev[3], st);
+  if (e != hipSuccess) { set_hip_error(e); return CP_EHIP; }
   if (info) {
-    info->K = K;
-    info->steps = K - 1;
+    info->K = qp.K;
+    info->steps = qp.K - 1;
     info->tail = qp.tail;
     info->tail_bound_l1 = NAN;  // ChebyPush's guarantee is the degree-normalised eps_a (Thm. 4)
     info->mass = NAN;
@@ -553,31 +784,106 @@ cp_status cp_push(const cp_graph* g, const cp_query* q, double eps_a, double* y,
     info->wait_ms = NAN;
     info->pushes = -1;
     info->arcs = -1;
+    info->walks = rw_counts ? -1 : 0;
+    info->walk_steps = rw_counts ? -1 : 0;
   }
-  if (stats || timing) {
-    CP_HIP_U(hipStreamSynchronize(st));
-    long long host[kCounts] = {0};
-    CP_HIP_U(hipMemcpy(host, counts, sizeof(host), hipMemcpyDeviceToHost));
-    if (info) {
-      info->pushes = host[3];
-      info->arcs = host[4];
-      if (stats) {
-        double m = 0;
-        CP_HIP_U(hipMemcpy(&m, sums, sizeof(double), hipMemcpyDeviceToHost));
-        info->mass = m;
-      }
-      if (timing) {
-        float ms = 0;
-        CP_HIP_U(hipEventElapsedTime(&ms, ev[0], ev[3]));
-        info->elapsed_ms = ms;
-        CP_HIP_U(hipEventElapsedTime(&ms, ev[1], ev[2]));
-        info->step_ms = ms;
-      }
+  if (!(stats || timing)) return CP_OK;
+  e = hipStreamSynchronize(st);
+  long long host[kCounts] = {0}, rwh[8] = {0};
+  if (e == hipSuccess) e = hipMemcpy(host, w + L.counts, sizeof(host), hipMemcpyDeviceToHost);
+  if (e == hipSuccess && rw_counts) e = hipMemcpy(rwh, rw_counts, sizeof(rwh), hipMemcpyDeviceToHost);
+  double m = NAN;
+  if (e == hipSuccess && stats) e = hipMemcpy(&m, sums, sizeof(double), hipMemcpyDeviceToHost);
+  float ms_all = NAN, ms_loop = NAN;
+  if (e == hipSuccess && timing) e = hipEventElapsedTime(&ms_all, ev[0], ev[3]);
+  if (e == hipSuccess && timing) e = hipEventElapsedTime(&ms_loop, ev[1], ev[2]);
+  if (e != hipSuccess) { set_hip_error(e); return CP_EHIP; }
+  if (info) {
+    info->pushes = host[3];
+    info->arcs = host[4];
+    if (rw_counts) {
+      info->walks = rwh[1];
+      info->walk_steps = rwh[2];
+    }
+    if (stats) info->mass = m;
+    if (timing) {
+      info->elapsed_ms = ms_all;
+      info->step_ms = ms_loop;
     }
   }
-  cleanup();
-#undef CP_HIP_U
   return CP_OK;
+}
+
+struct Events {
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  ~Events() {
+    for (hipEvent_t e : ev)
+      if (e) (void)hipEventDestroy(e);
+  }
+  hipError_t create() {
+    for (auto& e : ev) {
+      const hipError_t x = hipEventCreate(&e);
+      if (x != hipSuccess) return x;
+    }
+    return hipSuccess;
+  }
+};
+
+}  // namespace
+
+extern "C" {
+
+cp_status cp_push(const cp_graph* g, const cp_query* q, double eps_a, double* y, void* ws, size_t ws_bytes,
+                  void* stream, cp_info* info) {
+  if (!g || !q || !y || !(eps_a >= 0.0 && std::isfinite(eps_a))) return CP_EINVAL;
+  if (q->flags & CP_Q_PWMETHOD) return CP_EINVAL;
+  QueryPlan qp;
+  cp_status rc = plan_query(g, q, kDefaultKMax, &qp);
+  if (rc != CP_OK) return rc;
+  const PushLayout L = push_layout(g);
+  if (!ws || ws_bytes < L.total || (reinterpret_cast<uintptr_t>(ws) & 255)) return CP_EWORKSPACE;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  char* w = static_cast<char*>(ws);
+  const bool timing = q->flags & CP_Q_TIMING;
+  Events E;
+  hipError_t e = timing ? E.create() : hipSuccess;
+  if (e == hipSuccess && timing) e = hipEventRecord(E.ev[0], st);
+  if (e == hipSuccess && timing) e = hipEventRecord(E.ev[1], st);
+  if (e == hipSuccess) e = push_phase(g, qp, eps_a, w, L, st);
+  if (e == hipSuccess && timing) e = hipEventRecord(E.ev[2], st);
+  if (e != hipSuccess) { set_hip_error(e); return CP_EHIP; }
+  return push_finish(g, q, qp, w, L, nullptr, y, st, E.ev, info);
+}
+
+cp_status cp_push_rw(const cp_graph* g, const cp_query* q, double eps_r, double delta, double r_max,
+                     uint64_t seed, double* y, void* ws, size_t ws_bytes, void* stream, cp_info* info) {
+  if (!g || !q || !y || q->kind != CP_PPR || (q->flags & CP_Q_PWMETHOD)) return CP_EINVAL;
+  if (!(eps_r > 0.0 && std::isfinite(eps_r)) || !(delta > 0.0 && delta < 1.0) || !(r_max >= 0.0)) return CP_EINVAL;
+  const double alpha = q->param;
+  if (!(alpha > 0.0 && alpha < 1.0)) return CP_EINVAL;
+  // W and r_max of Alg. 5 (log read as natural); r_max > 0 overrides
+  const double W = 2.0 * (2.0 * eps_r / 3.0 + 2.0) * std::log((double)g->n) / (eps_r * eps_r * delta);
+  if (!(W >= 1.0 && W < 9.0e18)) return CP_EINVAL;
+  const double rmax = r_max > 0.0 ? r_max : std::sqrt(alpha) / W;
+  cp_query qk = *q;
+  qk.tol = std::min(rmax, 0.5);  // the truncation rules read the threshold as their tolerance
+  QueryPlan qp;
+  cp_status rc = plan_query(g, &qk, kDefaultKMax, &qp);
+  if (rc != CP_OK) return rc;
+  const RwLayout L = rw_layout(g);
+  if (!ws || ws_bytes < L.total || (reinterpret_cast<uintptr_t>(ws) & 255)) return CP_EWORKSPACE;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  char* w = static_cast<char*>(ws);
+  const bool timing = q->flags & CP_Q_TIMING;
+  Events E;
+  hipError_t e = timing ? E.create() : hipSuccess;
+  if (e == hipSuccess && timing) e = hipEventRecord(E.ev[0], st);
+  if (e == hipSuccess && timing) e = hipEventRecord(E.ev[1], st);
+  if (e == hipSuccess) e = push_phase(g, qp, rmax, w, L.push, st);
+  if (e == hipSuccess && timing) e = hipEventRecord(E.ev[2], st);
+  if (e == hipSuccess) e = rw_phase(g, qp, alpha, W, seed, w, L, st);
+  if (e != hipSuccess) { set_hip_error(e); return CP_EHIP; }
+  return push_finish(g, q, qp, w, L.push, reinterpret_cast<const long long*>(w + L.counts), y, st, E.ev, info);
 }
 
 }  // extern "C"

@@ -96,6 +96,8 @@ void fill_info(const Ticket& t, cp_info* info) {
   info->wait_ms = t.state >= kRunning ? ms_between(t.t_submit, t.t_admit) : NAN;
   info->pushes = 0;
   info->arcs = 0;
+  info->walks = 0;
+  info->walk_steps = 0;
 }
 
 }  // namespace

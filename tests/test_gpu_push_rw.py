@@ -1,0 +1,123 @@
+"""ChebyPush + random walks (Alg. 5) on the GPU (cp_push_rw through the C
+ABI) against the oracle's Alg. 5.
+
+Both sides draw the walks from their own SplitMix64 (same published
+definition, same counters), so on graphs kept in the caller's node order
+the walks are identical: same number of walks, same number of moves, same
+end nodes.  The estimates then differ only in summation order; a single
+different walk would move some entry by about 1/W, far above the
+tolerance.  The residual's walk counts ceil(|r(v)| W) are integer decisions
+taken in FP64 on both sides: each case checks first that no |r(v)| W sits
+on an integer to rounding (oracle diagnostic)."""
+
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from gpu_util import gpu_graph, require_gpu
+from oracle import bidirectional as BI
+from oracle import propagation as PR
+from oracle import truncation as T
+
+pytestmark = pytest.mark.gpu
+
+
+def _case(*a):
+    print("CASE", *a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def torch():
+    return require_gpu()
+
+
+def _check(G, g, s, alpha, eps_r, delta, seed, r_max, K):
+    """Identical walks unless some |r(v)| W sits on an integer to rounding
+    (then only the walk total may differ, by at most the number of such
+    nodes, and the exact comparison is skipped).  Returns (result, trace,
+    compared exactly)."""
+    ref, tr = BI.push_rw(g.row_ptr, g.col_idx, s, alpha, K, eps_r, delta, seed, trace=True, r_max=r_max)
+    r = G.push_rw(alpha, s, eps_r, delta, seed, r_max=r_max, kmode="fixed", K=K, flags=1)
+    if tr["ceil_margin"] <= 1e-7:
+        assert abs(r.info["walks"] - int(tr["walks"].sum())) <= int(np.count_nonzero(tr["walks"]))
+        return r, tr, False
+    assert r.info["walks"] == int(tr["walks"].sum())
+    assert r.info["walk_steps"] == tr["steps"]
+    y = r.y.cpu().numpy()
+    share = 1.0 / tr["W"]
+    assert np.max(np.abs(y - ref)) <= 1e-6 * share, (np.max(np.abs(y - ref)), share)
+    return r, tr, True
+
+
+def test_tiny_graphs_identical_walks(torch):
+    import pins
+
+    exact_cases = 0
+    for g in pins.tiny_graphs():
+        G = gpu_graph(g)
+        s = int(np.flatnonzero(g.degrees > 0)[1])
+        for alpha, K, r_max, seed in ((0.2, 4, 1e-2, 3), (0.15, 8, 1e-3, 11)):
+            _case("rw-tiny", g.name, alpha, K, r_max)
+            exact_cases += _check(G, g, s, alpha, 0.3, 1.0 / g.n, seed, r_max, K)[2]
+    assert exact_cases >= 6  # the symmetric star and path can tie
+
+
+def test_config1_walks_and_accuracy(torch):
+    """n=20,000 Chung-Lu: identical walks with a threshold that leaves mass to
+    the walks, and Alg. 5's guarantee against the exact vector."""
+    g = synth.chung_lu(20_000, 100_000, 2.5, seed=1)
+    P = PR.transition_matrix(g.row_ptr, g.col_idx)
+    G = gpu_graph(g)
+    alpha, eps_r = 0.2, 0.5
+    delta = 1.0 / g.n
+    for s in synth.sources(g, 2, seed=21):
+        s = int(s)
+        _case("rw-config1", s)
+        r, tr, exact = _check(G, g, s, alpha, eps_r, delta, 99, 2e-4, 6)
+        assert exact and tr["walks"].sum() > 1000
+        exact = PR.ground_truth(P, s, "ppr", alpha)
+        y = r.y.cpu().numpy()
+        big = exact > delta
+        assert np.max(np.abs(y[big] - exact[big]) / exact[big]) < eps_r
+
+
+def test_paper_threshold_and_reordered_layout(torch):
+    """Alg. 5's own r_max = sqrt(alpha) / W and K = ln(1/r_max) / sqrt(alpha)
+    on a 60k power-law graph in degree order (walks then follow the internal
+    neighbour order, so only the guarantee is compared)."""
+    g = synth.chung_lu(60_000, 400_000, 2.2, seed=21)
+    P = PR.transition_matrix(g.row_ptr, g.col_idx)
+    G = gpu_graph(g, reorder=True)
+    alpha, eps_r = 0.2, 0.5
+    delta = 1.0 / g.n
+    s = int(synth.sources(g, 1, seed=5)[0])
+    _case("rw-paper")
+    r = G.push_rw(alpha, s, eps_r, delta, 5, flags=1)
+    W = BI.walk_budget(g.n, eps_r, delta)
+    assert r.info["K"] == T.choose_K("ppr", alpha, math.sqrt(alpha) / W, mode="paper")
+    exact = PR.ground_truth(P, s, "ppr", alpha)
+    y = r.y.cpu().numpy()
+    big = exact > delta
+    assert np.max(np.abs(y[big] - exact[big]) / exact[big]) < eps_r
+    assert abs(r.info["mass"] - 1.0) < 1e-3
+
+
+def test_push_rw_argument_errors(torch):
+    from paper_2412_10789_amd import chebyprop as cp
+
+    G = gpu_graph(synth.star(4))
+    for kw in (dict(eps_r=0.0), dict(delta=1.0), dict(delta=0.0), dict(r_max=-1.0)):
+        args = dict(alpha=0.2, source=1, eps_r=0.5, delta=0.1, seed=1)
+        args.update(kw)
+        with pytest.raises(cp.ChebypropError) as ei:
+            G.push_rw(**args)
+        assert ei.value.status == cp.CP_EINVAL, kw
+    q = cp.make_query("hkpr", 5.0, 1, 0.5, kmode="paper")
+    ws = torch.empty(cp.cp_push_rw_workspace_bytes(G.handle), dtype=torch.uint8, device="cuda")
+    y = torch.empty(5, dtype=torch.float64, device="cuda")
+    with pytest.raises(cp.ChebypropError) as ei:
+        cp.cp_push_rw(G.handle, q, 0.5, 0.1, 0.0, 1, y.data_ptr(), ws.data_ptr(), ws.numel(),
+                      torch.cuda.current_stream().cuda_stream)
+    assert ei.value.status == cp.CP_EINVAL

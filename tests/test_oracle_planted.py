@@ -93,7 +93,7 @@ def _push_form_drops_compensation(row_ptr, col_idx, s, sets):
 
 
 def _walk_stops_with_wrong_probability(row_ptr, col_idx, key, j, start, alpha):
-    return PR.__dict__["_orig_walk_terminal"](row_ptr, col_idx, key, j, start, 1.0 - alpha)
+    return PR.__dict__["_orig_walk"](row_ptr, col_idx, key, j, start, 1.0 - alpha)
 
 
 def _residual_sign_flipped(row_ptr, col_idx, s, alpha, pi_hat):
@@ -115,7 +115,7 @@ MISTAKES = {
     "ChebyPush pushes nothing": ("push", "selected", _push_without_sign_flip),
     "ChebyPush threshold without degree": ("push", "selected", _threshold_without_degree),
     "Def. 7 without compensation": ("push", "subset_recurrence", _push_form_drops_compensation),
-    "walk stops with probability 1 - alpha": ("bidirectional", "walk_terminal", _walk_stops_with_wrong_probability),
+    "walk stops with probability 1 - alpha": ("bidirectional", "walk", _walk_stops_with_wrong_probability),
     "residual sign flipped": ("bidirectional", "residual", _residual_sign_flipped),
 }
 
