@@ -568,6 +568,42 @@ def run_push(args, torch, cp, synth, g):
                         "y_power| / d_u (Thm. 4 bounds the push's own error by eps_a)", "rows": rows}
 
 
+def run_push_rw(args, torch, cp, synth, g):
+    """ChebyPush + random walks (Alg. 5) for SSPPR on the main line's graph with
+    the paper's parameters: eps_r = 0.5, delta = 1/n, r_max = sqrt(alpha)/W,
+    K = ln(1/r_max)/sqrt(alpha); accuracy against a plain-C FP64 reference."""
+    alpha, eps_r = 0.2, 0.5
+    delta = 1.0 / g.n
+    G = cp.Graph(g.row_ptr, g.col_idx, reorder=args.layout == "degree", stripes=args.layout == "stripes")
+    srcs = [int(s) for s in synth.sources(g, 2, seed=17)]
+    G.push_rw(alpha, srcs[0], eps_r, delta, seed=1)  # warm-up
+    rows = []
+    for i, s in enumerate(srcs):
+        r = G.push_rw(alpha, s, eps_r, delta, seed=100 + i, flags=cp.CP_Q_TIMING | cp.CP_Q_STATS)
+        rc = G.power("ppr", alpha, s, tol=1e-7, prec="f64", flags=cp.CP_Q_TIMING)
+        row = {"source": s, "K": r.info["K"], "ms": round(r.info["elapsed_ms"], 2),
+               "ms_push_phase": round(r.info["step_ms"], 2), "pushes": r.info["pushes"], "arcs": r.info["arcs"],
+               "walks": r.info["walks"], "walk_moves": r.info["walk_steps"], "mass": r.info["mass"],
+               "chebypower_f64_ms_at_l1_1e-7": round(rc.info["elapsed_ms"], 2)}
+        if not args.no_cpu and i == 0:
+            from oracle import coefficients as C
+            from oracle import native as NO
+            from oracle import truncation as T
+
+            N = T.pwmethod_steps("ppr", alpha, 1e-15)
+            exact = NO.power_method(g.row_ptr, g.col_idx, s, C.taylor_coeffs("ppr", alpha, N), N)
+            y = r.y.cpu().numpy()
+            big = exact > delta
+            row["max_rel_err_where_pi_gt_delta"] = float(np.max(np.abs(y[big] - exact[big]) / exact[big]))
+            row["nodes_with_pi_gt_delta"] = int(np.count_nonzero(big))
+        rows.append(row)
+        log(f"[push_rw] {row}")
+    G.close()
+    return {"workload": f"Alg. 5 for SSPPR alpha={alpha}, eps_r={eps_r}, delta=1/n, r_max and K as the paper sets "
+                        f"them, on the main line's graph ({args.layout} layout); the relative error is checked "
+                        "against a plain-C FP64 PwMethod with tail 1e-15", "rows": rows}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -591,6 +627,7 @@ def main() -> int:
                     help="columns of the feature-matrix propagation measurement (0: skip it)")
     ap.add_argument("--push-eps", type=float, nargs="*", default=[1e-5, 1e-6, 1e-7, 1e-8],
                     help="eps_a values of the ChebyPush measurement (none: skip it)")
+    ap.add_argument("--no-push-rw", action="store_true", help="skip the ChebyPush + random walk measurement")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle legs")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run a plain 1 GiB device copy first (counter scaling for rocprofv3 --pmc)")
@@ -703,6 +740,8 @@ def main() -> int:
         result["propagate"] = run_propagate(args, torch, cp, synth, g_main)
     if args.push_eps:
         result["push"] = run_push(args, torch, cp, synth, g_main)
+    if not args.no_push_rw:
+        result["push_rw"] = run_push_rw(args, torch, cp, synth, g_main)
     if args.serve_seconds > 0:
         result["served"] = run_serve(args, torch, cp, synth, g_main)
     del g_main
