@@ -714,9 +714,9 @@ cp_status cp_power(const cp_graph* g, const cp_query* q, int32_t prec, void* y, 
       ga.partial = w + W.partial;
       CP_HIP_C(launch_stripe_gather(prec, ga, st));
       CombineArgs ca{g->row_ptr, g->n, w + W.partial, sa.z, yacc, sa.c};
-      CP_HIP_C(launch_stripe_combine(prec, ca, power, st));
+      CP_HIP_C(launch_stripe_combine(prec, ca, power ? kStepPower : kStepCheb, st));
     } else {
-      CP_HIP_C(launch_step(prec, sa, power, st));
+      CP_HIP_C(launch_step(prec, sa, power ? kStepPower : kStepCheb, st));
     }
     if (timing) CP_HIP_C(hipEventRecord(ev[2 * k + 1], st));
   }

@@ -96,6 +96,12 @@ struct StripeBlock {
   int32_t p0, cnt;
 };
 
+// Row update of a step (all step kernels): the Chebyshev step of Eq. 6,
+// z = 2 acc / d - z; the power step of Alg. 1, z = acc / d; or the pull of
+// ChebyPush's push form (Alg. 4, Sec. 4.2), z += acc with x the push values
+// 2 r(u) / d_u (FP64 only, no estimate update).
+enum StepMode : int32_t { kStepCheb = 0, kStepPower = 1, kStepAdd = 2 };
+
 struct StripeArgs {
   const int32_t* rp;                // [kStripes][n+1] per-stripe row offsets
   const int32_t* cols;              // stripe CSRs, concatenated
@@ -105,6 +111,7 @@ struct StripeArgs {
   int64_t n;
   const void* x;
   void* partial;                    // Acc[kStripes][n]
+  const long long* gate;            // non-null: the launch does nothing while *gate == 0
 };
 hipError_t launch_stripe_gather(int32_t prec, const StripeArgs& a, hipStream_t st);
 
@@ -115,9 +122,9 @@ struct CombineArgs {
   void* z;
   void* yacc;
   double c;
+  const long long* gate;            // as StripeArgs
 };
-// power: the power step of Alg. 1 (z[v] = acc / d_v) instead of Eq. 6.
-hipError_t launch_stripe_combine(int32_t prec, const CombineArgs& a, bool power, hipStream_t st);
+hipError_t launch_stripe_combine(int32_t prec, const CombineArgs& a, StepMode mode, hipStream_t st);
 
 // ------------------------------------------------------------------ kernels
 
@@ -125,8 +132,7 @@ hipError_t launch_stripe_combine(int32_t prec, const CombineArgs& a, bool power,
 //   acc = sum_{u in N(v)} x[u]            (x = D^{-1} r_k)
 //   z[v] = 2 acc / d_v - z[v]             (z: D^{-1} r_{k-1} -> D^{-1} r_{k+1})
 //   yacc[v] += c * z[v]                   (yacc = D^{-1} y)
-// With power = true the step is that of Alg. 1: z[v] = acc / d_v (z is
-// only written).
+// The mode selects the row update (see StepMode).
 struct StepArgs {
   const int64_t* row_ptr;
   const int32_t* col_idx;
@@ -140,9 +146,10 @@ struct StepArgs {
   double c;
   void* hub_partial;  // Acc[hub_segments]
   int32_t* hub_count; // int32[nhubs], zero between steps
+  const long long* gate;  // non-null: the launch does nothing while *gate == 0
 };
 
-hipError_t launch_step(int32_t prec, const StepArgs& a, bool power, hipStream_t st);
+hipError_t launch_step(int32_t prec, const StepArgs& a, StepMode mode, hipStream_t st);
 
 // Zero-fill `bytes` bytes (multiple of 4) at `p`.
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t st);

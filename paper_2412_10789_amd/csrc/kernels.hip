@@ -79,11 +79,16 @@ __device__ __forceinline__ int64_t logical_block(int64_t w, int64_t nblocks, int
 }
 
 // Chebyshev step (Eq. 6): z(v) <- 2 acc / d - z(v);  power step (Alg. 1):
-// z(v) <- acc / d.  Then yacc(v) += c z_new.
-template <typename T, typename A, bool PW>
+// z(v) <- acc / d.  Then yacc(v) += c z_new.  Push pull (Alg. 4):
+// z(v) <- z(v) + acc, no estimate.
+template <typename T, typename A, int MODE>
 __device__ __forceinline__ void row_update(T* z, A* yacc, int64_t v, A acc, int32_t d, A c) {
   A zn;
-  if constexpr (PW) zn = acc / A(d);
+  if constexpr (MODE == kStepAdd) {
+    st_stream(z + v, from_acc<T>(to_acc(ld_stream(z + v)) + acc));
+    return;
+  }
+  if constexpr (MODE == kStepPower) zn = acc / A(d);
   else zn = (A(2) * acc) / A(d) - to_acc(ld_stream(z + v));
   st_stream(z + v, from_acc<T>(zn));
   st_stream(yacc + v, ld_stream(yacc + v) + c * zn);
@@ -181,7 +186,7 @@ __device__ __forceinline__ void tile_rowsums(const VT* vals, const int32_t* rpl,
   __syncthreads();
 }
 
-template <typename T, bool PW>
+template <typename T, int MODE>
 __global__ void __launch_bounds__(kThreads) step_kernel(StepArgs a) {
   using A = typename Acc<T>::type;
   __shared__ A vals[kTileNnz];
@@ -189,6 +194,7 @@ __global__ void __launch_bounds__(kThreads) step_kernel(StepArgs a) {
   __shared__ A rowsum[kTileRows];
   __shared__ A wsum[kThreads / 64];
   __shared__ int32_t wflag[kThreads / 64];
+  if (a.gate && *a.gate == 0) return;
 
   const int tid = threadIdx.x;
   const int64_t b = logical_block(blockIdx.x, a.nblocks, a.nspecial);
@@ -229,7 +235,7 @@ __global__ void __launch_bounds__(kThreads) step_kernel(StepArgs a) {
     // Phase 3: row-parallel recurrence and accumulation.
     for (int j = tid; j < nr; j += kThreads) {
       const int32_t d = rpl[j + 1] - rpl[j];
-      if (d > 0) row_update<T, A, PW>(z, yacc, (int64_t)r0 + j, rowsum[j], d, c);
+      if (d > 0) row_update<T, A, MODE>(z, yacc, (int64_t)r0 + j, rowsum[j], d, c);
     }
     return;
   }
@@ -238,7 +244,7 @@ __global__ void __launch_bounds__(kThreads) step_kernel(StepArgs a) {
     const int64_t v = bd.r0;
     const int64_t p0 = rp[v], p1 = rp[v + 1];
     const A total = block_gather_sum<T, A>(col, x, p0, p1, wsum);
-    if (tid == 0) row_update<T, A, PW>(z, yacc, v, total, (int32_t)(p1 - p0), c);
+    if (tid == 0) row_update<T, A, MODE>(z, yacc, v, total, (int32_t)(p1 - p0), c);
     return;
   }
 
@@ -257,7 +263,7 @@ __global__ void __launch_bounds__(kThreads) step_kernel(StepArgs a) {
       A s = A(0);
       for (int q = 0; q < h.nseg; ++q)
         s += __hip_atomic_load(part + h.base + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      row_update<T, A, PW>(z, yacc, h.row, s, (int32_t)(re - rb), c);
+      row_update<T, A, MODE>(z, yacc, h.row, s, (int32_t)(re - rb), c);
       __hip_atomic_store(a.hub_count + bd.r1, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
   }
@@ -275,6 +281,7 @@ template <typename T>
 __global__ void __launch_bounds__(kThreads) stripe_gather_kernel(StripeArgs a) {
   using A = typename Acc<T>::type;
   using L = typename Lds<T>::type;
+  if (a.gate && *a.gate == 0) return;
   __shared__ L vals[kStripeTileNnz];
   __shared__ int32_t rpl[kStripeTileRows + 1];
   __shared__ A rowsum[kStripeTileRows];
@@ -321,9 +328,10 @@ __global__ void __launch_bounds__(kThreads) stripe_gather_kernel(StripeArgs a) {
 
 // Combine the 8 stripe partials of every row (in stripe order) and apply the
 // recurrence and estimate update.
-template <typename T, bool PW>
+template <typename T, int MODE>
 __global__ void __launch_bounds__(kThreads) stripe_combine_kernel(CombineArgs a) {
   using A = typename Acc<T>::type;
+  if (a.gate && *a.gate == 0) return;
   const A* __restrict__ part = static_cast<const A*>(a.partial);
   T* __restrict__ z = static_cast<T*>(a.z);
   A* __restrict__ yacc = static_cast<A*>(a.yacc);
@@ -335,7 +343,7 @@ __global__ void __launch_bounds__(kThreads) stripe_combine_kernel(CombineArgs a)
     A acc = A(0);
 #pragma unroll
     for (int j = 0; j < kStripes; ++j) acc += ld_stream(part + (size_t)j * (size_t)a.n + v);
-    row_update<T, A, PW>(z, yacc, v, acc, (int32_t)d, c);
+    row_update<T, A, MODE>(z, yacc, v, acc, (int32_t)d, c);
   }
 }
 
@@ -408,21 +416,29 @@ constexpr int kFinalBlocks = 1024;
 
 }  // namespace
 
-template <bool PW>
+template <int MODE>
 hipError_t launch_step_t(int32_t prec, const StepArgs& a, hipStream_t st) {
   dim3 grid((unsigned)a.nblocks), block(kThreads);
   switch (prec) {
-    case CP_F64: hipLaunchKernelGGL((step_kernel<double, PW>), grid, block, 0, st, a); break;
-    case CP_F32: hipLaunchKernelGGL((step_kernel<float, PW>), grid, block, 0, st, a); break;
-    case CP_BF16: hipLaunchKernelGGL((step_kernel<bf16, PW>), grid, block, 0, st, a); break;
+    case CP_F64: hipLaunchKernelGGL((step_kernel<double, MODE>), grid, block, 0, st, a); break;
+    case CP_F32: hipLaunchKernelGGL((step_kernel<float, MODE>), grid, block, 0, st, a); break;
+    case CP_BF16: hipLaunchKernelGGL((step_kernel<bf16, MODE>), grid, block, 0, st, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
-hipError_t launch_step(int32_t prec, const StepArgs& a, bool power, hipStream_t st) {
+hipError_t launch_step(int32_t prec, const StepArgs& a, StepMode mode, hipStream_t st) {
   if (a.nblocks <= 0) return hipSuccess;
-  return power ? launch_step_t<true>(prec, a, st) : launch_step_t<false>(prec, a, st);
+  switch (mode) {
+    case kStepCheb: return launch_step_t<kStepCheb>(prec, a, st);
+    case kStepPower: return launch_step_t<kStepPower>(prec, a, st);
+    case kStepAdd:  // the push pull runs in FP64 only
+      if (prec != CP_F64) return hipErrorInvalidValue;
+      hipLaunchKernelGGL((step_kernel<double, kStepAdd>), dim3((unsigned)a.nblocks), dim3(kThreads), 0, st, a);
+      return hipGetLastError();
+  }
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_stripe_gather(int32_t prec, const StripeArgs& a, hipStream_t st) {
@@ -437,23 +453,34 @@ hipError_t launch_stripe_gather(int32_t prec, const StripeArgs& a, hipStream_t s
   return hipGetLastError();
 }
 
-template <bool PW>
+template <int MODE>
 hipError_t launch_stripe_combine_t(int32_t prec, const CombineArgs& a, hipStream_t st) {
   int64_t blocks = (a.n + kThreads - 1) / kThreads;
   if (blocks > 4096) blocks = 4096;
   if (blocks < 1) blocks = 1;
   dim3 grid((unsigned)blocks), block(kThreads);
   switch (prec) {
-    case CP_F64: hipLaunchKernelGGL((stripe_combine_kernel<double, PW>), grid, block, 0, st, a); break;
-    case CP_F32: hipLaunchKernelGGL((stripe_combine_kernel<float, PW>), grid, block, 0, st, a); break;
-    case CP_BF16: hipLaunchKernelGGL((stripe_combine_kernel<bf16, PW>), grid, block, 0, st, a); break;
+    case CP_F64: hipLaunchKernelGGL((stripe_combine_kernel<double, MODE>), grid, block, 0, st, a); break;
+    case CP_F32:
+      if constexpr (MODE == kStepAdd) return hipErrorInvalidValue;
+      else hipLaunchKernelGGL((stripe_combine_kernel<float, MODE>), grid, block, 0, st, a);
+      break;
+    case CP_BF16:
+      if constexpr (MODE == kStepAdd) return hipErrorInvalidValue;
+      else hipLaunchKernelGGL((stripe_combine_kernel<bf16, MODE>), grid, block, 0, st, a);
+      break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
-hipError_t launch_stripe_combine(int32_t prec, const CombineArgs& a, bool power, hipStream_t st) {
-  return power ? launch_stripe_combine_t<true>(prec, a, st) : launch_stripe_combine_t<false>(prec, a, st);
+hipError_t launch_stripe_combine(int32_t prec, const CombineArgs& a, StepMode mode, hipStream_t st) {
+  switch (mode) {
+    case kStepCheb: return launch_stripe_combine_t<kStepCheb>(prec, a, st);
+    case kStepPower: return launch_stripe_combine_t<kStepPower>(prec, a, st);
+    case kStepAdd: return launch_stripe_combine_t<kStepAdd>(prec, a, st);
+  }
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t st) {

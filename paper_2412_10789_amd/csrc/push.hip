@@ -15,12 +15,15 @@
 //   5. the host swaps r_cur and r_new.
 // Step 4 is r_new += 2 P (r_cur|S_k) restricted to the rows it changes, so
 // the iteration is exactly the push form of Sec. 4.2.  When more than
-// n / kDenseDiv nodes are pushed, steps 2-3 are skipped and every row is
-// pulled (rows with no pushed neighbour add an exact zero).  Nothing depends on
-// timing, so results are bitwise reproducible run to run.  The arcs of the
-// pushed nodes are visited twice (marks, then the pulls of their
-// neighbours' rows), both at gather speed; the listing passes cost O(n) per
-// iteration in coalesced reads.
+// n / kDenseDiv nodes are pushed, steps 2-4 are skipped and the tiled
+// single-source step kernels (or their XCD-striped form) pull every row in
+// their add mode, r_new += sum of pv over the row (a row with no pushed
+// neighbour adds an exact zero).  The choice is made on the device: every
+// launch of both paths is queued and reads the dense flag, so the host never
+// waits.  Nothing depends on timing, so results are bitwise reproducible run
+// to run.  The arcs of the pushed nodes are visited twice (marks, then the
+// pulls of their neighbours' rows), both at gather speed; the listing passes
+// cost O(n) per iteration in coalesced reads.
 
 #include <hip/hip_runtime.h>
 
@@ -39,13 +42,13 @@ constexpr int kChunk = kThreads;    // selected nodes expanded together by one w
 constexpr int32_t kShortRow = 32;   // rows up to this degree are pulled by one thread
 
 struct PushLayout {
-  size_t r[2], y, pv, deg, sel, mark, slist, tshort, tlong, ashort, along, bcount, counts, sums, total;
+  size_t r[2], y, pv, deg, sel, mark, slist, tshort, tlong, bcount, counts, hubc, sums, part, total;
 };
 
 // counts (int64): [0] |S_k|, [1] short marked rows, [2] long marked rows,
 // [3] pushes (sum of |S_k|), [4] arcs (sum of vol(S_k)), [5] dense flag of
-// the current iteration, [6] / [7] all short / long rows
-constexpr int kCounts = 8;
+// the current iteration
+constexpr int kCounts = 6;
 // An iteration with more than n / kDenseDiv pushed nodes pulls every row
 // (no marks, no row lists): the marks would cost about as much as a full
 // gather over the graph.
@@ -65,11 +68,14 @@ PushLayout push_layout(const cp_graph* g) {
   L.slist = off; off += al(n * 4);
   L.tshort = off; off += al(n * 4);
   L.tlong = off; off += al(n * 4);
-  L.ashort = off; off += al(n * 4);
-  L.along = off; off += al(n * 4);
   L.bcount = off; off += al((size_t)3 * kRangeBlocks * 4);
   L.counts = off; off += al((size_t)kCounts * 8);
+  // hub row counters of the dense step (zero between launches)
+  L.hubc = off; off += al((size_t)(g->single.nhubs > 0 ? g->single.nhubs : 1) * 4);
   L.sums = off; off += al((size_t)(1 + kRangeBlocks) * 8);
+  // dense step partial sums: [kStripes][n] (striped) or one per hub segment
+  L.part = off;
+  off += al(g->striped ? (size_t)kStripes * n * 8 : (size_t)(g->single.hub_segments > 0 ? g->single.hub_segments : 1) * 8);
   L.total = off;
   return L;
 }
@@ -193,16 +199,13 @@ struct ListArgs {
   long long* count0;
   long long* count1;
   long long* dense;  // S pass: set when the iteration goes dense; row passes: skip when set
-  int32_t all_rows;  // list every row with an edge (the stamp is not read)
 };
 
-__device__ __forceinline__ bool listed(const ListArgs& a, int64_t v) {
-  return a.all_rows ? a.deg[v] > 0 : a.stamp[v] == a.k;
-}
+__device__ __forceinline__ bool listed(const ListArgs& a, int64_t v) { return a.stamp[v] == a.k; }
 
 __global__ void __launch_bounds__(kThreads) push_count_kernel(ListArgs a) {
   __shared__ int red[kThreads / 64];
-  if (!a.all_rows && *a.dense) return;
+  if (*a.dense) return;
   int64_t lo, hi;
   block_range(a.n, lo, hi);
   int c0 = 0, c1 = 0;
@@ -222,7 +225,7 @@ __global__ void __launch_bounds__(kThreads) push_list_kernel(ListArgs a) {
   __shared__ int wcnt[kThreads / 64];
   __shared__ int red[kThreads / 64];
   __shared__ long long off[2];
-  if (a.split_long && !a.all_rows && *a.dense) return;
+  if (a.split_long && *a.dense) return;
   // block offsets: the counts of the blocks before this one (block-wide sums)
   int p0 = 0, p1 = 0;
   for (int b = threadIdx.x; b < (int)blockIdx.x; b += kThreads) {
@@ -238,7 +241,7 @@ __global__ void __launch_bounds__(kThreads) push_list_kernel(ListArgs a) {
       const long long total0 = (long long)o0 + a.bcount0[blockIdx.x];
       *a.count0 = total0;
       if (a.split_long) *a.count1 = (long long)o1 + a.bcount1[blockIdx.x];
-      else if (!a.all_rows) *a.dense = total0 * kDenseDiv > a.n ? 1 : 0;
+      else *a.dense = total0 * kDenseDiv > a.n ? 1 : 0;
     }
   }
   __syncthreads();
@@ -311,19 +314,17 @@ struct PullArgs {
   const int32_t* col_idx;
   const double* pv;
   double* r;  // r_new
-  const int32_t* list;       // marked rows of the class
+  const int32_t* list;  // marked rows of the class
   const long long* count;
-  const int32_t* all_list;   // every row of the class (dense iterations)
-  const long long* all_count;
-  const long long* dense;
+  const long long* dense;  // set: the dense step pulls this iteration instead
 };
 
 // Short rows: one thread per row, arcs summed in CSR order (four loads in
 // flight, added in order).
 __global__ void __launch_bounds__(kThreads) push_pull_short_kernel(PullArgs a) {
-  const bool dense = *a.dense;
-  const int32_t* list = dense ? a.all_list : a.list;
-  const long long m = dense ? *a.all_count : *a.count;
+  if (*a.dense) return;
+  const int32_t* list = a.list;
+  const long long m = *a.count;
   const long long stride = (long long)gridDim.x * blockDim.x;
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += stride) {
     const int32_t v = list[i];
@@ -348,9 +349,9 @@ __global__ void __launch_bounds__(kThreads) push_pull_short_kernel(PullArgs a) {
 // sum of the four wave totals.
 __global__ void __launch_bounds__(kThreads) push_pull_long_kernel(PullArgs a) {
   __shared__ double wsum[kThreads / 64];
-  const bool dense = *a.dense;
-  const int32_t* list = dense ? a.all_list : a.list;
-  const long long m = dense ? *a.all_count : *a.count;
+  if (*a.dense) return;
+  const int32_t* list = a.list;
+  const long long m = *a.count;
   const int tid = threadIdx.x;
   for (long long i = blockIdx.x; i < m; i += gridDim.x) {
     const int32_t v = list[i];
@@ -425,10 +426,6 @@ __global__ void rw_zero_counts_kernel(long long* c) {
   if (threadIdx.x < 8) c[threadIdx.x] = 0;
 }
 
-__global__ void rw_force_dense_kernel(long long* flag) {
-  if (threadIdx.x == 0) *flag = 1;
-}
-
 // ---------------------------------------------------------------- Alg. 5
 
 // SplitMix64 (Steele, Lea & Flood, 2014): output c (0-based) of the stream
@@ -443,7 +440,7 @@ __device__ __forceinline__ uint64_t splitmix64(uint64_t seed, uint64_t c) {
 constexpr int64_t kMaxWalkSteps = 1ll << 20;
 
 // pv(u) = pi^(u) / d_u written as (1 / d_u) * pi^(u), the entry of P times
-// pi^, for every node (the pull kernels then form P pi^).
+// pi^, for every node (the dense step then forms P pi^).
 struct ScaleArgs {
   int64_t n;
   const int32_t* deg;
@@ -634,6 +631,41 @@ RwLayout rw_layout(const cp_graph* g) {
   return L;
 }
 
+// r += sum over each row of pv (every row), by the single-source step
+// kernels in their add mode; with a gate, only while *gate != 0.
+hipError_t dense_pull(const cp_graph* g, const double* pv, double* r, char* w, const PushLayout& L,
+                      const long long* gate, hipStream_t st) {
+  if (g->striped) {
+    StripeArgs ga{};
+    ga.rp = g->s_rp;
+    ga.cols = g->s_cols;
+    for (int j = 0; j < kStripes; ++j) ga.col_off[j] = g->s_col_off[j];
+    ga.blocks = g->s_blocks;
+    ga.ntiles = g->s_ntiles;
+    ga.n = g->n;
+    ga.x = pv;
+    ga.partial = w + L.part;
+    ga.gate = gate;
+    hipError_t e = launch_stripe_gather(CP_F64, ga, st);
+    if (e != hipSuccess) return e;
+    const CombineArgs ca{g->row_ptr, g->n, w + L.part, r, nullptr, 0.0, gate};
+    return launch_stripe_combine(CP_F64, ca, kStepAdd, st);
+  }
+  StepArgs sa{};
+  sa.row_ptr = g->row_ptr;
+  sa.col_idx = g->col_idx;
+  sa.blocks = g->single.blocks;
+  sa.hubs = g->single.hubs;
+  sa.nblocks = g->single.nblocks;
+  sa.nspecial = g->single.nspecial;
+  sa.x = pv;
+  sa.z = r;
+  sa.hub_partial = w + L.part;
+  sa.hub_count = reinterpret_cast<int32_t*>(w + L.hubc);
+  sa.gate = gate;
+  return launch_step(CP_F64, sa, kStepAdd, st);
+}
+
 // The push phase of Alg. 4 into the workspace: y (internal order, paper
 // space) and the push counters.  Launches only; errors as hipError_t.
 hipError_t push_phase(const cp_graph* g, const QueryPlan& qp, double eps_a, char* w, const PushLayout& L,
@@ -661,8 +693,6 @@ hipError_t push_phase(const cp_graph* g, const QueryPlan& qp, double eps_a, char
   int32_t* slist = reinterpret_cast<int32_t*>(w + L.slist);
   int32_t* tshort = reinterpret_cast<int32_t*>(w + L.tshort);
   int32_t* tlong = reinterpret_cast<int32_t*>(w + L.tlong);
-  int32_t* ashort = reinterpret_cast<int32_t*>(w + L.ashort);
-  int32_t* along = reinterpret_cast<int32_t*>(w + L.along);
   int32_t* bc = reinterpret_cast<int32_t*>(w + L.bcount);
   long long* counts = reinterpret_cast<long long*>(w + L.counts);
   const dim3 rb(kRangeBlocks), eb(kEdgeBlocks), tb(kThreads);
@@ -673,12 +703,6 @@ hipError_t push_phase(const cp_graph* g, const QueryPlan& qp, double eps_a, char
     if (e_ != hipSuccess) return e_;         \
   } while (0)
   CP_LAUNCH(push_degree_kernel, rb, tb, 0, st, DegreeArgs{g->row_ptr, g->n, deg});
-  {  // every row with an edge, short and long apart (pulled by dense iterations)
-    const ListArgs la{g->n, nullptr, deg, 0, 1, bc + kRangeBlocks, bc + 2 * kRangeBlocks, ashort, along,
-                      counts + 6, counts + 7, counts + 5, 1};
-    CP_LAUNCH(push_count_kernel, rb, tb, 0, st, la);
-    CP_LAUNCH(push_list_kernel, rb, tb, 0, st, la);
-  }
   CP_LAUNCH(push_seed_kernel, dim3(1), tb, 0, st,
             SeedArgs{g->row_ptr, g->col_idx, qp.s_int, c[0], rbuf[0], rbuf[1], yv});
   int cur = 0;  // rbuf[cur] is r_cur
@@ -686,18 +710,20 @@ hipError_t push_phase(const cp_graph* g, const QueryPlan& qp, double eps_a, char
     const int nxt = cur ^ 1;
     CP_LAUNCH(push_select_kernel, rb, tb, 0, st, SelectArgs{g->n, deg, rbuf[cur], yv, pv, sel, k, eps[k], c[k], bc});
     const ListArgs ls{g->n, sel, deg, k, 0, bc, bc + kRangeBlocks, slist, slist, counts + 0, counts + 0,
-                      counts + 5, 0};
+                      counts + 5};
     CP_LAUNCH(push_list_kernel, rb, tb, 0, st, ls);
     CP_LAUNCH(push_mark_kernel, eb, tb, 0, st,
               MarkArgs{g->row_ptr, g->col_idx, slist, counts + 0, mark, k, counts + 3, counts + 4, counts + 5});
     const ListArgs lt{g->n, mark, deg, k, 1, bc + kRangeBlocks, bc + 2 * kRangeBlocks, tshort, tlong,
-                      counts + 1, counts + 2, counts + 5, 0};
+                      counts + 1, counts + 2, counts + 5};
     CP_LAUNCH(push_count_kernel, rb, tb, 0, st, lt);
     CP_LAUNCH(push_list_kernel, rb, tb, 0, st, lt);
     CP_LAUNCH(push_pull_short_kernel, eb, tb, 0, st,
-              PullArgs{g->row_ptr, g->col_idx, pv, rbuf[nxt], tshort, counts + 1, ashort, counts + 6, counts + 5});
+              PullArgs{g->row_ptr, g->col_idx, pv, rbuf[nxt], tshort, counts + 1, counts + 5});
     CP_LAUNCH(push_pull_long_kernel, eb, tb, 0, st,
-              PullArgs{g->row_ptr, g->col_idx, pv, rbuf[nxt], tlong, counts + 2, along, counts + 7, counts + 5});
+              PullArgs{g->row_ptr, g->col_idx, pv, rbuf[nxt], tlong, counts + 2, counts + 5});
+    e = dense_pull(g, pv, rbuf[nxt], w, L, counts + 5, st);
+    if (e != hipSuccess) return e;
     cur = nxt;
   }
   return hipSuccess;
@@ -712,18 +738,14 @@ hipError_t rw_phase(const cp_graph* g, const QueryPlan& qp, double alpha, double
   double* pv = reinterpret_cast<double*>(w + P.pv);
   double* acc = reinterpret_cast<double*>(w + P.r[0]);
   int32_t* deg = reinterpret_cast<int32_t*>(w + P.deg);
-  long long* pc = reinterpret_cast<long long*>(w + P.counts);
   long long* rc = reinterpret_cast<long long*>(w + L.counts);
-  const dim3 rb(kRangeBlocks), eb(kEdgeBlocks), tb(kThreads);
+  const dim3 rb(kRangeBlocks), tb(kThreads);
   CP_LAUNCH(rw_zero_counts_kernel, dim3(1), dim3(64), 0, st, rc);
   CP_LAUNCH(rw_scale_kernel, rb, tb, 0, st, ScaleArgs{g->n, deg, yv, pv, acc});
-  CP_LAUNCH(rw_force_dense_kernel, dim3(1), dim3(64), 0, st, pc + 5);
-  CP_LAUNCH(push_pull_short_kernel, eb, tb, 0, st,
-            PullArgs{g->row_ptr, g->col_idx, pv, acc, nullptr, nullptr,
-                     reinterpret_cast<const int32_t*>(w + P.ashort), pc + 6, pc + 5});
-  CP_LAUNCH(push_pull_long_kernel, eb, tb, 0, st,
-            PullArgs{g->row_ptr, g->col_idx, pv, acc, nullptr, nullptr,
-                     reinterpret_cast<const int32_t*>(w + P.along), pc + 7, pc + 5});
+  {
+    const hipError_t e = dense_pull(g, pv, acc, w, P, nullptr, st);
+    if (e != hipSuccess) return e;
+  }
   double* res = reinterpret_cast<double*>(w + L.res);
   long long* wv = reinterpret_cast<long long*>(w + L.wv);
   int32_t* bnodes = reinterpret_cast<int32_t*>(w + L.bnodes);

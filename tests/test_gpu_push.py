@@ -1,9 +1,10 @@
 """ChebyPush (Alg. 4) on the GPU (cp_push through the C ABI) against the
 oracle's Alg. 4.
 
-Selection is a floating-point decision (|r(u)| > eps_k d_u) and the GPU adds
-residuals with FP64 atomics in arrival order, so the two sides can only
-disagree on a node whose residual sits on its threshold to rounding.  Each
+Selection is a floating-point decision (|r(u)| > eps_k d_u) and the GPU sums
+each row's pushed values in another order than the oracle, so the two sides
+can only disagree on a node whose residual sits on its threshold to
+rounding.  Each
 case checks the oracle's smallest relative distance of a residual to its
 threshold first (well above 1e-9 here); then the GPU must take the same
 decisions (same number of pushes and arcs) and match to FP64 rounding."""
