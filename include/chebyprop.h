@@ -147,6 +147,9 @@ typedef struct {
   int32_t reordered;
   int32_t borrowed;
   int64_t stripe_tiles; /* row tiles of the XCD-striped step (0 if not striped) */
+  int64_t stripe_packed; /* 1: striped tile arcs stored sorted by column with their
+                            CSR positions (every stripe holds at most 2^21 nodes,
+                            i.e. n <= 2^24); 0: plain column ids or not striped */
 } cp_graph_stats;
 
 /* Build a graph from symmetric CSR (Sec. 2.1: undirected, A in {0,1}):

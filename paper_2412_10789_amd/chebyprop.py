@@ -103,6 +103,7 @@ class cp_graph_stats(ctypes.Structure):
         ("reordered", ctypes.c_int32),
         ("borrowed", ctypes.c_int32),
         ("stripe_tiles", ctypes.c_int64),
+        ("stripe_packed", ctypes.c_int64),
     ]
 
 

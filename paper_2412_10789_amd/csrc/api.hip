@@ -90,6 +90,8 @@ struct StripeLayout {
   std::vector<int32_t> rp;    // [kStripes][n+1]
   std::vector<int32_t> cols;  // stripe CSRs concatenated
   int64_t col_off[kStripes] = {};
+  int64_t base[kStripes] = {};      // first node of each stripe
+  bool packed = false;              // tile blocks in the packed form (common.h)
   std::vector<StripeBlock> blocks;  // [tiles][kStripes]
   int64_t ntiles = 0, nlong = 0;
 };
@@ -177,6 +179,27 @@ bool build_stripes(const int64_t* rp, const int32_t* ci, int64_t n, StripeLayout
     for (int j = 0; j < kStripes; ++j) acc[j] += c[j];
   }
   close(n);
+  // packed form: each tile block's arcs sorted by column (ties in CSR
+  // order), stored as local column << kPackPosBits | CSR position
+  for (int j = 0; j < kStripes; ++j) sl.base[j] = start[j];
+  sl.packed = start[1] - start[0] <= ((int64_t)1 << kPackLocalBits);
+  if (sl.packed) {
+    const int64_t nb = (int64_t)sl.blocks.size();
+    parallel_rows(nb, [&](int64_t b, int64_t e) {
+      std::vector<uint64_t> key;
+      for (int64_t q = b; q < e; ++q) {
+        const StripeBlock& sb = sl.blocks[(size_t)q];
+        if (sb.cnt > kStripeTileNnz || sb.cnt == 0) continue;
+        const int j = (int)(q % kStripes);
+        int32_t* c = sl.cols.data() + sl.col_off[j] + sb.p0;
+        key.resize((size_t)sb.cnt);
+        for (int32_t i = 0; i < sb.cnt; ++i)
+          key[(size_t)i] = ((uint64_t)(c[i] - start[j]) << kPackPosBits) | (uint64_t)i;
+        std::sort(key.begin(), key.end());
+        for (int32_t i = 0; i < sb.cnt; ++i) c[i] = (int32_t)(uint32_t)key[(size_t)i];
+      }
+    });
+  }
   return true;
 }
 
@@ -550,6 +573,8 @@ cp_status cp_graph_create(int64_t n, int64_t nnz, const int64_t* row_ptr, const 
       g->s_ntiles = sl.ntiles;
       g->s_nlong = sl.nlong;
       for (int j = 0; j < kStripes; ++j) g->s_col_off[j] = sl.col_off[j];
+      for (int j = 0; j < kStripes; ++j) g->s_base[j] = sl.base[j];
+      g->s_packed = sl.packed;
       CP_HIP_G(hipMemcpyAsync(g->s_rp, sl.rp.data(), sizeof(int32_t) * sl.rp.size(), hipMemcpyHostToDevice, st));
       if (!sl.cols.empty())
         CP_HIP_G(hipMemcpyAsync(g->s_cols, sl.cols.data(), sizeof(int32_t) * sl.cols.size(), hipMemcpyHostToDevice,
@@ -631,6 +656,7 @@ cp_status cp_graph_get_stats(const cp_graph* g, cp_graph_stats* out) {
   out->reordered = g->reordered;
   out->borrowed = g->borrowed;
   out->stripe_tiles = g->s_ntiles;
+  out->stripe_packed = g->s_packed ? 1 : 0;
   return CP_OK;
 }
 
@@ -707,6 +733,8 @@ cp_status cp_power(const cp_graph* g, const cp_query* q, int32_t prec, void* y, 
       ga.rp = g->s_rp;
       ga.cols = g->s_cols;
       for (int j = 0; j < kStripes; ++j) ga.col_off[j] = g->s_col_off[j];
+      for (int j = 0; j < kStripes; ++j) ga.base[j] = g->s_base[j];
+      ga.packed = g->s_packed;
       ga.blocks = g->s_blocks;
       ga.ntiles = g->s_ntiles;
       ga.n = g->n;

@@ -85,12 +85,24 @@ struct DevPlan {
 
 constexpr int kStripes = 8;
 constexpr int kStripeTileNnz = 2048;   // arcs per (tile, stripe)
+constexpr int kPackPosBits = 11;       // position of an arc within its tile block
+constexpr int kPackLocalBits = 32 - kPackPosBits;
+static_assert(kStripeTileNnz <= (1 << kPackPosBits), "tile positions must fit the packed form");
 constexpr int kStripeTileRows = 1000;  // rows per tile (keeps 8 workgroups per CU in LDS)
 
 // One workgroup of the striped step: rows [r0, r0 + nr) of the tile,
 // restricted to stripe (block index % 8), whose arcs are cols[p0, p0 + cnt)
 // of that stripe's CSR.  cnt > kStripeTileNnz marks a single long row
 // streamed by the whole workgroup.
+//
+// Packed form (used when every stripe holds at most 2^kPackLocalBits
+// nodes): the arcs of a tile block (cnt <= kStripeTileNnz) are stored sorted by
+// column, each as (column - stripe start) << kPackPosBits | its position in
+// the block's CSR order, so that arcs of different rows that share a column
+// sit in the same wave's load and the hardware merges them into one cache
+// request; the gathered value is put back at its CSR position in LDS, so the
+// row sums are the same, bit for bit, as in CSR order.  Long-row blocks keep
+// plain column ids.
 struct StripeBlock {
   int32_t r0, nr;
   int32_t p0, cnt;
@@ -106,6 +118,8 @@ struct StripeArgs {
   const int32_t* rp;                // [kStripes][n+1] per-stripe row offsets
   const int32_t* cols;              // stripe CSRs, concatenated
   int64_t col_off[kStripes];        // start of stripe j's columns in cols
+  int64_t base[kStripes];           // first node of stripe j (packed form)
+  int32_t packed;                   // tile blocks hold the packed form
   const StripeBlock* blocks;        // [ntiles * kStripes], block index = 8 * tile + stripe
   int64_t ntiles;
   int64_t n;
@@ -335,6 +349,8 @@ struct cp_graph {
   int32_t* s_rp = nullptr;          // [8][n+1]
   int32_t* s_cols = nullptr;        // nnz
   int64_t s_col_off[cp::kStripes] = {};
+  int64_t s_base[cp::kStripes] = {};  // first node of each stripe
+  bool s_packed = false;              // tile blocks in the packed form
   cp::StripeBlock* s_blocks = nullptr;
   int64_t s_ntiles = 0, s_nlong = 0;
   cp::DevPlan single;  // plan of the single-source step kernel

@@ -277,7 +277,7 @@ template <> struct Lds<bf16> { using type = float; };
 // One (row tile, stripe) block of an XCD-striped step: partial row sums of
 // the tile's rows over the stripe's columns.  Workgroup w handles tile
 // w / 8 and stripe w % 8, so every workgroup of stripe j runs on XCD j.
-template <typename T>
+template <typename T, bool PACKED>
 __global__ void __launch_bounds__(kThreads) stripe_gather_kernel(StripeArgs a) {
   using A = typename Acc<T>::type;
   using L = typename Lds<T>::type;
@@ -300,21 +300,25 @@ __global__ void __launch_bounds__(kThreads) stripe_gather_kernel(StripeArgs a) {
   if (cnt <= kStripeTileNnz) {
     // column ids and row offsets only depend on the descriptor: issue both
     constexpr int CH = kStripeTileNnz / kThreads;
-    int32_t idx[CH];
+    uint32_t w[CH];
 #pragma unroll
     for (int u = 0; u < CH; ++u) {
       const int i = tid + u * kThreads;
-      idx[u] = i < cnt ? ld_stream(cols + p0 + i) : -1;
+      w[u] = i < cnt ? (uint32_t)ld_stream(cols + p0 + i) : 0u;
     }
     for (int i = tid; i <= nr; i += kThreads) rpl[i] = rpj[r0 + i] - p0;
     for (int i = tid; i < nr; i += kThreads) rowsum[i] = A(0);
+    const T* __restrict__ xs = PACKED ? x + a.base[j] : x;
     L v[CH];
-#pragma unroll
-    for (int u = 0; u < CH; ++u) v[u] = idx[u] >= 0 ? (L)to_acc(x[idx[u]]) : L(0);
 #pragma unroll
     for (int u = 0; u < CH; ++u) {
       const int i = tid + u * kThreads;
-      if (i < cnt) vals[i] = v[u];
+      v[u] = i < cnt ? (L)to_acc(xs[PACKED ? (w[u] >> kPackPosBits) : w[u]]) : L(0);
+    }
+#pragma unroll
+    for (int u = 0; u < CH; ++u) {
+      const int i = tid + u * kThreads;
+      if (i < cnt) vals[PACKED ? (int)(w[u] & ((1u << kPackPosBits) - 1u)) : i] = v[u];
     }
     __syncthreads();
     tile_rowsums<CH, L, A>(vals, rpl, nr, cnt, rowsum, wsum, wflag);
@@ -444,10 +448,13 @@ hipError_t launch_step(int32_t prec, const StepArgs& a, StepMode mode, hipStream
 hipError_t launch_stripe_gather(int32_t prec, const StripeArgs& a, hipStream_t st) {
   if (a.ntiles <= 0) return hipSuccess;
   dim3 grid((unsigned)(a.ntiles * kStripes)), block(kThreads);
-  switch (prec) {
-    case CP_F64: hipLaunchKernelGGL(stripe_gather_kernel<double>, grid, block, 0, st, a); break;
-    case CP_F32: hipLaunchKernelGGL(stripe_gather_kernel<float>, grid, block, 0, st, a); break;
-    case CP_BF16: hipLaunchKernelGGL(stripe_gather_kernel<bf16>, grid, block, 0, st, a); break;
+  switch (prec * 2 + (a.packed ? 1 : 0)) {
+    case CP_F64 * 2: hipLaunchKernelGGL((stripe_gather_kernel<double, false>), grid, block, 0, st, a); break;
+    case CP_F64 * 2 + 1: hipLaunchKernelGGL((stripe_gather_kernel<double, true>), grid, block, 0, st, a); break;
+    case CP_F32 * 2: hipLaunchKernelGGL((stripe_gather_kernel<float, false>), grid, block, 0, st, a); break;
+    case CP_F32 * 2 + 1: hipLaunchKernelGGL((stripe_gather_kernel<float, true>), grid, block, 0, st, a); break;
+    case CP_BF16 * 2: hipLaunchKernelGGL((stripe_gather_kernel<bf16, false>), grid, block, 0, st, a); break;
+    case CP_BF16 * 2 + 1: hipLaunchKernelGGL((stripe_gather_kernel<bf16, true>), grid, block, 0, st, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

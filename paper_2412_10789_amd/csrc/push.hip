@@ -640,6 +640,8 @@ hipError_t dense_pull(const cp_graph* g, const double* pv, double* r, char* w, c
     ga.rp = g->s_rp;
     ga.cols = g->s_cols;
     for (int j = 0; j < kStripes; ++j) ga.col_off[j] = g->s_col_off[j];
+    for (int j = 0; j < kStripes; ++j) ga.base[j] = g->s_base[j];
+    ga.packed = g->s_packed;
     ga.blocks = g->s_blocks;
     ga.ntiles = g->s_ntiles;
     ga.n = g->n;

@@ -217,7 +217,7 @@ def test_xcd_striped_layout(torch, prec):
     g = synth.chung_lu(150_003, 2_400_000, 2.0, seed=17)
     P = PR.transition_matrix(g.row_ptr, g.col_idx)
     G = gpu_graph(g, stripes=True)
-    assert G.stats["stripe_tiles"] > 0 and G.stats["reordered"] == 1
+    assert G.stats["stripe_tiles"] > 0 and G.stats["reordered"] == 1 and G.stats["stripe_packed"] == 1
     for kind, param in [("ppr", 0.2), ("hkpr", 5.0)]:
         for s in synth.sources(g, 2, seed=7):
             _print_case("striped", prec, kind, int(s))
@@ -226,6 +226,29 @@ def test_xcd_striped_layout(torch, prec):
             m = compare(r.y.cpu().numpy(), ref)
             assert m["max_abs"] <= (1e-13 if prec == "f64" else 1e-8), m
             assert m["l1"] <= (1e-12 if prec == "f64" else 2e-7), m
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_xcd_striped_plain_form_above_2_24_nodes(torch, prec):
+    """Stripes of more than 2^21 nodes keep plain column ids (no packed
+    form): a 100k-node power-law core padded with isolated nodes to
+    n = 2^24 + 9."""
+    core = synth.chung_lu(100_000, 800_000, 2.1, seed=23)
+    n = (1 << 24) + 9
+    rp = np.concatenate([core.row_ptr, np.full(n - core.n, core.nnz, dtype=np.int64)])
+    g = synth.CSRGraph(rp, core.col_idx, name="core + isolated")
+    P = PR.transition_matrix(g.row_ptr, g.col_idx)
+    G = gpu_graph(g, stripes=True)
+    assert G.stats["stripe_tiles"] > 0 and G.stats["stripe_packed"] == 0
+    for kind, param in [("ppr", 0.2), ("hkpr", 5.0)]:
+        s = int(synth.sources(core, 1, seed=3)[0])
+        _print_case("striped-plain", prec, kind, s)
+        r = G.power(kind, param, s, tol=1e-7, prec=prec)
+        ref = oracle_yK(g, s, kind, param, r.info["K"], P)
+        m = compare(r.y.cpu().numpy(), ref)
+        assert m["max_abs"] <= (1e-13 if prec == "f64" else 1e-8), m
+        assert m["l1"] <= (1e-12 if prec == "f64" else 2e-7), m
+    G.close()
 
 
 def test_xcd_striped_hub_and_tiny(torch):
