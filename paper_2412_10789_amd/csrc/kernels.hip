@@ -124,8 +124,17 @@ __device__ __forceinline__ A block_gather_sum(const int32_t* __restrict__ col, c
   return total;
 }
 
-// Row sums of an LDS tile: vals[0..cnt) holds the gathered values of the
-// tile's arcs, rpl[0..nr] the tile-relative row offsets (cnt <= kTileNnz).
+// LDS slot of arc p of a tile: the CH arcs a thread scans keep their chunk
+// but are rotated by an XOR with bits of the thread's wave position, so at
+// every step of the scan the 64 lanes of a wavefront read 64 different
+// banks (4-byte values; 8-byte values: two lanes per bank pair).
+template <int CH> __device__ __forceinline__ int lds_slot(int p) {
+  static_assert(CH > 0 && CH <= 64 && (CH & (CH - 1)) == 0, "chunk must be a power of two up to 64");
+  return p ^ ((p >> 6) & (CH - 1));
+}
+
+// Row sums of an LDS tile: vals[lds_slot(p)] holds the gathered value of arc
+// p of the tile, rpl[0..nr] the tile-relative row offsets (cnt <= kTileNnz).
 // Thread t owns arcs [CH t, CH t + CH); heads are row starts.  (F, V) = (chunk holds
 // a head, sum since the last head) is scanned over threads (wavefront
 // shuffles, then wavefront totals in LDS) to give each thread the partial
@@ -152,7 +161,7 @@ __device__ __forceinline__ void tile_rowsums(const VT* vals, const int32_t* rpl,
     for (int p = start; p < end; ++p) {
       while (rpl[r + 1] <= p) ++r;
       if (rpl[r] == p) { F = 1; V = A(0); }
-      V += (A)vals[p];
+      V += (A)vals[lds_slot<CH>(p)];
     }
   }
   const int lane = tid & 63, wv = tid >> 6;
@@ -179,7 +188,7 @@ __device__ __forceinline__ void tile_rowsums(const VT* vals, const int32_t* rpl,
     for (int p = start; p < end; ++p) {
       while (rpl[r + 1] <= p) ++r;
       if (rpl[r] == p) acc = A(0);
-      acc += (A)vals[p];
+      acc += (A)vals[lds_slot<CH>(p)];
       if (p + 1 == rpl[r + 1]) rowsum[r] = acc;
     }
   }
@@ -226,7 +235,7 @@ __global__ void __launch_bounds__(kThreads) step_kernel(StepArgs a) {
 #pragma unroll
     for (int u = 0; u < kPerThread; ++u) {
       const int i = tid + u * kThreads;
-      if (i < cnt) vals[i] = v[u];
+      if (i < cnt) vals[lds_slot<kPerThread>(i)] = v[u];
     }
     __syncthreads();
 
@@ -318,7 +327,7 @@ __global__ void __launch_bounds__(kThreads) stripe_gather_kernel(StripeArgs a) {
 #pragma unroll
     for (int u = 0; u < CH; ++u) {
       const int i = tid + u * kThreads;
-      if (i < cnt) vals[PACKED ? (int)(w[u] & ((1u << kPackPosBits) - 1u)) : i] = v[u];
+      if (i < cnt) vals[lds_slot<CH>(PACKED ? (int)(w[u] & ((1u << kPackPosBits) - 1u)) : i)] = v[u];
     }
     __syncthreads();
     tile_rowsums<CH, L, A>(vals, rpl, nr, cnt, rowsum, wsum, wflag);
