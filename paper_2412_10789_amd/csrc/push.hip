@@ -5,7 +5,9 @@
 //   1. select (one pass over the nodes): every u with |r_cur(u)| > eps_k d_u
 //      adds c_k r_cur(u) to y(u), stores its push value pv(u) = 2 r_cur(u)
 //      / d_u, flips the sign of r_cur(u) and is stamped sel(u) = k; the push
-//      values of the previous iteration are cleared in the same pass;
+//      values of the previous iteration are cleared in the same pass, and
+//      per-block counts and degree sums give |S_k| and vol(S_k), which
+//      decide whether the iteration is sparse or dense;
 //   2. the stamped nodes are listed in node order (S_k) and their arcs mark
 //      every neighbour with mark(v) = k (plain stores);
 //   3. the marked rows are listed in node order, short and long rows apart;
@@ -14,8 +16,8 @@
 //      combined in a fixed order);
 //   5. the host swaps r_cur and r_new.
 // Step 4 is r_new += 2 P (r_cur|S_k) restricted to the rows it changes, so
-// the iteration is exactly the push form of Sec. 4.2.  When more than
-// n / kDenseDiv nodes are pushed, steps 2-4 are skipped and the tiled
+// the iteration is exactly the push form of Sec. 4.2.  In a dense
+// iteration (see kDenseDiv, kDenseVolDiv) steps 2-4 are skipped and the tiled
 // single-source step kernels (or their XCD-striped form) pull every row in
 // their add mode, r_new += sum of pv over the row (a row with no pushed
 // neighbour adds an exact zero).  The choice is made on the device: every
@@ -42,17 +44,21 @@ constexpr int kChunk = kThreads;    // selected nodes expanded together by one w
 constexpr int32_t kShortRow = 32;   // rows up to this degree are pulled by one thread
 
 struct PushLayout {
-  size_t r[2], y, pv, deg, sel, mark, slist, tshort, tlong, bcount, counts, hubc, sums, part, total;
+  size_t r[2], y, pv, deg, sel, mark, slist, tshort, tlong, bcount, bvol, counts, hubc, sums, part, total;
 };
 
 // counts (int64): [0] |S_k|, [1] short marked rows, [2] long marked rows,
 // [3] pushes (sum of |S_k|), [4] arcs (sum of vol(S_k)), [5] dense flag of
 // the current iteration
 constexpr int kCounts = 6;
-// An iteration with more than n / kDenseDiv pushed nodes pulls every row
-// (no marks, no row lists): the marks would cost about as much as a full
-// gather over the graph.
+// An iteration that pushes more than n / kDenseDiv nodes, or nodes with
+// more than nnz / kDenseVolDiv arcs, pulls every row with the tiled step
+// kernels (no marks, no row lists).  Neighbours of pushed nodes lean to
+// high degrees, so the marked rows hold many more arcs than the pushed
+// ones: on power-law graphs the sparse form only pays for small volumes
+// (nnz / 128 was the best of 8 ... 4096 on a 4M-node, 70M-arc graph).
 constexpr int64_t kDenseDiv = 8;
+constexpr int64_t kDenseVolDiv = 128;
 
 PushLayout push_layout(const cp_graph* g) {
   auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
@@ -69,6 +75,7 @@ PushLayout push_layout(const cp_graph* g) {
   L.tshort = off; off += al(n * 4);
   L.tlong = off; off += al(n * 4);
   L.bcount = off; off += al((size_t)3 * kRangeBlocks * 4);
+  L.bvol = off; off += al((size_t)kRangeBlocks * 8);
   L.counts = off; off += al((size_t)kCounts * 8);
   // hub row counters of the dense step (zero between launches)
   L.hubc = off; off += al((size_t)(g->single.nhubs > 0 ? g->single.nhubs : 1) * 4);
@@ -85,6 +92,17 @@ __device__ __forceinline__ void block_range(int64_t n, int64_t& lo, int64_t& hi)
   const int64_t span = (n + kRangeBlocks - 1) / kRangeBlocks;
   lo = (int64_t)blockIdx.x * span;
   hi = lo + span < n ? lo + span : n;
+}
+
+__device__ __forceinline__ long long block_sum_ll(long long v, long long* red) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  long long t = 0;
+  for (int q = 0; q < kThreads / 64; ++q) t += red[q];
+  __syncthreads();
+  return t;
 }
 
 __device__ __forceinline__ int block_sum_int(int v, int* red) {
@@ -160,13 +178,16 @@ struct SelectArgs {
   int32_t k;
   double eps, c;
   int32_t* bcount;  // per range block: selected nodes
+  long long* bvol;  // per range block: their degree sum
 };
 
 __global__ void __launch_bounds__(kThreads) push_select_kernel(SelectArgs a) {
   __shared__ int red[kThreads / 64];
+  __shared__ long long redl[kThreads / 64];
   int64_t lo, hi;
   block_range(a.n, lo, hi);
   int cnt = 0;
+  long long vol = 0;
   for (int64_t v = lo + threadIdx.x; v < hi; v += kThreads) {
     const double val = a.r[v];
     const int32_t d = a.deg[v];
@@ -176,12 +197,43 @@ __global__ void __launch_bounds__(kThreads) push_select_kernel(SelectArgs a) {
       a.r[v] = -val;
       a.sel[v] = a.k;
       ++cnt;
+      vol += d;
     } else if (a.k > 1 && a.sel[v] == a.k - 1) {
       a.pv[v] = 0.0;  // pushed in the previous iteration only
     }
   }
   const int t = block_sum_int(cnt, red);
-  if (threadIdx.x == 0) a.bcount[blockIdx.x] = t;
+  const long long tv = block_sum_ll(vol, redl);
+  if (threadIdx.x == 0) {
+    a.bcount[blockIdx.x] = t;
+    a.bvol[blockIdx.x] = tv;
+  }
+}
+
+// After the select pass: |S_k| and vol(S_k) from the per-block sums, the
+// push and arc counters, and the dense decision of the iteration.
+struct DecideArgs {
+  int64_t n, nnz;
+  const int32_t* bcount;
+  const long long* bvol;
+  long long* counts;  // [0] |S_k| (set), [3] pushes, [4] arcs (accumulated), [5] dense flag (set)
+};
+
+__global__ void __launch_bounds__(kThreads) push_decide_kernel(DecideArgs a) {
+  __shared__ long long red[kThreads / 64];
+  long long m = 0, vol = 0;
+  for (int b = threadIdx.x; b < kRangeBlocks; b += kThreads) {
+    m += a.bcount[b];
+    vol += a.bvol[b];
+  }
+  m = block_sum_ll(m, red);
+  vol = block_sum_ll(vol, red);
+  if (threadIdx.x == 0) {
+    a.counts[0] = m;
+    a.counts[3] += m;
+    a.counts[4] += vol;
+    a.counts[5] = m * kDenseDiv > a.n || vol * kDenseVolDiv > a.nnz ? 1 : 0;
+  }
 }
 
 // Lists of the nodes stamped k, in node order.  With split_long, rows
@@ -198,7 +250,7 @@ struct ListArgs {
   int32_t* list1;
   long long* count0;
   long long* count1;
-  long long* dense;  // S pass: set when the iteration goes dense; row passes: skip when set
+  const long long* dense;  // set: the iteration is dense, nothing to list
 };
 
 __device__ __forceinline__ bool listed(const ListArgs& a, int64_t v) { return a.stamp[v] == a.k; }
@@ -225,7 +277,7 @@ __global__ void __launch_bounds__(kThreads) push_list_kernel(ListArgs a) {
   __shared__ int wcnt[kThreads / 64];
   __shared__ int red[kThreads / 64];
   __shared__ long long off[2];
-  if (a.split_long && *a.dense) return;
+  if (*a.dense) return;
   // block offsets: the counts of the blocks before this one (block-wide sums)
   int p0 = 0, p1 = 0;
   for (int b = threadIdx.x; b < (int)blockIdx.x; b += kThreads) {
@@ -238,10 +290,8 @@ __global__ void __launch_bounds__(kThreads) push_list_kernel(ListArgs a) {
     off[0] = o0;
     off[1] = o1;
     if (blockIdx.x == gridDim.x - 1) {
-      const long long total0 = (long long)o0 + a.bcount0[blockIdx.x];
-      *a.count0 = total0;
+      *a.count0 = (long long)o0 + a.bcount0[blockIdx.x];
       if (a.split_long) *a.count1 = (long long)o1 + a.bcount1[blockIdx.x];
-      else *a.dense = total0 * kDenseDiv > a.n ? 1 : 0;
     }
   }
   __syncthreads();
@@ -266,17 +316,15 @@ struct MarkArgs {
   const long long* scount;
   int32_t* mark;
   int32_t k;
-  long long* pushes;
-  long long* arcs;
-  const long long* dense;  // count arcs only, no marks
+  const long long* dense;  // set: no marks
 };
 
 __global__ void __launch_bounds__(kThreads) push_mark_kernel(MarkArgs a) {
   __shared__ long long pre[kChunk];  // inclusive prefix sum of the chunk's degrees
   __shared__ int64_t off[kChunk];
+  if (*a.dense) return;
   const long long m = *a.scount;
   const int tid = threadIdx.x;
-  if (blockIdx.x == 0 && tid == 0) atomicAdd((unsigned long long*)a.pushes, (unsigned long long)m);
   for (long long chunk = blockIdx.x; chunk * kChunk < m; chunk += gridDim.x) {
     const long long i = chunk * kChunk + tid;
     long long d = 0;
@@ -294,9 +342,7 @@ __global__ void __launch_bounds__(kThreads) push_mark_kernel(MarkArgs a) {
       __syncthreads();
     }
     const long long total = pre[kChunk - 1];
-    if (tid == 0) atomicAdd((unsigned long long*)a.arcs, (unsigned long long)total);
-    const long long todo = *a.dense ? 0 : total;
-    for (long long e = tid; e < todo; e += kChunk) {
+    for (long long e = tid; e < total; e += kChunk) {
       int lo = 0, hi = kChunk - 1;  // first entry whose inclusive prefix exceeds e
       while (lo < hi) {
         const int mid = (lo + hi) >> 1;
@@ -697,6 +743,7 @@ hipError_t push_phase(const cp_graph* g, const QueryPlan& qp, double eps_a, char
   int32_t* tlong = reinterpret_cast<int32_t*>(w + L.tlong);
   int32_t* bc = reinterpret_cast<int32_t*>(w + L.bcount);
   long long* counts = reinterpret_cast<long long*>(w + L.counts);
+  long long* bvol = reinterpret_cast<long long*>(w + L.bvol);
   const dim3 rb(kRangeBlocks), eb(kEdgeBlocks), tb(kThreads);
 #define CP_LAUNCH(...)                       \
   do {                                       \
@@ -710,12 +757,14 @@ hipError_t push_phase(const cp_graph* g, const QueryPlan& qp, double eps_a, char
   int cur = 0;  // rbuf[cur] is r_cur
   for (int32_t k = 1; k < K; ++k) {
     const int nxt = cur ^ 1;
-    CP_LAUNCH(push_select_kernel, rb, tb, 0, st, SelectArgs{g->n, deg, rbuf[cur], yv, pv, sel, k, eps[k], c[k], bc});
+    CP_LAUNCH(push_select_kernel, rb, tb, 0, st,
+              SelectArgs{g->n, deg, rbuf[cur], yv, pv, sel, k, eps[k], c[k], bc, bvol});
+    CP_LAUNCH(push_decide_kernel, dim3(1), tb, 0, st, DecideArgs{g->n, g->nnz, bc, bvol, counts});
     const ListArgs ls{g->n, sel, deg, k, 0, bc, bc + kRangeBlocks, slist, slist, counts + 0, counts + 0,
                       counts + 5};
     CP_LAUNCH(push_list_kernel, rb, tb, 0, st, ls);
     CP_LAUNCH(push_mark_kernel, eb, tb, 0, st,
-              MarkArgs{g->row_ptr, g->col_idx, slist, counts + 0, mark, k, counts + 3, counts + 4, counts + 5});
+              MarkArgs{g->row_ptr, g->col_idx, slist, counts + 0, mark, k, counts + 5});
     const ListArgs lt{g->n, mark, deg, k, 1, bc + kRangeBlocks, bc + 2 * kRangeBlocks, tshort, tlong,
                       counts + 1, counts + 2, counts + 5};
     CP_LAUNCH(push_count_kernel, rb, tb, 0, st, lt);
