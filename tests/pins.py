@@ -299,6 +299,28 @@ def pin_generalized_definition():
                 assert np.max(np.abs(Zp - ref)) < 1e-11, (g.name, kind, a, np.max(np.abs(Zp - ref)))
 
 
+def pin_clenshaw_truncated_series():
+    """Clenshaw's backward form equals sum_{k<=K} c_k T_k(P) x with T_k(P)
+    formed on A~'s spectrum (cos(k arccos lambda)), for every K <= 9 and
+    random coefficients and start vectors; and Def. 8 at a large K."""
+    for g in tiny_graphs()[:4]:
+        A = D.adjacency(g.row_ptr, g.col_idx)
+        P = PR.transition_matrix(g.row_ptr, g.col_idx)
+        Tk = [D.chebyshev_matrix_eigen(A, k) for k in range(10)]
+        x = _features(g.n, 1, seed=g.n + 7)[:, 0]
+        c = _features(10, 1, seed=g.n + 8)[:, 0]
+        for K in range(1, 10):
+            ref = sum(c[k] * (Tk[k] @ x) for k in range(K + 1))
+            got = GG.clenshaw_vector(P, x, c, K)
+            assert np.max(np.abs(got - ref)) < 1e-12 * max(1.0, np.max(np.abs(ref))), (g.name, K)
+        X = _features(g.n, 2, seed=g.n)
+        for kind, p, K in [("ppr", 0.2, 60), ("hkpr", 3.0, 40)]:
+            for a in (0.0, 0.5, 1.0):
+                ref = D.generalized_definition(A, X, a, kind, p)
+                Z = GG.generalized_gp(g.row_ptr, g.col_idx, X, a, kind, p, K, method="clenshaw")
+                assert np.max(np.abs(Z - ref)) < 1e-11, (g.name, kind, a)
+
+
 def pin_generalized_symmetric_half():
     """a = 1/2: f(D^{-1/2} A D^{-1/2}) is a symmetric matrix, so Z for X = I
     is symmetric (and not for a = 0 on an irregular graph)."""
@@ -549,6 +571,7 @@ ALL_PINS = [
     pin_certified_bound_and_certificate,
     pin_convergence_rate,
     pin_generalized_definition,
+    pin_clenshaw_truncated_series,
     pin_generalized_symmetric_half,
     pin_generalized_single_source,
     pin_generalized_degree_zero_reading,

@@ -100,6 +100,21 @@ def _residual_sign_flipped(row_ptr, col_idx, s, alpha, pi_hat):
     return -PR.__dict__["_orig_residual"](row_ptr, col_idx, s, alpha, pi_hat)
 
 
+def _clenshaw_without_b2(P, x, b_next, b_next2, c_k):
+    return c_k * x + 2.0 * (P @ b_next)
+
+
+def _clenshaw_final_doubled(P, x, c, K):
+    from oracle import generalized as GG
+
+    c = np.asarray(c, dtype=np.float64)
+    b1 = np.zeros_like(x)
+    b2 = np.zeros_like(x)
+    for k in range(K, 0, -1):
+        b1, b2 = GG._clenshaw_step(P, x, b1, b2, c[k]), b1
+    return c[0] * x + 2.0 * (P @ b1) - b2
+
+
 MISTAKES = {
     "recurrence sign": ("propagation", "_chebyshev_step", _wrong_sign_step),
     "recurrence factor 2": ("propagation", "_chebyshev_step", _missing_factor_two_step),
@@ -117,6 +132,8 @@ MISTAKES = {
     "Def. 7 without compensation": ("push", "subset_recurrence", _push_form_drops_compensation),
     "walk stops with probability 1 - alpha": ("bidirectional", "walk", _walk_stops_with_wrong_probability),
     "residual sign flipped": ("bidirectional", "residual", _residual_sign_flipped),
+    "Clenshaw without -b_{k+2}": ("generalized", "_clenshaw_step", _clenshaw_without_b2),
+    "Clenshaw last step with 2 P b_1": ("generalized", "clenshaw_vector", _clenshaw_final_doubled),
 }
 
 
