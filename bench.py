@@ -71,6 +71,15 @@ def step_bytes(n: int, nnz: int, prec: str, sources: int = 1) -> int:
     return 4 * nnz + 8 * (n + 1) + n * sources * (3 * s + 2 * a)
 
 
+def clenshaw_step_bytes(n: int, nnz: int, prec: str, sources: int) -> int:
+    """Algorithmic bytes of one step of Clenshaw's backward form: column ids
+    and row offsets once, and per node and column one gather of b_{k+1},
+    read of b_{k+2}, write of b_k and read of the start vector (kept at the
+    estimate's precision); no estimate stream."""
+    s, a = STORAGE_BYTES[prec], ACC_BYTES[prec]
+    return 4 * nnz + 8 * (n + 1) + n * sources * (3 * s + a)
+
+
 def measured_traffic(key: str):
     """HBM bytes per launch from the committed rocprofv3 counter summary,
     if it was taken with the current kernel sources (else None)."""
@@ -509,6 +518,18 @@ def run_propagate(args, torch, cp, synth, g):
     ms /= reps
     K = info["K"]
     bpl = step_bytes(g.n, g.nnz, "f32", k)
+    # the same series by Clenshaw's backward recurrence (no estimate vector)
+    Zc = torch.empty_like(X)
+    G.propagate(X, "ppr", alpha, a=a, tol=tol, prec="f32", Z=Zc, method="clenshaw")
+    msc = 0.0
+    for _ in range(reps):
+        _, ic = G.propagate(X, "ppr", alpha, a=a, tol=tol, prec="f32", Z=Zc, flags=cp.CP_Q_TIMING,
+                            method="clenshaw")
+        msc += ic["elapsed_ms"]
+    msc /= reps
+    bplc = clenshaw_step_bytes(g.n, g.nnz, "f32", k)
+    stepc = ic["step_ms"] / ic["steps"]
+    diff = float(((Zc - Z).abs().sum(0) / Z.abs().sum(0)).max())
     out = {"workload": f"Z = f(D^-1/2 A D^-1/2) X, X [n x {k}] FP32, PPR alpha={alpha}, K={K} (Thm. 2 tail "
                        f"{tol}), degree-ordered layout, on the main line's graph",
            "GTEPS": round(g.nnz * steps * k / (ms * 1e-3) / 1e9, 2), "ms": round(ms, 2), "K": K,
@@ -516,7 +537,15 @@ def run_propagate(args, torch, cp, synth, g):
            "roofline": {"bound": "hbm", "kernel": "batch_step_kernel", "achieved":
                         round(bpl / (step_ms / steps * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                         "frac": round(bpl / (step_ms / steps * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
-                        "avg_launch_ms": round(step_ms / steps, 3)}}
+                        "avg_launch_ms": round(step_ms / steps, 3)},
+           "clenshaw": {"ms": round(msc, 2), "K": ic["K"], "steps": ic["steps"],
+                        "GTEPS": round(g.nnz * ic["steps"] * k / (msc * 1e-3) / 1e9, 2),
+                        "speedup_vs_forward": round(ms / msc, 3),
+                        "roofline": {"bound": "hbm", "kernel": "batch_step_kernel (Clenshaw mode)",
+                                     "achieved": round(bplc / (stepc * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBPS,
+                                     "unit": "GB/s", "frac": round(bplc / (stepc * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
+                                     "avg_launch_ms": round(stepc, 3)},
+                        "max_column_rel_l1_vs_forward": diff}}
     if not args.no_cpu:
         from oracle import errors as E
         from oracle import generalized as GG
@@ -526,6 +555,9 @@ def run_propagate(args, torch, cp, synth, g):
         ref = GG.generalized_gp(g.row_ptr, g.col_idx, Xc, a, "ppr", alpha, K)[:, 0]
         zj = Z[:, j].double().cpu().numpy()
         out["accuracy_vs_fp64_oracle"] = {"column": j, "rel_l1": E.l1(zj, ref) / float(np.abs(ref).sum())}
+        refc = GG.generalized_gp(g.row_ptr, g.col_idx, Xc, a, "ppr", alpha, K, method="clenshaw")[:, 0]
+        zc = Zc[:, j].double().cpu().numpy()
+        out["clenshaw"]["accuracy_vs_fp64_oracle"] = {"column": j, "rel_l1": E.l1(zc, refc) / float(np.abs(refc).sum())}
     log(f"[propagate] {out}")
     G.close()
     return out

@@ -103,6 +103,13 @@ typedef enum { CP_K_CERTIFIED = 0, CP_K_TAIL = 1, CP_K_PAPER = 2, CP_K_FIXED = 3
                              the exact l1 truncation error (tail_bound_l1).
                              Runs max(N - 2, 0) full power steps after the
                              init, on the same kernels as Alg. 3. */
+#define CP_Q_CLENSHAW 0x8 /* cp_propagate only: evaluate the same K-term
+                             Chebyshev series by Clenshaw's backward recurrence
+                             (Clenshaw 1955), b_k = c_k x + 2 P b_{k+1} -
+                             b_{k+2}, sum = c_0 x + P b_1 - b_2: K full steps
+                             as in the forward form, but no estimate vector is
+                             read or written (the start vector is read
+                             instead).  Not with CP_Q_PWMETHOD (CP_EINVAL). */
 
 typedef struct cp_graph cp_graph;
 
@@ -215,10 +222,12 @@ cp_status cp_power_batch(const cp_graph* g, int32_t nq, const cp_query* q, int32
 
 /* Generalized graph propagation of a feature matrix (Def. 8, Thm. 5):
  * Z = f(D^{-a} A D^{-b}) X with b = 1 - a, computed as Z = D^{-a} y^ where y^
- * is the K-term series of Alg. 3 (or N terms of Alg. 1 with CP_Q_PWMETHOD)
- * started from D^{a} x_j, for the k columns of X together (batched steps,
- * k columns in source tiles).
- *   q     kind, param, a, K_fixed, flags (CP_Q_PWMETHOD, CP_Q_TIMING) and
+ * is the K-term series of Alg. 3 (or N terms of Alg. 1 with CP_Q_PWMETHOD;
+ * or Alg. 3's series by Clenshaw's recurrence with CP_Q_CLENSHAW) started
+ * from D^{a} x_j, for the k columns of X together (batched steps, k columns
+ * in source tiles).
+ *   q     kind, param, a, K_fixed, flags (CP_Q_PWMETHOD or CP_Q_CLENSHAW,
+ *         CP_Q_TIMING) and
  *         the truncation rule: CP_K_FIXED, CP_K_TAIL (tail(K) <= tol) or
  *         CP_K_PAPER; CP_K_CERTIFIED needs norms of X and gives CP_EINVAL;
  *         source is ignored

@@ -38,12 +38,14 @@ CP_F64, CP_F32, CP_BF16 = 0, 1, 2
 CP_K_CERTIFIED, CP_K_TAIL, CP_K_PAPER, CP_K_FIXED = 0, 1, 2, 3
 CP_GRAPH_BORROW, CP_GRAPH_VALIDATE, CP_GRAPH_REORDER, CP_GRAPH_HOST = 0x1, 0x2, 0x4, 0x8
 CP_GRAPH_XCD_STRIPES = 0x10
-CP_Q_STATS, CP_Q_TIMING, CP_Q_PWMETHOD = 0x1, 0x2, 0x4
+CP_Q_STATS, CP_Q_TIMING, CP_Q_PWMETHOD, CP_Q_CLENSHAW = 0x1, 0x2, 0x4, 0x8
 
 KINDS = {"ppr": CP_PPR, "hkpr": CP_HKPR}
 PRECS = {"f64": CP_F64, "f32": CP_F32, "bf16": CP_BF16}
 KMODES = {"certified": CP_K_CERTIFIED, "tail": CP_K_TAIL, "paper": CP_K_PAPER, "fixed": CP_K_FIXED}
-METHODS = {"cheby": 0, "power": CP_Q_PWMETHOD}  # Alg. 3 (ChebyPower) or Alg. 1 (PwMethod)
+# Alg. 3 (ChebyPower), Alg. 1 (PwMethod), Alg. 3's series by Clenshaw's
+# recurrence (cp_propagate only)
+METHODS = {"cheby": 0, "power": CP_Q_PWMETHOD, "clenshaw": CP_Q_CLENSHAW}
 
 # every symbol the header declares
 EXPORTED = [

@@ -934,7 +934,9 @@ cp_status cp_propagate(const cp_graph* g, const cp_query* q, int32_t k, int32_t 
                        void* ws, size_t ws_bytes, void* stream, cp_info* info) {
   if (!g || !q || k < 1 || !X || !Z || !valid_prec(prec)) return CP_EINVAL;
   if (q->kind != CP_PPR && q->kind != CP_HKPR) return CP_EINVAL;
-  if (q->flags & ~(CP_Q_TIMING | CP_Q_PWMETHOD)) return CP_EINVAL;
+  if (q->flags & ~(CP_Q_TIMING | CP_Q_PWMETHOD | CP_Q_CLENSHAW)) return CP_EINVAL;
+  const bool clenshaw = q->flags & CP_Q_CLENSHAW;
+  if (clenshaw && (q->flags & CP_Q_PWMETHOD)) return CP_EINVAL;
   if (!(q->a >= 0.0 && q->a <= 1.0)) return CP_EINVAL;
   if (q->kmode == CP_K_CERTIFIED) return CP_EINVAL;  // the certified rule needs norms of X
   const bool power = q->flags & CP_Q_PWMETHOD;
@@ -1002,7 +1004,8 @@ cp_status cp_propagate(const cp_graph* g, const cp_query* q, int32_t k, int32_t 
   CP_HIP_P(launch_upload(w + W.rec, sp.data(), sp.size() * sizeof(double), st));
   void* rA = w + W.rA;
   void* rB = w + W.rB;
-  DenseInitArgs ia{g->row_ptr, g->perm, g->n, bw, k, X, q->a, c[0], rA, w + W.yacc};
+  DenseInitArgs ia{g->row_ptr, g->perm, g->n, bw, k, X, q->a, clenshaw ? c[K] : 1.0, clenshaw ? 1.0 : c[0], rA,
+                   w + W.yacc};
   CP_HIP_P(launch_dense_init(prec, ia, st));
   BatchStepArgs sa{};
   sa.row_ptr = g->row_ptr;
@@ -1020,18 +1023,40 @@ cp_status cp_propagate(const cp_graph* g, const cp_query* q, int32_t k, int32_t 
   sa.hub_count = reinterpret_cast<int32_t*>(w + W.hub_count);
   sa.ntiles_total = W.ntiles;
   if (timing) CP_HIP_P(hipEventRecord(ev[1], st));
-  // r~_1 = D^{-1} P r_0: a power step from r~_0 into the zeroed second buffer
-  sa.x = rA;
-  sa.z = rB;
-  sa.coef_row = dcoef + np;
-  sa.rec = dsp + 3 * np;
-  CP_HIP_P(launch_batch_step(prec, sa, st));
-  sa.rec = dsp;
-  for (int32_t kk = 1; kk < top; ++kk) {
-    sa.x = (kk & 1) ? rB : rA;
-    sa.z = (kk & 1) ? rA : rB;
-    sa.coef_row = dcoef + (size_t)(kk + 1) * np;
+  if (clenshaw) {
+    // b~_K = c_K x~ in rA, b~_{K+1} = 0 in rB; b~_k for k = K-1 .. 1 over
+    // the older buffer, then c_0 x~ + D^{-1} P b_1 - b~_2 into yacc
+    void* cur = rA;   // b~_{k+1}
+    void* prev = rB;  // b~_{k+2}
+    sa.mode = kClenshawStep;
+    sa.rec = dsp;
+    for (int32_t kk = K - 1; kk >= 1; --kk) {
+      sa.x = cur;
+      sa.z = prev;
+      sa.coef_row = dcoef + (size_t)kk * np;
+      CP_HIP_P(launch_batch_step(prec, sa, st));
+      std::swap(cur, prev);
+    }
+    sa.mode = kClenshawLast;
+    sa.rec = dsp + 3 * np;
+    sa.x = cur;
+    sa.z = prev;
+    sa.coef_row = dcoef;
     CP_HIP_P(launch_batch_step(prec, sa, st));
+  } else {
+    // r~_1 = D^{-1} P r_0: a power step from r~_0 into the zeroed second buffer
+    sa.x = rA;
+    sa.z = rB;
+    sa.coef_row = dcoef + np;
+    sa.rec = dsp + 3 * np;
+    CP_HIP_P(launch_batch_step(prec, sa, st));
+    sa.rec = dsp;
+    for (int32_t kk = 1; kk < top; ++kk) {
+      sa.x = (kk & 1) ? rB : rA;
+      sa.z = (kk & 1) ? rA : rB;
+      sa.coef_row = dcoef + (size_t)(kk + 1) * np;
+      CP_HIP_P(launch_batch_step(prec, sa, st));
+    }
   }
   if (timing) CP_HIP_P(hipEventRecord(ev[2], st));
   BatchFinalArgs fa{g->row_ptr, g->perm, reinterpret_cast<const int32_t*>(w + W.slotmap), g->n, bw, k,

@@ -223,7 +223,14 @@ struct BatchStepArgs {
   void* hub_partial;     // A[hub_segments][nq_pad]
   int32_t* hub_count;    // int32[nhubs][ntiles_total]
   int32_t ntiles_total;
+  int32_t mode;          // kBatchForward, kClenshawStep or kClenshawLast
 };
+// Row update of a batched step.  Forward (Alg. 3 / Alg. 1): z = u acc / d -
+// (u - 1) z and yacc += c z.  Clenshaw's backward form of the same series,
+// with yacc holding the start vector x~: a step writes b_k = c x~ + u acc / d
+// - b_{k+2} over z (u = 2); the last one writes c_0 x~ + acc / d - b_2 over
+// yacc (u = 1).
+enum BatchMode : int32_t { kBatchForward = 0, kClenshawStep = 1, kClenshawLast = 2 };
 hipError_t launch_batch_step(int32_t prec, const BatchStepArgs& a, hipStream_t st);
 
 struct BatchInitArgs {
@@ -270,7 +277,7 @@ struct DenseInitArgs {
   int32_t k;
   const void* X;         // double for CP_F64, float otherwise
   double a;
-  double c0;
+  double cr, cy;         // r0 = cr x~ and yacc = cy x~, x~ = D^{a-1} x (D^{-1} basis)
   void* r0;
   void* yacc;
 };

@@ -56,13 +56,21 @@ __device__ __forceinline__ int64_t logical_block(int64_t w, int64_t nblocks, int
   return nspecial + x * q + (x < r ? x : r) + j;
 }
 
-// zn = u acc / d - (u - 1) z: u = 2 is the Chebyshev step (Eq. 6), u = 1
-// the power step of Alg. 1 (the old value is read but weighted by zero).
+// Forward: zn = u acc / d - (u - 1) z, u = 2 the Chebyshev step (Eq. 6),
+// u = 1 the power step of Alg. 1 (the old value is read but weighted by
+// zero), then y += c zn.  Clenshaw (y holds x~): bn = c x~ + u acc / d - z,
+// written over z (a step) or over y (the last one).
 template <typename T, typename A>
-__device__ __forceinline__ void row_update(T* z, A* y, size_t e, A acc, int32_t d, A c, A u) {
-  const A zn = (u * acc) / A(d) - (u - A(1)) * to_acc(ld_nt(z + e));
-  st_nt(z + e, from_acc<T>(zn));
-  st_nt(y + e, ld_nt(y + e) + c * zn);
+__device__ __forceinline__ void row_update(T* z, A* y, size_t e, A acc, int32_t d, A c, A u, int32_t mode) {
+  if (mode == kBatchForward) {
+    const A zn = (u * acc) / A(d) - (u - A(1)) * to_acc(ld_nt(z + e));
+    st_nt(z + e, from_acc<T>(zn));
+    st_nt(y + e, ld_nt(y + e) + c * zn);
+    return;
+  }
+  const A bn = c * ld_nt(y + e) + (u * acc) / A(d) - to_acc(ld_nt(z + e));
+  if (mode == kClenshawStep) st_nt(z + e, from_acc<T>(bn));
+  else st_nt(y + e, bn);
 }
 
 // Sum over arcs [p0, p1) of x[col[p]][lane]; the workgroup's lane groups
@@ -145,7 +153,7 @@ __global__ void __launch_bounds__(kThreads) batch_step_kernel(BatchStepArgs a) {
         acc += (v0 + v1) + (v2 + v3);
       }
       for (; p < pe; ++p) acc += to_acc(x[(size_t)cols[p] * BW + lane]);
-      row_update<T, A>(z, y, (size_t)(r0 + r) * BW + lane, acc, pe - pb, c, u);
+      row_update<T, A>(z, y, (size_t)(r0 + r) * BW + lane, acc, pe - pb, c, u, a.mode);
     }
     return;
   }
@@ -154,7 +162,7 @@ __global__ void __launch_bounds__(kThreads) batch_step_kernel(BatchStepArgs a) {
     const int64_t v = bd.r0;
     const int64_t p0 = rp[v], p1 = rp[v + 1];
     const A total = wg_row_sum<T, A, BW>(col, x, p0, p1, grp, lane, part);
-    if (grp == 0) row_update<T, A>(z, y, (size_t)v * BW + lane, total, (int32_t)(p1 - p0), c, u);
+    if (grp == 0) row_update<T, A>(z, y, (size_t)v * BW + lane, total, (int32_t)(p1 - p0), c, u, a.mode);
     return;
   }
 
@@ -184,7 +192,7 @@ __global__ void __launch_bounds__(kThreads) batch_step_kernel(BatchStepArgs a) {
     for (int q = 0; q < h.nseg; ++q)
       s += __hip_atomic_load(hp + (size_t)(h.base + q) * a.nq_pad + slot, __ATOMIC_RELAXED,
                              __HIP_MEMORY_SCOPE_AGENT);
-    row_update<T, A>(z, y, (size_t)h.row * BW + lane, s, (int32_t)(re - rb), c, u);
+    row_update<T, A>(z, y, (size_t)h.row * BW + lane, s, (int32_t)(re - rb), c, u, a.mode);
     if (lane == 0) __hip_atomic_store(counter, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
@@ -288,8 +296,8 @@ __global__ void __launch_bounds__(kThreads) dense_init_kernel(DenseInitArgs a) {
     const int64_t vo = a.perm ? a.perm[v] : v;
     const double x = f * (double)X[vo * a.k + j];
     const size_t e = ((size_t)(j / a.bw) * a.n + v) * a.bw + (j % a.bw);
-    r0[e] = from_acc<T>((A)x);
-    y[e] = (A)(a.c0 * x);
+    r0[e] = from_acc<T>((A)(a.cr * x));
+    y[e] = (A)(a.cy * x);
   }
 }
 

@@ -1,7 +1,8 @@
 """Generalized graph propagation on the GPU (Def. 8, Thm. 5) against the
 oracle: single-source outputs in the D^{-a} A D^{-b} space (cp_query.a) for
 single, batched and served queries, and feature matrices through
-cp_propagate (Alg. 3 and Alg. 1 from dense start vectors D^{a} x_j).
+cp_propagate (Alg. 3, its Clenshaw form and Alg. 1 from dense start vectors
+D^{a} x_j).
 
 Tolerances: FP64 results differ from the oracle only in summation order
 (max-abs within 1e-11 of the column's largest entry); FP32 storage rounds
@@ -119,6 +120,31 @@ def test_propagate_feature_matrix(torch, graph, prec, k):
             _check_cols(Z.double().cpu().numpy(), ref, prec, (kind, a))
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("k", [1, 37])
+def test_propagate_clenshaw(torch, graph, prec, k):
+    """CP_Q_CLENSHAW: Alg. 3's series by Clenshaw's backward recurrence
+    against the oracle's Clenshaw form; FP64 also against the GPU's forward
+    form (the same series, other rounding).  FP32 keeps b_k in float, whose
+    rounding is carried by later steps like the forward form's r_k."""
+    g = graph
+    G = gpu_graph(g, reorder=k == 37)
+    X = _features(g.n, k, seed=k + 100)
+    dt = torch.float64 if prec == "f64" else torch.float32
+    Xd = torch.tensor(X, dtype=dt, device="cuda")
+    Xref = Xd.double().cpu().numpy()
+    for kind, param, K in (("ppr", 0.2, 25), ("hkpr", 5.0, 18), ("ppr", 0.1, 1), ("hkpr", 3.0, 2)):
+        for a in (0.0, 0.5, 1.0):
+            _case("clenshaw", prec, k, kind, K, a)
+            Z, info = G.propagate(Xd, kind, param, a=a, kmode="fixed", K=K, prec=prec, method="clenshaw")
+            assert info["K"] == K and info["steps"] == K
+            ref = GG.generalized_gp(g.row_ptr, g.col_idx, Xref, a, kind, param, K, method="clenshaw")
+            _check_cols(Z.double().cpu().numpy(), ref, prec, ("clenshaw", kind, K, a))
+            if prec == "f64":
+                Zf, _ = G.propagate(Xd, kind, param, a=a, kmode="fixed", K=K, prec=prec)
+                _check_cols(Z.cpu().numpy(), Zf.cpu().numpy(), prec, ("clenshaw vs forward", kind, K, a))
+
+
 def test_propagate_pwmethod_tail_rule_and_in_place(torch, graph):
     """Alg. 1 from D^{a} x_j with N from the exact Taylor tail; Z may be X."""
     from oracle import truncation as T
@@ -166,10 +192,14 @@ def test_propagate_argument_errors(torch, graph):
     Xd = torch.zeros((5, 2), dtype=torch.float32, device="cuda")
     for kw, status in [(dict(kmode="certified"), cp.CP_EINVAL), (dict(a=1.5, kmode="fixed", K=3), cp.CP_EINVAL),
                        (dict(kmode="fixed", K=5000), cp.CP_EKMAX),
-                       (dict(kmode="fixed", K=3, flags=cp.CP_Q_STATS), cp.CP_EINVAL)]:
+                       (dict(kmode="fixed", K=3, flags=cp.CP_Q_STATS), cp.CP_EINVAL),
+                       (dict(kmode="fixed", K=3, flags=cp.CP_Q_CLENSHAW | cp.CP_Q_PWMETHOD), cp.CP_EINVAL)]:
         with pytest.raises(cp.ChebypropError) as ei:
             G.propagate(Xd, "ppr", 0.2, **kw)
         assert ei.value.status == status, kw
     with pytest.raises(cp.ChebypropError) as ei:
         G.power("ppr", 0.2, 1, a=-0.1)
+    assert ei.value.status == cp.CP_EINVAL
+    with pytest.raises(cp.ChebypropError) as ei:  # Clenshaw is for cp_propagate only
+        G.power("ppr", 0.2, 1, method="clenshaw")
     assert ei.value.status == cp.CP_EINVAL
