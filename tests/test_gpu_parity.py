@@ -194,16 +194,18 @@ def test_config2_full_size_f32(torch):
     against the FP64 oracle for sampled sources (full vectors)."""
     g = synth.chung_lu(4_000_000, 35_000_000, 2.3, seed=2)
     P = PR.transition_matrix(g.row_ptr, g.col_idx)
-    for reorder in (False, True):
-        G = gpu_graph(g, reorder=reorder)
+    for layout in ("native", "degree", "stripes"):  # stripes: the layout the benchmark times
+        G = gpu_graph(g, reorder=layout == "degree", stripes=layout == "stripes")
+        if layout == "stripes":
+            assert G.stats["stripe_packed"] == 1
         for s in synth.sources(g, 2, seed=2):
-            _print_case("config2", reorder, int(s))
+            _print_case("config2", layout, int(s))
             r = G.power("hkpr", 5.0, int(s), tol=1e-6, prec="f32")
             y = r.y.cpu().numpy()
             ref = oracle_yK(g, s, "hkpr", 5.0, r.info["K"], P)
             exact = PR.ground_truth(P, int(s), "hkpr", 5.0, tol=1e-12)
             m = compare(y, ref)
-            print("config2", reorder, int(s), r.info["K"], m, "vs exact", E.l1(y, exact), flush=True)
+            print("config2", layout, int(s), r.info["K"], m, "vs exact", E.l1(y, exact), flush=True)
             assert m["l1"] <= 2e-6
             assert E.l1(y, exact) <= 1e-6
         G.close()
