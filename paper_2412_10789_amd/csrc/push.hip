@@ -44,7 +44,7 @@ constexpr int kChunk = kThreads;    // selected nodes expanded together by one w
 constexpr int32_t kShortRow = 32;   // rows up to this degree are pulled by one thread
 
 struct PushLayout {
-  size_t r[2], y, pv, deg, sel, mark, slist, tshort, tlong, bcount, bvol, counts, hubc, sums, part, total;
+  size_t r[2], y, pv, deg, sel, mark, slist, tshort, tlong, bits, bcount, bvol, counts, hubc, sums, part, total;
 };
 
 // counts (int64): [0] |S_k|, [1] short marked rows, [2] long marked rows,
@@ -74,6 +74,7 @@ PushLayout push_layout(const cp_graph* g) {
   L.slist = off; off += al(n * 4);
   L.tshort = off; off += al(n * 4);
   L.tlong = off; off += al(n * 4);
+  L.bits = off; off += al((n + 31) / 32 * 4);
   L.bcount = off; off += al((size_t)3 * kRangeBlocks * 4);
   L.bvol = off; off += al((size_t)kRangeBlocks * 8);
   L.counts = off; off += al((size_t)kCounts * 8);
@@ -355,10 +356,39 @@ __global__ void __launch_bounds__(kThreads) push_mark_kernel(MarkArgs a) {
   }
 }
 
+// Bitmap of S_k (bit u of word u / 32), for the sparse pulls.
+struct BitsArgs {
+  int64_t n;
+  const int32_t* sel;
+  int32_t k;
+  uint32_t* bits;
+  const long long* dense;
+};
+
+__global__ void __launch_bounds__(kThreads) push_bits_kernel(BitsArgs a) {
+  if (*a.dense) return;
+  // each wavefront turns 64 consecutive nodes into two bitmap words
+  const int lane = threadIdx.x & 63;
+  const int64_t chunks = (a.n + 63) / 64;
+  const int64_t waves = (int64_t)gridDim.x * (kThreads / 64);
+  for (int64_t c = (int64_t)blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6); c < chunks; c += waves) {
+    const int64_t v = c * 64 + lane;
+    const unsigned long long m = __ballot(v < a.n && a.sel[v] == a.k);
+    const int64_t w = 2 * c + lane;
+    if (lane < 2 && w * 32 < a.n) a.bits[w] = (uint32_t)(m >> (32 * lane));
+  }
+}
+
+__device__ __forceinline__ bool in_set(const uint32_t* bits, int32_t u) { return (bits[u >> 5] >> (u & 31)) & 1u; }
+
+// The pulls add pv(u) only for u in S_k: every other pv is zero, so the
+// sum over the row is the same, and the bit test reads a bitmap that stays
+// in L2 instead of gathering pv.
 struct PullArgs {
   const int64_t* row_ptr;
   const int32_t* col_idx;
   const double* pv;
+  const uint32_t* bits;  // S_k
   double* r;  // r_new
   const int32_t* list;  // marked rows of the class
   const long long* count;
@@ -378,14 +408,17 @@ __global__ void __launch_bounds__(kThreads) push_pull_short_kernel(PullArgs a) {
     int64_t p = a.row_ptr[v];
     double acc = 0.0;
     for (; p + 4 <= pe; p += 4) {
-      const double x0 = a.pv[a.col_idx[p]], x1 = a.pv[a.col_idx[p + 1]];
-      const double x2 = a.pv[a.col_idx[p + 2]], x3 = a.pv[a.col_idx[p + 3]];
-      acc += x0;
-      acc += x1;
-      acc += x2;
-      acc += x3;
+      const int32_t u0 = a.col_idx[p], u1 = a.col_idx[p + 1], u2 = a.col_idx[p + 2], u3 = a.col_idx[p + 3];
+      const bool b0 = in_set(a.bits, u0), b1 = in_set(a.bits, u1), b2 = in_set(a.bits, u2), b3 = in_set(a.bits, u3);
+      if (b0) acc += a.pv[u0];
+      if (b1) acc += a.pv[u1];
+      if (b2) acc += a.pv[u2];
+      if (b3) acc += a.pv[u3];
     }
-    for (; p < pe; ++p) acc += a.pv[a.col_idx[p]];
+    for (; p < pe; ++p) {
+      const int32_t u = a.col_idx[p];
+      if (in_set(a.bits, u)) acc += a.pv[u];
+    }
     a.r[v] += acc;
   }
 }
@@ -405,14 +438,18 @@ __global__ void __launch_bounds__(kThreads) push_pull_long_kernel(PullArgs a) {
     double acc = 0.0;
     int64_t p = pb + tid;
     for (; p + 3 * kThreads < pe; p += 4 * kThreads) {
-      const double x0 = a.pv[a.col_idx[p]], x1 = a.pv[a.col_idx[p + kThreads]];
-      const double x2 = a.pv[a.col_idx[p + 2 * kThreads]], x3 = a.pv[a.col_idx[p + 3 * kThreads]];
-      acc += x0;
-      acc += x1;
-      acc += x2;
-      acc += x3;
+      const int32_t u0 = a.col_idx[p], u1 = a.col_idx[p + kThreads];
+      const int32_t u2 = a.col_idx[p + 2 * kThreads], u3 = a.col_idx[p + 3 * kThreads];
+      const bool b0 = in_set(a.bits, u0), b1 = in_set(a.bits, u1), b2 = in_set(a.bits, u2), b3 = in_set(a.bits, u3);
+      if (b0) acc += a.pv[u0];
+      if (b1) acc += a.pv[u1];
+      if (b2) acc += a.pv[u2];
+      if (b3) acc += a.pv[u3];
     }
-    for (; p < pe; p += kThreads) acc += a.pv[a.col_idx[p]];
+    for (; p < pe; p += kThreads) {
+      const int32_t u = a.col_idx[p];
+      if (in_set(a.bits, u)) acc += a.pv[u];
+    }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
     if ((tid & 63) == 0) wsum[tid >> 6] = acc;
@@ -744,6 +781,7 @@ hipError_t push_phase(const cp_graph* g, const QueryPlan& qp, double eps_a, char
   int32_t* bc = reinterpret_cast<int32_t*>(w + L.bcount);
   long long* counts = reinterpret_cast<long long*>(w + L.counts);
   long long* bvol = reinterpret_cast<long long*>(w + L.bvol);
+  uint32_t* bits = reinterpret_cast<uint32_t*>(w + L.bits);
   const dim3 rb(kRangeBlocks), eb(kEdgeBlocks), tb(kThreads);
 #define CP_LAUNCH(...)                       \
   do {                                       \
@@ -769,10 +807,11 @@ hipError_t push_phase(const cp_graph* g, const QueryPlan& qp, double eps_a, char
                       counts + 1, counts + 2, counts + 5};
     CP_LAUNCH(push_count_kernel, rb, tb, 0, st, lt);
     CP_LAUNCH(push_list_kernel, rb, tb, 0, st, lt);
+    CP_LAUNCH(push_bits_kernel, rb, tb, 0, st, BitsArgs{g->n, sel, k, bits, counts + 5});
     CP_LAUNCH(push_pull_short_kernel, eb, tb, 0, st,
-              PullArgs{g->row_ptr, g->col_idx, pv, rbuf[nxt], tshort, counts + 1, counts + 5});
+              PullArgs{g->row_ptr, g->col_idx, pv, bits, rbuf[nxt], tshort, counts + 1, counts + 5});
     CP_LAUNCH(push_pull_long_kernel, eb, tb, 0, st,
-              PullArgs{g->row_ptr, g->col_idx, pv, rbuf[nxt], tlong, counts + 2, counts + 5});
+              PullArgs{g->row_ptr, g->col_idx, pv, bits, rbuf[nxt], tlong, counts + 2, counts + 5});
     e = dense_pull(g, pv, rbuf[nxt], w, L, counts + 5, st);
     if (e != hipSuccess) return e;
     cur = nxt;
