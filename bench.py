@@ -293,6 +293,8 @@ def run_serve(args, torch, cp, synth, g):
             if i >= nbuf:
                 tickets[i - nbuf] = S.wait(tickets[i - nbuf])
             tickets[i] = S.submit(cp.make_query(kind, param, s, tol), bufs[i % nbuf])
+            if i and i % 4000 == 0:
+                log(f"[serve] server: {i} of {len(tr)} queries submitted")
         for i in range(max(0, len(tr) - nbuf), len(tr)):
             if not isinstance(tickets[i], tuple):
                 tickets[i] = S.wait(tickets[i])
@@ -346,6 +348,8 @@ def run_serve(args, torch, cp, synth, g):
         G.power(kind, param, s, tol=tol, prec="f32", y=bufs[0], stream=stream)
         torch.cuda.synchronize()
         lat_p.append((time.perf_counter() - t0 - ta) * 1e3)
+        if len(lat_p) % 4000 == 0:
+            log(f"[serve] plain: {len(lat_p)} of {len(trace)} queries done")
     t_end_p = time.perf_counter() - t0
     plain = {"completed": len(lat_p), "qps": round(len(lat_p) / t_end_p, 1), "p50_ms": _pct(lat_p, 50),
              "p99_ms": _pct(lat_p, 99), "mean_ms": float(np.mean(lat_p)), "span_s": round(t_end_p, 3)}
