@@ -738,34 +738,47 @@ def main() -> int:
         from oracle import errors as E
         from oracle import propagation as PR
 
-        g, s, K = S["g"], S["srcs"][0], S["Ks"][0]
+        # bounded sample: whole queries of the timed workload, in order, until
+        # about 10 s of single-thread oracle time
+        g = S["g"]
         P = PR.transition_matrix(g.row_ptr, g.col_idx)
-        c = C.chebyshev_coeffs(S["kind"], S["param"], K)
-        c0 = time.perf_counter()
-        y_ref = PR.cheby_power(P, s, c, K)
-        cpu_s = time.perf_counter() - c0
-        cpu_arcs = (K - 1) * g.nnz + int(g.degrees[s])
-        y_gpu = S["Y"][0].double().cpu().numpy()
+        cpu_s, cpu_arcs, done, l1s, maxs, refs = 0.0, 0, 0, [], [], []
+        for i, (s, K) in enumerate(zip(S["srcs"], S["Ks"])):
+            c = C.chebyshev_coeffs(S["kind"], S["param"], K)
+            c0 = time.perf_counter()
+            y_ref = PR.cheby_power(P, s, c, K)
+            cpu_s += time.perf_counter() - c0
+            cpu_arcs += (K - 1) * g.nnz + int(g.degrees[s])
+            y_gpu = S["Y"][i].double().cpu().numpy()
+            l1s.append(E.l1(y_gpu, y_ref))
+            maxs.append(E.max_abs(y_gpu, y_ref))
+            refs.append((s, K, c, y_ref))
+            done += 1
+            if cpu_s >= 10.0:
+                break
         result["cpu_baseline"] = {
             "value": round(cpu_arcs / cpu_s / 1e9, 4),
             "unit": "GTEPS",
             "cores": 1,
             "kind": "oracle",
-            "sample": f"1 of the {S['nsrc']} sources (same graph, same K={K}): FP64 Alg. 3 with scipy CSR "
-                      f"products, {cpu_s:.1f} s",
+            "sample": f"the first {done} of the {S['nsrc']} sources (same graph, same K per source): FP64 Alg. 3 "
+                      f"with scipy CSR products, {cpu_s:.1f} s",
         }
-        result["accuracy_vs_fp64_oracle"] = {"source": s, "K": K, "l1": E.l1(y_gpu, y_ref),
-                                             "max_abs": E.max_abs(y_gpu, y_ref)}
+        result["accuracy_vs_fp64_oracle"] = {"sources": done, "max_l1": max(l1s), "max_abs": max(maxs),
+                                             "K": [r[1] for r in refs]}
         # the same sample on every host thread: the plain-C oracle (OpenMP node loop)
         from oracle import native as NO
 
         c0 = time.perf_counter()
-        y_c = NO.cheby_power(g.row_ptr, g.col_idx, s, c, K)
-        cpu_s = time.perf_counter() - c0
+        agree = 0.0
+        for (s, K, c, y_ref) in refs:
+            y_c = NO.cheby_power(g.row_ptr, g.col_idx, s, c, K)
+            agree = max(agree, E.l1(y_c, y_ref))
+        cpu_t = time.perf_counter() - c0
         result["cpu_baseline_threads"] = {
-            "value": round(cpu_arcs / cpu_s / 1e9, 4), "unit": "GTEPS", "cores": NO.threads(), "kind": "oracle",
-            "sample": f"the same source and K: plain-C FP64 Alg. 3, {cpu_s:.2f} s",
-            "agrees_with_scipy_oracle_l1": E.l1(y_c, y_ref),
+            "value": round(cpu_arcs / cpu_t / 1e9, 4), "unit": "GTEPS", "cores": NO.threads(), "kind": "oracle",
+            "sample": f"the same {done} sources and K: plain-C FP64 Alg. 3, {cpu_t:.2f} s",
+            "agrees_with_scipy_oracle_l1": agree,
             "host": {"nproc": os.cpu_count(), "cpu_model": cpu_model()},
         }
     g_main = S["g"]
