@@ -482,6 +482,33 @@ def pin_chebypush_locality():
                         assert g.degrees[S].sum() * tr["eps"][k] <= mass.sum() * (1 + 1e-12), (g.name, k, rule)
 
 
+def pin_chebypush_candidates():
+    """Locality of Alg. 4: every pushed node of iteration k is a neighbour of
+    S_{k-1} or a node of S_{k-2} (with S_0 = {s}, N(S_0) = N(s), S_{-1}
+    empty), because only S's sign flips and the pushes into N(S) change
+    residuals and eps_k does not decrease with k."""
+    graphs = tiny_graphs() + [synth.chung_lu(20_000, 100_000, 2.5, seed=1),
+                              synth.chung_lu(30_000, 300_000, 2.1, seed=5)]
+    for g in graphs:
+        s = _connected_node(g, 2)
+        for kind, p in (("ppr", 0.2), ("hkpr", 5.0), ("ppr", 0.05)):
+            for eps_a in (1e-2, 1e-4, 1e-6):
+                K = T.choose_K(kind, p, eps_a / 2, mode="tail")
+                c = C.chebyshev_coeffs(kind, p, K)
+                assert np.all(np.diff(PU.thresholds(c, K, eps_a)[1:K]) >= 0)  # entries 1..K-1 are used
+                _, tr = PU.cheby_push(g.row_ptr, g.col_idx, s, c, K, eps_a, trace=True)
+                sets = [np.array([s])] + tr["sets"]  # sets[k] = S_k
+                for k in range(1, len(sets)):
+                    prev = sets[k - 1]
+                    nbr = np.zeros(g.n, dtype=bool)
+                    for u in prev:
+                        nbr[g.col_idx[g.row_ptr[u]:g.row_ptr[u + 1]]] = True
+                    cand = nbr.copy()
+                    if k >= 2:
+                        cand[sets[k - 2]] = True
+                    assert np.all(cand[sets[k]]), (g.name, kind, eps_a, k)
+
+
 # ---------------------------------------------------------------- Sec. 5.2 (ChebyPush + walks)
 
 
@@ -581,6 +608,7 @@ ALL_PINS = [
     pin_chebypush_without_threshold,
     pin_chebypush_degree_normalized_error,
     pin_chebypush_locality,
+    pin_chebypush_candidates,
     pin_splitmix64_published_outputs,
     pin_residual_invariant,
     pin_alpha_walk_end_distribution,
