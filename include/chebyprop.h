@@ -82,12 +82,14 @@ typedef enum { CP_K_CERTIFIED = 0, CP_K_TAIL = 1, CP_K_PAPER = 2, CP_K_FIXED = 3
 #define CP_GRAPH_REORDER 0x4  /* relabel nodes internally by decreasing degree
                                  (results are still returned in caller ids) */
 #define CP_GRAPH_HOST 0x8     /* row_ptr / col_idx are host pointers */
-#define CP_GRAPH_XCD_STRIPES 0x10 /* relabel nodes into 8 degree-interleaved column
-                                     stripes and keep one CSR per stripe, so that
-                                     single-source steps gather each stripe on one
-                                     XCD (from its L2); costs a second copy of the
-                                     column ids plus 8 (n+1) int32 offsets, so
-                                     each stripe must hold fewer than 2^31 arcs
+#define CP_GRAPH_XCD_STRIPES 0x10 /* relabel nodes into S degree-interleaved column
+                                     stripes (S = 2, 4 or 8, see
+                                     cp_graph_stats.stripe_count) and keep one CSR
+                                     per stripe, so that single-source steps
+                                     gather each stripe on its own XCDs (from
+                                     their L2); costs a second copy of the column
+                                     ids plus S (n+1) int32 offsets, so each
+                                     stripe must hold fewer than 2^31 arcs
                                      (CP_EINVAL otherwise) */
 
 /* cp_query.flags */
@@ -157,6 +159,9 @@ typedef struct {
   int64_t stripe_packed; /* 1: striped tile arcs stored sorted by column with their
                             CSR positions (every stripe holds at most 2^21 nodes,
                             i.e. n <= 2^24); 0: plain column ids or not striped */
+  int64_t stripe_count;  /* column stripes S of the XCD-striped layout (0 if not
+                            striped): the fewest of 2, 4, 8 whose FP32 slice of
+                            the vector, 4 n / S bytes, fits 4 MiB */
 } cp_graph_stats;
 
 /* Build a graph from symmetric CSR (Sec. 2.1: undirected, A in {0,1}):

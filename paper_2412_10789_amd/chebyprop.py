@@ -106,6 +106,7 @@ class cp_graph_stats(ctypes.Structure):
         ("borrowed", ctypes.c_int32),
         ("stripe_tiles", ctypes.c_int64),
         ("stripe_packed", ctypes.c_int64),
+        ("stripe_count", ctypes.c_int64),
     ]
 
 

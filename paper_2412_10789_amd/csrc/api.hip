@@ -87,48 +87,50 @@ bool validate_csr(int64_t n, int64_t nnz, const int64_t* rp, const int32_t* ci) 
 }  // namespace
 
 struct StripeLayout {
-  std::vector<int32_t> rp;    // [kStripes][n+1]
+  int32_t count = 0;          // S
+  std::vector<int32_t> rp;    // [S][n+1]
   std::vector<int32_t> cols;  // stripe CSRs concatenated
-  int64_t col_off[kStripes] = {};
-  int64_t base[kStripes] = {};      // first node of each stripe
+  int64_t col_off[kMaxStripes] = {};
+  int64_t base[kMaxStripes] = {};   // first node of each stripe
   bool packed = false;              // tile blocks in the packed form (common.h)
-  std::vector<StripeBlock> blocks;  // [tiles][kStripes]
+  std::vector<StripeBlock> blocks;  // [tiles][S]
   int64_t ntiles = 0, nlong = 0;
 };
 
-// Per-stripe CSRs of a graph already relabelled into kStripes contiguous
+// Per-stripe CSRs of a graph already relabelled into S contiguous
 // stripes, and the row tiles of the striped step (see common.h).  Stripe
 // offsets are int32: returns false when one stripe holds 2^31 arcs or more.
-bool build_stripes(const int64_t* rp, const int32_t* ci, int64_t n, StripeLayout& sl) {
-  int64_t start[kStripes + 1] = {0};
-  for (int j = 0; j < kStripes; ++j) start[j + 1] = start[j] + (n - j + kStripes - 1) / kStripes;
+bool build_stripes(const int64_t* rp, const int32_t* ci, int64_t n, int32_t S, StripeLayout& sl) {
+  sl.count = S;
+  int64_t start[kMaxStripes + 1] = {0};
+  for (int j = 0; j < S; ++j) start[j + 1] = start[j] + (n - j + S - 1) / S;
   // per row, per stripe arc counts (rows are sorted by column)
-  std::vector<int32_t> cnt((size_t)n * kStripes);
+  std::vector<int32_t> cnt((size_t)n * S);
   parallel_rows(n, [&](int64_t b, int64_t e) {
     for (int64_t v = b; v < e; ++v) {
       const int32_t* r = ci + rp[v];
       const int32_t* re = ci + rp[v + 1];
       const int32_t* lo = r;
-      for (int j = 0; j < kStripes; ++j) {
+      for (int j = 0; j < S; ++j) {
         const int32_t* hi = std::lower_bound(lo, re, (int32_t)start[j + 1]);
-        cnt[(size_t)v * kStripes + j] = (int32_t)(hi - lo);
+        cnt[(size_t)v * S + j] = (int32_t)(hi - lo);
         lo = hi;
       }
     }
   });
-  for (int j = 0; j < kStripes; ++j) {
+  for (int j = 0; j < S; ++j) {
     int64_t arcs = 0;
-    for (int64_t v = 0; v < n; ++v) arcs += cnt[(size_t)v * kStripes + j];
+    for (int64_t v = 0; v < n; ++v) arcs += cnt[(size_t)v * S + j];
     if (arcs > INT32_MAX) return false;
   }
-  sl.rp.assign((size_t)kStripes * (n + 1), 0);
+  sl.rp.assign((size_t)S * (n + 1), 0);
   int64_t total = 0;
-  for (int j = 0; j < kStripes; ++j) {
+  for (int j = 0; j < S; ++j) {
     int32_t* rj = sl.rp.data() + (size_t)j * (n + 1);
     int64_t acc = 0;
     for (int64_t v = 0; v < n; ++v) {
       rj[v] = (int32_t)acc;
-      acc += cnt[(size_t)v * kStripes + j];
+      acc += cnt[(size_t)v * S + j];
     }
     rj[n] = (int32_t)acc;
     sl.col_off[j] = total;
@@ -138,8 +140,8 @@ bool build_stripes(const int64_t* rp, const int32_t* ci, int64_t n, StripeLayout
   parallel_rows(n, [&](int64_t b, int64_t e) {
     for (int64_t v = b; v < e; ++v) {
       const int32_t* src = ci + rp[v];
-      for (int j = 0; j < kStripes; ++j) {
-        const int32_t c = cnt[(size_t)v * kStripes + j];
+      for (int j = 0; j < S; ++j) {
+        const int32_t c = cnt[(size_t)v * S + j];
         int32_t* dst = sl.cols.data() + sl.col_off[j] + sl.rp[(size_t)j * (n + 1) + v];
         std::copy(src, src + c, dst);
         src += c;
@@ -148,9 +150,9 @@ bool build_stripes(const int64_t* rp, const int32_t* ci, int64_t n, StripeLayout
   });
   // row tiles: at most kStripeTileRows rows and kStripeTileNnz arcs per stripe
   int64_t r0 = -1;
-  int64_t acc[kStripes] = {0};
-  auto emit = [&](int64_t a, int64_t b) {  // one tile = kStripes blocks
-    for (int j = 0; j < kStripes; ++j) {
+  int64_t acc[kMaxStripes] = {0};
+  auto emit = [&](int64_t a, int64_t b) {  // one tile = S blocks
+    for (int j = 0; j < S; ++j) {
       const int32_t* rj = sl.rp.data() + (size_t)j * (n + 1);
       sl.blocks.push_back(StripeBlock{(int32_t)a, (int32_t)(b - a), rj[a], rj[b] - rj[a]});
     }
@@ -161,8 +163,8 @@ bool build_stripes(const int64_t* rp, const int32_t* ci, int64_t n, StripeLayout
     r0 = -1;
   };
   for (int64_t v = 0; v < n; ++v) {
-    const int32_t* c = cnt.data() + (size_t)v * kStripes;
-    const int32_t cmax = *std::max_element(c, c + kStripes);
+    const int32_t* c = cnt.data() + (size_t)v * S;
+    const int32_t cmax = *std::max_element(c, c + S);
     if (cmax > kStripeTileNnz) {
       close(v);
       emit(v, v + 1);  // stripes of this row above the tile size stream it whole
@@ -170,18 +172,18 @@ bool build_stripes(const int64_t* rp, const int32_t* ci, int64_t n, StripeLayout
       continue;
     }
     bool full = r0 >= 0 && v - r0 == kStripeTileRows;
-    for (int j = 0; j < kStripes && !full; ++j) full = r0 >= 0 && acc[j] + c[j] > kStripeTileNnz;
+    for (int j = 0; j < S && !full; ++j) full = r0 >= 0 && acc[j] + c[j] > kStripeTileNnz;
     if (full) close(v);
     if (r0 < 0) {
       r0 = v;
-      for (int j = 0; j < kStripes; ++j) acc[j] = 0;
+      for (int j = 0; j < S; ++j) acc[j] = 0;
     }
-    for (int j = 0; j < kStripes; ++j) acc[j] += c[j];
+    for (int j = 0; j < S; ++j) acc[j] += c[j];
   }
   close(n);
   // packed form: each tile block's arcs sorted by column (ties in CSR
   // order), stored as local column << kPackPosBits | CSR position
-  for (int j = 0; j < kStripes; ++j) sl.base[j] = start[j];
+  for (int j = 0; j < S; ++j) sl.base[j] = start[j];
   sl.packed = start[1] - start[0] <= ((int64_t)1 << kPackLocalBits);
   if (sl.packed) {
     const int64_t nb = (int64_t)sl.blocks.size();
@@ -190,7 +192,7 @@ bool build_stripes(const int64_t* rp, const int32_t* ci, int64_t n, StripeLayout
       for (int64_t q = b; q < e; ++q) {
         const StripeBlock& sb = sl.blocks[(size_t)q];
         if (sb.cnt > kStripeTileNnz || sb.cnt == 0) continue;
-        const int j = (int)(q % kStripes);
+        const int j = (int)(q % S);
         int32_t* c = sl.cols.data() + sl.col_off[j] + sb.p0;
         key.resize((size_t)sb.cnt);
         for (int32_t i = 0; i < sb.cnt; ++i)
@@ -265,7 +267,7 @@ WsLayout ws_layout(const cp_graph* g, int32_t nq, int32_t prec) {
   L.hub_partial = off; off += align256((size_t)std::max<int64_t>(g->single.hub_segments, 1) * 8 * nq);
   L.mass = off; off += align256((1 + 1024) * 8);
   L.partial = off;
-  if (g->striped) off += align256((size_t)kStripes * (size_t)g->n * acc_bytes(prec));
+  if (g->striped) off += align256((size_t)g->s_count * (size_t)g->n * acc_bytes(prec));
   L.total = off;
   return L;
 }
@@ -444,6 +446,7 @@ cp_status cp_graph_create(int64_t n, int64_t nnz, const int64_t* row_ptr, const 
   hipStream_t st = static_cast<hipStream_t>(stream);
   const bool host_in = flags & CP_GRAPH_HOST;
   const bool striped = flags & CP_GRAPH_XCD_STRIPES;
+  const int32_t S = stripe_count(n);  // stripes, if striped
   const bool reorder = (flags & CP_GRAPH_REORDER) || striped;
   const bool borrow = (flags & CP_GRAPH_BORROW) && !host_in && !reorder;
   cp_graph* g = nullptr;
@@ -498,9 +501,9 @@ cp_status cp_graph_create(int64_t n, int64_t nnz, const int64_t* row_ptr, const 
       if (striped) {
         // degree rank r -> stripe r % 8, position r / 8 (stripes contiguous)
         std::vector<int32_t> by_rank(perm);
-        int64_t start[kStripes + 1] = {0};
-        for (int j = 0; j < kStripes; ++j) start[j + 1] = start[j] + (n - j + kStripes - 1) / kStripes;
-        for (int64_t r = 0; r < n; ++r) perm[start[r % kStripes] + r / kStripes] = by_rank[r];
+        int64_t start[kMaxStripes + 1] = {0};
+        for (int j = 0; j < S; ++j) start[j + 1] = start[j] + (n - j + S - 1) / S;
+        for (int64_t r = 0; r < n; ++r) perm[start[r % S] + r / S] = by_rank[r];
       }
       g->ext2int.resize(n);
       for (int64_t i = 0; i < n; ++i) g->ext2int[perm[i]] = (int32_t)i;
@@ -521,7 +524,7 @@ cp_status cp_graph_create(int64_t n, int64_t nnz, const int64_t* row_ptr, const 
     }
     const Plan plans[2] = {build_plan(rp.data(), n, kTileNnz), build_plan(rp.data(), n, kBatchLong)};
     StripeLayout sl;
-    if (striped && !build_stripes(rp.data(), ci.data(), n, sl)) {
+    if (striped && !build_stripes(rp.data(), ci.data(), n, S, sl)) {
       (void)release_graph(g);
       return CP_EINVAL;
     }
@@ -555,7 +558,7 @@ cp_status cp_graph_create(int64_t n, int64_t nnz, const int64_t* row_ptr, const 
     }
     size_t b_stripes = 0;
     if (striped) {
-      b_stripes = align256(sizeof(int32_t) * (size_t)kStripes * (n + 1)) +
+      b_stripes = align256(sizeof(int32_t) * (size_t)S * (n + 1)) +
                   align256(sizeof(int32_t) * std::max<size_t>(sl.cols.size(), 1)) +
                   align256(sizeof(StripeBlock) * std::max<size_t>(sl.blocks.size(), 1));
       char* sb = nullptr;
@@ -566,14 +569,15 @@ cp_status cp_graph_create(int64_t n, int64_t nnz, const int64_t* row_ptr, const 
       }
       g->striped = true;
       g->s_rp = reinterpret_cast<int32_t*>(sb);
-      sb += align256(sizeof(int32_t) * (size_t)kStripes * (n + 1));
+      sb += align256(sizeof(int32_t) * (size_t)S * (n + 1));
       g->s_cols = reinterpret_cast<int32_t*>(sb);
       sb += align256(sizeof(int32_t) * std::max<size_t>(sl.cols.size(), 1));
       g->s_blocks = reinterpret_cast<StripeBlock*>(sb);
       g->s_ntiles = sl.ntiles;
       g->s_nlong = sl.nlong;
-      for (int j = 0; j < kStripes; ++j) g->s_col_off[j] = sl.col_off[j];
-      for (int j = 0; j < kStripes; ++j) g->s_base[j] = sl.base[j];
+      g->s_count = S;
+      for (int j = 0; j < S; ++j) g->s_col_off[j] = sl.col_off[j];
+      for (int j = 0; j < S; ++j) g->s_base[j] = sl.base[j];
       g->s_packed = sl.packed;
       CP_HIP_G(hipMemcpyAsync(g->s_rp, sl.rp.data(), sizeof(int32_t) * sl.rp.size(), hipMemcpyHostToDevice, st));
       if (!sl.cols.empty())
@@ -657,6 +661,7 @@ cp_status cp_graph_get_stats(const cp_graph* g, cp_graph_stats* out) {
   out->borrowed = g->borrowed;
   out->stripe_tiles = g->s_ntiles;
   out->stripe_packed = g->s_packed ? 1 : 0;
+  out->stripe_count = g->striped ? g->s_count : 0;
   return CP_OK;
 }
 
@@ -732,16 +737,17 @@ cp_status cp_power(const cp_graph* g, const cp_query* q, int32_t prec, void* y, 
       StripeArgs ga{};
       ga.rp = g->s_rp;
       ga.cols = g->s_cols;
-      for (int j = 0; j < kStripes; ++j) ga.col_off[j] = g->s_col_off[j];
-      for (int j = 0; j < kStripes; ++j) ga.base[j] = g->s_base[j];
+      for (int j = 0; j < g->s_count; ++j) ga.col_off[j] = g->s_col_off[j];
+      for (int j = 0; j < g->s_count; ++j) ga.base[j] = g->s_base[j];
       ga.packed = g->s_packed;
+      ga.nstripes = g->s_count;
       ga.blocks = g->s_blocks;
       ga.ntiles = g->s_ntiles;
       ga.n = g->n;
       ga.x = sa.x;
       ga.partial = w + W.partial;
       CP_HIP_C(launch_stripe_gather(prec, ga, st));
-      CombineArgs ca{g->row_ptr, g->n, w + W.partial, sa.z, yacc, sa.c};
+      CombineArgs ca{g->row_ptr, g->n, w + W.partial, g->s_count, sa.z, yacc, sa.c};
       CP_HIP_C(launch_stripe_combine(prec, ca, power ? kStepPower : kStepCheb, st));
     } else {
       CP_HIP_C(launch_step(prec, sa, power ? kStepPower : kStepCheb, st));

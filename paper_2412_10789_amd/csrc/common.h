@@ -72,18 +72,29 @@ struct DevPlan {
 // ------------------------------------------------------------ XCD stripes
 //
 // With CP_GRAPH_XCD_STRIPES the nodes are relabelled so that degree rank r
-// goes to stripe r % 8, position r / 8: eight contiguous id ranges of equal
-// size and (statistically) equal arc mass, each degree-ordered.  Each
-// stripe's arcs are also stored as a CSR of their own (all rows, columns in
-// that stripe only).  A Chebyshev step then runs as
-//   1. stripe kernel: workgroup w = 8 t + j handles row tile t restricted
+// goes to stripe r % S, position r / S: S contiguous id ranges of equal
+// size and (statistically) equal arc mass, each degree-ordered, S in
+// {2, 4, 8} (stripe_count).  Each stripe's arcs are also stored as a CSR of
+// their own (all rows, columns in that stripe only).  A Chebyshev step then
+// runs as
+//   1. stripe kernel: workgroup w = S t + j handles row tile t restricted
 //      to stripe j; workgroups are dispatched round-robin over the 8 XCDs,
-//      so XCD j only ever gathers from stripe j's slice of x and that slice
-//      stays in its L2; each writes the partial row sums of its stripe;
-//   2. combine kernel: the 8 partials of every row are added in stripe
+//      so stripe j is only ever gathered on XCDs j, j + S, ... and its slice
+//      of x stays in their L2; each writes the partial row sums of its
+//      stripe;
+//   2. combine kernel: the S partials of every row are added in stripe
 //      order and the recurrence / estimate update is applied.
+// Fewer stripes mean fewer partials to write and read; more stripes mean a
+// smaller slice per L2.  stripe_count picks the fewest whose FP32 slice
+// fits one XCD's 4 MiB L2 (at least 2, at most 8).
 
-constexpr int kStripes = 8;
+constexpr int kMaxStripes = 8;
+constexpr int64_t kStripeSliceBytes = int64_t(4) << 20;
+inline int32_t stripe_count(int64_t n) {
+  int32_t s = 2;
+  while (s < kMaxStripes && n * 4 > kStripeSliceBytes * s) s *= 2;
+  return s;
+}
 constexpr int kStripeTileNnz = 2048;   // arcs per (tile, stripe)
 constexpr int kPackPosBits = 11;       // position of an arc within its tile block
 constexpr int kPackLocalBits = 32 - kPackPosBits;
@@ -91,7 +102,7 @@ static_assert(kStripeTileNnz <= (1 << kPackPosBits), "tile positions must fit th
 constexpr int kStripeTileRows = 1000;  // rows per tile (keeps 8 workgroups per CU in LDS)
 
 // One workgroup of the striped step: rows [r0, r0 + nr) of the tile,
-// restricted to stripe (block index % 8), whose arcs are cols[p0, p0 + cnt)
+// restricted to stripe (block index % S), whose arcs are cols[p0, p0 + cnt)
 // of that stripe's CSR.  cnt > kStripeTileNnz marks a single long row
 // streamed by the whole workgroup.
 //
@@ -115,16 +126,17 @@ struct StripeBlock {
 enum StepMode : int32_t { kStepCheb = 0, kStepPower = 1, kStepAdd = 2 };
 
 struct StripeArgs {
-  const int32_t* rp;                // [kStripes][n+1] per-stripe row offsets
+  const int32_t* rp;                // [S][n+1] per-stripe row offsets
   const int32_t* cols;              // stripe CSRs, concatenated
-  int64_t col_off[kStripes];        // start of stripe j's columns in cols
-  int64_t base[kStripes];           // first node of stripe j (packed form)
+  int64_t col_off[kMaxStripes];     // start of stripe j's columns in cols
+  int64_t base[kMaxStripes];        // first node of stripe j (packed form)
   int32_t packed;                   // tile blocks hold the packed form
-  const StripeBlock* blocks;        // [ntiles * kStripes], block index = 8 * tile + stripe
+  int32_t nstripes;                 // S
+  const StripeBlock* blocks;        // [ntiles * S], block index = S * tile + stripe
   int64_t ntiles;
   int64_t n;
   const void* x;
-  void* partial;                    // Acc[kStripes][n]
+  void* partial;                    // Acc[S][n]
   const long long* gate;            // non-null: the launch does nothing while *gate == 0
 };
 hipError_t launch_stripe_gather(int32_t prec, const StripeArgs& a, hipStream_t st);
@@ -132,7 +144,8 @@ hipError_t launch_stripe_gather(int32_t prec, const StripeArgs& a, hipStream_t s
 struct CombineArgs {
   const int64_t* row_ptr;
   int64_t n;
-  const void* partial;              // Acc[kStripes][n]
+  const void* partial;              // Acc[S][n]
+  int32_t nstripes;                 // S
   void* z;
   void* yacc;
   double c;
@@ -353,10 +366,11 @@ struct cp_graph {
   std::vector<int32_t> degree;       // by caller id
   // XCD-striped layout (CP_GRAPH_XCD_STRIPES)
   bool striped = false;
-  int32_t* s_rp = nullptr;          // [8][n+1]
+  int32_t s_count = 0;              // stripes S
+  int32_t* s_rp = nullptr;          // [S][n+1]
   int32_t* s_cols = nullptr;        // nnz
-  int64_t s_col_off[cp::kStripes] = {};
-  int64_t s_base[cp::kStripes] = {};  // first node of each stripe
+  int64_t s_col_off[cp::kMaxStripes] = {};
+  int64_t s_base[cp::kMaxStripes] = {};  // first node of each stripe
   bool s_packed = false;              // tile blocks in the packed form
   cp::StripeBlock* s_blocks = nullptr;
   int64_t s_ntiles = 0, s_nlong = 0;

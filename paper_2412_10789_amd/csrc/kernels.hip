@@ -285,7 +285,8 @@ template <> struct Lds<bf16> { using type = float; };
 
 // One (row tile, stripe) block of an XCD-striped step: partial row sums of
 // the tile's rows over the stripe's columns.  Workgroup w handles tile
-// w / 8 and stripe w % 8, so every workgroup of stripe j runs on XCD j.
+// w / S and stripe w % S, so the workgroups of stripe j run on the XCDs
+// j, j + S, ... (workgroups go round-robin over the 8 XCDs, S divides 8).
 template <typename T, bool PACKED>
 __global__ void __launch_bounds__(kThreads) stripe_gather_kernel(StripeArgs a) {
   using A = typename Acc<T>::type;
@@ -298,7 +299,7 @@ __global__ void __launch_bounds__(kThreads) stripe_gather_kernel(StripeArgs a) {
   __shared__ int32_t wflag[kThreads / 64];
 
   const int tid = threadIdx.x;
-  const int j = (int)(blockIdx.x % kStripes);
+  const int j = (int)(blockIdx.x % (unsigned)a.nstripes);
   const StripeBlock sb = a.blocks[blockIdx.x];
   const int32_t* __restrict__ rpj = a.rp + (size_t)j * (size_t)(a.n + 1);
   const int32_t* __restrict__ cols = a.cols + a.col_off[j];
@@ -339,7 +340,7 @@ __global__ void __launch_bounds__(kThreads) stripe_gather_kernel(StripeArgs a) {
   if (tid == 0) st_stream(part + r0, total);
 }
 
-// Combine the 8 stripe partials of every row (in stripe order) and apply the
+// Combine the S stripe partials of every row (in stripe order) and apply the
 // recurrence and estimate update.
 template <typename T, int MODE>
 __global__ void __launch_bounds__(kThreads) stripe_combine_kernel(CombineArgs a) {
@@ -354,8 +355,7 @@ __global__ void __launch_bounds__(kThreads) stripe_combine_kernel(CombineArgs a)
     const int64_t d = a.row_ptr[v + 1] - a.row_ptr[v];
     if (d == 0) continue;
     A acc = A(0);
-#pragma unroll
-    for (int j = 0; j < kStripes; ++j) acc += ld_stream(part + (size_t)j * (size_t)a.n + v);
+    for (int j = 0; j < a.nstripes; ++j) acc += ld_stream(part + (size_t)j * (size_t)a.n + v);
     row_update<T, A, MODE>(z, yacc, v, acc, (int32_t)d, c);
   }
 }
@@ -456,7 +456,8 @@ hipError_t launch_step(int32_t prec, const StepArgs& a, StepMode mode, hipStream
 
 hipError_t launch_stripe_gather(int32_t prec, const StripeArgs& a, hipStream_t st) {
   if (a.ntiles <= 0) return hipSuccess;
-  dim3 grid((unsigned)(a.ntiles * kStripes)), block(kThreads);
+  if (a.nstripes < 1 || a.nstripes > kMaxStripes || kMaxStripes % a.nstripes) return hipErrorInvalidValue;
+  dim3 grid((unsigned)(a.ntiles * a.nstripes)), block(kThreads);
   switch (prec * 2 + (a.packed ? 1 : 0)) {
     case CP_F64 * 2: hipLaunchKernelGGL((stripe_gather_kernel<double, false>), grid, block, 0, st, a); break;
     case CP_F64 * 2 + 1: hipLaunchKernelGGL((stripe_gather_kernel<double, true>), grid, block, 0, st, a); break;

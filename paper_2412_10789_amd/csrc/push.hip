@@ -81,9 +81,10 @@ PushLayout push_layout(const cp_graph* g) {
   // hub row counters of the dense step (zero between launches)
   L.hubc = off; off += al((size_t)(g->single.nhubs > 0 ? g->single.nhubs : 1) * 4);
   L.sums = off; off += al((size_t)(1 + kRangeBlocks) * 8);
-  // dense step partial sums: [kStripes][n] (striped) or one per hub segment
+  // dense step partial sums: [S][n] (striped) or one per hub segment
   L.part = off;
-  off += al(g->striped ? (size_t)kStripes * n * 8 : (size_t)(g->single.hub_segments > 0 ? g->single.hub_segments : 1) * 8);
+  off += al(g->striped ? (size_t)g->s_count * n * 8
+                       : (size_t)(g->single.hub_segments > 0 ? g->single.hub_segments : 1) * 8);
   L.total = off;
   return L;
 }
@@ -722,9 +723,10 @@ hipError_t dense_pull(const cp_graph* g, const double* pv, double* r, char* w, c
     StripeArgs ga{};
     ga.rp = g->s_rp;
     ga.cols = g->s_cols;
-    for (int j = 0; j < kStripes; ++j) ga.col_off[j] = g->s_col_off[j];
-    for (int j = 0; j < kStripes; ++j) ga.base[j] = g->s_base[j];
+    for (int j = 0; j < g->s_count; ++j) ga.col_off[j] = g->s_col_off[j];
+    for (int j = 0; j < g->s_count; ++j) ga.base[j] = g->s_base[j];
     ga.packed = g->s_packed;
+    ga.nstripes = g->s_count;
     ga.blocks = g->s_blocks;
     ga.ntiles = g->s_ntiles;
     ga.n = g->n;
@@ -733,7 +735,7 @@ hipError_t dense_pull(const cp_graph* g, const double* pv, double* r, char* w, c
     ga.gate = gate;
     hipError_t e = launch_stripe_gather(CP_F64, ga, st);
     if (e != hipSuccess) return e;
-    const CombineArgs ca{g->row_ptr, g->n, w + L.part, r, nullptr, 0.0, gate};
+    const CombineArgs ca{g->row_ptr, g->n, w + L.part, g->s_count, r, nullptr, 0.0, gate};
     return launch_stripe_combine(CP_F64, ca, kStepAdd, st);
   }
   StepArgs sa{};

@@ -197,7 +197,7 @@ def test_config2_full_size_f32(torch):
     for layout in ("native", "degree", "stripes"):  # stripes: the layout the benchmark times
         G = gpu_graph(g, reorder=layout == "degree", stripes=layout == "stripes")
         if layout == "stripes":
-            assert G.stats["stripe_packed"] == 1
+            assert G.stats["stripe_packed"] == 1 and G.stats["stripe_count"] == 4
         for s in synth.sources(g, 2, seed=2):
             _print_case("config2", layout, int(s))
             r = G.power("hkpr", 5.0, int(s), tol=1e-6, prec="f32")
@@ -220,6 +220,7 @@ def test_xcd_striped_layout(torch, prec):
     P = PR.transition_matrix(g.row_ptr, g.col_idx)
     G = gpu_graph(g, stripes=True)
     assert G.stats["stripe_tiles"] > 0 and G.stats["reordered"] == 1 and G.stats["stripe_packed"] == 1
+    assert G.stats["stripe_count"] == 2
     for kind, param in [("ppr", 0.2), ("hkpr", 5.0)]:
         for s in synth.sources(g, 2, seed=7):
             _print_case("striped", prec, kind, int(s))
@@ -228,6 +229,29 @@ def test_xcd_striped_layout(torch, prec):
             m = compare(r.y.cpu().numpy(), ref)
             assert m["max_abs"] <= (1e-13 if prec == "f64" else 1e-8), m
             assert m["l1"] <= (1e-12 if prec == "f64" else 2e-7), m
+
+
+@pytest.mark.parametrize("n_total,stripes", [(3_000_003, 4), (6_000_005, 8)])
+def test_xcd_stripe_counts(torch, n_total, stripes):
+    """The stripe count follows n (the fewest of 2, 4, 8 whose FP32 slice of
+    the vector fits 4 MiB); a 100k-node power-law core padded with isolated
+    nodes runs with 4 and with 8 stripes in the packed form."""
+    core = synth.chung_lu(100_000, 800_000, 2.1, seed=29)
+    rp = np.concatenate([core.row_ptr, np.full(n_total - core.n, core.nnz, dtype=np.int64)])
+    g = synth.CSRGraph(rp, core.col_idx, name="core + isolated")
+    P = PR.transition_matrix(g.row_ptr, g.col_idx)
+    G = gpu_graph(g, stripes=True)
+    assert G.stats["stripe_count"] == stripes and G.stats["stripe_packed"] == 1
+    s = int(synth.sources(core, 1, seed=4)[0])
+    for prec in ("f64", "f32"):
+        for kind, param in [("ppr", 0.2), ("hkpr", 5.0)]:
+            _print_case("stripe-count", stripes, prec, kind, s)
+            r = G.power(kind, param, s, tol=1e-7, prec=prec)
+            ref = oracle_yK(g, s, kind, param, r.info["K"], P)
+            m = compare(r.y.cpu().numpy(), ref)
+            assert m["max_abs"] <= (1e-13 if prec == "f64" else 1e-8), m
+            assert m["l1"] <= (1e-12 if prec == "f64" else 2e-7), m
+    G.close()
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
@@ -241,7 +265,7 @@ def test_xcd_striped_plain_form_above_2_24_nodes(torch, prec):
     g = synth.CSRGraph(rp, core.col_idx, name="core + isolated")
     P = PR.transition_matrix(g.row_ptr, g.col_idx)
     G = gpu_graph(g, stripes=True)
-    assert G.stats["stripe_tiles"] > 0 and G.stats["stripe_packed"] == 0
+    assert G.stats["stripe_tiles"] > 0 and G.stats["stripe_packed"] == 0 and G.stats["stripe_count"] == 8
     for kind, param in [("ppr", 0.2), ("hkpr", 5.0)]:
         s = int(synth.sources(core, 1, seed=3)[0])
         _print_case("striped-plain", prec, kind, s)
