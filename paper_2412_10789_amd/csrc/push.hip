@@ -13,7 +13,8 @@
 //   3. the marked rows are listed in node order, short and long rows apart;
 //   4. pull: every marked row adds sum_{u in N(v)} pv(u) to r_new(v), summed
 //      in CSR order (a long row: one workgroup, thread-strided partial sums
-//      combined in a fixed order);
+//      combined in a fixed order), gathering pv(u) only where u's bit is set
+//      in a bitmap of S_k (every other pv is zero);
 //   5. the host swaps r_cur and r_new.
 // Step 4 is r_new += 2 P (r_cur|S_k) restricted to the rows it changes, so
 // the iteration is exactly the push form of Sec. 4.2.  In a dense
