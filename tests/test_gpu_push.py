@@ -92,6 +92,26 @@ def test_degree_normalized_error_and_output_space(torch):
     _check(G, g, s, "ppr", 0.2, 20, 1e-5, a=0.5)
 
 
+@pytest.mark.parametrize("n_total,stripes", [(3_000_003, 4), (6_000_005, 8)])
+def test_striped_dense_pulls_with_4_and_8_stripes(torch, n_total, stripes):
+    """Dense iterations pull through the XCD-striped step kernels with the
+    graph's own stripe count: a 100k-node power-law core padded with
+    isolated nodes to 4 and 8 stripes, at thresholds that make some
+    iterations dense (vol(S_k) > nnz/128) and others sparse."""
+    core = synth.chung_lu(100_000, 800_000, 2.1, seed=33)
+    rp = np.concatenate([core.row_ptr, np.full(n_total - core.n, core.nnz, dtype=np.int64)])
+    g = synth.CSRGraph(rp, core.col_idx, name="core + isolated")
+    G = gpu_graph(g, stripes=True)
+    assert G.stats["stripe_count"] == stripes
+    s = int(synth.sources(core, 1, seed=6)[0])
+    for kind, param, eps_a in (("ppr", 0.2, 1e-6), ("hkpr", 5.0, 1e-8)):
+        K = T.choose_K(kind, param, eps_a / 2, mode="tail")
+        _case("push-stripes", stripes, kind, eps_a)
+        r, tr = _check(G, g, s, kind, param, K, eps_a)
+        vols = [int(g.degrees[S].sum()) for S in tr["sets"]]
+        assert max(vols) * 128 > g.nnz and min(vols) * 128 <= g.nnz, vols  # both forms ran
+
+
 def test_hub_and_isolated_nodes(torch):
     leaves = 40_000
     e = [(0, i) for i in range(1, leaves + 1)] + [(i, i + 1) for i in range(1, leaves, 3)]
