@@ -475,7 +475,7 @@ cp_status cp_graph_create(int64_t n, int64_t nnz, const int64_t* row_ptr, const 
     }
     if (need_cols) {
       ci.resize(nnz);
-      if (host_in) std::memcpy(ci.data(), col_idx, sizeof(int32_t) * nnz);
+      if (host_in && nnz) std::memcpy(ci.data(), col_idx, sizeof(int32_t) * nnz);
       else if (nnz)
         CP_HIP_G(hipMemcpyAsync(ci.data(), col_idx, sizeof(int32_t) * nnz, hipMemcpyDeviceToHost, st));
     }
