@@ -172,6 +172,27 @@ def test_edgeless_graph(torch, layout):
         assert info["K"] == 4 and bool(torch.all(Z == 0))
 
 
+@pytest.mark.parametrize("kind,param", [("ppr", 0.01), ("ppr", 0.003), ("hkpr", 20.0), ("hkpr", 60.0)])
+def test_long_recurrences_f64(torch, kind, param):
+    """Small alpha and large t (K from about 30 to several hundred) in FP64,
+    single-source on the striped layout and batched, against the oracle's
+    Alg. 3 at the same K (only summation order differs)."""
+    from paper_2412_10789_amd import chebyprop as cp
+
+    g = synth.chung_lu(50_000, 300_000, 2.3, seed=13)
+    P = PR.transition_matrix(g.row_ptr, g.col_idx)
+    srcs = [int(x) for x in synth.sources(g, 3, seed=8)]
+    G = gpu_graph(g, stripes=True)
+    _print_case("long", kind, param)
+    r = G.power(kind, param, srcs[0], tol=1e-10, prec="f64")
+    ref = oracle_yK(g, srcs[0], kind, param, r.info["K"], P)
+    assert compare(r.y.cpu().numpy(), ref)["max_abs"] <= 1e-12 * np.abs(ref).max(), r.info["K"]
+    Y, infos = G.power_batch([cp.make_query(kind, param, x, 1e-10) for x in srcs], prec="f64")
+    for j, x in enumerate(srcs):
+        ref = oracle_yK(g, x, kind, param, infos[j]["K"], P)
+        assert compare(Y[:, j].cpu().numpy(), ref)["max_abs"] <= 1e-12 * np.abs(ref).max(), (j, infos[j]["K"])
+
+
 def test_validation_rejects_bad_csr(torch):
     from paper_2412_10789_amd import chebyprop as cp
 
