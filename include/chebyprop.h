@@ -265,9 +265,12 @@ cp_status cp_propagate(const cp_graph* g, const cp_query* q, int32_t k, int32_t 
  *   ws     device workspace of cp_push_workspace_bytes(g) bytes, 256-byte
  *          aligned
  *   info   pushes and arcs need CP_Q_STATS or CP_Q_TIMING (synchronizes)
- * Work per iteration is proportional to the candidate nodes and vol(S_k),
- * not to n.  Residual updates use FP64 atomic adds, so results agree run to
- * run up to rounding.  Errors as cp_power. */
+ * An iteration makes a few coalesced passes over per-node flags (select,
+ * listing) and otherwise touches the arcs of S_k and of the rows they reach;
+ * an iteration that pushes more than n/8 nodes or nodes with more than
+ * nnz/128 arcs pulls every row with the single-source step kernels instead.
+ * No floating-point atomics: results are bitwise reproducible run to run.
+ * Errors as cp_power. */
 size_t cp_push_workspace_bytes(const cp_graph* g);
 cp_status cp_push(const cp_graph* g, const cp_query* q, double eps_a, double* y, void* ws, size_t ws_bytes,
                   void* stream, cp_info* info);
