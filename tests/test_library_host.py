@@ -140,3 +140,42 @@ def test_pwmethod_term_errors(cp):
     with pytest.raises(cp.ChebypropError) as ei:
         cp.cp_taylor(cp.CP_HKPR, -1.0, 3)
     assert ei.value.status == cp.CP_EINVAL
+
+
+@pytest.mark.parametrize("t", [100.0, 500.0, 700.0])
+def test_hkpr_coefficients_large_t(cp, t):
+    """Large heat-kernel times: Miller's recurrence keeps every coefficient
+    finite and matches the scaled Bessel functions; the coefficients sum to
+    f(1) = 1 and alternate to f(-1) = e^{-2t} (Lemma 3's series at
+    lambda = +-1)."""
+    K = int(t + 40 * np.sqrt(t) + 50)
+    c = cp.cp_coeffs(cp.CP_HKPR, t, K)
+    assert np.all(np.isfinite(c)) and np.all(c >= 0)
+    ref = np.r_[ss.ive(0, t), 2 * ss.ive(np.arange(1, K + 1), t)]
+    big = ref > 1e-250
+    np.testing.assert_allclose(c[big], ref[big], rtol=1e-10)
+    assert abs(c.sum() - 1.0) <= 1e-12
+    alt = np.sum(c * (-1.0) ** np.arange(K + 1))
+    assert abs(alt - np.exp(-2 * t)) <= 1e-12
+
+
+@pytest.mark.parametrize("alpha", [1e-4, 0.999])
+def test_ppr_coefficients_extreme_alpha(cp, alpha):
+    """Near the ends of (0, 1): the series sums to f(1) = 1 and alternates to
+    f(-1) = alpha / (2 - alpha) (Def. 3 at lambda = +-1), up to its tail."""
+    K = 4000 if alpha < 0.01 else 40
+    c = cp.cp_coeffs(cp.CP_PPR, alpha, K)
+    assert np.all(np.isfinite(c))
+    tail = T.chebyshev_tails("ppr", alpha, K + 1)[K]
+    assert abs(c.sum() - 1.0) <= tail + 1e-12
+    alt = np.sum(c * (-1.0) ** np.arange(K + 1))
+    assert abs(alt - alpha / (2 - alpha)) <= tail + 1e-12
+
+
+def test_truncation_step_limits(cp):
+    """A K beyond the library's cap gives CP_EKMAX rather than a wrong K."""
+    K, _ = cp.cp_choose_K(cp.CP_PPR, 0.2, 1e-9, 1, 0, 1e6, 1.0)
+    assert 1 <= K < 200
+    with pytest.raises(cp.ChebypropError) as ei:
+        cp.cp_choose_K(cp.CP_PPR, 1e-7, 1e-14, 0, 0, 1e9, 1.0)
+    assert ei.value.status == cp.CP_EKMAX
