@@ -219,17 +219,19 @@ def test_bitwise_reproducible_and_timing(torch):
     assert b.info["elapsed_ms"] > 0 and 0 < b.info["step_ms"] <= b.info["elapsed_ms"]
 
 
-def test_bf16_storage_error_reported(torch):
+@pytest.mark.parametrize("stripes", [False, True])
+def test_bf16_storage_error_reported(torch, stripes):
     g = synth.chung_lu(100_000, 900_000, 2.3, seed=2)
     P = PR.transition_matrix(g.row_ptr, g.col_idx)
-    G = gpu_graph(g)
+    G = gpu_graph(g, stripes=stripes)
     s = int(synth.sources(g, 1, seed=4)[0])
-    _print_case("bf16", s)
-    r = G.power("ppr", 0.2, s, tol=1e-6, prec="bf16")
-    ref = oracle_yK(g, s, "ppr", 0.2, r.info["K"], P)
-    m = compare(r.y.cpu().numpy(), ref)
-    print("bf16 storage error vs FP64 oracle:", m)
-    assert m["l1"] < 2e-2
+    _print_case("bf16", stripes, s)
+    for kind, param in (("ppr", 0.2), ("hkpr", 5.0)):
+        r = G.power(kind, param, s, tol=1e-6, prec="bf16")
+        ref = oracle_yK(g, s, kind, param, r.info["K"], P)
+        m = compare(r.y.cpu().numpy(), ref)
+        print("bf16 storage error vs FP64 oracle:", kind, stripes, m)
+        assert m["l1"] < 2e-2
 
 
 @pytest.mark.slow
