@@ -499,7 +499,7 @@ cp_status cp_graph_create(int64_t n, int64_t nnz, const int64_t* row_ptr, const 
       std::stable_sort(perm.begin(), perm.end(),
                        [&](int32_t a, int32_t b) { return g->degree[a] > g->degree[b]; });
       if (striped) {
-        // degree rank r -> stripe r % 8, position r / 8 (stripes contiguous)
+        // degree rank r -> stripe r % S, position r / S (stripes contiguous)
         std::vector<int32_t> by_rank(perm);
         int64_t start[kMaxStripes + 1] = {0};
         for (int j = 0; j < S; ++j) start[j + 1] = start[j] + (n - j + S - 1) / S;

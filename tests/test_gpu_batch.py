@@ -60,11 +60,15 @@ def test_batch_columns_match_oracle(torch, mid_graph, bw, prec):
             assert m["l1"] <= 2e-6, (j, m)
 
 
-def test_batch_equals_single_source_f64(torch, mid_graph):
+@pytest.mark.parametrize("stripes", [False, True])
+def test_batch_equals_single_source_f64(torch, mid_graph, stripes):
+    """Batch columns equal single-source runs on the same graph; on the
+    XCD-striped layout the single runs take the striped step kernels and the
+    batch the row-tiled ones over the same relabelled CSR."""
     g = mid_graph
-    G = gpu_graph(g)
+    G = gpu_graph(g, stripes=stripes)
     qs, meta = _queries(g, 12, seed=5)
-    print("CASE batch-vs-single", flush=True)
+    print("CASE batch-vs-single", stripes, flush=True)
     Y, infos = G.power_batch(qs, prec="f64")
     for j, (kind, param, s) in enumerate(meta):
         r = G.power(kind, param, s, tol=qs[j].tol, prec="f64")

@@ -32,17 +32,18 @@ def _mixed_queries(g, n, seed):
     return [cp.make_query(*kinds[i % 5], int(srcs[i]), float(tols[i])) for i in range(n)]
 
 
-def test_server_results_equal_single_queries_f64(torch, graph):
+@pytest.mark.parametrize("layout", ["degree", "stripes"])
+def test_server_results_equal_single_queries_f64(torch, graph, layout):
     from paper_2412_10789_amd import chebyprop as cp
 
     g = graph
-    G = gpu_graph(g, reorder=True)
+    G = gpu_graph(g, reorder=layout == "degree", stripes=layout == "stripes")
     per_tile = 3 * g.n * 16 * 8
     S = cp.Server(G, hbm_budget_bytes=2 * per_tile + 4096, prec="f64")
     assert S.stats()["slots"] == 32 and S.stats()["tile_width"] == 16
     qs = _mixed_queries(g, 70, seed=2)
     ys = [torch.full((g.n,), -1.0, dtype=torch.float64, device="cuda") for _ in qs]
-    print("CASE server-f64", flush=True)
+    print("CASE server-f64", layout, flush=True)
     tickets = [S.submit(q, y) for q, y in zip(qs, ys)]
     infos = []
     for t in tickets:
