@@ -658,6 +658,69 @@ def run_push_rw(args, torch, cp, synth, g):
                         "against a plain-C FP64 PwMethod with tail 1e-15", "rows": rows}
 
 
+def run_latency(args, torch, cp, synth):
+    """Query latency where launches dominate: PPR alpha = 0.2, FP64, l1
+    tolerance 1e-8 (certified K) on the small Chung-Lu graph (n = 20,000,
+    average degree 10, exponent 2.5).  The same query is issued eagerly and
+    as a replay of a HIP graph that captured it (the library issues kernels
+    only, with coefficients and ids as kernel arguments); every replay must
+    equal the eager result bit for bit."""
+    g = synth.chung_lu(20_000, 100_000, 2.5, seed=1)
+    s = int(synth.sources(g, 1, seed=5)[0])
+    G = cp.Graph(g.row_ptr, g.col_idx)
+    Gc = cp.Graph(g.row_ptr, g.col_idx)  # its workspace stays bound to the captured graph
+    y = torch.empty(g.n, dtype=torch.float64, device="cuda")
+    yc = torch.empty(g.n, dtype=torch.float64, device="cuda")
+    q = dict(kind="ppr", param=0.2, source=s, tol=1e-8, prec="f64")
+    st = torch.cuda.current_stream()
+    K = G.power(**q, y=y).info["K"]
+    ref = y.clone()
+
+    def one(fn, reps):
+        lat = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            fn()
+            st.synchronize()
+            lat.append((time.perf_counter() - t0) * 1e6)
+        lat.sort()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        st.synchronize()
+        return lat[len(lat) // 2], (time.perf_counter() - t0) * 1e6 / reps
+
+    eager = lambda: G.power(**q, y=y, stream=st.cuda_stream)
+    one(eager, 20)
+    e_p50, e_pipe = one(eager, 200)
+    Gc.power(**q, y=yc)  # sizes the workspace outside the capture
+    st.synchronize()
+    hg = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(hg):
+        Gc.power(**q, y=yc, stream=torch.cuda.current_stream().cuda_stream)
+    replay = hg.replay
+    one(replay, 20)
+    yc.fill_(-1.0)
+    g_p50, g_pipe = one(replay, 200)
+    same = bool(torch.equal(yc, ref))
+    G.close()
+    out = {"workload": "PPR alpha=0.2, 1 source, FP64, l1 tol 1e-8 (certified K) on a Chung-Lu graph "
+                       f"n={g.n}, nnz={g.nnz}, exponent 2.5 (caller order)",
+           "K": K, "eager_us_p50": round(e_p50, 1), "eager_us_back_to_back": round(e_pipe, 1),
+           "hipgraph_us_p50": round(g_p50, 1), "hipgraph_us_back_to_back": round(g_pipe, 1),
+           "hipgraph_equals_eager": same}
+    if not args.no_cpu:
+        from oracle import propagation as PR
+
+        P = PR.transition_matrix(g.row_ptr, g.col_idx)
+        exact = PR.ground_truth(P, s, "ppr", 0.2)
+        out["l1_vs_fp64_fixed_point"] = float(np.abs(ref.cpu().numpy() - exact).sum())
+    log(f"[latency] {out}")
+    if not same:
+        raise RuntimeError("HIP graph replay differs from the eager query")
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -683,6 +746,8 @@ def main() -> int:
                     help="eps_a values of the ChebyPush measurement (none: skip it)")
     ap.add_argument("--no-push-rw", action="store_true", help="skip the ChebyPush + random walk measurement")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle legs")
+    ap.add_argument("--no-latency", action="store_true",
+                    help="skip the small-graph latency measurement (eager vs HIP graph replay)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run a plain 1 GiB device copy first (counter scaling for rocprofv3 --pmc)")
     ap.add_argument("--large", action="store_true",
@@ -801,6 +866,8 @@ def main() -> int:
         }
     g_main = S["g"]
     del S
+    if not args.no_latency:
+        result["latency"] = run_latency(args, torch, cp, synth)
     if args.kvn_tol > 0:
         result["cheby_vs_power"] = run_kvn(args, torch, cp, synth, g_main)
     if args.propagate_cols > 0:

@@ -138,7 +138,7 @@ def test_autotune_picks_a_width(torch, mid_graph):
 
 
 @pytest.mark.slow
-def test_config3_full_size_batch_f32(torch):
+def test_orkut_shape_3m_full_size_batch_f32(torch):
     """The batched workload at full size, as the benchmark runs it: Chung-Lu
     n=3M, ~117M edges, exponent 2.2; 64 PPR alpha=0.2 sources with
     tolerances drawn from {1e-4, 1e-6, 1e-7}, certified K, FP32 storage,
@@ -153,13 +153,13 @@ def test_config3_full_size_batch_f32(torch):
     tols = [float(t) for t in synth.tolerance_choice(3, 64, (1e-4, 1e-6, 1e-7))]
     qs = [cp.make_query("ppr", 0.2, s, t) for s, t in zip(srcs, tols)]
     bw = G.autotune_batch(qs, prec="f32")
-    print("CASE config3 width", bw, flush=True)
+    print("CASE batch 3M width", bw, flush=True)
     Y, infos = G.power_batch(qs, prec="f32")
     cols = [min(range(64), key=lambda i: tols[i]), 0, 63]
     for j in cols:
         ref = oracle_yK(g, srcs[j], "ppr", 0.2, infos[j]["K"], P)
         m = compare(Y[:, j].double().cpu().numpy(), ref)
-        print("config3 column", j, tols[j], infos[j]["K"], m, flush=True)
+        print("batch 3M column", j, tols[j], infos[j]["K"], m, flush=True)
         # FP32 storage with double sums: rounding well below the tightest tolerance
         assert m["l1"] <= 1e-7, (j, m)
     G.close()

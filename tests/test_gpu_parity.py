@@ -54,14 +54,14 @@ def test_tiny_graphs_f64(torch, kind, param):
         np.testing.assert_allclose(r.y.cpu().numpy(), ref, atol=1e-13, rtol=1e-12)
 
 
-def test_config1_shape_f64(torch):
+def test_chung_lu_20k_f64(torch):
     """n=20,000 Chung-Lu, avg degree 10, exponent 2.5, PPR alpha=0.2, FP64,
     K certified for l1 <= 1e-8 against the exact vector."""
     g = synth.chung_lu(20_000, 100_000, 2.5, seed=1)
     P = PR.transition_matrix(g.row_ptr, g.col_idx)
     G = gpu_graph(g)
     for s in synth.sources(g, 4, seed=1):
-        _print_case("config1", int(s))
+        _print_case("20k", int(s))
         r = G.power("ppr", 0.2, int(s), tol=1e-8, prec="f64", flags=1)
         y = r.y.cpu().numpy()
         ref_K = oracle_yK(g, s, "ppr", 0.2, r.info["K"], P)
@@ -235,7 +235,7 @@ def test_bf16_storage_error_reported(torch, stripes):
 
 
 @pytest.mark.slow
-def test_config2_full_size_f32(torch):
+def test_livejournal_shape_4m_full_size_f32(torch):
     """Chung-Lu n=4M, ~35M edges, exponent 2.3; HKPR t=5, FP32, l1 <= 1e-6
     against the FP64 oracle for sampled sources (full vectors)."""
     g = synth.chung_lu(4_000_000, 35_000_000, 2.3, seed=2)
@@ -245,13 +245,13 @@ def test_config2_full_size_f32(torch):
         if layout == "stripes":
             assert G.stats["stripe_packed"] == 1 and G.stats["stripe_count"] == 4
         for s in synth.sources(g, 2, seed=2):
-            _print_case("config2", layout, int(s))
+            _print_case("4M", layout, int(s))
             r = G.power("hkpr", 5.0, int(s), tol=1e-6, prec="f32")
             y = r.y.cpu().numpy()
             ref = oracle_yK(g, s, "hkpr", 5.0, r.info["K"], P)
             exact = PR.ground_truth(P, int(s), "hkpr", 5.0, tol=1e-12)
             m = compare(y, ref)
-            print("config2", layout, int(s), r.info["K"], m, "vs exact", E.l1(y, exact), flush=True)
+            print("4M", layout, int(s), r.info["K"], m, "vs exact", E.l1(y, exact), flush=True)
             assert m["l1"] <= 2e-6
             assert E.l1(y, exact) <= 1e-6
         G.close()

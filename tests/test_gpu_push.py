@@ -62,7 +62,7 @@ def test_tiny_graphs(torch):
 
 
 @pytest.mark.parametrize("layout", ["native", "degree", "stripes"])
-def test_config1_shape(torch, layout):
+def test_chung_lu_20k(torch, layout):
     """n=20,000 Chung-Lu: local (small eps_a frontier) and nearly global runs,
     in three graph layouts (results in caller ids)."""
     g = synth.chung_lu(20_000, 100_000, 2.5, seed=1)
@@ -70,7 +70,7 @@ def test_config1_shape(torch, layout):
     for s in synth.sources(g, 2, seed=5):
         for kind, param, eps_a in (("ppr", 0.2, 1e-4), ("hkpr", 5.0, 1e-5), ("ppr", 0.1, 1e-7)):
             K = T.choose_K(kind, param, eps_a / 2, mode="tail")
-            _case("push-config1", layout, int(s), kind, eps_a)
+            _case("push-20k", layout, int(s), kind, eps_a)
             _check(G, g, int(s), kind, param, K, eps_a)
 
 

@@ -64,7 +64,7 @@ def test_tiny_graphs_identical_walks(torch):
     assert exact_cases >= 6  # the symmetric star and path can tie
 
 
-def test_config1_walks_and_accuracy(torch):
+def test_chung_lu_20k_walks_and_accuracy(torch):
     """n=20,000 Chung-Lu: identical walks with a threshold that leaves mass to
     the walks, and Alg. 5's guarantee against the exact vector."""
     g = synth.chung_lu(20_000, 100_000, 2.5, seed=1)
@@ -74,7 +74,7 @@ def test_config1_walks_and_accuracy(torch):
     delta = 1.0 / g.n
     for s in synth.sources(g, 2, seed=21):
         s = int(s)
-        _case("rw-config1", s)
+        _case("rw-20k", s)
         r, tr, exact = _check(G, g, s, alpha, eps_r, delta, 99, 2e-4, 6)
         assert exact and tr["walks"].sum() > 1000
         exact = PR.ground_truth(P, s, "ppr", alpha)

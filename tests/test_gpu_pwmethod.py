@@ -48,7 +48,7 @@ def test_small_N_on_tiny_graphs(torch):
 
 
 @pytest.mark.parametrize("layout", ["native", "degree", "stripes"])
-def test_config1_exact_error_identity_f64(torch, layout):
+def test_chung_lu_20k_exact_error_identity_f64(torch, layout):
     """n=20,000 Chung-Lu: GPU Alg. 1 equals the oracle's Alg. 1 at the same N,
     and its l1 error against f(P) e_s equals the Taylor tail."""
     g = synth.chung_lu(20_000, 100_000, 2.5, seed=1)
@@ -58,7 +58,7 @@ def test_config1_exact_error_identity_f64(torch, layout):
         exact_by_src = {}
         for s in synth.sources(g, 2, seed=3):
             s = int(s)
-            _case("pw-config1", layout, kind, s)
+            _case("pw-20k", layout, kind, s)
             r = G.power(kind, param, s, tol=tol, prec="f64", method="power", flags=1)
             N = r.info["K"]
             assert N == T.pwmethod_steps(kind, param, tol)

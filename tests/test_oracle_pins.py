@@ -18,7 +18,7 @@ def test_pin(pin):
     pin()
 
 
-def test_config1_shape_against_krylov_solve():
+def test_chung_lu_20k_against_krylov_solve():
     """Chung-Lu n=20,000, avg degree 10, exponent 2.5, PPR alpha=0.2:
     ChebyPower at the certified K meets l1 <= 1e-8 against a Krylov (GMRES)
     solve of Def. 3's linear system, whose own l1 error is bounded by the
