@@ -224,17 +224,17 @@ Plan build_plan(const int64_t* rp, int64_t n, int64_t long_threshold) {
     const int64_t d = rp[hubs[h] + 1] - rp[hubs[h]];
     const int32_t nseg = (int32_t)((d + kHubSeg - 1) / kHubSeg);
     p.hubs.push_back(HubDesc{hubs[h], nseg, base, 0});
-    for (int32_t s = 0; s < nseg; ++s) p.blocks.push_back(BlockDesc{hubs[h], (int32_t)h, kHub, s});
+    for (int32_t s = 0; s < nseg; ++s) p.blocks.push_back(BlockDesc{hubs[h], (int32_t)h, kHub, s, 0, 0});
     base += nseg;
   }
   p.hub_segments = base;
-  for (int32_t v : longs) p.blocks.push_back(BlockDesc{v, v + 1, kLong, 0});
+  for (int32_t v : longs) p.blocks.push_back(BlockDesc{v, v + 1, kLong, 0, 0, 0});
   p.nlong = (int64_t)longs.size();
   p.nspecial = (int64_t)p.blocks.size();
   // greedy stream tiles over the remaining rows, in row order
   int64_t r0 = -1, nnz = 0;
   auto close = [&](int64_t r1) {
-    if (r0 >= 0) p.blocks.push_back(BlockDesc{(int32_t)r0, (int32_t)r1, kStream, 0});
+    if (r0 >= 0) p.blocks.push_back(BlockDesc{(int32_t)r0, (int32_t)r1, kStream, (int32_t)nnz, rp[r0], 0});
     r0 = -1;
     nnz = 0;
   };

@@ -40,7 +40,10 @@ struct BlockDesc {
   int32_t r0;    // first row
   int32_t r1;    // one past the last row (stream, long); hub id (hub)
   int32_t kind;  // BlockKind
-  int32_t aux;   // hub: segment index within the row
+  int32_t aux;   // stream: arc count; hub: segment index within the row
+  int64_t p0;    // stream: CSR offset of the tile's first arc (so the column
+                 // stream starts without waiting for the row offsets)
+  int64_t pad;
 };
 
 struct HubDesc {

@@ -94,6 +94,20 @@ __device__ __forceinline__ void row_update(T* z, A* yacc, int64_t v, A acc, int3
   st_stream(yacc + v, ld_stream(yacc + v) + c * zn);
 }
 
+// row_update with z(v) and yacc(v) already loaded (as zold, yold).
+template <typename T, typename A, int MODE>
+__device__ __forceinline__ void row_update_loaded(T* z, A* yacc, int64_t v, A acc, int32_t d, A c, A zold, A yold) {
+  A zn;
+  if constexpr (MODE == kStepAdd) {
+    st_stream(z + v, from_acc<T>(zold + acc));
+    return;
+  }
+  if constexpr (MODE == kStepPower) zn = acc / A(d);
+  else zn = (A(2) * acc) / A(d) - zold;
+  st_stream(z + v, from_acc<T>(zn));
+  st_stream(yacc + v, yold + c * zn);
+}
+
 // Whole-workgroup gather-sum of x over arcs [p0, p1); result valid in thread 0.
 template <typename T, typename A>
 __device__ __forceinline__ A block_gather_sum(const int32_t* __restrict__ col, const T* __restrict__ x,
@@ -216,11 +230,20 @@ __global__ void __launch_bounds__(kThreads) step_kernel(StepArgs a) {
   const A c = (A)a.c;
 
   if (bd.kind == kStream) {
+    static_assert(kTileRows <= kThreads, "one row of a stream tile per thread");
     const int32_t r0 = bd.r0, nr = bd.r1 - bd.r0;
-    const int64_t p0 = rp[r0];
-    const int32_t cnt = (int32_t)(rp[bd.r1] - p0);
+    const int64_t p0 = bd.p0;
+    const int32_t cnt = bd.aux;
+    // Thread j's row: its old z and estimate are loaded now, beside the
+    // column stream and the gathers, not after the row sums.
+    const bool own = tid < nr;
+    A zold = A(0), yold = A(0);
+    if (own) {
+      if constexpr (MODE != kStepPower) zold = to_acc(ld_stream(z + r0 + tid));
+      if constexpr (MODE != kStepAdd) yold = ld_stream(yacc + r0 + tid);
+    }
     for (int j = tid; j <= nr; j += kThreads) rpl[j] = (int32_t)(rp[r0 + j] - p0);
-    for (int j = tid; j < nr; j += kThreads) rowsum[j] = A(0);
+    if (own) rowsum[tid] = A(0);
 
     // Phase 1: coalesced stream of the tile's column ids, gather, stage in LDS.
     int32_t idx[kPerThread];
@@ -242,9 +265,9 @@ __global__ void __launch_bounds__(kThreads) step_kernel(StepArgs a) {
     tile_rowsums<kPerThread, A, A>(vals, rpl, nr, cnt, rowsum, wsum, wflag);
 
     // Phase 3: row-parallel recurrence and accumulation.
-    for (int j = tid; j < nr; j += kThreads) {
-      const int32_t d = rpl[j + 1] - rpl[j];
-      if (d > 0) row_update<T, A, MODE>(z, yacc, (int64_t)r0 + j, rowsum[j], d, c);
+    if (own) {
+      const int32_t d = rpl[tid + 1] - rpl[tid];
+      if (d > 0) row_update_loaded<T, A, MODE>(z, yacc, (int64_t)r0 + tid, rowsum[tid], d, c, zold, yold);
     }
     return;
   }

@@ -124,10 +124,10 @@ __global__ void __launch_bounds__(kThreads) batch_step_kernel(BatchStepArgs a) {
 
   if (bd.kind == kStream) {
     const int32_t r0 = bd.r0, nr = bd.r1 - bd.r0;
-    const int64_t p0 = rp[r0];
-    const int32_t cnt = (int32_t)(rp[bd.r1] - p0);
-    for (int j = tid; j <= nr; j += kThreads) rpl[j] = (int32_t)(rp[r0 + j] - p0);
+    const int64_t p0 = bd.p0;
+    const int32_t cnt = bd.aux;
     for (int i = tid; i < cnt; i += kThreads) cols[i] = ld_nt(col + p0 + i);
+    for (int j = tid; j <= nr; j += kThreads) rpl[j] = (int32_t)(rp[r0 + j] - p0);
     __syncthreads();
     // rows of this group: those starting in arc range [grp*cnt/G, (grp+1)*cnt/G)
     auto first_row_at = [&](int target) {  // smallest j with rpl[j] >= target
