@@ -28,10 +28,12 @@ Modules
                 (Def. 7), with the two threshold readings of Sec. 4
   bidirectional ChebyPush + alpha-random walks for SSPPR (Alg. 5), walks
                 drawn from SplitMix64 counters
+  circulant     closed forms on circulant graphs through the DFT (exact
+                vectors and Algorithm 3's output at any size)
   generalized   Z = f(D^{-a} A D^{-b}) X (Def. 8) through Thm. 5: the series
                 of Alg. 3 / Alg. 1 on D^{a} X, scaled by D^{-a}
   native        the same Alg. 3 / Alg. 1 in plain C with an OpenMP node
                 loop (oracle/c/chebypower.c), for graphs with billions of arcs
 """
 
-from . import bidirectional, coefficients, dense, errors, generalized, propagation, push, truncation  # noqa: F401,E501
+from . import bidirectional, circulant, coefficients, dense, errors, generalized, propagation, push, truncation  # noqa: F401,E501

@@ -18,6 +18,7 @@ import scipy.special as ss
 import synth
 from conftest import load_golden
 from oracle import bidirectional as BI
+from oracle import circulant as CI
 from oracle import coefficients as C
 from oracle import dense as D
 from oracle import errors as E
@@ -100,6 +101,29 @@ def pin_cycle_closed_form():
         K = T.choose_K(kind, p, 1e-14, mode="tail")
         y = PR.cheby_power(P, s, C.chebyshev_coeffs(kind, p, K), K)
         np.testing.assert_allclose(y, exact, atol=1e-13)
+
+
+def pin_circulant_closed_forms():
+    """Circulant graphs (a band and an irregular symmetric offset set, n a
+    power of two and not): the DFT forms of f(P) e_s and of
+    sum_k c_k T_k(P) e_s against the dense definitions (Def. 3 solve,
+    Def. 4 expm) and against Algorithm 3 with sparse products; the CSR
+    builder against the edge set it should hold."""
+    for n, offs in ((64, CI.offsets_band(3)), (50, np.array([-12, -5, -1, 1, 5, 12]))):
+        rp, ci = CI.csr(n, offs)
+        want = {(v, (v + int(o)) % n) for v in range(n) for o in offs}
+        got = {(v, int(c)) for v in range(n) for c in ci[rp[v]:rp[v + 1]]}
+        assert got == want and len(got) == ci.shape[0]
+        assert all((b, a) in got for a, b in got) and all(a != b for a, b in got)
+        A = D.adjacency(rp, ci)
+        P = PR.transition_matrix(rp, ci)
+        for s in (0, 7):
+            np.testing.assert_allclose(CI.exact(n, offs, s, "ppr", 0.2), D.ppr_solve(A, s, 0.2), atol=1e-13)
+            np.testing.assert_allclose(CI.exact(n, offs, s, "hkpr", 3.0), D.hkpr_expm(A, s, 3.0), atol=1e-13)
+            for kind, p, K in (("ppr", 0.2, 6), ("hkpr", 5.0, 11)):
+                c = C.chebyshev_coeffs(kind, p, K)
+                np.testing.assert_allclose(CI.cheby_truncated(n, offs, s, c), PR.cheby_power(P, s, c, K),
+                                           atol=1e-13)
 
 
 def pin_complete_closed_form():
@@ -586,6 +610,7 @@ ALL_PINS = [
     pin_mass,
     pin_cycle_closed_form,
     pin_complete_closed_form,
+    pin_circulant_closed_forms,
     pin_ppr_closed_values,
     pin_coefficient_integrals,
     pin_hkpr_library,

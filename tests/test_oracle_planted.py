@@ -115,6 +115,19 @@ def _clenshaw_final_doubled(P, x, c, K):
     return c[0] * x + 2.0 * (P @ b1) - b2
 
 
+def _circulant_shift_backwards(n, offsets, s, g_lam):
+    from oracle import circulant as CI
+
+    return CI.__dict__["_orig_apply_spectral"](n, offsets, -s, g_lam)
+
+
+def _circulant_eigenvalues_unnormalised(n, offsets):
+    offsets = np.asarray(offsets, dtype=np.int64)
+    p = np.zeros(n)
+    np.add.at(p, offsets % n, 1.0)
+    return np.clip(np.fft.fft(p).real, -1.0, 1.0)
+
+
 MISTAKES = {
     "recurrence sign": ("propagation", "_chebyshev_step", _wrong_sign_step),
     "recurrence factor 2": ("propagation", "_chebyshev_step", _missing_factor_two_step),
@@ -134,6 +147,8 @@ MISTAKES = {
     "residual sign flipped": ("bidirectional", "residual", _residual_sign_flipped),
     "Clenshaw without -b_{k+2}": ("generalized", "_clenshaw_step", _clenshaw_without_b2),
     "Clenshaw last step with 2 P b_1": ("generalized", "clenshaw_vector", _clenshaw_final_doubled),
+    "circulant shift by -s": ("circulant", "apply_spectral", _circulant_shift_backwards),
+    "circulant eigenvalues without 1/|O|": ("circulant", "eigenvalues", _circulant_eigenvalues_unnormalised),
 }
 
 
@@ -145,6 +160,7 @@ def test_planted_mistake_is_caught(name, monkeypatch):
     mod = getattr(oracle, modname)
     # keep the real function reachable for wrappers that delegate to it
     monkeypatch.setitem(PR.__dict__, "_orig_" + attr, getattr(mod, attr))
+    monkeypatch.setitem(mod.__dict__, "_orig_" + attr, getattr(mod, attr))
     monkeypatch.setattr(mod, attr, fake)
     if modname == "coefficients" and attr in ("ppr_chebyshev_coeffs", "hkpr_chebyshev_coeffs"):
         # chebyshev_coeffs dispatches through module globals: patched above
