@@ -6,7 +6,9 @@ offsets that do not fit 32 bits.  The single-CSR layout, the XCD-striped
 layout and the batched kernel run on it, and every result is checked
 against the oracle's DFT closed forms: Algorithm 3's output at the GPU's K
 (rounding error of FP32 storage) and the exact vector f(P) e_s (the
-certified tolerance).  Sources sit next to the wrap-around rows, whose
+certified tolerance).  FP64 ChebyPower and ChebyPush without a threshold
+(Alg. 4 with eps_a = 0, which is Algorithm 3 with the terms c_0..c_{K-1})
+run on the same graph.  Sources sit next to the wrap-around rows, whose
 columns are not sorted, and in the middle of the ring."""
 
 import numpy as np
@@ -88,6 +90,37 @@ def test_batch_beyond_2_31_arcs(torch, circulant):
         for j, q in enumerate(qs):
             kind = "hkpr" if q.kind == 1 else "ppr"
             _check(Yh[:, j], offs, q.source, kind, q.param, infos[j]["K"])
+    finally:
+        G.close()
+        torch.cuda.empty_cache()
+
+
+def test_f64_and_chebypush_beyond_2_31_arcs(torch, circulant):
+    from paper_2412_10789_amd.chebyprop import CP_Q_STATS, Graph
+
+    offs, rp, ci = circulant
+    _case("large offsets f64/push create")
+    G = Graph(rp, ci)
+    try:
+        s = SOURCES[0]
+        _case("large offsets f64", s)
+        r = G.power("hkpr", 5.0, s, tol=1e-9, prec="f64")
+        K = r.info["K"]
+        yK = CI.cheby_truncated(N, offs, s, C.chebyshev_coeffs("hkpr", 5.0, K))
+        y = r.y.cpu().numpy()
+        # the DFT form itself carries about 1e-17 of rounding per entry
+        assert E.l1(y, yK) <= 1e-9 and E.max_abs(y, yK) <= 1e-13, (E.l1(y, yK), E.max_abs(y, yK))
+        assert E.l1(y, CI.exact(N, offs, s, "hkpr", 5.0)) <= 1e-9
+        # K = 80: the frontier passes nnz / 128 of volume, so late iterations are dense
+        for kind, param, K in (("ppr", 0.2, 80), ("hkpr", 5.0, 14)):
+            _case("large offsets push eps 0", kind, s)
+            r = G.push(kind, param, s, 0.0, kmode="fixed", K=K, flags=CP_Q_STATS)
+            ref = CI.cheby_truncated(N, offs, s, C.chebyshev_coeffs(kind, param, K)[:K])
+            y = r.y.cpu().numpy()
+            m = (E.l1(y, ref), E.max_abs(y, ref))
+            print("circulant 2^22 push eps 0", kind, K, m, r.info["pushes"], r.info["arcs"], flush=True)
+            assert m[0] <= 1e-9 and m[1] <= 1e-13, m
+            assert r.info["arcs"] == r.info["pushes"] * 2 * H
     finally:
         G.close()
         torch.cuda.empty_cache()
