@@ -136,48 +136,55 @@ def run_single(args, torch, cp, synth):
     Y = torch.empty((nsrc, g.n), dtype=G.out_dtype(cp.PRECS[prec]), device="cuda")
     stream = torch.cuda.current_stream().cuda_stream
 
-    def one_step(timing: bool):
+    def one_step(timing: bool, p: str, Yp):
         # HIP events time every step of the last query of the step; that
         # query's CP_Q_TIMING synchronises, so the other queries are queued
         # behind it without a host round trip each
         infos = []
         for i, s in enumerate(srcs):
             timed = timing and i == nsrc - 1
-            r = G.power(kind, param, s, tol=tol, prec=prec, flags=cp.CP_Q_TIMING if timed else 0,
-                        y=Y[i], stream=stream)
+            r = G.power(kind, param, s, tol=tol, prec=p, flags=cp.CP_Q_TIMING if timed else 0,
+                        y=Yp[i], stream=stream)
             infos.append(r.info)
         return infos
 
-    for _ in range(args.warmup):
-        one_step(False)
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    infos = []
-    torch.cuda.synchronize()
-    w0 = time.perf_counter()
-    ev0.record()
-    for _ in range(args.steps):
-        infos += one_step(True)
-    ev1.record()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - w0
-    total_s = max(wall, ev0.elapsed_time(ev1) * 1e-3)
+    def timed_run(p: str, Yp, warmup: int):
+        for _ in range(warmup):
+            one_step(False, p, Yp)
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        infos = []
+        torch.cuda.synchronize()
+        w0 = time.perf_counter()
+        ev0.record()
+        for _ in range(args.steps):
+            infos += one_step(True, p, Yp)
+        ev1.record()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - w0
+        total_s = max(wall, ev0.elapsed_time(ev1) * 1e-3)
+        arcs = sum((inf["K"] - 1) * g.nnz + int(g.degrees[s]) for inf, s in zip(infos, srcs * args.steps))
+        timed = [inf for inf in infos if inf["step_ms"] == inf["step_ms"]]  # not NaN: the timed queries
+        launches = sum(inf["steps"] for inf in timed)
+        avg_step_ms = sum(inf["step_ms"] for inf in timed) / max(launches, 1)
+        bpl = step_bytes(g.n, g.nnz, p)
+        Ks = [inf["K"] for inf in infos[:nsrc]]
+        log(f"[single] {p}: K per source: {Ks}; avg step kernel {avg_step_ms * 1e3:.1f} us; "
+            f"wall {wall * 1e3:.1f} ms")
+        return dict(value=arcs / total_s / 1e9, total_s=total_s, launches=launches, bpl=bpl,
+                    achieved=bpl / (avg_step_ms * 1e-3) / 1e9, avg_step_ms=avg_step_ms, Ks=Ks)
 
-    deg = g.degrees
-    arcs = sum((inf["K"] - 1) * g.nnz + int(deg[s]) for inf, s in zip(infos, srcs * args.steps))
-    timed = [inf for inf in infos if inf["step_ms"] == inf["step_ms"]]  # not NaN: the timed queries
-    launches = sum(inf["steps"] for inf in timed)
-    avg_step_ms = sum(inf["step_ms"] for inf in timed) / max(launches, 1)
-    bpl = step_bytes(g.n, g.nnz, prec)
-    achieved = bpl / (avg_step_ms * 1e-3) / 1e9
-    Ks = [inf["K"] for inf in infos[:nsrc]]
-    log(f"[single] K per source: {Ks}; avg step kernel {avg_step_ms * 1e3:.1f} us; wall {wall * 1e3:.1f} ms")
-    out = dict(
-        value=arcs / total_s / 1e9, total_s=total_s, launches=launches, bpl=bpl,
-        achieved=achieved, avg_step_ms=avg_step_ms, Ks=Ks, g=g, srcs=srcs, Y=Y, layout=args.layout,
-        create_s=create_s, kind=kind, param=param, tol=tol, nsrc=nsrc, prec=prec,
+    out = timed_run(prec, Y, args.warmup)
+    out.update(
+        g=g, srcs=srcs, Y=Y, layout=args.layout, create_s=create_s, kind=kind, param=param, tol=tol, nsrc=nsrc,
+        prec=prec,
         workload=f"{args.workload}: HKPR t={param}, {nsrc} sources one at a time, tol {tol} l1 (certified K), "
                  f"Chung-Lu n={n_t} m={m_t} gamma={gamma} seed={seed}",
     )
+    if not args.no_bf16:
+        # the same queries with BF16 vector storage (float arithmetic and estimate)
+        Yb = torch.empty((nsrc, g.n), dtype=torch.float32, device="cuda")
+        out["bf16"] = timed_run("bf16", Yb, 1)
+        out["bf16"]["Y"] = Yb
     G.close()
     return out
 
@@ -746,6 +753,8 @@ def main() -> int:
                     help="eps_a values of the ChebyPush measurement (none: skip it)")
     ap.add_argument("--no-push-rw", action="store_true", help="skip the ChebyPush + random walk measurement")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle legs")
+    ap.add_argument("--no-bf16", action="store_true",
+                    help="skip the main line's BF16-storage variant")
     ap.add_argument("--no-latency", action="store_true",
                     help="skip the small-graph latency measurement (eager vs HIP graph replay)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -864,6 +873,28 @@ def main() -> int:
             "agrees_with_scipy_oracle_l1": agree,
             "host": {"nproc": os.cpu_count(), "cpu_model": cpu_model()},
         }
+    if "bf16" in S:
+        B = S["bf16"]
+        entry = {
+            "workload": "the main line's queries (same graph, sources, steps and layout) with BF16 vector "
+                        "storage: float arithmetic and a float estimate",
+            "value": round(B["value"], 3), "unit": "GTEPS", "ms_per_step": round(B["total_s"] * 1e3 / args.steps, 4),
+            "K_per_source": B["Ks"],
+            "roofline": {"bound": "hbm", "achieved": round(B["achieved"], 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                         "frac": round(B["achieved"] / HBM_PEAK_GBPS, 4), "bytes_per_launch": B["bpl"],
+                         "avg_launch_us": round(B["avg_step_ms"] * 1e3, 2)},
+        }
+        if not args.no_cpu:
+            l1b, maxb = [], []
+            for i, (s, K, c, y_ref) in enumerate(refs):
+                if B["Ks"][i] != K:
+                    raise RuntimeError("BF16 query took another K than the FP32 one")
+                y_b = B["Y"][i].double().cpu().numpy()
+                l1b.append(E.l1(y_b, y_ref))
+                maxb.append(E.max_abs(y_b, y_ref))
+            entry["accuracy_vs_fp64_oracle"] = {"sources": len(refs), "max_l1": max(l1b), "max_abs": max(maxb)}
+        log(f"[single] bf16 storage: {entry}")
+        result["storage_bf16"] = entry
     g_main = S["g"]
     del S
     if not args.no_latency:
