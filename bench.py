@@ -201,30 +201,35 @@ def run_batch(args, torch, cp, synth):
     bw = G.autotune_batch(qs, prec=prec)
     log(f"[batch] autotuned source-tile width {bw}")
     qt = [cp.make_query("ppr", alpha, s, t, flags=cp.CP_Q_TIMING) for s, t in zip(srcs, tols)]
-    Yb = torch.empty((g.n, nq), dtype=G.out_dtype(cp.PRECS[prec]), device="cuda")
-    for _ in range(max(1, args.warmup)):
-        G.power_batch(qs, prec=prec, Y=Yb)
-    torch.cuda.synchronize()
     nb = max(1, args.steps // 2)
-    w0 = time.perf_counter()
-    step_ms = 0.0
-    launches = 0
-    infos = None
-    for _ in range(nb):
-        _, infos = G.power_batch(qt, prec=prec, Y=Yb)
-        step_ms += infos[0]["step_ms"]
-        launches += max(i["steps"] for i in infos)  # the batch runs until its longest query is done
-    torch.cuda.synchronize()
-    total_s = time.perf_counter() - w0
-    Ks = [i["K"] for i in infos]
-    arcs = nb * sum((k - 1) * g.nnz for k in Ks)
-    # algorithmic bytes of each launch: sources still active in it
-    per_batch_bytes = 0
-    for k in range(1, max(Ks)):
-        active = sum(1 for K in Ks if K > k)
-        per_batch_bytes += step_bytes(g.n, g.nnz, prec, active)
-    avg_launch_ms = step_ms / max(launches, 1)
-    achieved = per_batch_bytes * nb / (step_ms * 1e-3) / 1e9
+
+    def timed_batches(p: str, Yp):
+        for _ in range(max(1, args.warmup)):
+            G.power_batch(qs, prec=p, Y=Yp)
+        torch.cuda.synchronize()
+        w0 = time.perf_counter()
+        step_ms = 0.0
+        launches = 0
+        infos = None
+        for _ in range(nb):
+            _, infos = G.power_batch(qt, prec=p, Y=Yp)
+            step_ms += infos[0]["step_ms"]
+            launches += max(i["steps"] for i in infos)  # the batch runs until its longest query is done
+        torch.cuda.synchronize()
+        total_s = time.perf_counter() - w0
+        Ks = [i["K"] for i in infos]
+        arcs = nb * sum((k - 1) * g.nnz for k in Ks)
+        # algorithmic bytes of each launch: sources still active in it
+        per_batch_bytes = 0
+        for k in range(1, max(Ks)):
+            active = sum(1 for K in Ks if K > k)
+            per_batch_bytes += step_bytes(g.n, g.nnz, p, active)
+        avg_launch_ms = step_ms / max(launches, 1)
+        achieved = per_batch_bytes * nb / (step_ms * 1e-3) / 1e9
+        return total_s, Ks, arcs, avg_launch_ms, achieved
+
+    Yb = torch.empty((g.n, nq), dtype=G.out_dtype(cp.PRECS[prec]), device="cuda")
+    total_s, Ks, arcs, avg_launch_ms, achieved = timed_batches(prec, Yb)
     out = {
         "workload": f"{args.batch_workload}: {nq} PPR alpha={alpha} sources in one batch, tol per source from "
                     f"{list(tol_choices)} (certified K), Chung-Lu n={n_t} m={m_t} gamma={gamma} seed={seed}",
@@ -251,6 +256,25 @@ def run_batch(args, torch, cp, synth):
         col = Yb[:, j].double().cpu().numpy()
         out["accuracy_vs_fp64_oracle"] = {"column": j, "tol": tols[j], "K": Ks[j],
                                           "l1": E.l1(col, ref), "max_abs": E.max_abs(col, ref)}
+    if not args.no_bf16:
+        # the same batch with BF16 storage (float arithmetic and estimate), its own autotuned width
+        del Yb
+        bwb = G.autotune_batch(qs, prec="bf16")
+        Ybb = torch.empty((g.n, nq), dtype=torch.float32, device="cuda")
+        total_b, Ks_b, arcs_b, launch_b, achieved_b = timed_batches("bf16", Ybb)
+        ent = {"workload": "the same batch with BF16 vector storage (float arithmetic and estimate)",
+               "value": round(arcs_b / total_b / 1e9, 3), "unit": "GTEPS", "ms_per_batch": round(total_b * 1e3 / nb, 3),
+               "source_tile_width": bwb,
+               "roofline": {"bound": "hbm", "kernel": "batch_step_kernel", "achieved": round(achieved_b, 1),
+                            "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": round(achieved_b / HBM_PEAK_GBPS, 4),
+                            "avg_launch_ms": round(launch_b, 4)}}
+        if Ks_b != Ks:
+            raise RuntimeError("BF16 batch took other K than the FP32 one")
+        if not args.no_cpu:
+            col = Ybb[:, j].double().cpu().numpy()
+            ent["accuracy_vs_fp64_oracle"] = {"column": j, "l1": E.l1(col, ref), "max_abs": E.max_abs(col, ref)}
+        log(f"[batch] bf16 storage: {ent}")
+        out["storage_bf16"] = ent
     G.close()
     return out
 

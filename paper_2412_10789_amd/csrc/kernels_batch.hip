@@ -145,6 +145,17 @@ __global__ void __launch_bounds__(kThreads) batch_step_kernel(BatchStepArgs a) {
       if (pe == pb) continue;
       A acc = A(0);
       int p = pb;
+      if constexpr (BW >= 64) {
+        // one lane group per wavefront: eight gathers per lane keep about
+        // as many cache lines in flight per wavefront as the two groups of a
+        // 32-wide tile do with four
+        for (; p + 8 <= pe; p += 8) {
+          A v[8];
+#pragma unroll
+          for (int q = 0; q < 8; ++q) v[q] = to_acc(x[(size_t)cols[p + q] * BW + lane]);
+          acc += ((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7]));
+        }
+      }
       for (; p + 4 <= pe; p += 4) {
         const A v0 = to_acc(x[(size_t)cols[p] * BW + lane]);
         const A v1 = to_acc(x[(size_t)cols[p + 1] * BW + lane]);

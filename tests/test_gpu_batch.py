@@ -37,7 +37,7 @@ def mid_graph():
 
 
 @pytest.mark.parametrize("bw", [8, 16, 32, 64])
-@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16"])
 def test_batch_columns_match_oracle(torch, mid_graph, bw, prec):
     g = mid_graph
     P = PR.transition_matrix(g.row_ptr, g.col_idx)
@@ -56,8 +56,10 @@ def test_batch_columns_match_oracle(torch, mid_graph, bw, prec):
         m = compare(Y[:, j], ref)
         if prec == "f64":
             assert m["max_abs"] <= 1e-13, (j, m)
-        else:
+        elif prec == "f32":
             assert m["l1"] <= 2e-6, (j, m)
+        else:  # BF16 storage: reported, about 1e-3
+            assert m["l1"] <= 2e-2, (j, m)
 
 
 @pytest.mark.parametrize("stripes", [False, True])
