@@ -124,3 +124,54 @@ def test_server_cancel_busy_and_budget(torch, graph):
     assert ei.value.status == cp.CP_ESOURCE
     assert S.poll(123456789)[0] == cp.CP_ENOTFOUND
     S.close()
+
+
+@pytest.mark.slow
+def test_server_full_size_mixed_stream_f32(torch):
+    """The served workload at full size, with the server configured as the
+    benchmark runs it: Chung-Lu n=4M, ~35M edges, exponent 2.3, XCD-striped
+    graph, FP32 state, 512 slots; mixed PPR (alpha 0.1, 0.2) and HKPR
+    (t 3, 5, 10) queries with tolerances log-uniform in [1e-9, 1e-4] (a
+    wider range than the served trace's [1e-7, 1e-4]), some submitted while
+    others run.  Every result equals the single-source run
+    of its query (same K) to FP32 rounding, and sampled results (the
+    tightest tolerance of each kind) match the FP64 oracle at their K."""
+    from paper_2412_10789_amd import chebyprop as cp
+
+    g = synth.chung_lu(4_000_000, 35_000_000, 2.3, seed=2)
+    G = gpu_graph(g, stripes=True)
+    S = cp.Server(G, hbm_budget_bytes=16 << 30, max_slots=512, max_queue=100000, prec="f32")
+    qs = _mixed_queries(g, 40, seed=7)
+    ys = [torch.empty(g.n, dtype=torch.float32, device="cuda") for _ in qs]
+    print("CASE server-full-size", flush=True)
+    tickets = []
+    for i, (q, y) in enumerate(zip(qs, ys)):
+        tickets.append(S.submit(q, y))
+        if i % 8 == 7:
+            time.sleep(0.01)  # later queries join running batches
+    infos = []
+    for t in tickets:
+        st, info = S.wait(t, timeout_ms=120_000)
+        assert st == cp.CP_OK, st
+        infos.append(info)
+    S.close()
+    torch.cuda.synchronize()
+    ymat = [y.cpu().numpy() for y in ys]
+    for q, y, info in zip(qs, ymat, infos):
+        kind = "hkpr" if q.kind == 1 else "ppr"
+        r = G.power(kind, q.param, q.source, tol=q.tol, prec="f32")
+        assert r.info["K"] == info["K"]
+        assert compare(y, r.y.cpu().numpy().astype(np.float64))["l1"] <= 2e-6
+    P = PR.transition_matrix(g.row_ptr, g.col_idx)
+    sample = {}
+    for j, q in enumerate(qs):
+        key = (q.kind, q.param)
+        if key not in sample or q.tol < qs[sample[key]].tol:
+            sample[key] = j
+    for j in sorted(sample.values())[:3]:
+        q = qs[j]
+        kind = "hkpr" if q.kind == 1 else "ppr"
+        ref = oracle_yK(g, q.source, kind, q.param, infos[j]["K"], P)
+        m = compare(ymat[j], ref)
+        print("server full size", kind, q.param, q.tol, infos[j]["K"], m, flush=True)
+        assert m["l1"] <= 2e-6, m
