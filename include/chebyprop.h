@@ -337,6 +337,8 @@ typedef struct {
   int64_t device_bytes; /* HBM held by the server (state + scratch) */
   int32_t tile_width;   /* sources per tile in the step kernel */
   int32_t prec;
+  int32_t waiters;      /* threads blocked in cp_server_wait */
+  int32_t pad;
 } cp_server_stats;
 
 /* hbm_budget_bytes: HBM the server may use for query state (>= one slot).
@@ -363,7 +365,9 @@ cp_status cp_server_wait(cp_server* s, uint64_t ticket, int64_t timeout_ms, cp_i
 cp_status cp_server_cancel(cp_server* s, uint64_t ticket);
 cp_status cp_server_get_stats(cp_server* s, cp_server_stats* out);
 /* Stop the server thread (queued and running queries are cancelled) and
- * free its memory. */
+ * free its memory.  Threads blocked in cp_server_wait on this server return
+ * CP_ECANCELLED before it is freed; no other call on it may start once
+ * destroy has been called. */
 cp_status cp_server_destroy(cp_server* s);
 
 const char* cp_status_str(int32_t st);

@@ -121,6 +121,8 @@ class cp_server_stats(ctypes.Structure):
         ("device_bytes", ctypes.c_int64),
         ("tile_width", ctypes.c_int32),
         ("prec", ctypes.c_int32),
+        ("waiters", ctypes.c_int32),
+        ("pad", ctypes.c_int32),
     ]
 
 

@@ -61,6 +61,7 @@ struct cp_server {
   std::condition_variable cv;       // wakes the worker
   std::condition_variable done_cv;  // wakes waiters
   bool stop = false;
+  int32_t waiters = 0;  // threads inside cp_server_wait (destroy waits for them to leave)
   int32_t failed_hip = 0;
   std::unordered_map<uint64_t, Ticket> tickets;
   std::deque<uint64_t> queue;
@@ -412,9 +413,12 @@ cp_status cp_server_wait(cp_server* s, uint64_t ticket, int64_t timeout_ms, cp_i
     auto it = s->tickets.find(ticket);
     return it == s->tickets.end() || it->second.state >= kDone;
   };
+  ++s->waiters;
   if (timeout_ms < 0) s->done_cv.wait(lk, ready);
   else s->done_cv.wait_for(lk, std::chrono::milliseconds(timeout_ms), ready);
-  return poll_locked(s, ticket, info);
+  const cp_status rc = poll_locked(s, ticket, info);
+  if (--s->waiters == 0 && s->stop) s->done_cv.notify_all();
+  return rc;
 }
 
 cp_status cp_server_cancel(cp_server* s, uint64_t ticket) {
@@ -449,6 +453,8 @@ cp_status cp_server_get_stats(cp_server* s, cp_server_stats* out) {
   out->device_bytes = (int64_t)s->dev_bytes;
   out->tile_width = s->bw;
   out->prec = s->prec;
+  out->waiters = s->waiters;
+  out->pad = 0;
   return CP_OK;
 }
 
@@ -464,11 +470,14 @@ cp_status cp_server_destroy(cp_server* s) {
   hipError_t e2 = hipFree(s->dev);
   hipError_t e3 = hipStreamDestroy(s->st);
   {
-    std::lock_guard<std::mutex> lk(s->mu);
+    // cancel what is left, wake the waiters and let them leave before the
+    // server is freed
+    std::unique_lock<std::mutex> lk(s->mu);
     for (auto& kv : s->tickets)
       if (kv.second.state < kDone) kv.second.state = kCancelled;
+    s->done_cv.notify_all();
+    s->done_cv.wait(lk, [&] { return s->waiters == 0; });
   }
-  s->done_cv.notify_all();
   delete s;
   if (e != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
     set_hip_error(e != hipSuccess ? e : e2 != hipSuccess ? e2 : e3);

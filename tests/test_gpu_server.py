@@ -175,3 +175,38 @@ def test_server_full_size_mixed_stream_f32(torch):
         m = compare(ymat[j], ref)
         print("server full size", kind, q.param, q.tol, infos[j]["K"], m, flush=True)
         assert m["l1"] <= 2e-6, m
+
+
+def test_server_destroy_releases_blocked_waiters(torch, graph):
+    """cp_server_destroy cancels what is left and lets threads blocked in
+    cp_server_wait return before it frees the server."""
+    import threading
+
+    from paper_2412_10789_amd import chebyprop as cp
+
+    g = graph
+    G = gpu_graph(g)
+    S = cp.Server(G, hbm_budget_bytes=1 << 40, max_slots=16, max_queue=64, prec="f64")
+    s0 = int(synth.sources(g, 1, seed=9)[0])
+    slow = cp.make_query("ppr", 0.001, s0, 1e-12)  # long-running (K in the hundreds)
+    ys = [torch.empty(g.n, dtype=torch.float64, device="cuda") for _ in range(24)]
+    tickets = [S.submit(slow, y) for y in ys]
+    results = {}
+
+    def waiter(i):
+        results[i] = S.wait(tickets[i])[0]
+
+    print("CASE server-destroy-with-waiters", flush=True)
+    threads = [threading.Thread(target=waiter, args=(i,)) for i in (0, 23)]  # running, queued
+    for t in threads:
+        t.start()
+    t0 = time.time()
+    while S.stats()["waiters"] < 2 and time.time() - t0 < 30:
+        time.sleep(0.001)
+    assert S.stats()["waiters"] == 2
+    S.close()
+    for t in threads:
+        t.join(timeout=60)
+    assert not any(t.is_alive() for t in threads)
+    assert results[23] == cp.CP_ECANCELLED
+    assert results[0] in (cp.CP_OK, cp.CP_ECANCELLED)
