@@ -176,6 +176,9 @@ typedef struct {
  * allowed (they are never reached and get y = 0) but cannot be sources. */
 cp_status cp_graph_create(int64_t n, int64_t nnz, const int64_t* row_ptr, const int32_t* col_idx,
                           int32_t flags, void* stream, cp_graph** out);
+/* Free the graph's device memory.  Queries still running on it and servers
+ * created on it must be finished and destroyed first (a server keeps using
+ * the graph until cp_server_destroy returns). */
 cp_status cp_graph_destroy(cp_graph* g);
 cp_status cp_graph_get_stats(const cp_graph* g, cp_graph_stats* out);
 
@@ -341,7 +344,8 @@ typedef struct {
   int32_t pad;
 } cp_server_stats;
 
-/* hbm_budget_bytes: HBM the server may use for query state (>= one slot).
+/* g: the graph every query runs on; it must outlive the server.
+ * hbm_budget_bytes: HBM the server may use for query state (>= one slot).
  * max_slots: upper bound on resident queries (0: as many as the budget
  * allows, at most 1024).  max_queue: waiting-queue capacity.  prec: CP_F32 /
  * CP_F64 / CP_BF16 for all slots.  Errors: CP_EINVAL, CP_ENOMEM (budget below
