@@ -1,0 +1,52 @@
+"""Host-side parts of bench.py: the algorithmic byte counts of the roofline,
+the validity rule of the committed counter traffic, and the one-GPU
+contract (more GPUs exit with a message before anything touches a GPU)."""
+
+import importlib.util
+import json
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _bench():
+    spec = importlib.util.spec_from_file_location("bench_under_test", os.path.join(ROOT, "bench.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+def test_step_bytes_per_precision():
+    b = _bench()
+    n, nnz = 1000, 17000
+    # column ids + row offsets + per node: gather, z read + write (storage),
+    # estimate read + write (double for FP64 / FP32 storage, float for BF16)
+    assert b.step_bytes(n, nnz, "f32") == 4 * nnz + 8 * (n + 1) + n * (3 * 4 + 2 * 8)
+    assert b.step_bytes(n, nnz, "f64") == 4 * nnz + 8 * (n + 1) + n * (3 * 8 + 2 * 8)
+    assert b.step_bytes(n, nnz, "bf16") == 4 * nnz + 8 * (n + 1) + n * (3 * 2 + 2 * 4)
+    # batched: the index stream is shared, the vector terms scale with sources
+    assert b.step_bytes(n, nnz, "f32", 64) - b.step_bytes(n, nnz, "f32", 0) == 64 * n * 28
+    # Clenshaw: no estimate stream, one read of the start vector
+    assert b.clenshaw_step_bytes(n, nnz, "f32", 8) == 4 * nnz + 8 * (n + 1) + 8 * n * (3 * 4 + 8)
+
+
+def test_traffic_only_for_current_kernels():
+    b = _bench()
+    with open(os.path.join(ROOT, "profiles", "step_traffic.json")) as fh:
+        rec = json.load(fh)
+    for key, e in rec.items():
+        got = b.measured_traffic(key)
+        if e["kernel_hash"] == b.kernel_hash():
+            assert got == e["bytes_per_launch"] and got > 0
+        else:
+            assert got is None
+    assert b.measured_traffic("no such workload") is None
+
+
+def test_more_than_one_gpu_exits_with_a_message():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and r.stdout == ""
