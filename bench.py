@@ -49,6 +49,7 @@ BATCH_WORKLOADS = {
 
 STORAGE_BYTES = {"f64": 8, "f32": 4, "bf16": 2}
 ACC_BYTES = {"f64": 8, "f32": 8, "bf16": 4}  # estimate precision (FP32 storage keeps a double estimate)
+ARITH_DTYPE = {"f64": "f64", "f32": "f64", "bf16": "f32"}  # what the kernels add and multiply in
 
 
 def log(*a):
@@ -825,7 +826,8 @@ def main() -> int:
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": S["prec"],
+        "dtype": ARITH_DTYPE[S["prec"]],  # arithmetic; vectors are stored as config.prec
+        "storage_dtype": S["prec"],
         "data": "synthetic (seeded Chung-Lu graphs shaped like LiveJournal / Orkut; random sources)",
         "config": {
             "workload": S["workload"],
