@@ -50,3 +50,22 @@ def test_isolated_nodes_and_mass():
     assert np.all(y[3:] == 0.0) and abs(y.sum() - 1.0) < 1e-12
     with pytest.raises(RuntimeError):
         NO.cheby_power(g.row_ptr, g.col_idx, 9, c, 40)
+
+
+def test_matches_circulant_closed_form():
+    """Plain-C Alg. 3 (and Alg. 1) on a circulant graph with 2^16 nodes and
+    offsets -40..40 against the DFT closed forms (independent of any sparse
+    product), with the unsorted wrap-around rows of the CSR builder."""
+    from oracle import circulant as CI
+
+    n, offs = 1 << 16, CI.offsets_band(40)
+    rp, ci = CI.csr(n, offs)
+    for kind, param, K in (("ppr", 0.2, 30), ("hkpr", 5.0, 18)):
+        c = C.chebyshev_coeffs(kind, param, K)
+        for s in (3, n // 2):
+            y = NO.cheby_power(rp, ci, s, c, K)
+            ref = CI.cheby_truncated(n, offs, s, c)
+            assert np.abs(y - ref).sum() <= 1e-11, (kind, s)
+            N = T.pwmethod_steps(kind, param, 1e-13)
+            yp = NO.power_method(rp, ci, s, C.taylor_coeffs(kind, param, N), N)
+            assert np.abs(yp - CI.exact(n, offs, s, kind, param)).sum() <= 1e-11, (kind, s)
