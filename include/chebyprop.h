@@ -180,6 +180,7 @@ cp_status cp_graph_create(int64_t n, int64_t nnz, const int64_t* row_ptr, const 
  * created on it must be finished and destroyed first (a server keeps using
  * the graph until cp_server_destroy returns). */
 cp_status cp_graph_destroy(cp_graph* g);
+/* Sizes and layout of the graph into host *out.  Errors: CP_EINVAL. */
 cp_status cp_graph_get_stats(const cp_graph* g, cp_graph_stats* out);
 
 /* Chebyshev coefficients c_0..c_K into host c_out[K+1], FP64
@@ -374,8 +375,11 @@ cp_status cp_server_get_stats(cp_server* s, cp_server_stats* out);
  * destroy has been called. */
 cp_status cp_server_destroy(cp_server* s);
 
+/* Static text naming a status code ("unknown status" for other values). */
 const char* cp_status_str(int32_t st);
+/* The raw hipError_t behind the calling thread's last CP_EHIP (0 if none). */
 int32_t cp_last_hip_error(void);
+/* Static version string of the library. */
 const char* cp_version(void);
 
 #ifdef __cplusplus
