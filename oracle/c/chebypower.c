@@ -12,6 +12,12 @@
  *            for k = 1 .. K-1: y += c_k r_k; r_{k+1} = 2 P r_k - r_{k-1};
  *            y += c_K r_K.
  *   Alg. 1:  y = 0; r = e_s; for k = 0 .. N-1: y += zeta_k r; r = P r.
+ *
+ * oracle_chebypower_multi runs Alg. 3 for B sources side by side: column j
+ * of the [n][B] row-major matrices is source j's r_k, with its own K_j and
+ * coefficients.  Each column's additions are exactly those of
+ * oracle_chebypower, in the same order; the columns only share the pass
+ * over the CSR.
  */
 #include <stdint.h>
 #include <stdio.h>
@@ -104,6 +110,84 @@ int oracle_pwmethod(int64_t n, const int64_t* rp, const int32_t* ci, int64_t s, 
   }
   free(inv_d); free(r); free(r2);
   return 0;
+}
+
+/* P applied to the B columns of r ([n][B] row-major) at once. */
+static void apply_P_multi(int64_t n, int32_t B, const int64_t* rp, const int32_t* ci, const double* inv_d,
+                          const double* r, double* out) {
+#pragma omp parallel for schedule(dynamic, 1024)
+  for (int64_t v = 0; v < n; ++v) {
+    double* o = out + (size_t)v * (size_t)B;
+    for (int32_t j = 0; j < B; ++j) o[j] = 0.0;
+    for (int64_t q = rp[v]; q < rp[v + 1]; ++q) {
+      const int64_t u = ci[q];
+      const double w = inv_d[u];
+      const double* ru = r + (size_t)u * (size_t)B;
+      for (int32_t j = 0; j < B; ++j) o[j] += ru[j] * w;
+    }
+  }
+}
+
+/* Alg. 3 for B sources: src[j], K[j] >= 1, coefficients c[j * ldc + k] for
+ * k = 0..K[j] (ldc >= max K + 1); Y is [n][B] row-major. */
+int oracle_chebypower_multi(int64_t n, const int64_t* rp, const int32_t* ci, int32_t B, const int64_t* src,
+                            const double* c, int32_t ldc, const int32_t* K, double* Y) {
+  if (n < 1 || B < 1 || !rp || !ci || !src || !c || !K || !Y) return -1;
+  int32_t Kmax = 0;
+  for (int32_t j = 0; j < B; ++j) {
+    if (src[j] < 0 || src[j] >= n || K[j] < 1 || K[j] + 1 > ldc) return -1;
+    if (K[j] > Kmax) Kmax = K[j];
+  }
+  const size_t nb = (size_t)n * (size_t)B;
+  double* inv_d = inverse_degrees(n, rp);
+  double* r_prev = (double*)calloc(nb, sizeof(double));
+  double* r_cur = (double*)calloc(nb, sizeof(double));
+  double* r_next = (double*)malloc(sizeof(double) * nb);
+  if (!inv_d || !r_prev || !r_cur || !r_next) {
+    free(inv_d); free(r_prev); free(r_cur); free(r_next);
+    return -2;
+  }
+  memset(Y, 0, sizeof(double) * nb);
+  for (int32_t j = 0; j < B; ++j) {
+    Y[(size_t)src[j] * B + j] = c[(size_t)j * ldc];  /* y = c_0 e_s */
+    r_prev[(size_t)src[j] * B + j] = 1.0;            /* r_0 = e_s   */
+  }
+  apply_P_multi(n, B, rp, ci, inv_d, r_prev, r_cur); /* r_1 = P e_s */
+  for (int32_t k = 1; k <= Kmax; ++k) {
+    /* y += c_k r_k for the columns that still have a term k */
+#pragma omp parallel for
+    for (int64_t v = 0; v < n; ++v)
+      for (int32_t j = 0; j < B; ++j)
+        if (k <= K[j]) Y[(size_t)v * B + j] += c[(size_t)j * ldc + k] * r_cur[(size_t)v * B + j];
+    if (k == Kmax) break;
+    apply_P_multi(n, B, rp, ci, inv_d, r_cur, r_next);
+#pragma omp parallel for
+    for (int64_t i = 0; i < (int64_t)nb; ++i) r_next[i] = 2.0 * r_next[i] - r_prev[i];
+    double* t = r_prev;
+    r_prev = r_cur;
+    r_cur = r_next;
+    r_next = t;
+    if (g_verbose) {
+      fprintf(stderr, "[oracle] Alg. 3 x%d step %d/%d\n", B, k, Kmax - 1);
+      fflush(stderr);
+    }
+  }
+  free(inv_d); free(r_prev); free(r_cur); free(r_next);
+  return 0;
+}
+
+/* Threads of the OpenMP loops from here on (t <= 0: back to the count the
+ * process started with, e.g. from OMP_NUM_THREADS). */
+void oracle_set_threads(int t) {
+#ifdef _OPENMP
+  extern void omp_set_num_threads(int);
+  extern int omp_get_max_threads(void);
+  static int initial = 0;
+  if (!initial) initial = omp_get_max_threads();
+  omp_set_num_threads(t > 0 ? t : initial);
+#else
+  (void)t;
+#endif
 }
 
 int oracle_threads(void) {

@@ -38,6 +38,10 @@ def _load():
             f = getattr(lib, fn)
             f.argtypes = [ctypes.c_int64, P, P, ctypes.c_int64, P, ctypes.c_int32, P]
             f.restype = ctypes.c_int
+        lib.oracle_chebypower_multi.argtypes = [ctypes.c_int64, P, P, ctypes.c_int32, P, P, ctypes.c_int32, P, P]
+        lib.oracle_chebypower_multi.restype = ctypes.c_int
+        lib.oracle_set_threads.argtypes = [ctypes.c_int]
+        lib.oracle_set_threads.restype = None
         lib.oracle_threads.restype = ctypes.c_int
         lib.oracle_set_verbose.argtypes = [ctypes.c_int]
         lib.oracle_set_verbose.restype = None
@@ -52,6 +56,12 @@ def set_verbose(on: bool) -> None:
 
 def threads() -> int:
     return int(_load().oracle_threads())
+
+
+def set_threads(t: int) -> None:
+    """Threads of the oracle's OpenMP loops from here on (0: the count the
+    process started with)."""
+    _load().oracle_set_threads(int(t))
 
 
 def _call(name, row_ptr, col_idx, s, coeffs, K):
@@ -71,6 +81,33 @@ def cheby_power(row_ptr, col_idx, s: int, c, K: int) -> np.ndarray:
     if len(c) < K + 1:
         raise ValueError("need c_0..c_K")
     return _call("oracle_chebypower", row_ptr, col_idx, s, c, K)
+
+
+def cheby_power_multi(row_ptr, col_idx, sources, coeffs, Ks) -> np.ndarray:
+    """Alg. 3 for several sources in one pass per step: column j of the
+    [n][B] result is Alg. 3 from sources[j] with coefficients coeffs[j]
+    (c_0..c_{K_j}) and truncation step Ks[j], summed exactly as
+    cheby_power sums it."""
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
+    ci = np.ascontiguousarray(col_idx, dtype=np.int32)
+    src = np.ascontiguousarray(sources, dtype=np.int64)
+    Kv = np.ascontiguousarray(Ks, dtype=np.int32)
+    B = src.shape[0]
+    if Kv.shape[0] != B or len(coeffs) != B:
+        raise ValueError("one K and one coefficient row per source")
+    ldc = int(Kv.max()) + 1
+    c = np.zeros((B, ldc), dtype=np.float64)
+    for j, cj in enumerate(coeffs):
+        if len(cj) < Kv[j] + 1:
+            raise ValueError("need c_0..c_K for every source")
+        c[j, :Kv[j] + 1] = np.asarray(cj, dtype=np.float64)[:Kv[j] + 1]
+    n = rp.shape[0] - 1
+    Y = np.empty((n, B), dtype=np.float64)
+    rc = _load().oracle_chebypower_multi(n, rp.ctypes.data, ci.ctypes.data, B, src.ctypes.data, c.ctypes.data,
+                                         ldc, Kv.ctypes.data, Y.ctypes.data)
+    if rc != 0:
+        raise RuntimeError(f"oracle_chebypower_multi failed with {rc}")
+    return Y
 
 
 def power_method(row_ptr, col_idx, s: int, zeta, N: int) -> np.ndarray:

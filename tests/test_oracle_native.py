@@ -69,3 +69,43 @@ def test_matches_circulant_closed_form():
             N = T.pwmethod_steps(kind, param, 1e-13)
             yp = NO.power_method(rp, ci, s, C.taylor_coeffs(kind, param, N), N)
             assert np.abs(yp - CI.exact(n, offs, s, kind, param)).sum() <= 1e-11, (kind, s)
+
+
+def test_multi_source_columns_match_single_source():
+    """Alg. 3 for several sources in one pass per step: every column equals
+    the single-source run (same sums in the same order), with different K
+    and coefficient rows per column, a repeated source and K = 1."""
+    g = synth.chung_lu(30_000, 200_000, 2.2, seed=6)
+    srcs = [int(s) for s in synth.sources(g, 5, seed=2)] + [0]
+    srcs[5] = srcs[1]
+    Ks = [3, 17, 25, 1, 9, 31]
+    kinds = [("hkpr", 5.0), ("ppr", 0.2), ("ppr", 0.05), ("hkpr", 3.0), ("ppr", 0.2), ("hkpr", 5.0)]
+    cs = [C.chebyshev_coeffs(k, p, K) for (k, p), K in zip(kinds, Ks)]
+    Y = NO.cheby_power_multi(g.row_ptr, g.col_idx, srcs, cs, Ks)
+    P = PR.transition_matrix(g.row_ptr, g.col_idx)
+    for j in range(len(srcs)):
+        np.testing.assert_array_equal(Y[:, j], NO.cheby_power(g.row_ptr, g.col_idx, srcs[j], cs[j], Ks[j]))
+        np.testing.assert_allclose(Y[:, j], PR.cheby_power(P, srcs[j], cs[j], Ks[j]), atol=1e-15, rtol=1e-12)
+
+
+def test_multi_source_against_circulant_closed_form():
+    """The multi-source form on a circulant graph (2^15 nodes, offsets
+    -20..20) against the DFT form of Alg. 3's output, thread count 1 and
+    the default (the sums do not depend on it)."""
+    from oracle import circulant as CI
+
+    n, offs = 1 << 15, CI.offsets_band(20)
+    rp, ci = CI.csr(n, offs)
+    srcs, Ks = [7, n // 3, n - 1], [12, 30, 5]
+    cs = [C.chebyshev_coeffs("ppr", 0.2, 30)[:13], C.chebyshev_coeffs("ppr", 0.2, 30),
+          C.chebyshev_coeffs("hkpr", 5.0, 5)]
+    Y = NO.cheby_power_multi(rp, ci, srcs, cs, Ks)
+    NO.set_threads(1)
+    try:
+        Y1 = NO.cheby_power_multi(rp, ci, srcs, cs, Ks)
+    finally:
+        NO.set_threads(0)
+    np.testing.assert_array_equal(Y, Y1)
+    for j, s in enumerate(srcs):
+        ref = CI.cheby_truncated(n, offs, s, cs[j][:Ks[j] + 1])
+        assert np.abs(Y[:, j] - ref).sum() <= 1e-11, j
