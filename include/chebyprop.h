@@ -171,7 +171,9 @@ typedef struct {
  *   row_ptr  int64[n+1], device (host with CP_GRAPH_HOST)
  *   col_idx  int32[nnz], device (host with CP_GRAPH_HOST)
  *   flags    CP_GRAPH_*
- * Errors: CP_EINVAL (sizes, NULL), CP_EGRAPH (CP_GRAPH_VALIDATE failed),
+ * Errors: CP_EINVAL (sizes, NULL, row_ptr[0] != 0, row_ptr[n] != nnz, a
+ * decreasing offset or a degree of 2^31 or more; these offset checks run
+ * on every create), CP_EGRAPH (CP_GRAPH_VALIDATE failed),
  * CP_ENOMEM, CP_EHIP.  Synchronizes `stream`.  Nodes with degree 0 are
  * allowed (they are never reached and get y = 0) but cannot be sources. */
 cp_status cp_graph_create(int64_t n, int64_t nnz, const int64_t* row_ptr, const int32_t* col_idx,

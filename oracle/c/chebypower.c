@@ -17,7 +17,12 @@
  * of the [n][B] row-major matrices is source j's r_k, with its own K_j and
  * coefficients.  Each column's additions are exactly those of
  * oracle_chebypower, in the same order; the columns only share the pass
- * over the CSR.
+ * over the CSR.  oracle_pwmethod_multi does the same for Alg. 1.
+ *
+ * oracle_ppr_residual_multi evaluates Def. 3's fixed-point equation on B
+ * given vectors: for column j, ||alpha e_s + (1 - alpha) P y - y||_1.
+ * Because ||P||_1 = 1, ||(I - (1 - alpha) P)^{-1}||_1 = 1 / alpha, so this
+ * norm divided by alpha bounds ||pi_s - y||_1 without a reference vector.
  */
 #include <stdint.h>
 #include <stdio.h>
@@ -173,6 +178,75 @@ int oracle_chebypower_multi(int64_t n, const int64_t* rp, const int32_t* ci, int
     }
   }
   free(inv_d); free(r_prev); free(r_cur); free(r_next);
+  return 0;
+}
+
+/* Alg. 1 for B sources: src[j], N[j] >= 1, weights zeta[j * ldz + k] for
+ * k = 0..N[j]-1 (ldz >= max N); Y is [n][B] row-major. */
+int oracle_pwmethod_multi(int64_t n, const int64_t* rp, const int32_t* ci, int32_t B, const int64_t* src,
+                          const double* zeta, int32_t ldz, const int32_t* N, double* Y) {
+  if (n < 1 || B < 1 || !rp || !ci || !src || !zeta || !N || !Y) return -1;
+  int32_t Nmax = 0;
+  for (int32_t j = 0; j < B; ++j) {
+    if (src[j] < 0 || src[j] >= n || N[j] < 1 || N[j] > ldz) return -1;
+    if (N[j] > Nmax) Nmax = N[j];
+  }
+  const size_t nb = (size_t)n * (size_t)B;
+  double* inv_d = inverse_degrees(n, rp);
+  double* r = (double*)calloc(nb, sizeof(double));
+  double* r2 = (double*)malloc(sizeof(double) * nb);
+  if (!inv_d || !r || !r2) {
+    free(inv_d); free(r); free(r2);
+    return -2;
+  }
+  memset(Y, 0, sizeof(double) * nb);
+  for (int32_t j = 0; j < B; ++j) r[(size_t)src[j] * B + j] = 1.0; /* r = e_s */
+  for (int32_t k = 0; k < Nmax; ++k) {
+    /* y += zeta_k r for the columns that still have a term k */
+#pragma omp parallel for
+    for (int64_t v = 0; v < n; ++v)
+      for (int32_t j = 0; j < B; ++j)
+        if (k < N[j]) Y[(size_t)v * B + j] += zeta[(size_t)j * ldz + k] * r[(size_t)v * B + j];
+    if (k == Nmax - 1) break;
+    apply_P_multi(n, B, rp, ci, inv_d, r, r2); /* r = P r */
+    double* t = r;
+    r = r2;
+    r2 = t;
+    if (g_verbose) {
+      fprintf(stderr, "[oracle] Alg. 1 x%d step %d/%d\n", B, k + 1, Nmax - 1);
+      fflush(stderr);
+    }
+  }
+  free(inv_d); free(r); free(r2);
+  return 0;
+}
+
+/* res[j] = || alpha[j] e_{src[j]} + (1 - alpha[j]) P y_j - y_j ||_1 for the B
+ * columns y_j of Y ([n][B] row-major, double).  One pass over the CSR; the
+ * l1 sum of each column is taken in node order. */
+int oracle_ppr_residual_multi(int64_t n, const int64_t* rp, const int32_t* ci, int32_t B, const int64_t* src,
+                              const double* alpha, const double* Y, double* res) {
+  if (n < 1 || B < 1 || !rp || !ci || !src || !alpha || !Y || !res) return -1;
+  for (int32_t j = 0; j < B; ++j)
+    if (src[j] < 0 || src[j] >= n || !(alpha[j] > 0.0 && alpha[j] < 1.0)) return -1;
+  const size_t nb = (size_t)n * (size_t)B;
+  double* inv_d = inverse_degrees(n, rp);
+  double* py = (double*)malloc(sizeof(double) * nb);
+  if (!inv_d || !py) {
+    free(inv_d); free(py);
+    return -2;
+  }
+  apply_P_multi(n, B, rp, ci, inv_d, Y, py);
+  for (int32_t j = 0; j < B; ++j) {
+    double acc = 0.0;
+    for (int64_t v = 0; v < n; ++v) {
+      double e = (1.0 - alpha[j]) * py[(size_t)v * B + j] - Y[(size_t)v * B + j];
+      if (v == src[j]) e += alpha[j];
+      acc += e < 0.0 ? -e : e;
+    }
+    res[j] = acc;
+  }
+  free(inv_d); free(py);
   return 0;
 }
 

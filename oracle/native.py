@@ -40,6 +40,10 @@ def _load():
             f.restype = ctypes.c_int
         lib.oracle_chebypower_multi.argtypes = [ctypes.c_int64, P, P, ctypes.c_int32, P, P, ctypes.c_int32, P, P]
         lib.oracle_chebypower_multi.restype = ctypes.c_int
+        lib.oracle_pwmethod_multi.argtypes = [ctypes.c_int64, P, P, ctypes.c_int32, P, P, ctypes.c_int32, P, P]
+        lib.oracle_pwmethod_multi.restype = ctypes.c_int
+        lib.oracle_ppr_residual_multi.argtypes = [ctypes.c_int64, P, P, ctypes.c_int32, P, P, P, P]
+        lib.oracle_ppr_residual_multi.restype = ctypes.c_int
         lib.oracle_set_threads.argtypes = [ctypes.c_int]
         lib.oracle_set_threads.restype = None
         lib.oracle_threads.restype = ctypes.c_int
@@ -83,31 +87,66 @@ def cheby_power(row_ptr, col_idx, s: int, c, K: int) -> np.ndarray:
     return _call("oracle_chebypower", row_ptr, col_idx, s, c, K)
 
 
-def cheby_power_multi(row_ptr, col_idx, sources, coeffs, Ks) -> np.ndarray:
-    """Alg. 3 for several sources in one pass per step: column j of the
-    [n][B] result is Alg. 3 from sources[j] with coefficients coeffs[j]
-    (c_0..c_{K_j}) and truncation step Ks[j], summed exactly as
-    cheby_power sums it."""
+def _multi(name, row_ptr, col_idx, sources, coeffs, Ks, extra: int) -> np.ndarray:
+    """Shared marshalling of the several-source calls: coefficient row j
+    holds Ks[j] + extra leading entries (extra = 1: c_0..c_K; extra = 0:
+    zeta_0..zeta_{N-1})."""
     rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
     ci = np.ascontiguousarray(col_idx, dtype=np.int32)
     src = np.ascontiguousarray(sources, dtype=np.int64)
     Kv = np.ascontiguousarray(Ks, dtype=np.int32)
     B = src.shape[0]
     if Kv.shape[0] != B or len(coeffs) != B:
-        raise ValueError("one K and one coefficient row per source")
-    ldc = int(Kv.max()) + 1
+        raise ValueError("one truncation step and one coefficient row per source")
+    ldc = int(Kv.max()) + extra
     c = np.zeros((B, ldc), dtype=np.float64)
     for j, cj in enumerate(coeffs):
-        if len(cj) < Kv[j] + 1:
-            raise ValueError("need c_0..c_K for every source")
-        c[j, :Kv[j] + 1] = np.asarray(cj, dtype=np.float64)[:Kv[j] + 1]
+        need = int(Kv[j]) + extra
+        if len(cj) < need:
+            raise ValueError("coefficient row too short")
+        c[j, :need] = np.asarray(cj, dtype=np.float64)[:need]
     n = rp.shape[0] - 1
     Y = np.empty((n, B), dtype=np.float64)
-    rc = _load().oracle_chebypower_multi(n, rp.ctypes.data, ci.ctypes.data, B, src.ctypes.data, c.ctypes.data,
-                                         ldc, Kv.ctypes.data, Y.ctypes.data)
+    rc = getattr(_load(), name)(n, rp.ctypes.data, ci.ctypes.data, B, src.ctypes.data, c.ctypes.data, ldc,
+                                Kv.ctypes.data, Y.ctypes.data)
     if rc != 0:
-        raise RuntimeError(f"oracle_chebypower_multi failed with {rc}")
+        raise RuntimeError(f"{name} failed with {rc}")
     return Y
+
+
+def cheby_power_multi(row_ptr, col_idx, sources, coeffs, Ks) -> np.ndarray:
+    """Alg. 3 for several sources in one pass per step: column j of the
+    [n][B] result is Alg. 3 from sources[j] with coefficients coeffs[j]
+    (c_0..c_{K_j}) and truncation step Ks[j], summed exactly as
+    cheby_power sums it."""
+    return _multi("oracle_chebypower_multi", row_ptr, col_idx, sources, coeffs, Ks, 1)
+
+
+def power_method_multi(row_ptr, col_idx, sources, zetas, Ns) -> np.ndarray:
+    """Alg. 1 for several sources in one pass per step: column j is
+    power_method from sources[j] with weights zetas[j] (zeta_0..zeta_{N_j-1})."""
+    return _multi("oracle_pwmethod_multi", row_ptr, col_idx, sources, zetas, Ns, 0)
+
+
+def ppr_residual_multi(row_ptr, col_idx, sources, alphas, Y) -> np.ndarray:
+    """For each column y_j of Y [n][B]: ||alpha_j e_s + (1 - alpha_j) P y_j -
+    y_j||_1, the residual of Def. 3's fixed-point equation.  Divided by
+    alpha_j it bounds ||pi_s - y_j||_1 (see oracle.errors.ppr_certificate)."""
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
+    ci = np.ascontiguousarray(col_idx, dtype=np.int32)
+    src = np.ascontiguousarray(sources, dtype=np.int64)
+    al = np.ascontiguousarray(alphas, dtype=np.float64)
+    Yd = np.ascontiguousarray(Y, dtype=np.float64)
+    n = rp.shape[0] - 1
+    B = src.shape[0]
+    if Yd.shape != (n, B) or al.shape[0] != B:
+        raise ValueError("Y must be [n][B] with one alpha per column")
+    res = np.empty(B, dtype=np.float64)
+    rc = _load().oracle_ppr_residual_multi(n, rp.ctypes.data, ci.ctypes.data, B, src.ctypes.data, al.ctypes.data,
+                                           Yd.ctypes.data, res.ctypes.data)
+    if rc != 0:
+        raise RuntimeError(f"oracle_ppr_residual_multi failed with {rc}")
+    return res
 
 
 def power_method(row_ptr, col_idx, s: int, zeta, N: int) -> np.ndarray:

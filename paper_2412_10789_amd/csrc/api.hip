@@ -488,6 +488,10 @@ cp_status cp_graph_create(int64_t n, int64_t nnz, const int64_t* row_ptr, const 
     g->degree.resize(n);
     for (int64_t v = 0; v < n; ++v) {
       const int64_t d = rp[v + 1] - rp[v];
+      if (d < 0 || d > INT32_MAX) {  // non-monotone offsets would make negative-length tiles
+        (void)release_graph(g);
+        return CP_EINVAL;
+      }
       g->degree[v] = (int32_t)d;
       g->d_max = std::max(g->d_max, d);
     }

@@ -109,3 +109,59 @@ def test_multi_source_against_circulant_closed_form():
     for j, s in enumerate(srcs):
         ref = CI.cheby_truncated(n, offs, s, cs[j][:Ks[j] + 1])
         assert np.abs(Y[:, j] - ref).sum() <= 1e-11, j
+
+
+def test_pwmethod_multi_columns_match_single_source_and_closed_form():
+    """Alg. 1 for several sources in one pass per step: every column equals
+    the single-source run bit for bit, with its own N and weights; on a
+    circulant graph the columns match the DFT form of f(P) e_s to the exact
+    Taylor tail."""
+    g = synth.chung_lu(30_000, 200_000, 2.2, seed=6)
+    srcs = [int(s) for s in synth.sources(g, 4, seed=3)]
+    kinds = [("hkpr", 5.0), ("ppr", 0.2), ("hkpr", 3.0), ("ppr", 0.1)]
+    Ns = [T.pwmethod_steps(k, p, 1e-10) for k, p in kinds]
+    Ns[2] = 1
+    zs = [C.taylor_coeffs(k, p, N) for (k, p), N in zip(kinds, Ns)]
+    Y = NO.power_method_multi(g.row_ptr, g.col_idx, srcs, zs, Ns)
+    for j in range(len(srcs)):
+        np.testing.assert_array_equal(Y[:, j], NO.power_method(g.row_ptr, g.col_idx, srcs[j], zs[j], Ns[j]))
+    from oracle import circulant as CI
+
+    n, offs = 1 << 15, CI.offsets_band(20)
+    rp, ci = CI.csr(n, offs)
+    srcs = [5, n // 2]
+    kinds = [("ppr", 0.2), ("hkpr", 5.0)]
+    Ns = [T.pwmethod_steps(k, p, 1e-13) for k, p in kinds]
+    Y = NO.power_method_multi(rp, ci, srcs, [C.taylor_coeffs(k, p, N) for (k, p), N in zip(kinds, Ns)], Ns)
+    for j, ((k, p), s) in enumerate(zip(kinds, srcs)):
+        assert np.abs(Y[:, j] - CI.exact(n, offs, s, k, p)).sum() <= 1e-11, j
+
+
+def test_ppr_residual_multi_is_the_fixed_point_residual():
+    """The residual of Def. 3's fixed-point equation: about zero at the exact
+    PPR vector (dense solve), equal to the Python certificate times alpha on
+    perturbed vectors, and (divided by alpha) never below the true l1 error."""
+    from oracle import dense as D
+    from oracle import errors as E
+
+    g = synth.chung_lu(150, 600, 2.3, seed=4)
+    P = PR.transition_matrix(g.row_ptr, g.col_idx)
+    srcs = [int(s) for s in synth.sources(g, 3, seed=5)]
+    alphas = [0.2, 0.05, 0.5]
+    A = D.adjacency(g.row_ptr, g.col_idx)
+    exact = np.stack([D.ppr_solve(A, s, a) for s, a in zip(srcs, alphas)], axis=1)
+    res0 = NO.ppr_residual_multi(g.row_ptr, g.col_idx, srcs, alphas, exact)
+    assert np.all(res0 <= 1e-13), res0
+    rng = np.random.default_rng(0)
+    Yp = exact + rng.uniform(-1e-4, 1e-4, size=exact.shape)
+    res = NO.ppr_residual_multi(g.row_ptr, g.col_idx, srcs, alphas, Yp)
+    for j, (s, a) in enumerate(zip(srcs, alphas)):
+        assert res[j] == pytest.approx(a * E.ppr_certificate(P, s, a, Yp[:, j]), rel=1e-12, abs=1e-15)
+        assert res[j] / a >= E.l1(exact[:, j], Yp[:, j])
+    # a truncated series: the bound holds and shrinks with K
+    big = synth.chung_lu(30_000, 200_000, 2.2, seed=6)
+    s = int(synth.sources(big, 1, seed=8)[0])
+    ys = np.stack([NO.cheby_power(big.row_ptr, big.col_idx, s, C.ppr_chebyshev_coeffs(0.2, K), K)
+                   for K in (10, 20, 30)], axis=1)
+    rk = NO.ppr_residual_multi(big.row_ptr, big.col_idx, [s] * 3, [0.2] * 3, ys)
+    assert rk[0] > rk[1] > rk[2] > 0.0
