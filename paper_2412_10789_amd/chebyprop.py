@@ -352,21 +352,37 @@ class Graph:
     """A graph resident in HBM (owned by the library)."""
 
     def __init__(self, row_ptr, col_idx, reorder: bool = False, validate: bool = False, device=None,
-                 stripes: bool = False):
+                 stripes: bool = False, host_input: bool | None = None):
+        """row_ptr / col_idx: host arrays (numpy), handed to the library as
+        host pointers (CP_GRAPH_HOST), or device tensors (host_input=False
+        uploads host arrays first and passes device pointers)."""
         import torch
 
         self.torch = torch
         dev = torch.device(device or "cuda")
-        rp = torch.as_tensor(np.asarray(row_ptr, dtype=np.int64)).to(dev)
-        ci = torch.as_tensor(np.asarray(col_idx, dtype=np.int32)).to(dev)
-        self.n = int(rp.numel() - 1)
-        self.nnz = int(ci.numel())
+        on_device = isinstance(row_ptr, torch.Tensor) and row_ptr.is_cuda
+        if host_input is None:
+            host_input = not on_device
+        if host_input:
+            rp = np.ascontiguousarray(row_ptr.cpu().numpy() if isinstance(row_ptr, torch.Tensor) else row_ptr,
+                                      dtype=np.int64)
+            ci = np.ascontiguousarray(col_idx.cpu().numpy() if isinstance(col_idx, torch.Tensor) else col_idx,
+                                      dtype=np.int32)
+            rp_ptr, ci_ptr = rp.ctypes.data, ci.ctypes.data
+            n, nnz = rp.shape[0] - 1, ci.shape[0]
+        else:
+            rp = torch.as_tensor(row_ptr, dtype=torch.int64).to(dev).contiguous()
+            ci = torch.as_tensor(col_idx, dtype=torch.int32).to(dev).contiguous()
+            rp_ptr, ci_ptr = rp.data_ptr(), ci.data_ptr()
+            n, nnz = int(rp.numel() - 1), int(ci.numel())
+        self.n = int(n)
+        self.nnz = int(nnz)
         self.device = dev
         flags = ((CP_GRAPH_REORDER if reorder else 0) | (CP_GRAPH_VALIDATE if validate else 0)
-                 | (CP_GRAPH_XCD_STRIPES if stripes else 0))
+                 | (CP_GRAPH_XCD_STRIPES if stripes else 0) | (CP_GRAPH_HOST if host_input else 0))
         with torch.cuda.device(dev):
             stream = torch.cuda.current_stream().cuda_stream
-            self.handle = cp_graph_create(self.n, self.nnz, rp.data_ptr(), ci.data_ptr(), flags, stream)
+            self.handle = cp_graph_create(self.n, self.nnz, rp_ptr, ci_ptr, flags, stream)
         self.stats = cp_graph_get_stats(self.handle)
         self._ws = {}
         self._push_ws = None

@@ -4,7 +4,10 @@
 
 #include <algorithm>
 #include <atomic>
+#include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <numeric>
@@ -40,6 +43,20 @@ int host_threads() {
   return (int)std::max(1u, std::min(h ? h : 1u, 16u));
 }
 
+// Wall-clock phases of cp_graph_create, printed to stderr when the
+// environment variable CHEBYPROP_TRACE is set (diagnostics only).
+struct PhaseClock {
+  bool on = std::getenv("CHEBYPROP_TRACE") != nullptr;
+  std::chrono::steady_clock::time_point t = std::chrono::steady_clock::now();
+  void mark(const char* what) {
+    if (!on) return;
+    const auto now = std::chrono::steady_clock::now();
+    std::fprintf(stderr, "[chebyprop] graph create: %s %.1f ms\n", what,
+                 std::chrono::duration<double, std::milli>(now - t).count());
+    t = now;
+  }
+};
+
 template <typename F>
 void parallel_rows(int64_t n, F&& fn) {
   const int nt = host_threads();
@@ -49,6 +66,40 @@ void parallel_rows(int64_t n, F&& fn) {
     const int64_t b = std::min<int64_t>(n, t * chunk), e = std::min<int64_t>(n, b + chunk);
     pool.emplace_back([=, &fn] { fn(b, e); });
   }
+  for (auto& th : pool) th.join();
+}
+
+// Rows [0, n) of a CSR in chunks of about equal work (arcs plus rows),
+// taken by the threads in turn: degree-ordered graphs hold most arcs in
+// their first rows, so equal row counts would leave one thread the hubs.
+template <typename F>
+void parallel_rows_balanced(const int64_t* rp, int64_t n, F&& fn) {
+  const int nt = host_threads();
+  const int64_t nchunks = std::min<int64_t>(n, (int64_t)nt * 8);
+  if (nchunks <= 1 || nt == 1) {
+    fn((int64_t)0, n);
+    return;
+  }
+  const int64_t total = rp[n] + n;
+  std::vector<int64_t> cut((size_t)nchunks + 1, n);
+  cut[0] = 0;
+  for (int64_t c = 1; c < nchunks; ++c) {
+    const int64_t target = total / nchunks * c;
+    int64_t lo = cut[(size_t)c - 1], hi = n;  // smallest v with rp[v] + v >= target
+    while (lo < hi) {
+      const int64_t mid = (lo + hi) / 2;
+      if (rp[mid] + mid >= target) hi = mid;
+      else lo = mid + 1;
+    }
+    cut[(size_t)c] = lo;
+  }
+  std::atomic<int64_t> next{0};
+  std::vector<std::thread> pool;
+  for (int t = 0; t < nt; ++t)
+    pool.emplace_back([&] {
+      for (int64_t c = next++; c < nchunks; c = next++)
+        if (cut[(size_t)c] < cut[(size_t)c + 1]) fn(cut[(size_t)c], cut[(size_t)c + 1]);
+    });
   for (auto& th : pool) th.join();
 }
 
@@ -106,7 +157,7 @@ bool build_stripes(const int64_t* rp, const int32_t* ci, int64_t n, int32_t S, S
   for (int j = 0; j < S; ++j) start[j + 1] = start[j] + (n - j + S - 1) / S;
   // per row, per stripe arc counts (rows are sorted by column)
   std::vector<int32_t> cnt((size_t)n * S);
-  parallel_rows(n, [&](int64_t b, int64_t e) {
+  parallel_rows_balanced(rp, n, [&](int64_t b, int64_t e) {
     for (int64_t v = b; v < e; ++v) {
       const int32_t* r = ci + rp[v];
       const int32_t* re = ci + rp[v + 1];
@@ -137,7 +188,7 @@ bool build_stripes(const int64_t* rp, const int32_t* ci, int64_t n, int32_t S, S
     total += acc;
   }
   sl.cols.resize((size_t)total);
-  parallel_rows(n, [&](int64_t b, int64_t e) {
+  parallel_rows_balanced(rp, n, [&](int64_t b, int64_t e) {
     for (int64_t v = b; v < e; ++v) {
       const int32_t* src = ci + rp[v];
       for (int j = 0; j < S; ++j) {
@@ -395,6 +446,13 @@ hipError_t release_graph(cp_graph* g) {
 
 }  // namespace
 
+namespace {
+
+cp_status power_impl(const cp_graph* g, const cp_query* q, int32_t prec, void* y, void* ws, size_t ws_bytes,
+                     void* stream, cp_info* info);
+
+}  // namespace
+
 extern "C" {
 
 const char* cp_version(void) { return "chebyprop 0.1 (gfx950)"; }
@@ -464,24 +522,28 @@ cp_status cp_graph_create(int64_t n, int64_t nnz, const int64_t* row_ptr, const 
     g->n = n;
     g->nnz = nnz;
     CP_HIP_G(hipGetDevice(&g->device));
-    // host copies of the CSR (row offsets always; columns when needed)
+    PhaseClock clock;
+    // host copy of the row offsets; host view of the columns when needed:
+    // the caller's array (CP_GRAPH_HOST) or a copy from the device
     std::vector<int64_t> rp(n + 1);
     std::vector<int32_t> ci;
-    const bool need_cols = (flags & CP_GRAPH_VALIDATE) || reorder || host_in;
+    const int32_t* hci = host_in ? col_idx : nullptr;
+    const bool need_cols = (flags & CP_GRAPH_VALIDATE) || reorder;
     if (host_in) {
       std::memcpy(rp.data(), row_ptr, sizeof(int64_t) * (n + 1));
     } else {
       CP_HIP_G(hipMemcpyAsync(rp.data(), row_ptr, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToHost, st));
-    }
-    if (need_cols) {
-      ci.resize(nnz);
-      if (host_in && nnz) std::memcpy(ci.data(), col_idx, sizeof(int32_t) * nnz);
-      else if (nnz)
-        CP_HIP_G(hipMemcpyAsync(ci.data(), col_idx, sizeof(int32_t) * nnz, hipMemcpyDeviceToHost, st));
+      if (need_cols) {
+        ci.resize(nnz);
+        if (nnz)
+          CP_HIP_G(hipMemcpyAsync(ci.data(), col_idx, sizeof(int32_t) * nnz, hipMemcpyDeviceToHost, st));
+        hci = ci.data();
+      }
     }
     CP_HIP_G(hipStreamSynchronize(st));
+    clock.mark("host copy");
     if (rp[0] != 0 || rp[n] != nnz) { (void)release_graph(g); return CP_EINVAL; }
-    if ((flags & CP_GRAPH_VALIDATE) && !validate_csr(n, nnz, rp.data(), ci.data())) {
+    if ((flags & CP_GRAPH_VALIDATE) && !validate_csr(n, nnz, rp.data(), hci)) {
       (void)release_graph(g);
       return CP_EGRAPH;
     }
@@ -498,10 +560,19 @@ cp_status cp_graph_create(int64_t n, int64_t nnz, const int64_t* row_ptr, const 
     // internal order
     std::vector<int32_t> perm;  // internal -> caller
     if (reorder) {
+      // decreasing degree, ties in caller order: a counting sort on degrees
       perm.resize(n);
-      std::iota(perm.begin(), perm.end(), 0);
-      std::stable_sort(perm.begin(), perm.end(),
-                       [&](int32_t a, int32_t b) { return g->degree[a] > g->degree[b]; });
+      {
+        std::vector<int64_t> first((size_t)g->d_max + 1, 0);
+        for (int64_t v = 0; v < n; ++v) ++first[(size_t)g->degree[v]];
+        int64_t acc = 0;
+        for (int64_t d = g->d_max; d >= 0; --d) {
+          const int64_t c = first[(size_t)d];
+          first[(size_t)d] = acc;
+          acc += c;
+        }
+        for (int64_t v = 0; v < n; ++v) perm[(size_t)first[(size_t)g->degree[v]]++] = (int32_t)v;
+      }
       if (striped) {
         // degree rank r -> stripe r % S, position r / S (stripes contiguous)
         std::vector<int32_t> by_rank(perm);
@@ -513,25 +584,30 @@ cp_status cp_graph_create(int64_t n, int64_t nnz, const int64_t* row_ptr, const 
       for (int64_t i = 0; i < n; ++i) g->ext2int[perm[i]] = (int32_t)i;
       std::vector<int64_t> rp2(n + 1, 0);
       for (int64_t i = 0; i < n; ++i) rp2[i + 1] = rp2[i] + g->degree[perm[i]];
+      clock.mark("order");
       std::vector<int32_t> ci2(nnz);
-      parallel_rows(n, [&](int64_t b, int64_t e) {
+      parallel_rows_balanced(rp2.data(), n, [&](int64_t b, int64_t e) {
         for (int64_t i = b; i < e; ++i) {
           const int32_t v = perm[i];
           int32_t* dst = ci2.data() + rp2[i];
-          for (int64_t q = rp[v]; q < rp[v + 1]; ++q) *dst++ = g->ext2int[ci[q]];
+          for (int64_t q = rp[v]; q < rp[v + 1]; ++q) *dst++ = g->ext2int[hci[q]];
           std::sort(ci2.data() + rp2[i], dst);
         }
       });
       rp.swap(rp2);
       ci.swap(ci2);
+      hci = ci.data();
       g->reordered = true;
+      clock.mark("relabel");
     }
     const Plan plans[2] = {build_plan(rp.data(), n, kTileNnz), build_plan(rp.data(), n, kBatchLong)};
+    clock.mark("plans");
     StripeLayout sl;
-    if (striped && !build_stripes(rp.data(), ci.data(), n, S, sl)) {
+    if (striped && !build_stripes(rp.data(), hci, n, S, sl)) {
       (void)release_graph(g);
       return CP_EINVAL;
     }
+    if (striped) clock.mark("stripes");
 
     // device copies: [row_ptr | col_idx | perm] in one allocation, plans in another
     const size_t b_rp = borrow ? 0 : align256(sizeof(int64_t) * (n + 1));
@@ -602,8 +678,8 @@ cp_status cp_graph_create(int64_t n, int64_t nnz, const int64_t* row_ptr, const 
       int32_t* dci = reinterpret_cast<int32_t*>(p); p += b_ci;
       CP_HIP_G(hipMemcpyAsync(drp, rp.data(), sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice, st));
       if (nnz) {
-        if (need_cols)
-          CP_HIP_G(hipMemcpyAsync(dci, ci.data(), sizeof(int32_t) * nnz, hipMemcpyHostToDevice, st));
+        if (hci)
+          CP_HIP_G(hipMemcpyAsync(dci, hci, sizeof(int32_t) * nnz, hipMemcpyHostToDevice, st));
         else
           CP_HIP_G(hipMemcpyAsync(dci, col_idx, sizeof(int32_t) * nnz, hipMemcpyDeviceToDevice, st));
       }
@@ -636,6 +712,7 @@ cp_status cp_graph_create(int64_t n, int64_t nnz, const int64_t* row_ptr, const 
                               hipMemcpyHostToDevice, st));
     }
     CP_HIP_G(hipStreamSynchronize(st));
+    clock.mark("upload");
     *out = g;
     return CP_OK;
   } catch (const std::bad_alloc&) {
@@ -677,6 +754,15 @@ size_t cp_workspace_bytes(const cp_graph* g, int32_t nq, int32_t prec) {
 
 cp_status cp_power(const cp_graph* g, const cp_query* q, int32_t prec, void* y, void* ws,
                    size_t ws_bytes, void* stream, cp_info* info) {
+  return power_impl(g, q, prec, y, ws, ws_bytes, stream, info);
+}
+
+}  // extern "C"
+
+namespace {
+
+cp_status power_impl(const cp_graph* g, const cp_query* q, int32_t prec, void* y, void* ws, size_t ws_bytes,
+                     void* stream, cp_info* info) {
   if (!g || !q || !y || !valid_prec(prec)) return CP_EINVAL;
   QueryPlan qp;
   cp_status rc = plan_query(g, q, kDefaultKMax, &qp);
@@ -802,7 +888,7 @@ cp_status cp_power(const cp_graph* g, const cp_query* q, int32_t prec, void* y, 
   return CP_OK;
 }
 
-}  // extern "C"
+}  // namespace
 
 namespace cp {
 namespace {
