@@ -1,23 +1,33 @@
 #!/usr/bin/env python3
 """ChebyPower benchmark on one MI355X.
 
-Main line (the JSON's "value"): heat-kernel PageRank (t = 5) on a seeded
-Chung-Lu graph shaped like LiveJournal (n = 4,000,000 target nodes,
-35,000,000 undirected edges, degree exponent 2.3, int64 offsets / int32
-columns), 16 random sources run one at a time, FP32 vectors, l1 tolerance
-1e-6 with the certified truncation step.  One "step" of this benchmark is
-one pass of the whole path (coefficients, K, init, K-1 Chebyshev steps,
-finalize) for all 16 sources.
+Headline (the JSON's "value"): a batch of 8 personalized-PageRank sources
+(alpha = 0.2, l1 tolerance 1e-6 with the certified truncation step) on a
+seeded Chung-Lu graph shaped like Friendster (n = 65,000,000 target nodes,
+1,800,000,000 undirected edges, degree exponent 2.1, int64 offsets / int32
+columns, 3.6 billion CSR arcs), FP32 vector storage.  One "step" of this
+benchmark is one pass of the whole path (coefficients, K, init, the
+Chebyshev steps, finalize) for the 8 sources.
 
-Beside it ("batched"): 64 PPR (alpha = 0.2) sources with per-source
-tolerances drawn from {1e-4, 1e-6, 1e-7} in one batch on a Chung-Lu graph
-shaped like Orkut (n = 3,000,000, 117,000,000 edges, exponent 2.2), FP32,
-autotuned source-tile width.
+Beside it:
+  "single":  heat-kernel PageRank (t = 5), 16 sources one at a time, on a
+             Chung-Lu graph shaped like LiveJournal (n = 4M, 35M edges,
+             exponent 2.3), FP32 storage, XCD-striped layout;
+  "batched": 64 PPR sources with tolerances from {1e-4, 1e-6, 1e-7} in one
+             batch on a graph shaped like Orkut (n = 3M, 117M edges,
+             exponent 2.2), autotuned source-tile width;
+  "served":  a Poisson query stream on the LiveJournal-shaped graph (60 s at
+             200 queries/s after a 5-s warm-up, and 50 queries/s), the
+             batched server against plain one-query-at-a-time runs;
+  and the PwMethod, feature-matrix, ChebyPush and small-graph latency
+  measurements.
 
 Prints one JSON line: GTEPS (CSR arcs traversed per second, summed over
-sources), the roofline of the dominant kernel (the Chebyshev step) against
-MI355X's 8 TB/s HBM, accuracy against the FP64 oracle, and the FP64 CPU
-oracle timed on a bounded sample of the same workload.
+sources), the roofline of the dominant kernel against MI355X's 8 TB/s HBM
+(algorithmic bytes per launch: column ids, row offsets and five vector
+terms per node and source at the storage width), the error of every result
+against the FP64 oracle, and the FP64 CPU oracle timed on a bounded sample
+of the same workload.
 """
 
 from __future__ import annotations
@@ -35,6 +45,12 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBPS = 8000.0
 METRIC = "GTEPS of Chebyshev steps, % HBM peak; served queries/s + p50/p99 vs plain"
 
+HEADLINES = {
+    # name: (n, m, gamma, seed, alpha, sources, tol, prec)
+    "ppr-batch-friendster": (65_000_000, 1_800_000_000, 2.1, 5, 0.2, 8, 1e-6, "f32"),
+    "ppr-batch-friendster-small": (2_000_000, 55_000_000, 2.1, 5, 0.2, 8, 1e-6, "f32"),
+}
+
 WORKLOADS = {
     # name: (n, m, gamma, seed, kind, param, tol, sources, prec)
     "hkpr-livejournal": (4_000_000, 35_000_000, 2.3, 2, "hkpr", 5.0, 1e-6, 16, "f32"),
@@ -48,7 +64,7 @@ BATCH_WORKLOADS = {
 }
 
 STORAGE_BYTES = {"f64": 8, "f32": 4, "bf16": 2}
-ACC_BYTES = {"f64": 8, "f32": 8, "bf16": 4}  # estimate precision (FP32 storage keeps a double estimate)
+ACC_BYTES = {"f64": 8, "f32": 8, "bf16": 4}  # estimate as the kernels keep it (FP32 storage: double estimate)
 ARITH_DTYPE = {"f64": "f64", "f32": "f64", "bf16": "f32"}  # what the kernels add and multiply in
 
 
@@ -66,19 +82,28 @@ def kernel_hash(files=("kernels.hip", "kernels_batch.hip", "common.h")) -> str:
 
 def step_bytes(n: int, nnz: int, prec: str, sources: int = 1) -> int:
     """Algorithmic bytes of one Chebyshev step launch: column ids and row
-    offsets once, and per node and source one compulsory gather of x,
-    read + write of z, read + write of the estimate."""
+    offsets once, and per node and source five vector terms at the storage
+    width s: one compulsory gather of x, read + write of z, read + write of
+    the estimate."""
+    s = STORAGE_BYTES[prec]
+    return 4 * nnz + 8 * (n + 1) + 5 * n * sources * s
+
+
+def impl_step_bytes(n: int, nnz: int, prec: str, sources: int = 1) -> int:
+    """The same step with the estimate at the width the kernels keep it
+    (double for FP32 storage): the implementation's compulsory bytes, not the
+    roofline's."""
     s, a = STORAGE_BYTES[prec], ACC_BYTES[prec]
     return 4 * nnz + 8 * (n + 1) + n * sources * (3 * s + 2 * a)
 
 
 def clenshaw_step_bytes(n: int, nnz: int, prec: str, sources: int) -> int:
     """Algorithmic bytes of one step of Clenshaw's backward form: column ids
-    and row offsets once, and per node and column one gather of b_{k+1},
-    read of b_{k+2}, write of b_k and read of the start vector (kept at the
-    estimate's precision); no estimate stream."""
-    s, a = STORAGE_BYTES[prec], ACC_BYTES[prec]
-    return 4 * nnz + 8 * (n + 1) + n * sources * (3 * s + a)
+    and row offsets once, and per node and column four vector terms at the
+    storage width: gather of b_{k+1}, read of b_{k+2}, write of b_k, read of
+    the start vector (no estimate stream)."""
+    s = STORAGE_BYTES[prec]
+    return 4 * nnz + 8 * (n + 1) + 4 * n * sources * s
 
 
 def measured_traffic(key: str):
@@ -124,10 +149,230 @@ def copy_ceiling(torch, nbytes: int = 1 << 30) -> float:
     return 2 * nbytes / (ms * 1e-3) / 1e9
 
 
+def roofline(bytes_per_launch: float, avg_launch_ms: float, kernel: str, traffic=None, **extra) -> dict:
+    achieved = bytes_per_launch / (avg_launch_ms * 1e-3) / 1e9
+    out = {"bound": "hbm", "kernel": kernel, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+           "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
+           "bytes_per_launch": int(bytes_per_launch), "avg_launch_us": round(avg_launch_ms * 1e3, 2)}
+    out.update(extra)
+    return out
+
+
+def batch_launch_bytes(n: int, nnz: int, prec: str, Ks, fn=step_bytes) -> int:
+    """Algorithmic bytes of one batch's step launches: launch k (k = 1 ..
+    max K - 1) carries the sources whose K exceeds k."""
+    return sum(fn(n, nnz, prec, sum(1 for K in Ks if K > k)) for k in range(1, max(Ks)))
+
+
+def worst(rows, keys):
+    """Largest value of each key over a list of per-result dicts."""
+    return {k: max(r[k] for r in rows) for k in keys if rows and all(k in r for r in rows)}
+
+
+# ------------------------------------------------------------------ oracle checks
+
+
+def check_same_k_and_exact(g, Yg, kinds, params, srcs, Ks, exact="pwmethod"):
+    """Every column of Yg ([n][B], caller ids) against the FP64 oracle: Alg. 3
+    at the GPU's K (the plain-C several-source form; rounding error of the
+    GPU variant) and the converged vector: l1, max-abs, the
+    degree-normalized error of Def. 5 (Normalized RelErr) and mass.  The
+    converged vector is the plain-C PwMethod with its exact l1 tail below
+    1e-15 (exact="pwmethod"), or, where PwMethod needs hundreds of steps
+    (small alpha), the plain-C Alg. 3 with the certified K for l1 1e-13
+    (exact="chebyshev").  Returns the per-column rows and the oracle's wall
+    time."""
+    from oracle import coefficients as C
+    from oracle import errors as E
+    from oracle import native as NO
+    from oracle import truncation as T
+
+    t0 = time.perf_counter()
+    cs = [C.chebyshev_coeffs(k, p, K) for k, p, K in zip(kinds, params, Ks)]
+    ref_K = NO.cheby_power_multi(g.row_ptr, g.col_idx, srcs, cs, Ks)
+    if exact == "pwmethod":
+        Ns = [T.pwmethod_steps(k, p, 1e-15) for k, p in zip(kinds, params)]
+        ex = NO.power_method_multi(g.row_ptr, g.col_idx, srcs,
+                                   [C.taylor_coeffs(k, p, N) for (k, p, N) in zip(kinds, params, Ns)], Ns)
+    else:
+        Kx = [T.choose_K(k, p, 1e-13, vol=g.nnz, d_s=int(g.degrees[s])) for k, p, s in zip(kinds, params, srcs)]
+        ex = NO.cheby_power_multi(g.row_ptr, g.col_idx, srcs,
+                                  [C.chebyshev_coeffs(k, p, K) for k, p, K in zip(kinds, params, Kx)], Kx)
+    exact = ex
+    oracle_s = time.perf_counter() - t0
+    deg = g.degrees
+    rows = []
+    for j in range(len(srcs)):
+        y = np.asarray(Yg[:, j], dtype=np.float64)
+        rows.append({"source": int(srcs[j]), "kind": kinds[j], "param": params[j], "K": int(Ks[j]),
+                     "l1_vs_same_K": E.l1(y, ref_K[:, j]), "max_abs_vs_same_K": E.max_abs(y, ref_K[:, j]),
+                     "l1_vs_exact": E.l1(y, exact[:, j]), "max_abs_vs_exact": E.max_abs(y, exact[:, j]),
+                     "norm_rel_err_vs_exact": E.degree_normalized(y, exact[:, j], deg),
+                     "mass": float(y.sum())})
+    return rows, oracle_s
+
+
+def check_ppr_certificate(g, Yg, srcs, alphas):
+    """Every column of Yg ([n][B], caller ids, PPR results) against the
+    fixed-point equation of Def. 3: the l1 residual divided by alpha bounds
+    the l1 distance to the exact PPR vector (no reference vector needed; one
+    plain-C FP64 pass over the CSR for all columns), plus mass."""
+    from oracle import native as NO
+
+    t0 = time.perf_counter()
+    res = NO.ppr_residual_multi(g.row_ptr, g.col_idx, srcs, alphas, Yg)
+    oracle_s = time.perf_counter() - t0
+    mass = np.asarray(Yg, dtype=np.float64).sum(axis=0)
+    rows = [{"source": int(s), "alpha": float(a), "l1_bound_vs_exact": float(r / a), "mass": float(m)}
+            for s, a, r, m in zip(srcs, alphas, res, mass)]
+    return rows, oracle_s
+
+
+def _host(t):
+    """A device result as a host float64 array."""
+    return t.double().cpu().numpy()
+
+
+GRAPH_CACHE = None  # directory for generated graphs (--graph-cache), shared by profiling passes
+
+
+def chung_lu(synth, n, m, gamma, seed, tune_passes=3):
+    """synth.chung_lu, optionally kept as .npy files in GRAPH_CACHE so that
+    repeated runs (profiler passes) read the graph instead of generating it."""
+    if not GRAPH_CACHE:
+        return synth.chung_lu(n, m, gamma, seed=seed, tune_passes=tune_passes)
+    base = os.path.join(GRAPH_CACHE, f"chunglu_{n}_{m}_{gamma}_{seed}_{tune_passes}")
+    if os.path.exists(base + "_ci.npy"):
+        rp = np.load(base + "_rp.npy", mmap_mode="r")
+        ci = np.load(base + "_ci.npy", mmap_mode="r")
+        meta = {"d_max": int(np.diff(rp).max())}
+        return synth.CSRGraph(np.ascontiguousarray(rp), np.ascontiguousarray(ci), meta=meta)
+    g = synth.chung_lu(n, m, gamma, seed=seed, tune_passes=tune_passes)
+    os.makedirs(GRAPH_CACHE, exist_ok=True)
+    np.save(base + "_rp.npy", g.row_ptr)
+    np.save(base + "_ci.npy", g.col_idx)
+    return g
+
+
+def run_headline(args, torch, cp, synth):
+    """The headline: a batch of PPR sources on the Friendster-shaped graph,
+    timed over args.steps batches after args.warmup, with FP32 storage; the
+    same batch with BF16 storage; every result's certified l1 distance to the
+    exact vector; the plain-C oracle timed on one step of the same batch."""
+    n_t, m_t, gamma, seed, alpha, nq, tol, prec = HEADLINES[args.headline]
+    t0 = time.time()
+    g = chung_lu(synth, n_t, m_t, gamma, seed, tune_passes=0 if n_t > 10_000_000 else 3)
+    gen_s = time.time() - t0
+    log(f"[headline] graph: n={g.n} nnz={g.nnz} d_max={g.meta['d_max']} ({gen_s:.1f}s)")
+    t0 = time.time()
+    G = cp.Graph(g.row_ptr, g.col_idx, reorder=True)
+    create_s = time.time() - t0
+    log(f"[headline] graph create (degree order) {create_s:.1f}s, device bytes {G.stats['device_bytes']}")
+    srcs = [int(s) for s in synth.sources(g, nq, seed=seed)]
+    qs = [cp.make_query("ppr", alpha, s, tol) for s in srcs]
+    qt = [cp.make_query("ppr", alpha, s, tol, flags=cp.CP_Q_TIMING) for s in srcs]
+    bw = G.autotune_batch(qs, prec=prec) if nq > 8 else 8
+    G.set_batch_width(nq, prec, bw)
+    deg = g.degrees
+
+    def timed(p: str, Yp, warmup: int, steps: int):
+        for _ in range(warmup):
+            G.power_batch(qs, prec=p, Y=Yp)
+        torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        w0 = time.perf_counter()
+        ev0.record()
+        step_ms, launches, infos = 0.0, 0, None
+        for _ in range(steps):
+            _, infos = G.power_batch(qt, prec=p, Y=Yp)
+            step_ms += infos[0]["step_ms"]
+            launches += max(i["steps"] for i in infos)  # the batch runs until its longest query is done
+        ev1.record()
+        torch.cuda.synchronize()
+        total_s = max(time.perf_counter() - w0, ev0.elapsed_time(ev1) * 1e-3)
+        Ks = [i["K"] for i in infos]
+        arcs = steps * sum((K - 1) * g.nnz + int(deg[s]) for K, s in zip(Ks, srcs))
+        avg_launch_ms = step_ms / max(launches, 1)
+        per_batch = batch_launch_bytes(g.n, g.nnz, p, Ks)
+        per_batch_impl = batch_launch_bytes(g.n, g.nnz, p, Ks, impl_step_bytes)
+        nl = max(Ks) - 1
+        log(f"[headline] {p}: K {Ks}; {total_s / steps * 1e3:.1f} ms per batch; avg launch {avg_launch_ms:.3f} ms")
+        return dict(total_s=total_s, Ks=Ks, arcs=arcs, avg_launch_ms=avg_launch_ms,
+                    bytes_per_launch=per_batch / nl, impl_bytes_per_launch=per_batch_impl / nl, launches=launches)
+
+    Y = torch.empty((g.n, nq), dtype=G.out_dtype(cp.PRECS[prec]), device="cuda")
+    R = timed(prec, Y, args.warmup, args.steps)
+    out = {
+        "workload": f"{args.headline}: {nq} PPR alpha={alpha} sources in one batch, tol {tol} l1 (certified K), "
+                    f"Chung-Lu n={n_t} m={m_t} gamma={gamma} seed={seed}, degree-ordered layout",
+        "value": R["arcs"] / R["total_s"] / 1e9,
+        "total_s": R["total_s"], "n": g.n, "nnz": g.nnz, "d_max": int(deg.max()), "sources": nq, "Ks": R["Ks"],
+        "prec": prec, "source_tile_width": bw, "generate_s": round(gen_s, 1), "create_s": round(create_s, 1),
+        "roofline": roofline(R["bytes_per_launch"], R["avg_launch_ms"], f"batch_step_kernel (width {bw})",
+                             traffic=measured_traffic(f"{args.headline}:batch"),
+                             implementation_bytes_per_launch=int(R["impl_bytes_per_launch"]),
+                             launches_timed=R["launches"]),
+        "launch_bytes_rule": "4 nnz + 8 (n+1) + 5 n B_k s per launch, B_k the sources still active in launch k",
+    }
+    results = {"f32": _host(Y)}
+    if not args.no_bf16:
+        Yb = torch.empty((g.n, nq), dtype=torch.float32, device="cuda")
+        Rb = timed("bf16", Yb, 1, args.bf16_steps)
+        if Rb["Ks"] != R["Ks"]:
+            raise RuntimeError("BF16 batch took other K than the FP32 one")
+        out["storage_bf16"] = {
+            "workload": "the same batch with BF16 vector storage (float arithmetic and estimate)",
+            "value": round(Rb["arcs"] / Rb["total_s"] / 1e9, 3), "unit": "GTEPS",
+            "ms_per_batch": round(Rb["total_s"] * 1e3 / args.bf16_steps, 2), "steps": args.bf16_steps,
+            "roofline": roofline(Rb["bytes_per_launch"], Rb["avg_launch_ms"], f"batch_step_kernel (width {bw})")}
+        results["bf16"] = _host(Yb)
+        del Yb
+    del Y
+    G.close()
+    torch.cuda.empty_cache()
+    if not args.no_cpu:
+        from oracle import coefficients as C
+        from oracle import native as NO
+
+        # every result: certified l1 distance to the exact PPR vector (FP32 and BF16 columns in one pass)
+        names = list(results)
+        Yall = np.concatenate([results[k] for k in names], axis=1)
+        rows, cert_s = check_ppr_certificate(g, Yall, srcs * len(names), [alpha] * (nq * len(names)))
+        acc = {}
+        for i, k in enumerate(names):
+            rk = rows[i * nq:(i + 1) * nq]
+            acc[k] = {"worst": worst(rk, ["l1_bound_vs_exact"]),
+                      "mass_range": [min(r["mass"] for r in rk), max(r["mass"] for r in rk)],
+                      "per_source": rk}
+        acc["method"] = (f"plain-C FP64 residual of Def. 3's fixed point, ||alpha e_s + (1-alpha) P y - y||_1 / "
+                         f"alpha, for every result ({cert_s:.1f} s for {Yall.shape[1]} columns)")
+        out["accuracy_vs_fp64_oracle"] = acc
+        log(f"[headline] accuracy: f32 worst {acc['f32']['worst']}"
+            + (f", bf16 worst {acc['bf16']['worst']}" if "bf16" in acc else ""))
+        del Yall, results
+        # CPU baseline: the oracle's several-source Alg. 3 on the same batch, init and one full step
+        c2 = [C.ppr_chebyshev_coeffs(alpha, 2)] * nq
+        t0 = time.perf_counter()
+        NO.cheby_power_multi(g.row_ptr, g.col_idx, srcs, c2, [2] * nq)
+        cpu_s = time.perf_counter() - t0
+        arcs_cpu = sum(g.nnz + int(deg[s]) for s in srcs)
+        out["cpu_baseline"] = {
+            "value": round(arcs_cpu / cpu_s / 1e9, 4), "unit": "GTEPS", "cores": NO.threads(), "kind": "oracle",
+            "sample": f"the same {nq} sources, init plus one of their {max(R['Ks']) - 1} Chebyshev steps: plain-C "
+                      f"FP64 Alg. 3 (several-source form, OpenMP node loop), {cpu_s:.1f} s",
+            "host": {"nproc": os.cpu_count(), "cpu_model": cpu_model()}}
+        log(f"[headline] cpu baseline {out['cpu_baseline']}")
+    return out
+
+
 def run_single(args, torch, cp, synth):
+    """Single-source queries one at a time (the LiveJournal-shaped HKPR
+    workload) on the XCD-striped layout, FP32 and BF16 storage; every result
+    against the FP64 oracle; the oracle timed on the same queries on all
+    host threads and on one."""
     n_t, m_t, gamma, seed, kind, param, tol, nsrc, prec = WORKLOADS[args.workload]
     t0 = time.time()
-    g = synth.chung_lu(n_t, m_t, gamma, seed=seed)
+    g = chung_lu(synth, n_t, m_t, gamma, seed)
     log(f"[single] graph: n={g.n} nnz={g.nnz} d_max={g.meta['d_max']} ({time.time() - t0:.1f}s)")
     t0 = time.time()
     G = cp.Graph(g.row_ptr, g.col_idx, reorder=args.layout == "degree", stripes=args.layout == "stripes")
@@ -136,6 +381,7 @@ def run_single(args, torch, cp, synth):
     srcs = [int(s) for s in synth.sources(g, nsrc, seed=seed)]
     Y = torch.empty((nsrc, g.n), dtype=G.out_dtype(cp.PRECS[prec]), device="cuda")
     stream = torch.cuda.current_stream().cuda_stream
+    steps = args.single_steps
 
     def one_step(timing: bool, p: str, Yp):
         # HIP events time every step of the last query of the step; that
@@ -157,43 +403,104 @@ def run_single(args, torch, cp, synth):
         torch.cuda.synchronize()
         w0 = time.perf_counter()
         ev0.record()
-        for _ in range(args.steps):
+        for _ in range(steps):
             infos += one_step(True, p, Yp)
         ev1.record()
         torch.cuda.synchronize()
         wall = time.perf_counter() - w0
         total_s = max(wall, ev0.elapsed_time(ev1) * 1e-3)
-        arcs = sum((inf["K"] - 1) * g.nnz + int(g.degrees[s]) for inf, s in zip(infos, srcs * args.steps))
+        arcs = sum((inf["K"] - 1) * g.nnz + int(g.degrees[s]) for inf, s in zip(infos, srcs * steps))
         timed = [inf for inf in infos if inf["step_ms"] == inf["step_ms"]]  # not NaN: the timed queries
         launches = sum(inf["steps"] for inf in timed)
         avg_step_ms = sum(inf["step_ms"] for inf in timed) / max(launches, 1)
-        bpl = step_bytes(g.n, g.nnz, p)
         Ks = [inf["K"] for inf in infos[:nsrc]]
         log(f"[single] {p}: K per source: {Ks}; avg step kernel {avg_step_ms * 1e3:.1f} us; "
             f"wall {wall * 1e3:.1f} ms")
-        return dict(value=arcs / total_s / 1e9, total_s=total_s, launches=launches, bpl=bpl,
-                    achieved=bpl / (avg_step_ms * 1e-3) / 1e9, avg_step_ms=avg_step_ms, Ks=Ks)
+        return dict(value=arcs / total_s / 1e9, total_s=total_s, launches=launches, avg_step_ms=avg_step_ms,
+                    Ks=Ks)
 
-    out = timed_run(prec, Y, args.warmup)
-    out.update(
-        g=g, srcs=srcs, Y=Y, layout=args.layout, create_s=create_s, kind=kind, param=param, tol=tol, nsrc=nsrc,
-        prec=prec,
-        workload=f"{args.workload}: HKPR t={param}, {nsrc} sources one at a time, tol {tol} l1 (certified K), "
-                 f"Chung-Lu n={n_t} m={m_t} gamma={gamma} seed={seed}",
-    )
+    R = timed_run(prec, Y, args.warmup)
+    kern = "stripe_gather_kernel + stripe_combine_kernel" if args.layout == "stripes" else "step_kernel"
+    out = {
+        "workload": f"{args.workload}: HKPR t={param}, {nsrc} sources one at a time, tol {tol} l1 (certified K), "
+                    f"Chung-Lu n={n_t} m={m_t} gamma={gamma} seed={seed}",
+        "value": round(R["value"], 3), "unit": "GTEPS", "steps": steps,
+        "ms_per_step": round(R["total_s"] * 1e3 / steps, 3),
+        "n": g.n, "nnz": g.nnz, "d_max": int(g.degrees.max()), "K_per_source": R["Ks"], "layout": args.layout,
+        "prec": prec, "dtype": ARITH_DTYPE[prec], "graph_create_s": round(create_s, 3),
+        "roofline": roofline(step_bytes(g.n, g.nnz, prec), R["avg_step_ms"], kern,
+                             traffic=measured_traffic(f"{args.workload}:{args.layout}"),
+                             implementation_bytes_per_launch=impl_step_bytes(g.n, g.nnz, prec),
+                             launches_timed=R["launches"]),
+    }
+    results = {prec: Y.double().cpu().numpy().T}
     if not args.no_bf16:
         # the same queries with BF16 vector storage (float arithmetic and estimate)
         Yb = torch.empty((nsrc, g.n), dtype=torch.float32, device="cuda")
-        out["bf16"] = timed_run("bf16", Yb, 1)
-        out["bf16"]["Y"] = Yb
+        B = timed_run("bf16", Yb, 1)
+        if B["Ks"] != R["Ks"]:
+            raise RuntimeError("BF16 query took another K than the FP32 one")
+        out["storage_bf16"] = {
+            "workload": "the same queries (graph, sources, steps, layout) with BF16 vector storage: float "
+                        "arithmetic and a float estimate",
+            "value": round(B["value"], 3), "unit": "GTEPS", "ms_per_step": round(B["total_s"] * 1e3 / steps, 3),
+            "roofline": roofline(step_bytes(g.n, g.nnz, "bf16"), B["avg_step_ms"], kern)}
+        results["bf16"] = Yb.double().cpu().numpy().T
+        del Yb
     G.close()
-    return out
+    del Y
+    if not args.no_cpu:
+        from oracle import coefficients as C
+        from oracle import native as NO
+
+        acc = {}
+        for p, Yh in results.items():
+            rows, oracle_s = check_same_k_and_exact(g, Yh, [kind] * nsrc, [param] * nsrc, srcs, R["Ks"])
+            acc[p] = {"results": len(rows),
+                      "worst": worst(rows, ["l1_vs_same_K", "max_abs_vs_same_K", "l1_vs_exact", "max_abs_vs_exact",
+                                            "norm_rel_err_vs_exact"]),
+                      "mass_range": [min(r["mass"] for r in rows), max(r["mass"] for r in rows)]}
+            log(f"[single] accuracy {p}: {acc[p]}")
+        acc["method"] = ("every result against plain-C FP64 Alg. 3 at the same K (several-source form) and the "
+                         "converged vector (plain-C FP64 PwMethod, exact tail 1e-15); Normalized RelErr is Def. 5's "
+                         "degree-normalized error")
+        out["accuracy_vs_fp64_oracle"] = acc
+        # the oracle on the timed workload: the 16 queries one at a time on all host threads, and the
+        # first query on one thread
+        cs = [C.chebyshev_coeffs(kind, param, K) for K in R["Ks"]]
+        arcs = sum((K - 1) * g.nnz + int(g.degrees[s]) for K, s in zip(R["Ks"], srcs))
+        t0 = time.perf_counter()
+        for s, c, K in zip(srcs, cs, R["Ks"]):
+            NO.cheby_power(g.row_ptr, g.col_idx, s, c, K)
+        all_s = time.perf_counter() - t0
+        out["cpu_baseline"] = {
+            "value": round(arcs / all_s / 1e9, 4), "unit": "GTEPS", "cores": NO.threads(), "kind": "oracle",
+            "sample": f"all {nsrc} queries of one step, one at a time, same K: plain-C FP64 Alg. 3 (OpenMP node "
+                      f"loop), {all_s:.2f} s"}
+        NO.set_threads(1)
+        try:
+            t0 = time.perf_counter()
+            NO.cheby_power(g.row_ptr, g.col_idx, srcs[0], cs[0], R["Ks"][0])
+            one_s = time.perf_counter() - t0
+        finally:
+            NO.set_threads(0)
+        out["cpu_baseline_1thread"] = {
+            "value": round(((R["Ks"][0] - 1) * g.nnz + int(g.degrees[srcs[0]])) / one_s / 1e9, 4), "unit": "GTEPS",
+            "cores": 1, "kind": "oracle",
+            "sample": f"the first of the {nsrc} queries, same K: plain-C FP64 Alg. 3 on one thread, {one_s:.2f} s"}
+        log(f"[single] cpu baselines {out['cpu_baseline']} {out['cpu_baseline_1thread']}")
+    return out, g
 
 
 def run_batch(args, torch, cp, synth):
+    """64 PPR sources with mixed tolerances in one batch (the Orkut-shaped
+    workload), FP32 and BF16 storage, autotuned source-tile width; every
+    column's certified distance to the exact vector, and the rounding error
+    of the tightest column of each tolerance class against Alg. 3 at the
+    same K."""
     n_t, m_t, gamma, seed, alpha, nq, tol_choices, prec = BATCH_WORKLOADS[args.batch_workload]
     t0 = time.time()
-    g = synth.chung_lu(n_t, m_t, gamma, seed=seed)
+    g = chung_lu(synth, n_t, m_t, gamma, seed)
     log(f"[batch] graph: n={g.n} nnz={g.nnz} d_max={g.meta['d_max']} ({time.time() - t0:.1f}s)")
     G = cp.Graph(g.row_ptr, g.col_idx, reorder=args.layout != "native")
     srcs = [int(s) for s in synth.sources(g, nq, seed=seed)]
@@ -203,6 +510,7 @@ def run_batch(args, torch, cp, synth):
     log(f"[batch] autotuned source-tile width {bw}")
     qt = [cp.make_query("ppr", alpha, s, t, flags=cp.CP_Q_TIMING) for s, t in zip(srcs, tols)]
     nb = max(1, args.steps // 2)
+    deg = g.degrees
 
     def timed_batches(p: str, Yp):
         for _ in range(max(1, args.warmup)):
@@ -219,64 +527,76 @@ def run_batch(args, torch, cp, synth):
         torch.cuda.synchronize()
         total_s = time.perf_counter() - w0
         Ks = [i["K"] for i in infos]
-        arcs = nb * sum((k - 1) * g.nnz for k in Ks)
-        # algorithmic bytes of each launch: sources still active in it
-        per_batch_bytes = 0
-        for k in range(1, max(Ks)):
-            active = sum(1 for K in Ks if K > k)
-            per_batch_bytes += step_bytes(g.n, g.nnz, p, active)
-        avg_launch_ms = step_ms / max(launches, 1)
-        achieved = per_batch_bytes * nb / (step_ms * 1e-3) / 1e9
-        return total_s, Ks, arcs, avg_launch_ms, achieved
+        arcs = nb * sum((k - 1) * g.nnz + int(deg[s]) for k, s in zip(Ks, srcs))
+        nl = max(Ks) - 1
+        return dict(total_s=total_s, Ks=Ks, arcs=arcs, avg_launch_ms=step_ms / max(launches, 1),
+                    bytes_per_launch=batch_launch_bytes(g.n, g.nnz, p, Ks) / nl,
+                    impl_bytes_per_launch=batch_launch_bytes(g.n, g.nnz, p, Ks, impl_step_bytes) / nl,
+                    launches=launches)
 
     Yb = torch.empty((g.n, nq), dtype=G.out_dtype(cp.PRECS[prec]), device="cuda")
-    total_s, Ks, arcs, avg_launch_ms, achieved = timed_batches(prec, Yb)
+    R = timed_batches(prec, Yb)
     out = {
         "workload": f"{args.batch_workload}: {nq} PPR alpha={alpha} sources in one batch, tol per source from "
                     f"{list(tol_choices)} (certified K), Chung-Lu n={n_t} m={m_t} gamma={gamma} seed={seed}",
-        "value": round(arcs / total_s / 1e9, 3),
-        "unit": "GTEPS",
-        "ms_per_batch": round(total_s * 1e3 / nb, 3),
-        "n": g.n, "nnz": g.nnz, "source_tile_width": bw, "K_min": min(Ks), "K_max": max(Ks),
-        "roofline": {
-            "bound": "hbm", "kernel": "batch_step_kernel",
-            "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBPS, 4),
-            "traffic": measured_traffic(f"{args.batch_workload}:batch"),
-            "avg_launch_ms": round(avg_launch_ms, 4),
-        },
+        "value": round(R["arcs"] / R["total_s"] / 1e9, 3), "unit": "GTEPS",
+        "ms_per_batch": round(R["total_s"] * 1e3 / nb, 3), "batches": nb,
+        "n": g.n, "nnz": g.nnz, "source_tile_width": bw, "K_min": min(R["Ks"]), "K_max": max(R["Ks"]),
+        "roofline": roofline(R["bytes_per_launch"], R["avg_launch_ms"], f"batch_step_kernel (width {bw})",
+                             traffic=measured_traffic(f"{args.batch_workload}:batch"),
+                             implementation_bytes_per_launch=int(R["impl_bytes_per_launch"]),
+                             launches_timed=R["launches"]),
     }
-    if not args.no_cpu:
-        from oracle import coefficients as C
-        from oracle import errors as E
-        from oracle import propagation as PR
-
-        j = min(range(nq), key=lambda i: tols[i])  # the tightest tolerance
-        P = PR.transition_matrix(g.row_ptr, g.col_idx)
-        ref = PR.cheby_power(P, srcs[j], C.ppr_chebyshev_coeffs(alpha, Ks[j]), Ks[j])
-        col = Yb[:, j].double().cpu().numpy()
-        out["accuracy_vs_fp64_oracle"] = {"column": j, "tol": tols[j], "K": Ks[j],
-                                          "l1": E.l1(col, ref), "max_abs": E.max_abs(col, ref)}
+    results = {prec: _host(Yb)}
+    Ks = R["Ks"]
     if not args.no_bf16:
         # the same batch with BF16 storage (float arithmetic and estimate), its own autotuned width
         del Yb
         bwb = G.autotune_batch(qs, prec="bf16")
         Ybb = torch.empty((g.n, nq), dtype=torch.float32, device="cuda")
-        total_b, Ks_b, arcs_b, launch_b, achieved_b = timed_batches("bf16", Ybb)
-        ent = {"workload": "the same batch with BF16 vector storage (float arithmetic and estimate)",
-               "value": round(arcs_b / total_b / 1e9, 3), "unit": "GTEPS", "ms_per_batch": round(total_b * 1e3 / nb, 3),
-               "source_tile_width": bwb,
-               "roofline": {"bound": "hbm", "kernel": "batch_step_kernel", "achieved": round(achieved_b, 1),
-                            "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": round(achieved_b / HBM_PEAK_GBPS, 4),
-                            "avg_launch_ms": round(launch_b, 4)}}
-        if Ks_b != Ks:
+        Rb = timed_batches("bf16", Ybb)
+        if Rb["Ks"] != Ks:
             raise RuntimeError("BF16 batch took other K than the FP32 one")
-        if not args.no_cpu:
-            col = Ybb[:, j].double().cpu().numpy()
-            ent["accuracy_vs_fp64_oracle"] = {"column": j, "l1": E.l1(col, ref), "max_abs": E.max_abs(col, ref)}
-        log(f"[batch] bf16 storage: {ent}")
-        out["storage_bf16"] = ent
+        out["storage_bf16"] = {
+            "workload": "the same batch with BF16 vector storage (float arithmetic and estimate)",
+            "value": round(Rb["arcs"] / Rb["total_s"] / 1e9, 3), "unit": "GTEPS",
+            "ms_per_batch": round(Rb["total_s"] * 1e3 / nb, 3), "source_tile_width": bwb,
+            "roofline": roofline(Rb["bytes_per_launch"], Rb["avg_launch_ms"], f"batch_step_kernel (width {bwb})")}
+        results["bf16"] = _host(Ybb)
+        del Ybb
+        log(f"[batch] bf16 storage: {out['storage_bf16']}")
     G.close()
+    torch.cuda.empty_cache()
+    if not args.no_cpu:
+        from oracle import coefficients as C
+        from oracle import errors as E
+        from oracle import native as NO
+
+        acc = {}
+        # the tightest-tolerance column of each class: rounding error against Alg. 3 at the same K
+        pick = sorted({min((j for j in range(nq) if tols[j] == t), key=lambda j: -Ks[j]) for t in set(tols)})
+        t0 = time.perf_counter()
+        ref = NO.cheby_power_multi(g.row_ptr, g.col_idx, [srcs[j] for j in pick],
+                                   [C.ppr_chebyshev_coeffs(alpha, Ks[j]) for j in pick], [Ks[j] for j in pick])
+        same_k_s = time.perf_counter() - t0
+        for p, Yh in results.items():
+            rows, cert_s = check_ppr_certificate(g, Yh, srcs, [alpha] * nq)
+            for r, t in zip(rows, tols):
+                r["tol"] = t
+                r["meets_tol"] = r["l1_bound_vs_exact"] <= t
+            same_k = [{"column": j, "tol": tols[j], "K": Ks[j], "l1": E.l1(Yh[:, j], ref[:, i]),
+                       "max_abs": E.max_abs(Yh[:, j], ref[:, i])} for i, j in enumerate(pick)]
+            acc[p] = {"results": len(rows),
+                      "worst_l1_bound_by_tol": {str(t): max(r["l1_bound_vs_exact"] for r in rows if r["tol"] == t)
+                                                for t in sorted(set(tols))},
+                      "all_meet_tol": all(r["meets_tol"] for r in rows),
+                      "mass_range": [min(r["mass"] for r in rows), max(r["mass"] for r in rows)],
+                      "same_K_rounding": same_k}
+            log(f"[batch] accuracy {p}: {acc[p]}")
+        acc["method"] = (f"every column: plain-C FP64 residual of Def. 3's fixed point / alpha, a certified bound on "
+                         f"the l1 distance to the exact vector ({cert_s:.1f} s per precision); the tightest column of "
+                         f"each tolerance class also against plain-C FP64 Alg. 3 at the same K ({same_k_s:.1f} s)")
+        out["accuracy_vs_fp64_oracle"] = acc
     return out
 
 
@@ -301,24 +621,35 @@ def _pct(xs, p):
     return float(np.percentile(np.asarray(xs), p)) if len(xs) else None
 
 
+def _lat_summary(lat, span_s, extra=None):
+    out = {"completed": len(lat), "qps": round(len(lat) / span_s, 1) if span_s > 0 else None,
+           "p50_ms": _pct(lat, 50), "p99_ms": _pct(lat, 99), "mean_ms": float(np.mean(lat)) if lat else None,
+           "span_s": round(span_s, 3)}
+    if extra:
+        out.update(extra)
+    return out
+
+
 def run_serve(args, torch, cp, synth, g):
-    """Served query stream: the batched server vs plain one-at-a-time
-    queries on the same arrival trace (same graph, same FP32 precision)."""
-    trace = serve_trace(g, synth, args.serve_seconds, args.serve_rate)
+    """Served query stream on the LiveJournal-shaped graph: the batched
+    server against plain one-at-a-time queries (same graph, FP32) on the
+    same seeded Poisson traces, at the configured rate for the configured
+    time after a warm-up, and at a lower rate that plain sustains.  The
+    latency of a query is its completion time minus its arrival time; the
+    first warm-up seconds of a trace are not counted."""
+    warm = args.serve_warmup
     G = cp.Graph(g.row_ptr, g.col_idx, reorder=args.layout != "native", stripes=args.layout == "stripes")
     nbuf = 512  # one result buffer per server slot
     bufs = [torch.empty(g.n, dtype=torch.float32, device="cuda") for _ in range(nbuf)]
-    # warm both paths (code objects, caches)
-    for (_, kind, param, s, tol) in trace[:4]:
+    S = cp.Server(G, hbm_budget_bytes=16 << 30, max_slots=512, max_queue=100000, prec="f32")
+    stream = torch.cuda.current_stream().cuda_stream
+    first = serve_trace(g, synth, 1.0, 50.0, seed=3)
+    for (_, kind, param, s, tol) in first[:8]:  # code objects and caches, both paths
         G.power(kind, param, s, tol=tol, prec="f32", y=bufs[0])
+        S.wait(S.submit(cp.make_query(kind, param, s, tol), bufs[1]))
     torch.cuda.synchronize()
 
-    # ---- batched server
-    S = cp.Server(G, hbm_budget_bytes=16 << 30, max_slots=512, max_queue=100000, prec="f32")
-    for (_, kind, param, s, tol) in trace[:8]:
-        S.wait(S.submit(cp.make_query(kind, param, s, tol), bufs[1]))
-
-    def replay(tr):
+    def replay_server(tr):
         """Submit at the trace's arrival times; results land in a ring of
         buffers (a buffer is reused once its previous query is done)."""
         tickets = [None] * len(tr)
@@ -337,152 +668,96 @@ def run_serve(args, torch, cp, synth, g):
                 tickets[i] = S.wait(tickets[i])
         return tickets, time.perf_counter() - t0
 
-    ticks0 = S.stats()["ticks"]
-    tickets, t_end = replay(trace)
-    lat = [info["latency_ms"] for st, info in tickets if st == cp.CP_OK]
-    Ks = [info["K"] for st, info in tickets if st == cp.CP_OK]
-    sstats = S.stats()
-    sat = None
+    def server_leg(tr, rate):
+        ticks0 = S.stats()["ticks"]
+        tickets, t_end = replay_server(tr)
+        counted = [(info["latency_ms"], info["K"]) for (ta, *_), (st, info) in zip(tr, tickets)
+                   if st == cp.CP_OK and ta >= warm]
+        lat = [x for x, _ in counted]
+        span = t_end - warm
+        st = S.stats()
+        return _lat_summary(lat, span, {"offered_qps": rate, "arrivals_counted": sum(1 for x in tr if x[0] >= warm),
+                                        "batched_launches": st["ticks"] - ticks0, "slots": st["slots"],
+                                        "tile_width": st["tile_width"],
+                                        "mean_K": float(np.mean([k for _, k in counted])) if counted else None})
+
+    def plain_leg(tr, rate, limit_s):
+        """FIFO, one cp_power at a time; stops once limit_s of wall time has
+        passed (the queue of an overloaded plain path only grows)."""
+        lat, t0, stopped = [], time.perf_counter(), False
+        for (ta, kind, param, s, tol) in tr:
+            now = time.perf_counter() - t0
+            if now > limit_s:
+                stopped = True
+                break
+            if ta > now:
+                time.sleep(ta - now)
+            G.power(kind, param, s, tol=tol, prec="f32", y=bufs[0], stream=stream)
+            torch.cuda.synchronize()
+            if ta >= warm:
+                lat.append((time.perf_counter() - t0 - ta) * 1e3)
+        span = time.perf_counter() - t0 - warm
+        extra = {"offered_qps": rate}
+        if stopped:
+            extra["stopped_after_s"] = limit_s
+            extra["note"] = (f"plain falls behind the offered rate, so its queue grows for as long as the trace "
+                             f"runs; it was stopped after {limit_s:g} s of wall time, and its latencies are those of "
+                             f"the queries completed by then")
+        return _lat_summary(lat, span, extra)
+
+    out = {"workload": f"Poisson arrivals, PPR alpha in {{0.1, 0.2}}, HKPR t in {{3, 5, 10}} uniformly, tol "
+                       f"log-uniform [1e-7, 1e-4] (certified K), FP32 resident state, on the single-source "
+                       f"workload's graph; latency = completion - arrival, the first {warm:g} s of each trace are "
+                       f"warm-up and not counted",
+           "rates": []}
+    for rate, seconds, plain_limit in ((args.serve_rate, args.serve_seconds, args.plain_limit_s),
+                                       (args.serve_rate_low, args.serve_seconds_low, None)):
+        if seconds <= 0 or rate <= 0:
+            continue
+        tr = serve_trace(g, synth, seconds + warm, rate, seed=4 if rate == args.serve_rate else 6)
+        srv = server_leg(tr, rate)
+        log(f"[serve] {rate}/s server: {srv}")
+        pl = plain_leg(tr, rate, plain_limit if plain_limit else float("inf"))
+        log(f"[serve] {rate}/s plain: {pl}")
+        out["rates"].append({"offered_qps": rate, "trace_s": seconds + warm, "queries": len(tr), "server": srv,
+                             "plain": pl, "p99_ratio_plain_over_server":
+                             round(pl["p99_ms"] / srv["p99_ms"], 2) if pl["p99_ms"] and srv["p99_ms"] else None})
     if args.saturation_rate > 0:
         burst = serve_trace(g, synth, 1.0, args.saturation_rate, seed=7)
-        bt, b_end = replay(burst)
+        bt, b_end = replay_server(burst)
         blat = [info["latency_ms"] for st, info in bt if st == cp.CP_OK]
-        sat = {"offered_qps": args.saturation_rate, "queries": len(burst), "completed": len(blat),
-               "qps": round(len(blat) / b_end, 1), "p50_ms": _pct(blat, 50), "p99_ms": _pct(blat, 99),
-               "span_s": round(b_end, 3), "latency_from": "submission (a submit waits for a free result buffer)"}
-        log(f"[serve] saturation burst: {sat}")
-    # accuracy of two served results (rerun into a fresh buffer through the server)
-    acc = None
-    if not args.no_cpu:
-        from oracle import coefficients as C
-        from oracle import errors as E
-        from oracle import propagation as PR
-
-        P = PR.transition_matrix(g.row_ptr, g.col_idx)
-        acc = []
-        for i in (0, len(trace) // 2):
-            _, kind, param, s, tol = trace[i]
-            st, info = S.wait(S.submit(cp.make_query(kind, param, s, tol), bufs[2]))
-            ref = PR.cheby_power(P, s, C.chebyshev_coeffs(kind, param, info["K"]), info["K"])
-            y = bufs[2].double().cpu().numpy()
-            acc.append({"kind": kind, "param": param, "tol": tol, "K": info["K"],
-                        "l1": E.l1(y, ref), "max_abs": E.max_abs(y, ref)})
+        out["server_saturation"] = _lat_summary(blat, b_end, {
+            "offered_qps": args.saturation_rate, "queries": len(burst),
+            "latency_from": "submission (a submit waits for a free result buffer)"})
+        log(f"[serve] saturation burst: {out['server_saturation']}")
+    if not args.no_cpu and args.serve_check > 0:
+        # served results against the FP64 oracle: queries spread over the first trace, rerun
+        # through the server into buffers of their own
+        tr = serve_trace(g, synth, args.serve_seconds + warm, args.serve_rate, seed=4)
+        idx = np.linspace(0, len(tr) - 1, min(args.serve_check, len(tr))).astype(int)
+        pend = [(S.submit(cp.make_query(tr[i][1], tr[i][2], tr[i][3], tr[i][4]), bufs[k]), i)
+                for k, i in enumerate(idx)]
+        got = [(S.wait(t), i) for t, i in pend]
+        if any(st != cp.CP_OK for (st, _), _ in got):
+            raise RuntimeError("served check query failed")
+        Yh = torch.stack([bufs[k] for k in range(len(idx))], dim=1).double().cpu().numpy()
+        rows, oracle_s = check_same_k_and_exact(g, Yh, [tr[i][1] for i in idx], [tr[i][2] for i in idx],
+                                                [tr[i][3] for i in idx], [info["K"] for (_, info), _ in got],
+                                                exact="chebyshev")
+        for r, i in zip(rows, idx):
+            r["tol"] = tr[i][4]
+            r["meets_tol"] = r["l1_vs_exact"] <= tr[i][4]
+        out["accuracy_vs_fp64_oracle"] = {
+            "results": len(rows), "all_meet_tol": all(r["meets_tol"] for r in rows),
+            "worst": worst(rows, ["l1_vs_same_K", "max_abs_vs_same_K", "l1_vs_exact", "norm_rel_err_vs_exact"]),
+            "worst_l1_over_tol": max(r["l1_vs_exact"] / r["tol"] for r in rows),
+            "mass_range": [min(r["mass"] for r in rows), max(r["mass"] for r in rows)],
+            "method": f"{len(rows)} queries spread over the trace, rerun through the server: plain-C FP64 Alg. 3 at "
+                      f"the same K and the converged vector (plain-C Alg. 3 with the certified K for l1 1e-13), "
+                      f"{oracle_s:.1f} s"}
+        log(f"[serve] accuracy {out['accuracy_vs_fp64_oracle']}")
     S.close()
-    server = {"completed": len(lat), "qps": round(len(lat) / t_end, 1), "p50_ms": _pct(lat, 50),
-              "p99_ms": _pct(lat, 99), "mean_ms": float(np.mean(lat)) if lat else None,
-              "span_s": round(t_end, 3), "slots": sstats["slots"], "tile_width": sstats["tile_width"],
-              "batched_launches": sstats["ticks"] - ticks0, "mean_K": float(np.mean(Ks)) if Ks else None}
-    log(f"[serve] server: {server}")
-
-    # ---- plain: one query at a time, FIFO, single-source path
-    lat_p = []
-    stream = torch.cuda.current_stream().cuda_stream
-    t0 = time.perf_counter()
-    for (ta, kind, param, s, tol) in trace:
-        now = time.perf_counter() - t0
-        if ta > now:
-            time.sleep(ta - now)
-        G.power(kind, param, s, tol=tol, prec="f32", y=bufs[0], stream=stream)
-        torch.cuda.synchronize()
-        lat_p.append((time.perf_counter() - t0 - ta) * 1e3)
-        if len(lat_p) % 4000 == 0:
-            log(f"[serve] plain: {len(lat_p)} of {len(trace)} queries done")
-    t_end_p = time.perf_counter() - t0
-    plain = {"completed": len(lat_p), "qps": round(len(lat_p) / t_end_p, 1), "p50_ms": _pct(lat_p, 50),
-             "p99_ms": _pct(lat_p, 99), "mean_ms": float(np.mean(lat_p)), "span_s": round(t_end_p, 3)}
-    log(f"[serve] plain: {plain}")
     G.close()
-    out = {
-        "workload": f"Poisson arrivals at {args.serve_rate}/s for {args.serve_seconds} s ({len(trace)} queries): "
-                    f"PPR alpha in {{0.1, 0.2}}, HKPR t in {{3, 5, 10}} uniformly, tol log-uniform [1e-7, 1e-4] "
-                    f"(certified K), FP32 resident state, on the main line's graph",
-        "offered_qps": args.serve_rate,
-        "server": server,
-        "plain": plain,
-        "speedup_qps": round(server["qps"] / plain["qps"], 2) if plain["qps"] else None,
-    }
-    if sat is not None:
-        out["server_saturation"] = sat
-        out["capacity_vs_plain"] = round(sat["qps"] / plain["qps"], 2) if plain["qps"] else None
-    if acc is not None:
-        out["accuracy_vs_fp64_oracle"] = acc
-    return out
-
-
-LARGE = (65_000_000, 1_800_000_000, 2.1, 5, 0.2, 8, 1e-6)
-
-
-def run_large(args, torch, cp, synth):
-    """Friendster-sized graph (n = 65M target nodes, 1.8B undirected edges,
-    exponent 2.1): a batch of 8 PPR sources with FP32 and with BF16 storage,
-    one single-source query, and the l1 / max error of each against the
-    plain-C FP64 oracle on one source (full vector)."""
-    n_t, m_t, gamma, seed, alpha, nq, tol = LARGE
-    t0 = time.time()
-    g = synth.chung_lu(n_t, m_t, gamma, seed=seed, tune_passes=0, verbose=True)
-    gen_s = time.time() - t0
-    log(f"[large] graph: n={g.n} nnz={g.nnz} d_max={g.meta['d_max']} ({gen_s:.0f}s)")
-    t0 = time.time()
-    G = cp.Graph(g.row_ptr, g.col_idx, reorder=True)
-    create_s = time.time() - t0
-    log(f"[large] graph create {create_s:.0f}s, device bytes {G.stats['device_bytes']}")
-    srcs = [int(s) for s in synth.sources(g, nq, seed=seed)]
-    qs = [cp.make_query("ppr", alpha, s, tol, flags=cp.CP_Q_TIMING) for s in srcs]
-    out = {"workload": f"large: {nq} PPR alpha={alpha} sources, tol {tol} l1 (certified K), Chung-Lu n={n_t} "
-                       f"m={m_t} gamma={gamma} seed={seed} (one generation pass)",
-           "n": g.n, "nnz": g.nnz, "d_max": int(g.degrees.max()), "generate_s": round(gen_s, 1),
-           "graph_create_s": round(create_s, 1)}
-    cols = {}
-    for prec in ("f32", "bf16"):
-        G.set_batch_width(nq, prec, 8)
-        Yb, infos = G.power_batch(qs, prec=prec)  # warm-up
-        Yb, infos = G.power_batch(qs, prec=prec, Y=Yb)
-        Ks = [i["K"] for i in infos]
-        ms = infos[0]["elapsed_ms"]
-        arcs = sum((k - 1) * g.nnz for k in Ks)
-        out[f"batch_{prec}"] = {"GTEPS": round(arcs / ms / 1e6, 2), "ms_per_batch": round(ms, 1),
-                                "avg_launch_ms": round(infos[0]["step_ms"] / max(i["steps"] for i in infos), 3),
-                                "K": Ks, "source_tile_width": 8}
-        cols[prec] = Yb[:, 0].double().cpu().numpy()
-        log(f"[large] batch {prec}: {out[f'batch_{prec}']}")
-        del Yb
-    r = G.power("ppr", alpha, srcs[0], tol=tol, prec="f32", flags=cp.CP_Q_TIMING)
-    out["single_f32"] = {"GTEPS": round((r.info["K"] - 1) * g.nnz / r.info["elapsed_ms"] / 1e6, 2),
-                         "ms": round(r.info["elapsed_ms"], 1), "K": r.info["K"],
-                         "avg_step_ms": round(r.info["step_ms"] / r.info["steps"], 3)}
-    cols["single_f32"] = r.y.double().cpu().numpy()
-    log(f"[large] single: {out['single_f32']}")
-    G.close()
-    # the main line's layout (XCD stripes; plain column ids at this n)
-    t0 = time.time()
-    Gs = cp.Graph(g.row_ptr, g.col_idx, stripes=True)
-    log(f"[large] striped graph create {time.time() - t0:.0f}s, stats {Gs.stats}")
-    Gs.power("ppr", alpha, srcs[0], tol=tol, prec="f32")  # warm-up
-    r = Gs.power("ppr", alpha, srcs[0], tol=tol, prec="f32", flags=cp.CP_Q_TIMING)
-    out["single_f32_stripes"] = {"GTEPS": round((r.info["K"] - 1) * g.nnz / r.info["elapsed_ms"] / 1e6, 2),
-                                 "ms": round(r.info["elapsed_ms"], 1), "K": r.info["K"],
-                                 "avg_step_ms": round(r.info["step_ms"] / r.info["steps"], 3),
-                                 "stripe_packed": Gs.stats["stripe_packed"]}
-    cols["single_f32_stripes"] = r.y.double().cpu().numpy()
-    log(f"[large] single (stripes): {out['single_f32_stripes']}")
-    Gs.close()
-    if not args.no_cpu:
-        from oracle import coefficients as C
-        from oracle import errors as E
-        from oracle import native as NO
-
-        NO.set_verbose(True)
-        K = out["batch_f32"]["K"][0]
-        t0 = time.perf_counter()
-        ref = NO.cheby_power(g.row_ptr, g.col_idx, srcs[0], C.ppr_chebyshev_coeffs(alpha, K), K)
-        cpu_s = time.perf_counter() - t0
-        out["cpu_baseline"] = {"value": round((K - 1) * g.nnz / cpu_s / 1e9, 4), "unit": "GTEPS",
-                               "cores": NO.threads(), "kind": "oracle",
-                               "sample": f"1 of the {nq} sources, same K={K}: plain-C FP64 Alg. 3 with an OpenMP "
-                                         f"node loop, {cpu_s:.0f} s"}
-        out["accuracy_vs_fp64_oracle"] = {k: {"l1": E.l1(v, ref), "max_abs": E.max_abs(v, ref)}
-                                          for k, v in cols.items()}
-        log(f"[large] accuracy {out['accuracy_vs_fp64_oracle']}")
     return out
 
 
@@ -753,17 +1028,70 @@ def run_latency(args, torch, cp, synth):
     return out
 
 
+def run_gather_footprint(args, torch, cp):
+    """Gather rate of the batched step kernel against the size of the set of
+    rows it gathers from.  Synthetic CSR: n rows of d arcs whose columns are
+    uniform over the first F rows, so one launch gathers n d rows of bw
+    values from a slice of F bw s bytes; F from L2-sized (4 MiB per XCD)
+    through Infinity-Cache-sized (256 MiB) to HBM-sized.  Timing only: the
+    graph is not symmetric and the values are not a propagation."""
+    n, d = args.footprint_rows, 8
+    rows = []
+    stream = torch.cuda.current_stream().cuda_stream
+    rp = np.arange(n + 1, dtype=np.int64) * d
+    gen = torch.Generator(device="cuda").manual_seed(11)
+    for bw in (8, 32):
+        for F in (16_384, 65_536, 131_072, 524_288, 2_097_152, 8_388_608, n):
+            if F > n:
+                continue
+            ci = torch.randint(0, F, (n * d,), generator=gen, device="cuda", dtype=torch.int32)
+            G = cp.Graph(torch.from_numpy(rp).cuda(), ci, host_input=False)
+            del ci
+            qs = [cp.make_query("ppr", 0.2, s, kmode="fixed", K=8, flags=cp.CP_Q_TIMING) for s in range(bw)]
+            G.set_batch_width(bw, "f32", bw)
+            Y = torch.empty((n, bw), dtype=torch.float32, device="cuda")
+            G.power_batch(qs, prec="f32", Y=Y, stream=stream)
+            ms, launches = 0.0, 0
+            for _ in range(3):
+                _, infos = G.power_batch(qs, prec="f32", Y=Y, stream=stream)
+                ms += infos[0]["step_ms"]
+                launches += infos[0]["steps"]
+            per = ms / launches
+            row = {"width": bw, "slice_rows": F, "slice_MiB": round(F * bw * 4 / 2**20, 2),
+                   "launch_ms": round(per, 4), "G_gathers_per_s": round(n * d / (per * 1e-3) / 1e9, 1),
+                   "G_lines_per_s": round(n * d * max(1, bw * 4 // 128) / (per * 1e-3) / 1e9, 1)}
+            log(f"[footprint] {row}")
+            rows.append(row)
+            G.close()
+            del Y
+            torch.cuda.empty_cache()
+    return {"workload": f"batched step kernel, FP32, {n} rows x {d} arcs, columns uniform over the first "
+                        f"slice_rows rows (one gather = width x 4 bytes), K = 8", "rows": rows}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="hkpr-livejournal", choices=sorted(WORKLOADS))
+    ap.add_argument("--steps", type=int, default=10, help="timed headline batches (the JSON's steps)")
+    ap.add_argument("--warmup", type=int, default=2, help="untimed headline batches before them")
+    ap.add_argument("--headline", default="ppr-batch-friendster", choices=sorted(HEADLINES))
+    ap.add_argument("--bf16-steps", type=int, default=3, help="timed batches of the headline's BF16 variant")
+    ap.add_argument("--workload", default="hkpr-livejournal", choices=sorted(WORKLOADS) + ["none"],
+                    help="single-source measurement reported beside the headline")
+    ap.add_argument("--single-steps", type=int, default=10,
+                    help="timed passes over the single-source workload's queries")
     ap.add_argument("--batch-workload", default="ppr-batch-orkut", choices=sorted(BATCH_WORKLOADS) + ["none"],
-                    help="batched measurement reported beside the main line")
-    ap.add_argument("--serve-seconds", type=float, default=3.0,
-                    help="length of the Poisson arrival trace for the served measurement (0: skip)")
+                    help="batched measurement reported beside the headline")
+    ap.add_argument("--serve-seconds", type=float, default=60.0,
+                    help="counted length of the Poisson trace at --serve-rate (0: skip the served measurement)")
+    ap.add_argument("--serve-warmup", type=float, default=5.0, help="warm-up seconds at the start of each trace")
     ap.add_argument("--serve-rate", type=float, default=200.0, help="offered queries per second")
+    ap.add_argument("--plain-limit-s", type=float, default=12.0,
+                    help="wall time after which the plain leg of the --serve-rate trace stops")
+    ap.add_argument("--serve-rate-low", type=float, default=50.0,
+                    help="second offered rate, one the plain path sustains (0: skip)")
+    ap.add_argument("--serve-seconds-low", type=float, default=20.0, help="counted length of that trace")
+    ap.add_argument("--serve-check", type=int, default=16, help="served queries checked against the oracle")
     ap.add_argument("--saturation-rate", type=float, default=2000.0,
                     help="offered rate of a 1-second burst that measures the server's capacity (0: skip)")
     ap.add_argument("--layout", default="stripes", choices=["stripes", "degree", "native"],
@@ -778,14 +1106,14 @@ def main() -> int:
                     help="eps_a values of the ChebyPush measurement (none: skip it)")
     ap.add_argument("--no-push-rw", action="store_true", help="skip the ChebyPush + random walk measurement")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle legs")
-    ap.add_argument("--no-bf16", action="store_true",
-                    help="skip the main line's BF16-storage variant")
+    ap.add_argument("--no-bf16", action="store_true", help="skip the BF16-storage variants")
     ap.add_argument("--no-latency", action="store_true",
                     help="skip the small-graph latency measurement (eager vs HIP graph replay)")
-    ap.add_argument("--copy-probe", action="store_true",
-                    help="run a plain 1 GiB device copy first (counter scaling for rocprofv3 --pmc)")
-    ap.add_argument("--large", action="store_true",
-                    help="run only the Friendster-sized measurement (n=65M, 1.8B edges; minutes, ~60 GB host RAM)")
+    ap.add_argument("--gather-footprint", action="store_true",
+                    help="only measure the batched kernel's gather rate against the gathered slice's size")
+    ap.add_argument("--footprint-rows", type=int, default=16_777_216, help="rows of that measurement's graph")
+    ap.add_argument("--graph-cache", default="",
+                    help="directory where generated graphs are kept as .npy files and read back by later runs")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -807,134 +1135,59 @@ def main() -> int:
         print("bench.py needs a GPU", file=sys.stderr)
         return 2
     torch.cuda.set_device(0)
-    if args.large:
-        res = {"metric": METRIC, "n_gpus": 1, "large": run_large(args, torch, cp, synth)}
-        print(json.dumps(res), flush=True)
+    global GRAPH_CACHE
+    GRAPH_CACHE = args.graph_cache or None
+    if args.gather_footprint:
+        print(json.dumps({"metric": "gather rate against gathered slice size", "n_gpus": 1,
+                          "gather_footprint": run_gather_footprint(args, torch, cp)}), flush=True)
         return 0
     copy_gbps = copy_ceiling(torch)
     log(f"device copy ceiling: {copy_gbps:.0f} GB/s")
 
-    S = run_single(args, torch, cp, synth)
+    H = run_headline(args, torch, cp, synth)
     result = {
         "metric": METRIC,
-        "value": round(S["value"], 3),
+        "value": round(H["value"], 3),
         "unit": "GTEPS",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(S["total_s"] * 1e3 / args.steps, 4),
+        "ms_per_step": round(H["total_s"] * 1e3 / args.steps, 3),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": ARITH_DTYPE[S["prec"]],  # arithmetic; vectors are stored as config.prec
-        "storage_dtype": S["prec"],
-        "data": "synthetic (seeded Chung-Lu graphs shaped like LiveJournal / Orkut; random sources)",
+        "dtype": ARITH_DTYPE[H["prec"]],  # arithmetic; vectors are stored as config.prec
+        "storage_dtype": H["prec"],
+        "data": "synthetic (seeded Chung-Lu graphs shaped like Friendster / LiveJournal / Orkut; random sources)",
         "config": {
-            "workload": S["workload"],
-            "n": S["g"].n, "nnz": S["g"].nnz, "d_max": int(S["g"].degrees.max()), "sources": S["nsrc"],
-            "K_per_source": S["Ks"], "layout": S["layout"], "prec": S["prec"],
-            "graph_create_s": round(S["create_s"], 3), "parallelism": "single-gpu",
+            "workload": H["workload"], "n": H["n"], "nnz": H["nnz"], "d_max": H["d_max"], "sources": H["sources"],
+            "K_per_source": H["Ks"], "prec": H["prec"], "layout": "degree", "source_tile_width": H["source_tile_width"],
+            "graph_generate_s": H["generate_s"], "graph_create_s": H["create_s"], "parallelism": "single-gpu",
         },
-        "hbm_frac_whole_run": round(S["launches"] * S["bpl"] / S["total_s"] / 1e9 / HBM_PEAK_GBPS, 4),
-        "roofline": {
-            "bound": "hbm",
-            "kernel": "stripe_gather_kernel + stripe_combine_kernel" if S["layout"] == "stripes" else "step_kernel",
-            "achieved": round(S["achieved"], 1),
-            "peak": HBM_PEAK_GBPS,
-            "unit": "GB/s",
-            "frac": round(S["achieved"] / HBM_PEAK_GBPS, 4),
-            "traffic": measured_traffic(f"{args.workload}:{S['layout']}"),
-            "bytes_per_launch": S["bpl"],
-            "avg_launch_us": round(S["avg_step_ms"] * 1e3, 2),
-            "launches_timed": S["launches"],
-        },
+        "roofline": H["roofline"],
+        "launch_bytes_rule": H["launch_bytes_rule"],
         "copy_ceiling_gbps": round(copy_gbps, 1),
     }
-
-    if not args.no_cpu:
-        from oracle import coefficients as C
-        from oracle import errors as E
-        from oracle import propagation as PR
-
-        # bounded sample: whole queries of the timed workload, in order, until
-        # about 10 s of single-thread oracle time
-        g = S["g"]
-        P = PR.transition_matrix(g.row_ptr, g.col_idx)
-        cpu_s, cpu_arcs, done, l1s, maxs, refs = 0.0, 0, 0, [], [], []
-        for i, (s, K) in enumerate(zip(S["srcs"], S["Ks"])):
-            c = C.chebyshev_coeffs(S["kind"], S["param"], K)
-            c0 = time.perf_counter()
-            y_ref = PR.cheby_power(P, s, c, K)
-            cpu_s += time.perf_counter() - c0
-            cpu_arcs += (K - 1) * g.nnz + int(g.degrees[s])
-            y_gpu = S["Y"][i].double().cpu().numpy()
-            l1s.append(E.l1(y_gpu, y_ref))
-            maxs.append(E.max_abs(y_gpu, y_ref))
-            refs.append((s, K, c, y_ref))
-            done += 1
-            if cpu_s >= 10.0:
-                break
-        result["cpu_baseline"] = {
-            "value": round(cpu_arcs / cpu_s / 1e9, 4),
-            "unit": "GTEPS",
-            "cores": 1,
-            "kind": "oracle",
-            "sample": f"the first {done} of the {S['nsrc']} sources (same graph, same K per source): FP64 Alg. 3 "
-                      f"with scipy CSR products, {cpu_s:.1f} s",
-        }
-        result["accuracy_vs_fp64_oracle"] = {"sources": done, "max_l1": max(l1s), "max_abs": max(maxs),
-                                             "K": [r[1] for r in refs]}
-        # the same sample on every host thread: the plain-C oracle (OpenMP node loop)
-        from oracle import native as NO
-
-        c0 = time.perf_counter()
-        agree = 0.0
-        for (s, K, c, y_ref) in refs:
-            y_c = NO.cheby_power(g.row_ptr, g.col_idx, s, c, K)
-            agree = max(agree, E.l1(y_c, y_ref))
-        cpu_t = time.perf_counter() - c0
-        result["cpu_baseline_threads"] = {
-            "value": round(cpu_arcs / cpu_t / 1e9, 4), "unit": "GTEPS", "cores": NO.threads(), "kind": "oracle",
-            "sample": f"the same {done} sources and K: plain-C FP64 Alg. 3, {cpu_t:.2f} s",
-            "agrees_with_scipy_oracle_l1": agree,
-            "host": {"nproc": os.cpu_count(), "cpu_model": cpu_model()},
-        }
-    if "bf16" in S:
-        B = S["bf16"]
-        entry = {
-            "workload": "the main line's queries (same graph, sources, steps and layout) with BF16 vector "
-                        "storage: float arithmetic and a float estimate",
-            "value": round(B["value"], 3), "unit": "GTEPS", "ms_per_step": round(B["total_s"] * 1e3 / args.steps, 4),
-            "K_per_source": B["Ks"],
-            "roofline": {"bound": "hbm", "achieved": round(B["achieved"], 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                         "frac": round(B["achieved"] / HBM_PEAK_GBPS, 4), "bytes_per_launch": B["bpl"],
-                         "avg_launch_us": round(B["avg_step_ms"] * 1e3, 2)},
-        }
-        if not args.no_cpu:
-            l1b, maxb = [], []
-            for i, (s, K, c, y_ref) in enumerate(refs):
-                if B["Ks"][i] != K:
-                    raise RuntimeError("BF16 query took another K than the FP32 one")
-                y_b = B["Y"][i].double().cpu().numpy()
-                l1b.append(E.l1(y_b, y_ref))
-                maxb.append(E.max_abs(y_b, y_ref))
-            entry["accuracy_vs_fp64_oracle"] = {"sources": len(refs), "max_l1": max(l1b), "max_abs": max(maxb)}
-        log(f"[single] bf16 storage: {entry}")
-        result["storage_bf16"] = entry
-    g_main = S["g"]
-    del S
+    for k in ("cpu_baseline", "accuracy_vs_fp64_oracle", "storage_bf16"):
+        if k in H:
+            result[k] = H[k]
+    del H
+    g_main = None
+    if args.workload != "none":
+        result["single"], g_main = run_single(args, torch, cp, synth)
     if not args.no_latency:
         result["latency"] = run_latency(args, torch, cp, synth)
-    if args.kvn_tol > 0:
-        result["cheby_vs_power"] = run_kvn(args, torch, cp, synth, g_main)
-    if args.propagate_cols > 0:
-        result["propagate"] = run_propagate(args, torch, cp, synth, g_main)
-    if args.push_eps:
-        result["push"] = run_push(args, torch, cp, synth, g_main)
-    if not args.no_push_rw:
-        result["push_rw"] = run_push_rw(args, torch, cp, synth, g_main)
-    if args.serve_seconds > 0:
-        result["served"] = run_serve(args, torch, cp, synth, g_main)
+    if g_main is not None:
+        if args.kvn_tol > 0:
+            result["cheby_vs_power"] = run_kvn(args, torch, cp, synth, g_main)
+        if args.propagate_cols > 0:
+            result["propagate"] = run_propagate(args, torch, cp, synth, g_main)
+        if args.push_eps:
+            result["push"] = run_push(args, torch, cp, synth, g_main)
+        if not args.no_push_rw:
+            result["push_rw"] = run_push_rw(args, torch, cp, synth, g_main)
+        if args.serve_seconds > 0:
+            result["served"] = run_serve(args, torch, cp, synth, g_main)
     del g_main
     if args.batch_workload != "none":
         result["batched"] = run_batch(args, torch, cp, synth)

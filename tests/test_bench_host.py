@@ -21,15 +21,33 @@ def _bench():
 def test_step_bytes_per_precision():
     b = _bench()
     n, nnz = 1000, 17000
-    # column ids + row offsets + per node: gather, z read + write (storage),
-    # estimate read + write (double for FP64 / FP32 storage, float for BF16)
-    assert b.step_bytes(n, nnz, "f32") == 4 * nnz + 8 * (n + 1) + n * (3 * 4 + 2 * 8)
-    assert b.step_bytes(n, nnz, "f64") == 4 * nnz + 8 * (n + 1) + n * (3 * 8 + 2 * 8)
-    assert b.step_bytes(n, nnz, "bf16") == 4 * nnz + 8 * (n + 1) + n * (3 * 2 + 2 * 4)
+    # column ids + row offsets + per node five vector terms at the storage
+    # width: gather, z read + write, estimate read + write
+    assert b.step_bytes(n, nnz, "f32") == 4 * nnz + 8 * (n + 1) + 5 * n * 4
+    assert b.step_bytes(n, nnz, "f64") == 4 * nnz + 8 * (n + 1) + 5 * n * 8
+    assert b.step_bytes(n, nnz, "bf16") == 4 * nnz + 8 * (n + 1) + 5 * n * 2
     # batched: the index stream is shared, the vector terms scale with sources
-    assert b.step_bytes(n, nnz, "f32", 64) - b.step_bytes(n, nnz, "f32", 0) == 64 * n * 28
+    assert b.step_bytes(n, nnz, "f32", 64) - b.step_bytes(n, nnz, "f32", 0) == 64 * n * 20
+    # the implementation keeps a double estimate for FP32 storage
+    assert b.impl_step_bytes(n, nnz, "f32") == 4 * nnz + 8 * (n + 1) + n * (3 * 4 + 2 * 8)
+    assert b.impl_step_bytes(n, nnz, "bf16") == b.step_bytes(n, nnz, "bf16") + n * 2 * 2
     # Clenshaw: no estimate stream, one read of the start vector
-    assert b.clenshaw_step_bytes(n, nnz, "f32", 8) == 4 * nnz + 8 * (n + 1) + 8 * n * (3 * 4 + 8)
+    assert b.clenshaw_step_bytes(n, nnz, "f32", 8) == 4 * nnz + 8 * (n + 1) + 8 * n * 4 * 4
+
+
+def test_batch_launch_bytes_count_active_sources():
+    b = _bench()
+    n, nnz = 1000, 17000
+    Ks = [3, 5, 5]
+    # launches k = 1..4: sources with K > k are active: 3, 3, 2, 2
+    want = sum(b.step_bytes(n, nnz, "f32", a) for a in (3, 3, 2, 2))
+    assert b.batch_launch_bytes(n, nnz, "f32", Ks) == want
+
+
+def test_roofline_fraction():
+    b = _bench()
+    r = b.roofline(8e9, 2.0, "k")  # 8 GB in 2 ms = 4 TB/s
+    assert r["achieved"] == 4000.0 and r["frac"] == 0.5 and r["peak"] == 8000.0 and r["bound"] == "hbm"
 
 
 def test_traffic_only_for_current_kernels():
