@@ -40,3 +40,31 @@ def compare(y_gpu, y_ref, degrees=None) -> dict:
     if degrees is not None:
         out["deg_norm"] = E.degree_normalized(y, y_ref, degrees)
     return out
+
+
+def oracle_yK_multi(g, metas, Ks):
+    """Alg. 3 in FP64 at the GPU's K for several (kind, param, source)
+    queries at once: the plain-C oracle's several-source form, [n][B]."""
+    from oracle import native as NO
+
+    cs = [C.chebyshev_coeffs(kind, param, K) for (kind, param, _), K in zip(metas, Ks)]
+    return NO.cheby_power_multi(g.row_ptr, g.col_idx, [int(s) for _, _, s in metas], cs, list(Ks))
+
+
+def oracle_exact_multi(g, metas, tail=1e-15):
+    """The converged vectors f(P) e_s of several queries: the plain-C
+    PwMethod with its exact l1 tail below `tail`, [n][B]."""
+    from oracle import native as NO
+    from oracle import truncation as T
+
+    Ns = [T.pwmethod_steps(kind, param, tail) for kind, param, _ in metas]
+    zs = [C.taylor_coeffs(kind, param, N) for (kind, param, _), N in zip(metas, Ns)]
+    return NO.power_method_multi(g.row_ptr, g.col_idx, [int(s) for _, _, s in metas], zs, Ns)
+
+
+# Rounding bars (l1 against Alg. 3 in FP64 at the same K).  FP32 storage with
+# double sums measures about 6e-8 at 4M nodes and below that on smaller
+# graphs; float sums measured 1.7e-7, which these bars reject.  BF16 storage
+# (float sums) measures 1e-3 to 3e-3.
+F32_L1 = 1.2e-7
+BF16_L1 = 5e-3

@@ -12,7 +12,6 @@ from __future__ import annotations
 import math
 
 import numpy as np
-import scipy.integrate as si
 import scipy.special as ss
 
 import synth
@@ -157,17 +156,31 @@ def pin_ppr_closed_values():
     assert abs(alt - gold["f_minus_one"][0]) < 1e-14
 
 
+def _gauss_legendre(fn, a: float, b: float, nodes: int) -> float:
+    x, w = ss.roots_legendre(nodes)
+    t = 0.5 * (b - a) * x + 0.5 * (b + a)
+    return float(0.5 * (b - a) * np.sum(w * fn(t)))
+
+
 def pin_coefficient_integrals():
     """Lemma 1's definition integrated numerically in theta = arccos x:
-    c_k = (2/pi) int_0^pi f(cos th) cos(k th) dth (1/pi for k = 0)."""
+    c_k = (2/pi) int_0^pi f(cos th) cos(k th) dth (1/pi for k = 0), by
+    Gauss-Legendre quadrature (a method independent of the trapezoid rule
+    and the recurrences the oracle uses) at 96 and 128 nodes; the two must
+    agree (the integrand is analytic, so the rule has converged) before the
+    value is compared."""
     for kind, p in GP_CASES:
         f = C.gp_function(kind, p)
         c = C.chebyshev_coeffs(kind, p, 12)
         for k in range(13):
-            val, _ = si.quad(lambda th: float(f(math.cos(th))) * math.cos(k * th), 0.0, math.pi,
-                             epsabs=1e-14, epsrel=1e-12, limit=400)
-            ref = val * (1.0 if k == 0 else 2.0) / math.pi
-            assert abs(c[k] - ref) <= 1e-12 + 1e-10 * abs(ref), (kind, p, k, c[k], ref)
+            def fn(th, k=k):
+                return np.asarray(f(np.cos(th)), dtype=np.float64) * np.cos(k * th)
+
+            v1 = _gauss_legendre(fn, 0.0, math.pi, 96)
+            v2 = _gauss_legendre(fn, 0.0, math.pi, 128)
+            assert abs(v1 - v2) <= 1e-13, (kind, p, k, v1, v2)
+            ref = v2 * (1.0 if k == 0 else 2.0) / math.pi
+            assert abs(c[k] - ref) <= 1e-13 + 1e-11 * abs(ref), (kind, p, k, c[k], ref)
 
 
 def pin_hkpr_library():

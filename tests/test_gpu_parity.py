@@ -1,19 +1,20 @@
 """GPU ChebyPower (HIP library through the C ABI) against the FP64 oracle.
 
 Tolerances: FP64 vectors are compared element by element with the oracle's
-Alg. 3 at the same K to 1e-12 (only summation order differs).  FP32 vectors
-carry a relative rounding of 2^-24 per operation; across K <= 40 steps of a
-recurrence whose iterates have l1 norm up to sqrt(vol/d_s) this gives l1
-deviations of order 1e-7 on these graphs, and the tests allow 2e-6.  The
-contract against the exact vector (l1 <= tol, here 1e-6) is checked with
-the certified K.
+Alg. 3 at the same K to 1e-12 (only summation order differs).  FP32 storage
+rounds each stored value to 2^-24 relative while the sums run in double;
+measured l1 deviations are about 6e-8 at 4M nodes and smaller on smaller
+graphs, and the tests allow F32_L1 = 1.2e-7 (float sums, measured 1.7e-7,
+fail it).  BF16 storage measures 1e-3 to 3e-3 and is held to 5e-3.  The
+contract against the exact vector (l1 <= tol) is checked with the certified
+K, plus the rounding bar for FP32.
 """
 
 import numpy as np
 import pytest
 
 import synth
-from gpu_util import compare, gpu_graph, oracle_yK, require_gpu
+from gpu_util import BF16_L1, F32_L1, compare, gpu_graph, oracle_exact_multi, oracle_yK, oracle_yK_multi, require_gpu
 from oracle import errors as E
 from oracle import propagation as PR
 
@@ -91,9 +92,9 @@ def test_powerlaw_tiles_and_long_rows(torch, prec, reorder):
             if prec == "f64":
                 assert m["max_abs"] <= 1e-13, m
             else:
-                assert m["l1"] <= 2e-6, m
+                assert m["l1"] <= F32_L1, m
             exact = PR.ground_truth(P, int(s), kind, param)
-            assert E.l1(y, exact) <= 1e-6 + (0 if prec == "f64" else 2e-6)
+            assert E.l1(y, exact) <= 1e-6 + (0 if prec == "f64" else F32_L1)
 
 
 def test_hub_rows_split_f64(torch):
@@ -208,6 +209,46 @@ def test_validation_rejects_bad_csr(torch):
     assert ei.value.status == cp.CP_EGRAPH
 
 
+def test_decreasing_offsets_rejected_without_validation(torch):
+    """Offsets that decrease (a negative degree) are rejected on every create,
+    validation flag or not, for host and device inputs."""
+    from paper_2412_10789_amd import chebyprop as cp
+
+    rp = np.array([0, 2, 1, 3], np.int64)
+    ci = np.array([1, 2, 0], np.int32)
+    for host in (True, False):
+        with pytest.raises(cp.ChebypropError) as ei:
+            cp.Graph(rp, ci, host_input=host)
+        assert ei.value.status == cp.CP_EINVAL
+
+
+@pytest.mark.parametrize("layout", ["native", "degree", "stripes"])
+def test_host_and_device_inputs_build_the_same_graph(torch, layout):
+    """A graph created from host arrays (CP_GRAPH_HOST) and one created from
+    device arrays give the same layout and bitwise the same results, single
+    source and batched."""
+    from paper_2412_10789_amd import chebyprop as cp
+
+    g = synth.chung_lu(200_000, 2_400_000, 2.1, seed=12)
+    kw = dict(reorder=layout == "degree", stripes=layout == "stripes")
+    Gh = gpu_graph(g, **kw)
+    Gd = gpu_graph(g, host_input=False, **kw)
+    assert Gh.stats == Gd.stats
+    srcs = [int(s) for s in synth.sources(g, 3, seed=9)]
+    for s in srcs:
+        _print_case("host/device input", layout, s)
+        for prec in ("f64", "f32"):
+            a = Gh.power("hkpr", 5.0, s, tol=1e-7, prec=prec).y
+            b = Gd.power("hkpr", 5.0, s, tol=1e-7, prec=prec).y
+            assert torch.equal(a, b), (layout, s, prec)
+    qs = [cp.make_query("ppr", 0.2, s, 1e-6) for s in srcs]
+    Ya, _ = Gh.power_batch(qs, prec="f32")
+    Yb, _ = Gd.power_batch(qs, prec="f32")
+    assert torch.equal(Ya, Yb)
+    Gh.close()
+    Gd.close()
+
+
 def test_bitwise_reproducible_and_timing(torch):
     g = synth.chung_lu(100_000, 900_000, 2.3, seed=2)
     G = gpu_graph(g)
@@ -231,30 +272,38 @@ def test_bf16_storage_error_reported(torch, stripes):
         ref = oracle_yK(g, s, kind, param, r.info["K"], P)
         m = compare(r.y.cpu().numpy(), ref)
         print("bf16 storage error vs FP64 oracle:", kind, stripes, m)
-        assert m["l1"] < 2e-2
+        assert m["l1"] <= BF16_L1, m
 
 
 @pytest.mark.slow
 def test_livejournal_shape_4m_full_size_f32(torch):
-    """Chung-Lu n=4M, ~35M edges, exponent 2.3; HKPR t=5, FP32, l1 <= 1e-6
-    against the FP64 oracle for sampled sources (full vectors)."""
+    """Chung-Lu n=4M, ~35M edges, exponent 2.3; HKPR t=5, FP32, l1 tol 1e-6:
+    on the XCD-striped layout (the one the benchmark times) all 16 of the
+    benchmark's sources, on the other layouts two, each full vector against
+    Alg. 3 in FP64 at its K and against the converged vector."""
     g = synth.chung_lu(4_000_000, 35_000_000, 2.3, seed=2)
-    P = PR.transition_matrix(g.row_ptr, g.col_idx)
-    for layout in ("native", "degree", "stripes"):  # stripes: the layout the benchmark times
+    srcs16 = [int(s) for s in synth.sources(g, 16, seed=2)]
+    for layout in ("stripes", "native", "degree"):
         G = gpu_graph(g, reorder=layout == "degree", stripes=layout == "stripes")
         if layout == "stripes":
             assert G.stats["stripe_packed"] == 1 and G.stats["stripe_count"] == 4
-        for s in synth.sources(g, 2, seed=2):
-            _print_case("4M", layout, int(s))
-            r = G.power("hkpr", 5.0, int(s), tol=1e-6, prec="f32")
-            y = r.y.cpu().numpy()
-            ref = oracle_yK(g, s, "hkpr", 5.0, r.info["K"], P)
-            exact = PR.ground_truth(P, int(s), "hkpr", 5.0, tol=1e-12)
-            m = compare(y, ref)
-            print("4M", layout, int(s), r.info["K"], m, "vs exact", E.l1(y, exact), flush=True)
-            assert m["l1"] <= 2e-6
-            assert E.l1(y, exact) <= 1e-6
+        srcs = srcs16 if layout == "stripes" else srcs16[:2]
+        ys, Ks = [], []
+        for s in srcs:
+            _print_case("4M", layout, s)
+            r = G.power("hkpr", 5.0, s, tol=1e-6, prec="f32")
+            ys.append(r.y.double().cpu().numpy())
+            Ks.append(r.info["K"])
         G.close()
+        metas = [("hkpr", 5.0, s) for s in srcs]
+        ref = oracle_yK_multi(g, metas, Ks)
+        exact = oracle_exact_multi(g, metas)
+        for j, s in enumerate(srcs):
+            m = compare(ys[j], ref[:, j])
+            ex = E.l1(ys[j], exact[:, j])
+            print("4M", layout, s, Ks[j], m, "vs exact", ex, flush=True)
+            assert m["l1"] <= F32_L1, (s, m)
+            assert ex <= 1e-6, (s, ex)
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])

@@ -8,7 +8,7 @@ import numpy as np
 import pytest
 
 import synth
-from gpu_util import compare, gpu_graph, oracle_yK, require_gpu
+from gpu_util import F32_L1, compare, gpu_graph, oracle_yK, require_gpu
 from oracle import coefficients as C
 from oracle import errors as E
 from oracle import propagation as PR
@@ -132,7 +132,15 @@ def test_batch_mixes_algorithms(torch, prec):
         K = infos[j]["K"]
         ref = oracle_pw(g, s, kind, param, K, P) if method == "power" else oracle_yK(g, s, kind, param, K, P)
         m = compare(Y[:, j], ref)
-        assert m["max_abs"] <= 1e-13 if prec == "f64" else m["l1"] <= 2e-6, (j, method, m)
+        if prec == "f64":
+            assert m["max_abs"] <= 1e-13, (j, method, m)
+        elif method == "cheby":
+            assert m["l1"] <= F32_L1, (j, method, m)
+        else:
+            # Alg. 1 with FP32 storage: each stored iterate (l1 norm 1) rounds to
+            # 2^-24 relative, carried by the later weights: <= 2^-24 (1 - alpha) / alpha
+            bound = 2.0**-24 * (1 - param) / param if kind == "ppr" else 2.0**-24 * param
+            assert m["l1"] <= 1.1 * bound, (j, method, m, bound)
         if prec == "f64" and j < 6:
             r = G.power(kind, param, s, tol=1e-7, prec="f64", method=method)
             assert r.info["K"] == K and r.info["steps"] == infos[j]["steps"]
