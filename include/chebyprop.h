@@ -91,6 +91,23 @@ typedef enum { CP_K_CERTIFIED = 0, CP_K_TAIL = 1, CP_K_PAPER = 2, CP_K_FIXED = 3
                                      ids plus S (n+1) int32 offsets, so each
                                      stripe must hold fewer than 2^31 arcs
                                      (CP_EINVAL otherwise) */
+#define CP_GRAPH_HOT_SPLIT 0x20   /* relabel by degree (as CP_GRAPH_REORDER, or the
+                                     stripes of CP_GRAPH_XCD_STRIPES) and keep the
+                                     batched step's arcs in two CSRs: arcs into the
+                                     cp_graph_stats.hot_nodes highest-degree nodes,
+                                     and the rest.  A batched step (cp_power_batch,
+                                     cp_propagate, the server) then sums each row's
+                                     hot arcs first, gathering from a slice of the
+                                     vectors small enough for the caches to keep,
+                                     and the rest second, starting from that sum.
+                                     hot_nodes is sized so that the slice of an
+                                     8-wide FP32 tile (32 bytes a node) is 16 MiB
+                                     (524,288 nodes), or set by the environment variable
+                                     CHEBYPROP_HOT_NODES at create.  Costs a second
+                                     copy of the column ids, two (n+1) int64 offset
+                                     arrays, and an estimate-sized partial buffer in
+                                     every batched workspace.  Results equal the
+                                     unsplit step's up to the order of the sums. */
 
 /* cp_query.flags */
 #define CP_Q_STATS 0x1  /* after the run, synchronize and fill cp_info.mass */
@@ -162,6 +179,14 @@ typedef struct {
   int64_t stripe_count;  /* column stripes S of the XCD-striped layout (0 if not
                             striped): the fewest of 2, 4, 8 whose FP32 slice of
                             the vector, 4 n / S bytes, fits 4 MiB */
+  int64_t hot_nodes;     /* hot nodes of the CP_GRAPH_HOT_SPLIT layout (0 without) */
+  int64_t hot_arcs;      /* arcs into them (the hot pass's share of nnz) */
+  /* row splits of the work plans (set at create, changed by the autotuners):
+   * rows above long_cut arcs are streamed by a whole workgroup instead of
+   * sharing a tile, rows above hub_cut arcs are split into hub_seg-arc
+   * segments over several workgroups */
+  int64_t single_long_cut, single_hub_cut, single_hub_seg;  /* cp_power, single CSR */
+  int64_t batch_long_cut, batch_hub_cut, batch_hub_seg;     /* batched steps */
 } cp_graph_stats;
 
 /* Build a graph from symmetric CSR (Sec. 2.1: undirected, A in {0,1}):
@@ -312,9 +337,29 @@ cp_status cp_push_rw(const cp_graph* g, const cp_query* q, double eps_r, double 
  * these nq queries fastest on this graph and remember it for later
  * cp_power_batch calls with the same nq and precision.  Runs the queries
  * once per candidate width (Y, ws as for cp_power_batch; Y holds the last
- * run's result).  Synchronizes `stream`.  bw_out may be NULL. */
+ * run's result).  Then, at that width and on a graph without
+ * CP_GRAPH_HOT_SPLIT, tunes the batched plan's row splits as
+ * cp_autotune_single does (long-row cuts 64, 128, 256, 512, 1024 arcs and
+ * the same hub shapes) and keeps the fastest for every batched call on the
+ * graph (servers and cp_propagate included).  Workspaces are sized for any
+ * of these plans, so one sized before the call stays valid.  Must not run
+ * while other calls use the graph.  Synchronizes `stream`.  bw_out may be
+ * NULL. */
 cp_status cp_autotune_batch(cp_graph* g, int32_t nq, const cp_query* q, int32_t prec, void* Y, void* ws,
                             size_t ws_bytes, void* stream, int32_t* bw_out);
+
+/* Row-split autotuner of the single-source step on a graph without XCD
+ * stripes (striped graphs run fixed stripe tiles; the call returns CP_OK and
+ * changes nothing): runs the query (y, ws as for cp_power; y holds the last
+ * run's result) with each candidate long-row cut (256, 512, 1024, 2048 arcs)
+ * and hub shape (rows above 16384 / 4096 / 65536 arcs in segments of 8192 /
+ * 2048 / 16384), each against the best so far, and keeps the fastest plan
+ * for every later single-source query on the graph (cp_graph_stats reports
+ * it).  Results change only in the order of the sums of split rows.  Must
+ * not run while other calls use the graph.  Synchronizes `stream`.  Errors
+ * as cp_power, CP_ENOMEM. */
+cp_status cp_autotune_single(cp_graph* g, const cp_query* q, int32_t prec, void* y, void* ws, size_t ws_bytes,
+                             void* stream);
 
 /* Fix the source-tile width used by cp_power_batch for (nq, prec) on this
  * graph (bw in {8, 16, 32, 64}; 0 forgets the choice and returns to the
@@ -345,14 +390,21 @@ typedef struct {
   int32_t prec;
   int32_t waiters;      /* threads blocked in cp_server_wait */
   int32_t pad;
+  int64_t direct;       /* queries run on the single-source path (see below) */
 } cp_server_stats;
 
-/* g: the graph every query runs on; it must outlive the server.
+/* A query that arrives at an idle server (no query resident, none other
+ * waiting) runs on the single-source path (cp_power's kernels on the
+ * server's stream) instead of a batched launch, where it would pay a whole
+ * tile's gathers for one source; queries that arrive meanwhile wait and are
+ * batched.  Results of the two paths differ only in the order of sums.
+ * g: the graph every query runs on; it must outlive the server.
  * hbm_budget_bytes: HBM the server may use for query state (>= one slot).
  * max_slots: upper bound on resident queries (0: as many as the budget
  * allows, at most 1024).  max_queue: waiting-queue capacity.  prec: CP_F32 /
  * CP_F64 / CP_BF16 for all slots.  Errors: CP_EINVAL, CP_ENOMEM (budget below
- * one slot or allocation failure), CP_EHIP. */
+ * one slot or allocation failure), CP_EHIP.  Besides the slots, the server
+ * holds one cp_power workspace in HBM. */
 cp_status cp_server_create(const cp_graph* g, size_t hbm_budget_bytes, int32_t max_slots, int32_t max_queue,
                            int32_t prec, cp_server** out);
 /* Queue a query whose result y (device, n elements: float, or double for

@@ -37,6 +37,7 @@ CP_PPR, CP_HKPR = 0, 1
 CP_F64, CP_F32, CP_BF16 = 0, 1, 2
 CP_K_CERTIFIED, CP_K_TAIL, CP_K_PAPER, CP_K_FIXED = 0, 1, 2, 3
 CP_GRAPH_BORROW, CP_GRAPH_VALIDATE, CP_GRAPH_REORDER, CP_GRAPH_HOST = 0x1, 0x2, 0x4, 0x8
+CP_GRAPH_HOT_SPLIT = 0x20
 CP_GRAPH_XCD_STRIPES = 0x10
 CP_Q_STATS, CP_Q_TIMING, CP_Q_PWMETHOD, CP_Q_CLENSHAW = 0x1, 0x2, 0x4, 0x8
 
@@ -52,7 +53,7 @@ EXPORTED = [
     "cp_graph_create", "cp_graph_destroy", "cp_graph_get_stats", "cp_coeffs", "cp_choose_K",
     "cp_taylor", "cp_choose_N",
     "cp_workspace_bytes", "cp_power", "cp_power_batch", "cp_propagate", "cp_push", "cp_push_workspace_bytes",
-    "cp_push_rw", "cp_push_rw_workspace_bytes", "cp_autotune_batch", "cp_set_batch_width",
+    "cp_push_rw", "cp_push_rw_workspace_bytes", "cp_autotune_batch", "cp_autotune_single", "cp_set_batch_width",
     "cp_status_str", "cp_last_hip_error", "cp_version",
     "cp_server_create", "cp_server_submit", "cp_server_poll", "cp_server_wait", "cp_server_cancel",
     "cp_server_get_stats", "cp_server_destroy",
@@ -107,6 +108,14 @@ class cp_graph_stats(ctypes.Structure):
         ("stripe_tiles", ctypes.c_int64),
         ("stripe_packed", ctypes.c_int64),
         ("stripe_count", ctypes.c_int64),
+        ("hot_nodes", ctypes.c_int64),
+        ("hot_arcs", ctypes.c_int64),
+        ("single_long_cut", ctypes.c_int64),
+        ("single_hub_cut", ctypes.c_int64),
+        ("single_hub_seg", ctypes.c_int64),
+        ("batch_long_cut", ctypes.c_int64),
+        ("batch_hub_cut", ctypes.c_int64),
+        ("batch_hub_seg", ctypes.c_int64),
     ]
 
 
@@ -123,6 +132,7 @@ class cp_server_stats(ctypes.Structure):
         ("prec", ctypes.c_int32),
         ("waiters", ctypes.c_int32),
         ("pad", ctypes.c_int32),
+        ("direct", ctypes.c_int64),
     ]
 
 
@@ -178,6 +188,7 @@ def load() -> ctypes.CDLL:
         "cp_propagate": (i32, [P, ctypes.POINTER(cp_query), i32, i32, P, P, P, sz, P, ctypes.POINTER(cp_info)]),
         "cp_autotune_batch": (i32, [P, i32, ctypes.POINTER(cp_query), i32, P, P, sz, P, ctypes.POINTER(i32)]),
         "cp_set_batch_width": (i32, [P, i32, i32, i32]),
+        "cp_autotune_single": (i32, [P, ctypes.POINTER(cp_query), i32, P, P, sz, P]),
         "cp_server_create": (i32, [P, sz, i32, i32, i32, ctypes.POINTER(P)]),
         "cp_server_submit": (i32, [P, ctypes.POINTER(cp_query), P, ctypes.POINTER(ctypes.c_uint64)]),
         "cp_server_poll": (i32, [P, ctypes.c_uint64, ctypes.POINTER(cp_info)]),
@@ -352,7 +363,7 @@ class Graph:
     """A graph resident in HBM (owned by the library)."""
 
     def __init__(self, row_ptr, col_idx, reorder: bool = False, validate: bool = False, device=None,
-                 stripes: bool = False, host_input: bool | None = None):
+                 stripes: bool = False, host_input: bool | None = None, hot_split: bool = False):
         """row_ptr / col_idx: host arrays (numpy), handed to the library as
         host pointers (CP_GRAPH_HOST), or device tensors (host_input=False
         uploads host arrays first and passes device pointers)."""
@@ -379,7 +390,8 @@ class Graph:
         self.nnz = int(nnz)
         self.device = dev
         flags = ((CP_GRAPH_REORDER if reorder else 0) | (CP_GRAPH_VALIDATE if validate else 0)
-                 | (CP_GRAPH_XCD_STRIPES if stripes else 0) | (CP_GRAPH_HOST if host_input else 0))
+                 | (CP_GRAPH_XCD_STRIPES if stripes else 0) | (CP_GRAPH_HOST if host_input else 0)
+                 | (CP_GRAPH_HOT_SPLIT if hot_split else 0))
         with torch.cuda.device(dev):
             stream = torch.cuda.current_stream().cuda_stream
             self.handle = cp_graph_create(self.n, self.nnz, rp_ptr, ci_ptr, flags, stream)
@@ -423,6 +435,20 @@ class Graph:
         info = cp_power(self.handle, q, p, y.data_ptr(), ws.data_ptr(), nbytes, st)
         return Result(y, info.as_dict())
 
+    def autotune_single(self, kind: str, param: float, source: int, tol: float = 1e-6, prec: str = "f32",
+                        stream=None) -> dict:
+        """cp_autotune_single: time the query under each candidate row split
+        and keep the fastest plan; returns the graph's stats afterwards."""
+        p = PRECS[prec]
+        y = self.torch.empty(self.n, dtype=self.out_dtype(p), device=self.device)
+        ws, nbytes = self.workspace(1, p)
+        st = stream if stream is not None else self.torch.cuda.current_stream(self.device).cuda_stream
+        q = make_query(kind, param, source, tol)
+        _check(load().cp_autotune_single(self.handle, ctypes.byref(q), p, y.data_ptr(), ws.data_ptr(), nbytes, st),
+               "cp_autotune_single")
+        self.stats = cp_graph_get_stats(self.handle)
+        return self.stats
+
     def set_batch_width(self, nq: int, prec: str, bw: int) -> None:
         cp_set_batch_width(self.handle, nq, PRECS[prec], bw)
 
@@ -433,7 +459,9 @@ class Graph:
         Y = torch.empty((self.n, nq), dtype=self.out_dtype(p), device=self.device)
         ws, nbytes = self.workspace(nq, p)
         st = stream if stream is not None else torch.cuda.current_stream(self.device).cuda_stream
-        return cp_autotune_batch(self.handle, queries, p, Y.data_ptr(), ws.data_ptr(), nbytes, st)
+        bw = cp_autotune_batch(self.handle, queries, p, Y.data_ptr(), ws.data_ptr(), nbytes, st)
+        self.stats = cp_graph_get_stats(self.handle)
+        return bw
 
     def power_batch(self, queries, prec: str = "f32", Y=None, stream=None):
         torch = self.torch

@@ -256,12 +256,83 @@ bool build_stripes(const int64_t* rp, const int32_t* ci, int64_t n, int32_t S, S
   return true;
 }
 
-Plan build_plan(const int64_t* rp, int64_t n, int64_t long_threshold) {
+// Host image of the hot/cold split of the batched step (CP_GRAPH_HOT_SPLIT).
+struct SplitHost {
+  int64_t hot_nodes = 0;
+  std::vector<int64_t> hrp, crp;   // [n+1] row offsets of the hot and cold CSRs
+  std::vector<int32_t> hci, cci;   // their columns, each row in the graph's order
+  Plan hot, cold;
+};
+
+// Hot nodes: CHEBYPROP_HOT_NODES if set, else a 16 MiB slice of 8-wide FP32
+// rows (32 bytes a node, 524,288 nodes); at most n.
+int64_t hot_nodes_for(int64_t n) {
+  int64_t h = (int64_t(16) << 20) / 32;
+  if (const char* env = std::getenv("CHEBYPROP_HOT_NODES")) {
+    const long long v = std::atoll(env);
+    if (v >= 0) h = v;
+  }
+  return std::min<int64_t>(h, n);
+}
+
+// Split each row of the (relabelled) CSR into its arcs into the H
+// highest-degree nodes and the rest, keeping their order.  In degree order
+// the hot nodes are ids [0, H); with S stripes (degree rank r at stripe
+// r % S, position r / S) they are the first ceil((H - j) / S) ids of each
+// stripe j.
+void build_split(const int64_t* rp, const int32_t* ci, int64_t n, int32_t S, int64_t H, SplitHost& sp) {
+  sp.hot_nodes = H;
+  std::vector<uint8_t> hot((size_t)n, 0);
+  if (S == 0) {
+    std::fill(hot.begin(), hot.begin() + H, 1);
+  } else {
+    int64_t start = 0;
+    for (int j = 0; j < S; ++j) {
+      const int64_t size = (n - j + S - 1) / S;
+      const int64_t nh = H > j ? (H - j + S - 1) / S : 0;
+      std::fill(hot.begin() + start, hot.begin() + start + std::min(nh, size), 1);
+      start += size;
+    }
+  }
+  std::vector<int32_t> cnt((size_t)n);
+  parallel_rows_balanced(rp, n, [&](int64_t b, int64_t e) {
+    for (int64_t v = b; v < e; ++v) {
+      int32_t c = 0;
+      for (int64_t q = rp[v]; q < rp[v + 1]; ++q) c += hot[(size_t)ci[q]];
+      cnt[(size_t)v] = c;
+    }
+  });
+  sp.hrp.assign((size_t)n + 1, 0);
+  sp.crp.assign((size_t)n + 1, 0);
+  for (int64_t v = 0; v < n; ++v) {
+    sp.hrp[(size_t)v + 1] = sp.hrp[(size_t)v] + cnt[(size_t)v];
+    sp.crp[(size_t)v + 1] = sp.crp[(size_t)v] + (rp[v + 1] - rp[v] - cnt[(size_t)v]);
+  }
+  sp.hci.resize((size_t)sp.hrp[(size_t)n]);
+  sp.cci.resize((size_t)sp.crp[(size_t)n]);
+  parallel_rows_balanced(rp, n, [&](int64_t b, int64_t e) {
+    for (int64_t v = b; v < e; ++v) {
+      int32_t* h = sp.hci.data() + sp.hrp[(size_t)v];
+      int32_t* c = sp.cci.data() + sp.crp[(size_t)v];
+      for (int64_t q = rp[v]; q < rp[v + 1]; ++q) {
+        const int32_t u = ci[q];
+        if (hot[(size_t)u]) *h++ = u;
+        else *c++ = u;
+      }
+    }
+  });
+  sp.hot = build_plan(sp.hrp.data(), n, PlanShape{kBatchLong});
+  sp.cold = build_plan(sp.crp.data(), n, PlanShape{kBatchLong});
+}
+
+Plan build_plan(const int64_t* rp, int64_t n, const PlanShape& shape) {
   Plan p;
+  p.shape = shape;
+  const int64_t long_threshold = shape.long_cut;
   std::vector<int32_t> hubs, longs;
   for (int64_t v = 0; v < n; ++v) {
     const int64_t d = rp[v + 1] - rp[v];
-    if (d > kHubThreshold) hubs.push_back((int32_t)v);
+    if (d > shape.hub_cut) hubs.push_back((int32_t)v);
     else if (d > long_threshold) longs.push_back((int32_t)v);
   }
   auto by_degree = [&](int32_t a, int32_t b) {
@@ -273,8 +344,8 @@ Plan build_plan(const int64_t* rp, int64_t n, int64_t long_threshold) {
   int32_t base = 0;
   for (size_t h = 0; h < hubs.size(); ++h) {
     const int64_t d = rp[hubs[h] + 1] - rp[hubs[h]];
-    const int32_t nseg = (int32_t)((d + kHubSeg - 1) / kHubSeg);
-    p.hubs.push_back(HubDesc{hubs[h], nseg, base, 0});
+    const int32_t nseg = (int32_t)((d + shape.hub_seg - 1) / shape.hub_seg);
+    p.hubs.push_back(HubDesc{hubs[h], nseg, base, (int32_t)shape.hub_seg});
     for (int32_t s = 0; s < nseg; ++s) p.blocks.push_back(BlockDesc{hubs[h], (int32_t)h, kHub, s, 0, 0});
     base += nseg;
   }
@@ -300,6 +371,45 @@ Plan build_plan(const int64_t* rp, int64_t n, int64_t long_threshold) {
   return p;
 }
 
+int64_t batch_hub_rows(const cp_graph* g) { return g->hub_rows_cap; }
+
+int64_t batch_hub_segments(const cp_graph* g) { return g->hub_segs_cap; }
+
+// Row-split shapes of hubs the autotuners try (the first is the default).
+const PlanShape kHubShapes[3] = {{0, kHubThreshold, kHubSeg}, {0, 4096, 2048}, {0, 65536, 16384}};
+
+// The most hub rows and segments any of those shapes makes of these rows (a
+// split CSR's rows are no longer than the graph's, so this bounds them too).
+void hub_caps(const int64_t* rp, int64_t n, int64_t* rows_cap, int64_t* segs_cap) {
+  int64_t rc = 1, sc = 1;
+  for (const PlanShape& sh : kHubShapes) {
+    int64_t r = 0, sg = 0;
+    for (int64_t v = 0; v < n; ++v) {
+      const int64_t d = rp[v + 1] - rp[v];
+      if (d > sh.hub_cut) {
+        ++r;
+        sg += (d + sh.hub_seg - 1) / sh.hub_seg;
+      }
+    }
+    rc = std::max(rc, r);
+    sc = std::max(sc, sg);
+  }
+  *rows_cap = rc;
+  *segs_cap = sc;
+}
+
+void set_batch_plan(const cp_graph* g, BatchStepArgs& a, void* part) {
+  a.row_ptr = g->row_ptr;
+  a.col_idx = g->col_idx;
+  a.blocks = g->batch.blocks;
+  a.hubs = g->batch.hubs;
+  a.nblocks = g->batch.nblocks;
+  a.nspecial = g->batch.nspecial;
+  a.split = g->hot_split ? &g->split : nullptr;
+  a.deg_rp = nullptr;
+  a.part = g->hot_split ? part : nullptr;
+}
+
 namespace {
 
 struct WsLayout {
@@ -314,8 +424,8 @@ WsLayout ws_layout(const cp_graph* g, int32_t nq, int32_t prec) {
   L.rA = off; off += vec;
   L.rB = off; off += vec;
   L.yacc = off; off += yv;
-  L.hub_count = off; off += align256((size_t)std::max<int64_t>(g->single.nhubs, 1) * 4);
-  L.hub_partial = off; off += align256((size_t)std::max<int64_t>(g->single.hub_segments, 1) * 8 * nq);
+  L.hub_count = off; off += align256((size_t)batch_hub_rows(g) * 4);
+  L.hub_partial = off; off += align256((size_t)batch_hub_segments(g) * 8 * nq);
   L.mass = off; off += align256((1 + 1024) * 8);
   L.partial = off;
   if (g->striped) off += align256((size_t)g->s_count * (size_t)g->n * acc_bytes(prec));
@@ -324,6 +434,8 @@ WsLayout ws_layout(const cp_graph* g, int32_t nq, int32_t prec) {
 }
 
 }  // namespace
+
+size_t single_ws_bytes(const cp_graph* g, int32_t prec) { return ws_layout(g, 1, prec).total; }
 
 cp_status plan_query(const cp_graph* g, const cp_query* q, int32_t K_max, QueryPlan* p) {
   if (!q || !p) return CP_EINVAL;
@@ -370,7 +482,7 @@ namespace {
 struct BatchLayout {
   int32_t bw = 0, nq_pad = 0, ntiles = 0;
   size_t rA = 0, rB = 0, yacc = 0, hub_count = 0, hub_partial = 0, coef = 0, src = 0, rec = 0, slotmap = 0,
-         total = 0;
+         part = 0, total = 0;
 };
 
 int32_t round_up(int32_t a, int32_t b) { return (a + b - 1) / b * b; }
@@ -386,12 +498,14 @@ BatchLayout batch_layout(const cp_graph* g, int32_t nq, int32_t prec, int32_t bw
   L.rA = off; off += vec;
   L.rB = off; off += vec;
   L.yacc = off; off += yv;
-  L.hub_count = off; off += align256((size_t)std::max<int64_t>(g->batch.nhubs, 1) * L.ntiles * 4);
-  L.hub_partial = off; off += align256((size_t)std::max<int64_t>(g->batch.hub_segments, 1) * L.nq_pad * 8);
+  L.hub_count = off; off += align256((size_t)batch_hub_rows(g) * L.ntiles * 4);
+  L.hub_partial = off; off += align256((size_t)batch_hub_segments(g) * L.nq_pad * 8);
   L.coef = off; off += align256((size_t)(kBatchKCap + 1) * L.nq_pad * 8);
   L.src = off; off += align256((size_t)L.nq_pad * 8);
   L.rec = off; off += align256((size_t)kSlotParams * L.nq_pad * 8);
   L.slotmap = off; off += align256((size_t)nq * 4);
+  L.part = off;
+  if (g->hot_split) off += yv;  // partial row sums of the hot pass
   L.total = off;
   return L;
 }
@@ -435,7 +549,8 @@ namespace {
 hipError_t release_graph(cp_graph* g) {
   if (!g) return hipSuccess;
   hipError_t e = hipSuccess;
-  for (void* p : {g->owned_csr, g->plan_mem, static_cast<void*>(g->s_rp)}) {
+  for (void* p : {g->owned_csr, g->plan_mem, static_cast<void*>(g->s_rp), g->split_mem, g->tuned_plan_mem[0],
+                  g->tuned_plan_mem[1]}) {
     if (!p) continue;
     const hipError_t x = hipFree(p);
     if (e == hipSuccess) e = x;
@@ -505,7 +620,8 @@ cp_status cp_graph_create(int64_t n, int64_t nnz, const int64_t* row_ptr, const 
   const bool host_in = flags & CP_GRAPH_HOST;
   const bool striped = flags & CP_GRAPH_XCD_STRIPES;
   const int32_t S = stripe_count(n);  // stripes, if striped
-  const bool reorder = (flags & CP_GRAPH_REORDER) || striped;
+  const bool hot_split = flags & CP_GRAPH_HOT_SPLIT;
+  const bool reorder = (flags & CP_GRAPH_REORDER) || striped || hot_split;
   const bool borrow = (flags & CP_GRAPH_BORROW) && !host_in && !reorder;
   cp_graph* g = nullptr;
 #define CP_HIP_G(call)      \
@@ -600,7 +716,8 @@ cp_status cp_graph_create(int64_t n, int64_t nnz, const int64_t* row_ptr, const 
       g->reordered = true;
       clock.mark("relabel");
     }
-    const Plan plans[2] = {build_plan(rp.data(), n, kTileNnz), build_plan(rp.data(), n, kBatchLong)};
+    const Plan plans[2] = {build_plan(rp.data(), n, PlanShape{kTileNnz}), build_plan(rp.data(), n, PlanShape{kBatchLong})};
+    hub_caps(rp.data(), n, &g->hub_rows_cap, &g->hub_segs_cap);
     clock.mark("plans");
     StripeLayout sl;
     if (striped && !build_stripes(rp.data(), hci, n, S, sl)) {
@@ -608,6 +725,11 @@ cp_status cp_graph_create(int64_t n, int64_t nnz, const int64_t* row_ptr, const 
       return CP_EINVAL;
     }
     if (striped) clock.mark("stripes");
+    SplitHost sp;
+    if (hot_split) {
+      build_split(rp.data(), hci, n, striped ? S : 0, hot_nodes_for(n), sp);
+      clock.mark("hot split");
+    }
 
     // device copies: [row_ptr | col_idx | perm] in one allocation, plans in another
     const size_t b_rp = borrow ? 0 : align256(sizeof(int64_t) * (n + 1));
@@ -667,7 +789,63 @@ cp_status cp_graph_create(int64_t n, int64_t nnz, const int64_t* row_ptr, const 
         CP_HIP_G(hipMemcpyAsync(g->s_blocks, sl.blocks.data(), sizeof(StripeBlock) * sl.blocks.size(),
                               hipMemcpyHostToDevice, st));
     }
-    g->device_bytes = (int64_t)(total + b_plans + b_stripes);
+    size_t b_split = 0;
+    if (hot_split) {
+      const size_t b_rps = align256(sizeof(int64_t) * (n + 1));
+      const size_t b_hci = align256(sizeof(int32_t) * std::max<size_t>(sp.hci.size(), 1));
+      const size_t b_cci = align256(sizeof(int32_t) * std::max<size_t>(sp.cci.size(), 1));
+      size_t b_pl = 0;
+      for (const Plan* pl : {&sp.hot, &sp.cold})
+        b_pl += align256(sizeof(BlockDesc) * std::max<size_t>(pl->blocks.size(), 1)) +
+                align256(sizeof(HubDesc) * std::max<size_t>(pl->hubs.size(), 1));
+      b_split = 2 * b_rps + b_hci + b_cci + b_pl;
+      char* m = nullptr;
+      hipError_t e = hipMalloc(&m, b_split);
+      if (e != hipSuccess) {
+        (void)release_graph(g);
+        return e == hipErrorOutOfMemory ? CP_ENOMEM : (set_hip_error(e), CP_EHIP);
+      }
+      g->split_mem = m;
+      g->hot_split = true;
+      g->split.hot_nodes = sp.hot_nodes;
+      g->hot_arcs = (int64_t)sp.hci.size();
+      int64_t* drh = reinterpret_cast<int64_t*>(m); m += b_rps;
+      int64_t* drc = reinterpret_cast<int64_t*>(m); m += b_rps;
+      int32_t* dch = reinterpret_cast<int32_t*>(m); m += b_hci;
+      int32_t* dcc = reinterpret_cast<int32_t*>(m); m += b_cci;
+      CP_HIP_G(hipMemcpyAsync(drh, sp.hrp.data(), sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice, st));
+      CP_HIP_G(hipMemcpyAsync(drc, sp.crp.data(), sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice, st));
+      if (!sp.hci.empty())
+        CP_HIP_G(hipMemcpyAsync(dch, sp.hci.data(), sizeof(int32_t) * sp.hci.size(), hipMemcpyHostToDevice, st));
+      if (!sp.cci.empty())
+        CP_HIP_G(hipMemcpyAsync(dcc, sp.cci.data(), sizeof(int32_t) * sp.cci.size(), hipMemcpyHostToDevice, st));
+      DevPlan* dps[2] = {&g->hot_plan, &g->cold_plan};
+      const Plan* pls[2] = {&sp.hot, &sp.cold};
+      for (int i = 0; i < 2; ++i) {
+        DevPlan& dp = *dps[i];
+        const Plan& pl = *pls[i];
+        dp.nblocks = (int64_t)pl.blocks.size();
+        dp.nspecial = pl.nspecial;
+        dp.nlong = pl.nlong;
+        dp.nhubs = (int64_t)pl.hubs.size();
+        dp.hub_segments = pl.hub_segments;
+        dp.shape = pl.shape;
+        dp.blocks = reinterpret_cast<BlockDesc*>(m);
+        m += align256(sizeof(BlockDesc) * std::max<size_t>(pl.blocks.size(), 1));
+        dp.hubs = reinterpret_cast<HubDesc*>(m);
+        m += align256(sizeof(HubDesc) * std::max<size_t>(pl.hubs.size(), 1));
+        if (dp.nblocks)
+          CP_HIP_G(hipMemcpyAsync(dp.blocks, pl.blocks.data(), sizeof(BlockDesc) * dp.nblocks,
+                                  hipMemcpyHostToDevice, st));
+        if (dp.nhubs)
+          CP_HIP_G(hipMemcpyAsync(dp.hubs, pl.hubs.data(), sizeof(HubDesc) * dp.nhubs, hipMemcpyHostToDevice, st));
+      }
+      g->split.hot = BatchPass{drh, dch, g->hot_plan.blocks, g->hot_plan.hubs, g->hot_plan.nblocks,
+                               g->hot_plan.nspecial};
+      g->split.cold = BatchPass{drc, dcc, g->cold_plan.blocks, g->cold_plan.hubs, g->cold_plan.nblocks,
+                                g->cold_plan.nspecial};
+    }
+    g->device_bytes = (int64_t)(total + b_plans + b_stripes + b_split);
     char* p = base;
     if (borrow) {
       g->row_ptr = row_ptr;
@@ -700,6 +878,7 @@ cp_status cp_graph_create(int64_t n, int64_t nnz, const int64_t* row_ptr, const 
       dp.nlong = pl.nlong;
       dp.nhubs = (int64_t)pl.hubs.size();
       dp.hub_segments = pl.hub_segments;
+      dp.shape = pl.shape;
       dp.blocks = reinterpret_cast<BlockDesc*>(q);
       q += align256(sizeof(BlockDesc) * std::max<size_t>(pl.blocks.size(), 1));
       dp.hubs = reinterpret_cast<HubDesc*>(q);
@@ -713,6 +892,7 @@ cp_status cp_graph_create(int64_t n, int64_t nnz, const int64_t* row_ptr, const 
     }
     CP_HIP_G(hipStreamSynchronize(st));
     clock.mark("upload");
+    g->host_rp.swap(rp);
     *out = g;
     return CP_OK;
   } catch (const std::bad_alloc&) {
@@ -743,6 +923,14 @@ cp_status cp_graph_get_stats(const cp_graph* g, cp_graph_stats* out) {
   out->stripe_tiles = g->s_ntiles;
   out->stripe_packed = g->s_packed ? 1 : 0;
   out->stripe_count = g->striped ? g->s_count : 0;
+  out->hot_nodes = g->hot_split ? g->split.hot_nodes : 0;
+  out->single_long_cut = g->single.shape.long_cut;
+  out->single_hub_cut = g->single.shape.hub_cut;
+  out->single_hub_seg = g->single.shape.hub_seg;
+  out->batch_long_cut = g->batch.shape.long_cut;
+  out->batch_hub_cut = g->batch.shape.hub_cut;
+  out->batch_hub_seg = g->batch.shape.hub_seg;
+  out->hot_arcs = g->hot_split ? g->hot_arcs : 0;
   return CP_OK;
 }
 
@@ -893,6 +1081,87 @@ cp_status power_impl(const cp_graph* g, const cp_query* q, int32_t prec, void* y
 namespace cp {
 namespace {
 
+// Build the plan of `shape` from the graph's host row offsets and make it
+// the graph's plan `which` (0 single-source, 1 batched), freeing the plan a
+// previous call installed there.  Synchronizes st.
+cp_status install_plan(cp_graph* g, int which, const PlanShape& shape, hipStream_t st) {
+  const Plan pl = build_plan(g->host_rp.data(), g->n, shape);
+  const size_t b_blocks = align256(sizeof(BlockDesc) * std::max<size_t>(pl.blocks.size(), 1));
+  const size_t b_hubs = align256(sizeof(HubDesc) * std::max<size_t>(pl.hubs.size(), 1));
+  char* m = nullptr;
+  hipError_t e = hipMalloc(&m, b_blocks + b_hubs);
+  if (e != hipSuccess) {
+    set_hip_error(e);
+    return e == hipErrorOutOfMemory ? CP_ENOMEM : CP_EHIP;
+  }
+  DevPlan dp;
+  dp.nblocks = (int64_t)pl.blocks.size();
+  dp.nspecial = pl.nspecial;
+  dp.nlong = pl.nlong;
+  dp.nhubs = (int64_t)pl.hubs.size();
+  dp.hub_segments = pl.hub_segments;
+  dp.shape = pl.shape;
+  dp.blocks = reinterpret_cast<BlockDesc*>(m);
+  dp.hubs = reinterpret_cast<HubDesc*>(m + b_blocks);
+  if (dp.nblocks) e = hipMemcpyAsync(dp.blocks, pl.blocks.data(), sizeof(BlockDesc) * dp.nblocks,
+                                     hipMemcpyHostToDevice, st);
+  if (e == hipSuccess && dp.nhubs)
+    e = hipMemcpyAsync(dp.hubs, pl.hubs.data(), sizeof(HubDesc) * dp.nhubs, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) {
+    set_hip_error(e);
+    (void)hipFree(m);
+    return CP_EHIP;
+  }
+  if (g->tuned_plan_mem[which]) (void)hipFree(g->tuned_plan_mem[which]);
+  g->tuned_plan_mem[which] = m;
+  (which == 0 ? g->single : g->batch) = dp;
+  return CP_OK;
+}
+
+// Row-split shapes the autotuners try, each against the best so far: long
+// cuts first, then hub cut and segment size.
+const int64_t kLongCuts[2][5] = {{256, 512, 1024, 2048, 0}, {64, 128, 256, 512, 1024}};
+
+// Time `run` (which reports its device time in ms) for each candidate shape of
+// plan `which`, install the fastest, and return it.
+template <typename Run>
+cp_status tune_shape(cp_graph* g, int which, hipStream_t st, Run&& run, PlanShape* best_out) {
+  PlanShape best = (which == 0 ? g->single : g->batch).shape;
+  double best_ms = 1e300;
+  auto trial = [&](const PlanShape& sh) -> cp_status {
+    cp_status rc = install_plan(g, which, sh, st);
+    if (rc != CP_OK) return rc;
+    double ms = 0;
+    for (int rep = 0; rep < 2; ++rep) {  // the first run warms caches
+      rc = run(&ms);
+      if (rc != CP_OK) return rc;
+    }
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = sh;
+    }
+    return CP_OK;
+  };
+  for (int64_t cut : kLongCuts[which]) {
+    if (cut <= 0) continue;
+    PlanShape sh = best;
+    sh.long_cut = cut;
+    cp_status rc = trial(sh);
+    if (rc != CP_OK) return rc;
+  }
+  for (const PlanShape& hs : kHubShapes) {
+    PlanShape sh = best;
+    sh.hub_cut = hs.hub_cut;
+    sh.hub_seg = hs.hub_seg;
+    cp_status rc = trial(sh);
+    if (rc != CP_OK) return rc;
+  }
+  cp_status rc = install_plan(g, which, best, st);
+  if (rc == CP_OK && best_out) *best_out = best;
+  return rc;
+}
+
 cp_status power_batch_bw(cp_graph* g, int32_t nq, const cp_query* q, int32_t prec, void* Y, void* ws,
                          size_t ws_bytes, hipStream_t st, cp_info* infos, int32_t bw) {
   std::vector<QueryPlan> P(nq);
@@ -954,12 +1223,7 @@ cp_status power_batch_bw(cp_graph* g, int32_t nq, const cp_query* q, int32_t pre
                    W.nq_pad, rA, rB, w + W.yacc, dcoef};
   CP_HIP_B(launch_batch_init(prec, ia, nq, st));
   BatchStepArgs sa{};
-  sa.row_ptr = g->row_ptr;
-  sa.col_idx = g->col_idx;
-  sa.blocks = g->batch.blocks;
-  sa.hubs = g->batch.hubs;
-  sa.nblocks = g->batch.nblocks;
-  sa.nspecial = g->batch.nspecial;
+  set_batch_plan(g, sa, w + W.part);
   sa.n = g->n;
   sa.bw = bw;
   sa.nq_pad = W.nq_pad;
@@ -1104,12 +1368,7 @@ cp_status cp_propagate(const cp_graph* g, const cp_query* q, int32_t k, int32_t 
                    w + W.yacc};
   CP_HIP_P(launch_dense_init(prec, ia, st));
   BatchStepArgs sa{};
-  sa.row_ptr = g->row_ptr;
-  sa.col_idx = g->col_idx;
-  sa.blocks = g->batch.blocks;
-  sa.hubs = g->batch.hubs;
-  sa.nblocks = g->batch.nblocks;
-  sa.nspecial = g->batch.nspecial;
+  set_batch_plan(g, sa, w + W.part);
   sa.n = g->n;
   sa.bw = bw;
   sa.nq_pad = W.nq_pad;
@@ -1221,8 +1480,34 @@ cp_status cp_autotune_batch(cp_graph* g, int32_t nq, const cp_query* q, int32_t 
     std::lock_guard<std::mutex> lk(g->tune_mu);
     g->tuned_bw[tune_key(nq, prec)] = best;
   }
+  // the batched plan's row splits at that width (the hot/cold split keeps its own plans)
+  if (!g->hot_split) {
+    auto run = [&](double* ms) {
+      cp_status rc = power_batch_bw(g, nq, qq.data(), prec, Y, ws, ws_bytes, st, infos.data(), best);
+      *ms = infos[0].step_ms;
+      return rc;
+    };
+    cp_status rc = tune_shape(g, 1, st, run, nullptr);
+    if (rc != CP_OK) return rc;
+  }
   if (bw_out) *bw_out = best;
   return CP_OK;
+}
+
+cp_status cp_autotune_single(cp_graph* g, const cp_query* q, int32_t prec, void* y, void* ws, size_t ws_bytes,
+                             void* stream) {
+  if (!g || !q || !y || !valid_prec(prec)) return CP_EINVAL;
+  if (g->striped) return CP_OK;  // striped steps run fixed stripe tiles, not the plan
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  cp_query qq = *q;
+  qq.flags = (q->flags & CP_Q_PWMETHOD) | CP_Q_TIMING;
+  auto run = [&](double* ms) {
+    cp_info info{};
+    cp_status rc = cp_power(g, &qq, prec, y, ws, ws_bytes, stream, &info);
+    *ms = info.step_ms;
+    return rc;
+  };
+  return tune_shape(g, 0, st, run, nullptr);
 }
 
 }  // extern "C"

@@ -50,7 +50,16 @@ struct HubDesc {
   int32_t row;
   int32_t nseg;
   int32_t base;  // index of segment 0 in the partial-sum array
-  int32_t pad;
+  int32_t seg;   // arcs per segment (the last one may hold fewer)
+};
+
+// Row-split parameters of a work plan: rows above long_cut arcs leave the
+// stream tiles (at most kTileNnz: a stream tile's arcs sit in LDS), rows
+// above hub_cut arcs are split into segments of hub_seg arcs.
+struct PlanShape {
+  int64_t long_cut;
+  int64_t hub_cut = kHubThreshold;
+  int64_t hub_seg = kHubSeg;
 };
 
 struct Plan {
@@ -59,17 +68,19 @@ struct Plan {
   int64_t nspecial = 0;  // hub + long blocks at the front
   int64_t nlong = 0;
   int64_t hub_segments = 0;
+  PlanShape shape{kTileNnz};
 };
 
-// long_threshold: rows with more arcs than this leave the stream tiles
-// (kTileNnz for the single-source kernel, kBatchLong for the batched one).
-Plan build_plan(const int64_t* row_ptr, int64_t n, int64_t long_threshold);
+// The default long_cut is kTileNnz for the single-source kernel and
+// kBatchLong for the batched one; the autotuner tries others.
+Plan build_plan(const int64_t* row_ptr, int64_t n, const PlanShape& shape);
 
 // Plan as uploaded to the device.
 struct DevPlan {
   BlockDesc* blocks = nullptr;
   HubDesc* hubs = nullptr;
   int64_t nblocks = 0, nspecial = 0, nlong = 0, nhubs = 0, hub_segments = 0;
+  PlanShape shape{kTileNnz};
 };
 
 // ------------------------------------------------------------ XCD stripes
@@ -219,6 +230,29 @@ hipError_t launch_finalize(int32_t prec, const FinalArgs& a, hipStream_t st);
 // (accumulator type).  coef is a [(Kmax+1)][nq_pad] table of c_k per slot
 // (zero once k exceeds the slot's own K).
 
+// One pass of the batched step over a CSR: its row offsets, columns and
+// work plan.
+struct BatchPass {
+  const int64_t* row_ptr;
+  const int32_t* col_idx;
+  const BlockDesc* blocks;
+  const HubDesc* hubs;
+  int64_t nblocks;
+  int64_t nspecial;
+};
+
+// Hot/cold split of the batched step (CP_GRAPH_HOT_SPLIT, degree-ordered
+// graphs): `hot` holds the arcs whose column is one of the hot_nodes
+// highest-degree nodes (ids below hot_nodes), `cold` the others, each row's
+// arcs in the same (column) order as in the graph.  A step runs the hot
+// pass, which gathers only from the first hot_nodes rows of x, a slice the
+// caches can keep, and stores each row's sum in a partial; then the cold
+// pass, which adds its gathers to that partial and applies the row update.
+struct BatchSplit {
+  BatchPass hot, cold;
+  int64_t hot_nodes;
+};
+
 struct BatchStepArgs {
   const int64_t* row_ptr;
   const int32_t* col_idx;
@@ -226,6 +260,9 @@ struct BatchStepArgs {
   const HubDesc* hubs;
   int64_t nblocks;
   int64_t nspecial;
+  const BatchSplit* split;  // host pointer: non-null runs the hot and cold passes (launch_batch_step)
+  const int64_t* deg_rp;    // row offsets the degree d_v comes from (null: row_ptr)
+  void* part;               // A[ntiles][n][bw] partial sums of the hot pass (split only)
   int64_t n;
   int32_t bw;
   int32_t ntiles;        // active tiles in this launch (grid.y)
@@ -246,8 +283,19 @@ struct BatchStepArgs {
 // with yacc holding the start vector x~: a step writes b_k = c x~ + u acc / d
 // - b_{k+2} over z (u = 2); the last one writes c_0 x~ + acc / d - b_2 over
 // yacc (u = 1).
-enum BatchMode : int32_t { kBatchForward = 0, kClenshawStep = 1, kClenshawLast = 2 };
+// kBatchHot: the hot pass of a split step, writing each row's sum to part.
+enum BatchMode : int32_t { kBatchForward = 0, kClenshawStep = 1, kClenshawLast = 2, kBatchHot = 3 };
 hipError_t launch_batch_step(int32_t prec, const BatchStepArgs& a, hipStream_t st);
+
+// Hub scratch a step needs on graph g (single-source or batched, every
+// pass, every plan shape the autotuners may install): rows split into
+// segments and their segments.
+int64_t batch_hub_rows(const cp_graph* g);
+int64_t batch_hub_segments(const cp_graph* g);
+extern const PlanShape kHubShapes[3];
+// The graph's CSR and work plan for the batched step (and its hot/cold
+// split, if any) into a; `part` is the split's partial buffer (workspace).
+void set_batch_plan(const cp_graph* g, BatchStepArgs& a, void* part);
 
 struct BatchInitArgs {
   const int64_t* row_ptr;
@@ -349,6 +397,8 @@ struct QueryPlan {
   std::vector<double> c;
 };
 cp_status plan_query(const cp_graph* g, const cp_query* q, int32_t K_max, QueryPlan* p);
+// Workspace of one cp_power query on g at precision prec.
+size_t single_ws_bytes(const cp_graph* g, int32_t prec);
 cp_status taylor_impl(int32_t kind, double param, int32_t N, double* zeta);
 cp_status choose_N_impl(int32_t kind, double param, double tol, int32_t kmode, int32_t N_fixed,
                         int32_t N_max, int32_t* N_out, double* tail_out);
@@ -379,10 +429,24 @@ struct cp_graph {
   int64_t s_ntiles = 0, s_nlong = 0;
   cp::DevPlan single;  // plan of the single-source step kernel
   cp::DevPlan batch;   // plan of the batched step kernel
+  // hot/cold split of the batched step (CP_GRAPH_HOT_SPLIT)
+  bool hot_split = false;
+  cp::BatchSplit split{};
+  cp::DevPlan hot_plan, cold_plan;
+  void* split_mem = nullptr;          // allocation holding both split CSRs and their plans
+  int64_t hot_arcs = 0;
   void* plan_mem = nullptr;
   int64_t device_bytes = 0;
   bool reordered = false, borrowed = false;
   // batched source-tile width chosen by cp_autotune_batch, keyed by (nq, prec)
   std::map<int64_t, int32_t> tuned_bw;
   std::mutex tune_mu;
+  // row offsets in internal order (host), from which the autotuners rebuild
+  // plans, and the device memory of plans they installed
+  std::vector<int64_t> host_rp;
+  void* tuned_plan_mem[2] = {nullptr, nullptr};  // single, batch
+  // hub rows and segments of the plan shape with the most of them, over
+  // every shape the autotuners may install: workspaces are sized by these,
+  // so a plan installed later never outgrows a workspace sized earlier
+  int64_t hub_rows_cap = 1, hub_segs_cap = 1;
 };

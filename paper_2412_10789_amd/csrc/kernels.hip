@@ -283,8 +283,8 @@ __global__ void __launch_bounds__(kThreads) step_kernel(StepArgs a) {
   // Hub segment.
   const HubDesc h = a.hubs[bd.r1];
   const int64_t rb = rp[h.row], re = rp[h.row + 1];
-  const int64_t p0 = rb + (int64_t)bd.aux * kHubSeg;
-  const int64_t p1 = p0 + kHubSeg < re ? p0 + kHubSeg : re;
+  const int64_t p0 = rb + (int64_t)bd.aux * h.seg;
+  const int64_t p1 = p0 + h.seg < re ? p0 + h.seg : re;
   const A total = block_gather_sum<T, A>(col, x, p0, p1, wsum);
   if (tid == 0) {
     A* part = static_cast<A*>(a.hub_partial);

@@ -106,6 +106,7 @@ __global__ void __launch_bounds__(kThreads) batch_step_kernel(BatchStepArgs a) {
   constexpr int G = kThreads / BW;
   __shared__ int32_t cols[kTileNnz];
   __shared__ int32_t rpl[kTileRows + 1];
+  __shared__ int32_t dgl[kTileRows];
   __shared__ A part[G][BW];
   __shared__ int32_t last_flag;
 
@@ -115,12 +116,28 @@ __global__ void __launch_bounds__(kThreads) batch_step_kernel(BatchStepArgs a) {
   const T* __restrict__ x = static_cast<const T*>(a.x) + toff;
   T* __restrict__ z = static_cast<T*>(a.z) + toff;
   A* __restrict__ y = static_cast<A*>(a.yacc) + toff;
+  // split step: the hot pass writes its row sums here, the cold pass starts from them
+  A* __restrict__ hp_row = a.part ? static_cast<A*>(a.part) + toff : nullptr;
+  const bool hot = a.mode == kBatchHot;
   const A c = (A)a.coef_row[tile * BW + lane];
   const A u = (A)a.rec[tile * BW + lane];
   const int64_t* __restrict__ rp = a.row_ptr;
+  const int64_t* __restrict__ drp = a.deg_rp ? a.deg_rp : a.row_ptr;
   const int32_t* __restrict__ col = a.col_idx;
   const int64_t b = logical_block(blockIdx.x, a.nblocks, a.nspecial);
   const BlockDesc bd = a.blocks[b];
+
+  // the end of a row: the hot pass stores the sum; otherwise the partial of
+  // the hot pass (if any) is added and the row update applied with the full degree
+  auto finish_row = [&](int64_t v, A acc, int32_t d) {
+    const size_t e = (size_t)v * BW + lane;
+    if (hot) {
+      st_nt(hp_row + e, acc);
+      return;
+    }
+    if (hp_row) acc += ld_nt(hp_row + e);
+    if (d > 0) row_update<T, A>(z, y, e, acc, d, c, u, a.mode);
+  };
 
   if (bd.kind == kStream) {
     const int32_t r0 = bd.r0, nr = bd.r1 - bd.r0;
@@ -128,6 +145,8 @@ __global__ void __launch_bounds__(kThreads) batch_step_kernel(BatchStepArgs a) {
     const int32_t cnt = bd.aux;
     for (int i = tid; i < cnt; i += kThreads) cols[i] = ld_nt(col + p0 + i);
     for (int j = tid; j <= nr; j += kThreads) rpl[j] = (int32_t)(rp[r0 + j] - p0);
+    if (a.deg_rp)
+      for (int j = tid; j < nr; j += kThreads) dgl[j] = (int32_t)(drp[r0 + j + 1] - drp[r0 + j]);
     __syncthreads();
     // rows of this group: those starting in arc range [grp*cnt/G, (grp+1)*cnt/G)
     auto first_row_at = [&](int target) {  // smallest j with rpl[j] >= target
@@ -138,11 +157,14 @@ __global__ void __launch_bounds__(kThreads) batch_step_kernel(BatchStepArgs a) {
       }
       return lo;
     };
+    // in a split step every row is finished (rows without arcs of this pass
+    // too), so the groups own whole row ranges: rows starting at the same
+    // arc go to the first group whose range reaches them
     const int rlo = grp == 0 ? 0 : first_row_at((grp * cnt + G - 1) / G);
     const int rhi = grp == G - 1 ? nr : first_row_at(((grp + 1) * cnt + G - 1) / G);
     for (int r = rlo; r < rhi; ++r) {
       const int pb = rpl[r], pe = rpl[r + 1];
-      if (pe == pb) continue;
+      if (pe == pb && !hp_row) continue;
       A acc = A(0);
       int p = pb;
       if constexpr (BW >= 64) {
@@ -164,7 +186,7 @@ __global__ void __launch_bounds__(kThreads) batch_step_kernel(BatchStepArgs a) {
         acc += (v0 + v1) + (v2 + v3);
       }
       for (; p < pe; ++p) acc += to_acc(x[(size_t)cols[p] * BW + lane]);
-      row_update<T, A>(z, y, (size_t)(r0 + r) * BW + lane, acc, pe - pb, c, u, a.mode);
+      finish_row(r0 + r, acc, a.deg_rp ? dgl[r] : pe - pb);
     }
     return;
   }
@@ -173,15 +195,15 @@ __global__ void __launch_bounds__(kThreads) batch_step_kernel(BatchStepArgs a) {
     const int64_t v = bd.r0;
     const int64_t p0 = rp[v], p1 = rp[v + 1];
     const A total = wg_row_sum<T, A, BW>(col, x, p0, p1, grp, lane, part);
-    if (grp == 0) row_update<T, A>(z, y, (size_t)v * BW + lane, total, (int32_t)(p1 - p0), c, u, a.mode);
+    if (grp == 0) finish_row(v, total, (int32_t)(drp[v + 1] - drp[v]));
     return;
   }
 
   // hub segment: partial per (segment, slot); last workgroup of (hub, tile) combines
   const HubDesc h = a.hubs[bd.r1];
   const int64_t rb = rp[h.row], re = rp[h.row + 1];
-  const int64_t p0 = rb + (int64_t)bd.aux * kHubSeg;
-  const int64_t p1 = p0 + kHubSeg < re ? p0 + kHubSeg : re;
+  const int64_t p0 = rb + (int64_t)bd.aux * h.seg;
+  const int64_t p1 = p0 + h.seg < re ? p0 + h.seg : re;
   const A total = wg_row_sum<T, A, BW>(col, x, p0, p1, grp, lane, part);
   A* hp = static_cast<A*>(a.hub_partial);
   const int slot = tile * BW + lane;
@@ -203,7 +225,7 @@ __global__ void __launch_bounds__(kThreads) batch_step_kernel(BatchStepArgs a) {
     for (int q = 0; q < h.nseg; ++q)
       s += __hip_atomic_load(hp + (size_t)(h.base + q) * a.nq_pad + slot, __ATOMIC_RELAXED,
                              __HIP_MEMORY_SCOPE_AGENT);
-    row_update<T, A>(z, y, (size_t)h.row * BW + lane, s, (int32_t)(re - rb), c, u, a.mode);
+    finish_row(h.row, s, (int32_t)(drp[h.row + 1] - drp[h.row]));
     if (lane == 0) __hip_atomic_store(counter, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
@@ -337,7 +359,9 @@ hipError_t launch_bs(const BatchStepArgs& a, hipStream_t st) {
 
 }  // namespace
 
-hipError_t launch_batch_step(int32_t prec, const BatchStepArgs& a, hipStream_t st) {
+namespace {
+
+hipError_t launch_bs_prec(int32_t prec, const BatchStepArgs& a, hipStream_t st) {
   if (a.nblocks <= 0 || a.ntiles <= 0) return hipSuccess;
   switch (prec) {
     case CP_F64: return launch_bs<double>(a, st);
@@ -345,6 +369,40 @@ hipError_t launch_batch_step(int32_t prec, const BatchStepArgs& a, hipStream_t s
     case CP_BF16: return launch_bs<bf16>(a, st);
     default: return hipErrorInvalidValue;
   }
+}
+
+BatchStepArgs with_pass(const BatchStepArgs& a, const BatchPass& p) {
+  BatchStepArgs b = a;
+  b.row_ptr = p.row_ptr;
+  b.col_idx = p.col_idx;
+  b.blocks = p.blocks;
+  b.hubs = p.hubs;
+  b.nblocks = p.nblocks;
+  b.nspecial = p.nspecial;
+  b.split = nullptr;
+  return b;
+}
+
+}  // namespace
+
+hipError_t launch_batch_step(int32_t prec, const BatchStepArgs& a, hipStream_t st) {
+  if (a.ntiles <= 0) return hipSuccess;
+  if (!a.split) {
+    BatchStepArgs b = a;
+    b.deg_rp = nullptr;
+    b.part = nullptr;
+    return launch_bs_prec(prec, b, st);
+  }
+  // hot pass: sums over the hot columns into part; cold pass: part + the
+  // rest, then the row update with the degree from the full row offsets
+  BatchStepArgs h = with_pass(a, a.split->hot);
+  h.mode = kBatchHot;
+  h.deg_rp = nullptr;  // the hot pass applies no row update
+  hipError_t e = launch_bs_prec(prec, h, st);
+  if (e != hipSuccess) return e;
+  BatchStepArgs c = with_pass(a, a.split->cold);
+  c.deg_rp = a.row_ptr;
+  return launch_bs_prec(prec, c, st);
 }
 
 hipError_t launch_batch_init(int32_t prec, const BatchInitArgs& a, int32_t nslots, hipStream_t st) {

@@ -80,12 +80,11 @@ PushLayout push_layout(const cp_graph* g) {
   L.bvol = off; off += al((size_t)kRangeBlocks * 8);
   L.counts = off; off += al((size_t)kCounts * 8);
   // hub row counters of the dense step (zero between launches)
-  L.hubc = off; off += al((size_t)(g->single.nhubs > 0 ? g->single.nhubs : 1) * 4);
+  L.hubc = off; off += al((size_t)batch_hub_rows(g) * 4);
   L.sums = off; off += al((size_t)(1 + kRangeBlocks) * 8);
   // dense step partial sums: [S][n] (striped) or one per hub segment
   L.part = off;
-  off += al(g->striped ? (size_t)g->s_count * n * 8
-                       : (size_t)(g->single.hub_segments > 0 ? g->single.hub_segments : 1) * 8);
+  off += al(g->striped ? (size_t)g->s_count * n * 8 : (size_t)batch_hub_segments(g) * 8);
   L.total = off;
   return L;
 }
