@@ -54,7 +54,10 @@ struct cp_server {
   size_t dev_bytes = 0;
   // device layout
   size_t o_rA = 0, o_rB = 0, o_y = 0, o_hcount = 0, o_hpart = 0, o_coef = 0, o_src = 0, o_c01 = 0,
-         o_rec = 0, o_fslots = 0, o_fouts = 0;
+         o_rec = 0, o_fslots = 0, o_fouts = 0, o_part = 0, o_ws1 = 0;
+  size_t ws1_bytes = 0;       // workspace of the single-source path (idle-server queries)
+  uint64_t direct_ticket = 0; // query running on the single-source path, 0 if none
+  int64_t direct = 0;         // queries run on the single-source path
   std::vector<double> sp;  // host image of the slot parameters [kSlotParams][slots]
 
   std::mutex mu;
@@ -110,6 +113,8 @@ void cp_server::run() {
   std::vector<int64_t> src(nslot);
   std::vector<int32_t> fin_slots;
   std::vector<void*> fin_outs;
+  cp_query direct_q{};
+  void* direct_y = nullptr;
   for (;;) {
     std::vector<int32_t> admitted, stepping, finishing, clearing;
     std::vector<uint64_t> fin_tickets;
@@ -125,6 +130,45 @@ void cp_server::run() {
         return false;
       });
       if (stop) break;
+      // an idle server with one query waiting runs it on the single-source
+      // path: a query alone in a batched launch would pay a whole tile's
+      // gathers for one source
+      if (queue.size() == 1 && std::all_of(slot_ticket.begin(), slot_ticket.end(), [](uint64_t t) { return !t; })) {
+        direct_ticket = queue.front();
+        queue.pop_front();
+        Ticket& tk = tickets[direct_ticket];
+        tk.state = kRunning;
+        tk.t_admit = Clock::now();
+        direct_q = tk.q;
+        direct_q.flags &= CP_Q_PWMETHOD;
+        direct_y = tk.y;
+      }
+    }
+    if (direct_ticket) {
+      const cp_status rc = cp_power(g, &direct_q, prec, direct_y, dev + o_ws1, ws1_bytes, st, nullptr);
+      hipError_t e = rc == CP_OK ? hipStreamSynchronize(st) : (hipError_t)cp_last_hip_error();
+      if (rc != CP_OK && e == hipSuccess) e = hipErrorUnknown;
+      {
+        std::lock_guard<std::mutex> lk(mu);
+        Ticket& tk = tickets[direct_ticket];
+        direct_ticket = 0;
+        if (e != hipSuccess) {
+          failed_hip = (int32_t)e;
+          for (auto& kv : tickets)
+            if (kv.second.state == kQueued || kv.second.state == kRunning) kv.second.state = kFailed;
+          queue.clear();
+        } else {
+          tk.state = tk.cancel_requested ? kCancelled : kDone;
+          tk.t_done = Clock::now();
+          if (tk.state == kDone) ++completed; else ++cancelled;
+          ++direct;
+        }
+      }
+      done_cv.notify_all();
+      continue;
+    }
+    {
+      std::lock_guard<std::mutex> lk(mu);
       // running queries whose cancellation was requested: clear their slots
       for (int32_t s = 0; s < nslots; ++s) {
         const uint64_t t = slot_ticket[s];
@@ -215,12 +259,7 @@ void cp_server::run() {
       for (int32_t s : stepping) tiles = std::max(tiles, s / bw + 1);
       chk(launch_upload(w + o_coef, coef_row.data(), nslot * sizeof(double), st));
       BatchStepArgs sa{};
-      sa.row_ptr = g->row_ptr;
-      sa.col_idx = g->col_idx;
-      sa.blocks = g->batch.blocks;
-      sa.hubs = g->batch.hubs;
-      sa.nblocks = g->batch.nblocks;
-      sa.nspecial = g->batch.nspecial;
+      set_batch_plan(g, sa, w + o_part);
       sa.n = g->n;
       sa.bw = bw;
       sa.ntiles = tiles;
@@ -296,7 +335,7 @@ cp_status cp_server_create(const cp_graph* g, size_t hbm_budget_bytes, int32_t m
   // one tile row is one 128-byte line per gathered node
   s->bw = prec == CP_F64 ? 16 : prec == CP_F32 ? 32 : 64;
   const size_t per_tile = a256((size_t)g->n * s->bw * storage_bytes(prec)) * 2 +
-                          a256((size_t)g->n * s->bw * acc_bytes(prec));
+                          a256((size_t)g->n * s->bw * acc_bytes(prec)) * (g->hot_split ? 2 : 1);
   int64_t tiles = (int64_t)(hbm_budget_bytes / per_tile);
   const int32_t cap = max_slots > 0 ? std::min(max_slots, 1024) : 1024;
   tiles = std::min<int64_t>(tiles, (cap + s->bw - 1) / s->bw);
@@ -312,14 +351,19 @@ cp_status cp_server_create(const cp_graph* g, size_t hbm_budget_bytes, int32_t m
   s->o_rA = off; off += a256((size_t)g->n * ns * storage_bytes(prec));
   s->o_rB = off; off += a256((size_t)g->n * ns * storage_bytes(prec));
   s->o_y = off; off += a256((size_t)g->n * ns * acc_bytes(prec));
-  s->o_hcount = off; off += a256((size_t)std::max<int64_t>(g->batch.nhubs, 1) * s->ntiles * 4);
-  s->o_hpart = off; off += a256((size_t)std::max<int64_t>(g->batch.hub_segments, 1) * ns * 8);
+  s->o_hcount = off; off += a256((size_t)batch_hub_rows(g) * s->ntiles * 4);
+  s->o_hpart = off; off += a256((size_t)batch_hub_segments(g) * ns * 8);
   s->o_coef = off; off += a256(ns * 8);
   s->o_src = off; off += a256(ns * 8);
   s->o_c01 = off; off += a256(2 * ns * 8);
   s->o_rec = off; off += a256(kSlotParams * ns * 8);
   s->o_fslots = off; off += a256(ns * 4);
   s->o_fouts = off; off += a256(ns * 8);
+  s->o_part = off;
+  if (g->hot_split) off += a256((size_t)g->n * ns * acc_bytes(prec));  // partial row sums of the hot pass
+  s->o_ws1 = off;
+  s->ws1_bytes = single_ws_bytes(g, prec);
+  off += a256(s->ws1_bytes);
   s->dev_bytes = off;
   hipError_t e = hipStreamCreate(&s->st);
   if (e != hipSuccess) { set_hip_error(e); delete s; return CP_EHIP; }
@@ -368,7 +412,9 @@ cp_status cp_server_submit(cp_server* s, const cp_query* q, void* y_out, uint64_
     std::lock_guard<std::mutex> lk(s->mu);
     if (s->failed_hip) { set_hip_error((hipError_t)s->failed_hip); return CP_EHIP; }
     // the queue holds max_queue waiting queries beyond those about to take a free slot
-    const size_t free_slots = (size_t)std::count(s->slot_ticket.begin(), s->slot_ticket.end(), (uint64_t)0);
+    // (a query on the single-source path holds one of them)
+    const size_t free_slots = (size_t)std::count(s->slot_ticket.begin(), s->slot_ticket.end(), (uint64_t)0) -
+                              (s->direct_ticket ? 1 : 0);
     if (s->queue.size() >= s->max_queue + free_slots) return CP_EBUSY;
     const uint64_t id = s->next_ticket++;
     s->tickets.emplace(id, std::move(tk));
@@ -445,7 +491,9 @@ cp_status cp_server_get_stats(cp_server* s, cp_server_stats* out) {
   if (!s || !out) return CP_EINVAL;
   std::lock_guard<std::mutex> lk(s->mu);
   out->slots = s->nslots;
-  out->active = (int64_t)std::count_if(s->slot_ticket.begin(), s->slot_ticket.end(), [](uint64_t t) { return t; });
+  out->active = (int64_t)std::count_if(s->slot_ticket.begin(), s->slot_ticket.end(), [](uint64_t t) { return t; }) +
+                (s->direct_ticket ? 1 : 0);
+  out->direct = s->direct;
   out->queued = (int64_t)s->queue.size();
   out->completed = s->completed;
   out->cancelled = s->cancelled;
