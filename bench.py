@@ -265,9 +265,10 @@ def run_headline(args, torch, cp, synth):
     gen_s = time.time() - t0
     log(f"[headline] graph: n={g.n} nnz={g.nnz} d_max={g.meta['d_max']} ({gen_s:.1f}s)")
     t0 = time.time()
-    G = cp.Graph(g.row_ptr, g.col_idx, reorder=True)
+    G = cp.Graph(g.row_ptr, g.col_idx, reorder=True, hot_split=not args.no_hot_split)
     create_s = time.time() - t0
-    log(f"[headline] graph create (degree order) {create_s:.1f}s, device bytes {G.stats['device_bytes']}")
+    log(f"[headline] graph create (degree order, hot split {G.stats['hot_nodes']} nodes / "
+        f"{G.stats['hot_arcs'] / g.nnz:.3f} of arcs) {create_s:.1f}s, device bytes {G.stats['device_bytes']}")
     srcs = [int(s) for s in synth.sources(g, nq, seed=seed)]
     qs = [cp.make_query("ppr", alpha, s, tol) for s in srcs]
     qt = [cp.make_query("ppr", alpha, s, tol, flags=cp.CP_Q_TIMING) for s in srcs]
@@ -304,10 +305,12 @@ def run_headline(args, torch, cp, synth):
     R = timed(prec, Y, args.warmup, args.steps)
     out = {
         "workload": f"{args.headline}: {nq} PPR alpha={alpha} sources in one batch, tol {tol} l1 (certified K), "
-                    f"Chung-Lu n={n_t} m={m_t} gamma={gamma} seed={seed}, degree-ordered layout",
+                    f"Chung-Lu n={n_t} m={m_t} gamma={gamma} seed={seed}, degree-ordered layout"
+                    + ("" if args.no_hot_split else " with the hot/cold split of the batched step"),
         "value": R["arcs"] / R["total_s"] / 1e9,
         "total_s": R["total_s"], "n": g.n, "nnz": g.nnz, "d_max": int(deg.max()), "sources": nq, "Ks": R["Ks"],
         "prec": prec, "source_tile_width": bw, "generate_s": round(gen_s, 1), "create_s": round(create_s, 1),
+        "hot_nodes": G.stats["hot_nodes"], "hot_arc_share": round(G.stats["hot_arcs"] / g.nnz, 4),
         "roofline": roofline(R["bytes_per_launch"], R["avg_launch_ms"], f"batch_step_kernel (width {bw})",
                              traffic=measured_traffic(f"{args.headline}:batch"),
                              implementation_bytes_per_launch=int(R["impl_bytes_per_launch"]),
@@ -1074,8 +1077,11 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10, help="timed headline batches (the JSON's steps)")
     ap.add_argument("--warmup", type=int, default=2, help="untimed headline batches before them")
-    ap.add_argument("--headline", default="ppr-batch-friendster", choices=sorted(HEADLINES))
+    ap.add_argument("--headline", default="ppr-batch-friendster", choices=sorted(HEADLINES) + ["none"],
+                    help="the headline workload (none: only the other legs, e.g. for profiler runs)")
     ap.add_argument("--bf16-steps", type=int, default=3, help="timed batches of the headline's BF16 variant")
+    ap.add_argument("--no-hot-split", action="store_true",
+                    help="run the headline's batched steps without the hot/cold split (CP_GRAPH_HOT_SPLIT)")
     ap.add_argument("--workload", default="hkpr-livejournal", choices=sorted(WORKLOADS) + ["none"],
                     help="single-source measurement reported beside the headline")
     ap.add_argument("--single-steps", type=int, default=10,
@@ -1144,6 +1150,17 @@ def main() -> int:
     copy_gbps = copy_ceiling(torch)
     log(f"device copy ceiling: {copy_gbps:.0f} GB/s")
 
+    if args.headline == "none":
+        result = {"metric": METRIC, "n_gpus": 1, "note": "headline skipped (--headline none)"}
+        if args.workload != "none":
+            result["single"], g_main = run_single(args, torch, cp, synth)
+            if args.serve_seconds > 0:
+                result["served"] = run_serve(args, torch, cp, synth, g_main)
+            del g_main
+        if args.batch_workload != "none":
+            result["batched"] = run_batch(args, torch, cp, synth)
+        print(json.dumps(result), flush=True)
+        return 0
     H = run_headline(args, torch, cp, synth)
     result = {
         "metric": METRIC,
@@ -1162,6 +1179,7 @@ def main() -> int:
         "config": {
             "workload": H["workload"], "n": H["n"], "nnz": H["nnz"], "d_max": H["d_max"], "sources": H["sources"],
             "K_per_source": H["Ks"], "prec": H["prec"], "layout": "degree", "source_tile_width": H["source_tile_width"],
+            "hot_nodes": H["hot_nodes"], "hot_arc_share": H["hot_arc_share"],
             "graph_generate_s": H["generate_s"], "graph_create_s": H["create_s"], "parallelism": "single-gpu",
         },
         "roofline": H["roofline"],

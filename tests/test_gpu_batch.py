@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 import synth
-from gpu_util import BF16_L1, F32_L1, compare, gpu_graph, oracle_exact_multi, oracle_yK, oracle_yK_multi, require_gpu
+from gpu_util import BF16_L1, compare, f32_bar, gpu_graph, oracle_exact_multi, oracle_yK, oracle_yK_multi, require_gpu
 from oracle import errors as E
 from oracle import propagation as PR
 
@@ -69,8 +69,8 @@ def test_batch_columns_match_oracle(torch, mid_graph, mid_oracle, bw, prec):
             assert m["max_abs"] <= 1e-13, (j, m)
             assert ex <= qs[j].tol, (j, ex, qs[j].tol)
         elif prec == "f32":
-            assert m["l1"] <= F32_L1, (j, m)
-            assert ex <= qs[j].tol + F32_L1, (j, ex, qs[j].tol)
+            assert m["l1"] <= f32_bar(Ks[j]), (j, Ks[j], m)
+            assert ex <= qs[j].tol + f32_bar(Ks[j]), (j, ex, qs[j].tol)
         else:  # BF16 storage: reported, about 1e-3
             assert m["l1"] <= BF16_L1, (j, m)
 
@@ -184,7 +184,7 @@ def test_orkut_shape_3m_full_size_batch_f32(torch):
         m = compare(Y[:, j], ref[:, i])
         m64 = compare(Y64[:, j], ref[:, i])
         print("batch 3M column", j, tols[j], Ks[j], m, "f64", m64, flush=True)
-        assert m["l1"] <= F32_L1, (j, m)
+        assert m["l1"] <= f32_bar(Ks[j]), (j, m)
         assert m64["max_abs"] <= 1e-13, (j, m64)
     # every column: FP32 storage against the FP64 path (pinned to the oracle above and in the
     # smaller tests) to FP32 rounding, and Def. 3's fixed-point certificate
@@ -193,7 +193,144 @@ def test_orkut_shape_3m_full_size_batch_f32(torch):
     res = NO.ppr_residual_multi(g.row_ptr, g.col_idx, srcs, [0.2] * 64, Y)
     for j in range(64):
         d = E.l1(Y[:, j], Y64[:, j])
-        assert d <= F32_L1, (j, d)
+        assert d <= f32_bar(Ks[j]), (j, d)
         # ||res||_1 <= (2 - alpha) ||pi - y||_1, and ||pi - y||_1 <= tol + FP32 rounding
-        assert res[j] / 0.2 <= 9.0 * (tols[j] + F32_L1), (j, res[j], tols[j])
-        assert abs(Y[:, j].sum() - 1.0) <= tols[j] + F32_L1, j
+        assert res[j] / 0.2 <= 9.0 * (tols[j] + f32_bar(Ks[j])), (j, res[j], tols[j])
+        assert abs(Y[:, j].sum() - 1.0) <= tols[j] + f32_bar(Ks[j]), j
+
+
+@pytest.mark.parametrize("hot_nodes,stripes", [(None, False), (2000, False), (0, False), (3000, True)])
+def test_hot_split_batch_matches_oracle(torch, mid_graph, monkeypatch, hot_nodes, stripes):
+    """CP_GRAPH_HOT_SPLIT: the batched step sums each row's arcs into the
+    hot_nodes highest-degree nodes in one pass and the rest in a second; every
+    column still matches the oracle (all nodes hot, a few thousand hot, none
+    hot, and the striped relabelling), in FP64 and FP32."""
+    g = mid_graph
+    if hot_nodes is not None:
+        monkeypatch.setenv("CHEBYPROP_HOT_NODES", str(hot_nodes))
+    else:
+        monkeypatch.delenv("CHEBYPROP_HOT_NODES", raising=False)
+    G = gpu_graph(g, hot_split=True, stripes=stripes)
+    st = G.stats
+    want = g.n if hot_nodes is None else min(hot_nodes, g.n)
+    assert st["hot_nodes"] == want and st["reordered"] == 1
+    assert (st["hot_arcs"] == g.nnz) if want == g.n else (0 <= st["hot_arcs"] < g.nnz)
+    qs, meta = _queries(g, 21, seed=13)
+    for prec in ("f64", "f32"):
+        for bw in (8, 32):
+            G.set_batch_width(21, prec, bw)
+            print("CASE hot split", hot_nodes, stripes, prec, bw, flush=True)
+            Y, infos = G.power_batch(qs, prec=prec)
+            Y = Y.double().cpu().numpy()
+            Ks = [i["K"] for i in infos]
+            ref = oracle_yK_multi(g, meta, Ks)
+            for j in range(len(qs)):
+                m = compare(Y[:, j], ref[:, j])
+                if prec == "f64":
+                    assert m["max_abs"] <= 1e-13, (j, m)
+                else:
+                    assert m["l1"] <= f32_bar(Ks[j]), (j, Ks[j], m)
+    G.close()
+
+
+def test_hot_split_hubs_server_and_propagate(torch, monkeypatch):
+    """The split with hub rows (a 40,000-arc row whose cold part is split into
+    segments, and 40,000 rows whose only arc is hot), through the batch, the
+    server and feature propagation (forward and Clenshaw), against the
+    unsplit graph's results and the oracle."""
+    from paper_2412_10789_amd import chebyprop as cp
+
+    leaves = 40_000
+    base = synth.erdos_renyi(1_500, 0.005, seed=9)
+    e = [(0, i) for i in range(1, leaves + 1)]
+    rows = np.repeat(np.arange(base.n), base.degrees)
+    e += [(int(a) + 1, int(b) + 1) for a, b in zip(rows, base.col_idx) if a < b]
+    g = synth.from_edges(leaves + 1, e, name="hub")
+    monkeypatch.setenv("CHEBYPROP_HOT_NODES", "100")
+    Gs = gpu_graph(g, hot_split=True)
+    monkeypatch.delenv("CHEBYPROP_HOT_NODES")
+    G0 = gpu_graph(g, reorder=True)
+    assert Gs.stats["hot_nodes"] == 100 and 0 < Gs.stats["hot_arcs"] < g.nnz
+    srcs = [0, 3, 17, leaves, 1200, 5]
+    qs = [cp.make_query("hkpr", 3.0, s, 1e-9) for s in srcs] + [cp.make_query("ppr", 0.2, s, 1e-7) for s in srcs]
+    metas = [("hkpr", 3.0, s) for s in srcs] + [("ppr", 0.2, s) for s in srcs]
+    print("CASE hot split hub batch", flush=True)
+    Ys, infos = Gs.power_batch(qs, prec="f64")
+    Y0, _ = G0.power_batch(qs, prec="f64")
+    ref = oracle_yK_multi(g, metas, [i["K"] for i in infos])
+    Ys, Y0 = Ys.cpu().numpy(), Y0.cpu().numpy()
+    for j in range(len(qs)):
+        assert compare(Ys[:, j], ref[:, j])["max_abs"] <= 1e-11, j
+        assert compare(Ys[:, j], Y0[:, j])["max_abs"] <= 1e-12, j
+    print("CASE hot split hub server", flush=True)
+    S = cp.Server(Gs, hbm_budget_bytes=1 << 30, max_slots=16, prec="f64")
+    ys = [torch.empty(g.n, dtype=torch.float64, device="cuda") for _ in qs]
+    tickets = [S.submit(q, y) for q, y in zip(qs, ys)]
+    for j, t in enumerate(tickets):
+        st, info = S.wait(t, timeout_ms=60_000)
+        assert st == cp.CP_OK
+        assert compare(ys[j].cpu().numpy(), ref[:, j])["max_abs"] <= 1e-11, j
+    S.close()
+    X = (torch.rand((g.n, 5), generator=torch.Generator().manual_seed(3), dtype=torch.float64) - 0.5).cuda()
+    for method in ("cheby", "clenshaw"):
+        print("CASE hot split propagate", method, flush=True)
+        Zs, _ = Gs.propagate(X, "ppr", 0.2, a=0.5, K=12, kmode="fixed", prec="f64", method=method)
+        Z0, _ = G0.propagate(X, "ppr", 0.2, a=0.5, K=12, kmode="fixed", prec="f64", method=method)
+        d = (Zs - Z0).abs().max().item()
+        assert d <= 1e-12 * Z0.abs().max().item(), (method, d)
+    Gs.close()
+    G0.close()
+
+
+@pytest.mark.parametrize("shape", ["powerlaw", "hub"])
+def test_autotune_row_splits(torch, shape):
+    """cp_autotune_batch and cp_autotune_single time several row-split plans
+    (long-row cuts, hub cut and segment size) and install the fastest: the
+    stats report a candidate plan, results match the default plan's to FP64
+    rounding (only the order of the sums of split rows changes) and the
+    oracle, and a workspace sized before tuning stays valid."""
+    from paper_2412_10789_amd import chebyprop as cp
+
+    if shape == "powerlaw":
+        g = synth.chung_lu(200_000, 2_400_000, 2.1, seed=12)
+    else:
+        leaves = 40_000
+        base = synth.erdos_renyi(1_500, 0.005, seed=9)
+        e = [(0, i) for i in range(1, leaves + 1)] + [(1, i) for i in range(2, 9_000)]
+        rows = np.repeat(np.arange(base.n), base.degrees)
+        e += [(int(a) + 1, int(b) + 1) for a, b in zip(rows, base.col_idx) if a < b]
+        g = synth.from_edges(leaves + 1, e, name="hubs")
+    G0 = gpu_graph(g)
+    G = gpu_graph(g)
+    qs, meta = _queries(g, 16, seed=21)
+    ws_before, _ = G.workspace(16, cp.CP_F64)
+    Y0, infos = G0.power_batch(qs, prec="f64")
+    print("CASE autotune row splits", shape, flush=True)
+    bw = G.autotune_batch(qs, prec="f64")
+    st = G.stats
+    print("autotuned", shape, "width", bw, "batch plan", st["batch_long_cut"], st["batch_hub_cut"],
+          st["batch_hub_seg"], flush=True)
+    assert st["batch_long_cut"] in (64, 128, 256, 512, 1024)
+    assert (st["batch_hub_cut"], st["batch_hub_seg"]) in ((16384, 8192), (4096, 2048), (65536, 16384))
+    ws_after, nbytes = G.workspace(16, cp.CP_F64)
+    assert ws_after.numel() == ws_before.numel()  # sized for every candidate plan
+    Y1, _ = G.power_batch(qs, prec="f64")
+    Y0, Y1 = Y0.cpu().numpy(), Y1.cpu().numpy()
+    ref = oracle_yK_multi(g, meta, [i["K"] for i in infos])
+    for j in range(len(qs)):
+        assert compare(Y1[:, j], Y0[:, j])["max_abs"] <= 1e-13 * max(1.0, np.abs(Y0[:, j]).max()), j
+        assert compare(Y1[:, j], ref[:, j])["max_abs"] <= 1e-12, j
+    kind, param, s = meta[0]
+    r0 = G0.power(kind, param, s, tol=1e-9, prec="f64")
+    st = G.autotune_single(kind, param, s, tol=1e-9, prec="f64")
+    print("autotuned", shape, "single plan", st["single_long_cut"], st["single_hub_cut"], st["single_hub_seg"],
+          flush=True)
+    assert st["single_long_cut"] in (256, 512, 1024, 2048)
+    r1 = G.power(kind, param, s, tol=1e-9, prec="f64")
+    assert compare(r1.y.cpu().numpy(), r0.y.cpu().numpy())["max_abs"] <= 1e-13
+    # striped graphs keep their stripe tiles
+    Gs = gpu_graph(g, stripes=True)
+    before = dict(Gs.stats)
+    assert Gs.autotune_single(kind, param, s, tol=1e-9, prec="f64") == before
+    for x in (G0, G, Gs):
+        x.close()
