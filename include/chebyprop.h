@@ -249,6 +249,31 @@ size_t cp_workspace_bytes(const cp_graph* g, int32_t nq, int32_t prec);
 cp_status cp_power(const cp_graph* g, const cp_query* q, int32_t prec, void* y, void* ws,
                    size_t ws_bytes, void* stream, cp_info* info);
 
+/* Bytes of the device array cp_power_noalloc works in. */
+#define CP_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+
+/* cp_power for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): no
+ * workspace argument, and no hipMalloc, hipFree, event or other allocating
+ * call.  The workspace is one static device array of CP_NOALLOC_SCRATCH_BYTES
+ * (64 MiB), which each GPU the library runs on holds until the process
+ * ends; its address is looked up once per device, on the first call with
+ * that device current.
+ *   y, info  as cp_power; the current device must be the graph's
+ * Every call on a GPU works in that GPU's one array and leaves its contents
+ * there (each call clears what it needs zero first), so calls that overlap
+ * on one GPU (other streams, other host threads) race: serialize them.
+ * Results are bitwise those of cp_power.
+ * Errors: those of cp_power; CP_EWORKSPACE when the query's workspace
+ * exceeds CP_NOALLOC_SCRATCH_BYTES: two recurrence vectors of n storage
+ * elements, an n-element estimate (double; float for CP_BF16), S n more
+ * estimate-width partials on a graph with S XCD stripes, and a few KiB of
+ * counters (FP32: 16 n bytes, about 4M nodes, or 16 n + 8 S n with
+ * stripes); CP_EINVAL for CP_Q_TIMING (its events would be created per
+ * call) or when the current device is not the graph's. */
+cp_status cp_power_noalloc(const cp_graph* g, const cp_query* q, int32_t prec, void* y, void* stream,
+                           cp_info* info);
+
 /* nq queries at once (each with its own kind, parameter, tolerance and K):
  * the batched form of Alg. 3.  Y is device [n][nq] row-major in caller ids
  * (double for CP_F64, float otherwise); infos is host [nq] or NULL.

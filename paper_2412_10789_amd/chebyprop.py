@@ -40,6 +40,7 @@ CP_GRAPH_BORROW, CP_GRAPH_VALIDATE, CP_GRAPH_REORDER, CP_GRAPH_HOST = 0x1, 0x2, 
 CP_GRAPH_HOT_SPLIT = 0x20
 CP_GRAPH_XCD_STRIPES = 0x10
 CP_Q_STATS, CP_Q_TIMING, CP_Q_PWMETHOD, CP_Q_CLENSHAW = 0x1, 0x2, 0x4, 0x8
+CP_NOALLOC_SCRATCH_BYTES = 64 << 20  # the static device array cp_power_noalloc works in
 
 KINDS = {"ppr": CP_PPR, "hkpr": CP_HKPR}
 PRECS = {"f64": CP_F64, "f32": CP_F32, "bf16": CP_BF16}
@@ -52,7 +53,7 @@ METHODS = {"cheby": 0, "power": CP_Q_PWMETHOD, "clenshaw": CP_Q_CLENSHAW}
 EXPORTED = [
     "cp_graph_create", "cp_graph_destroy", "cp_graph_get_stats", "cp_coeffs", "cp_choose_K",
     "cp_taylor", "cp_choose_N",
-    "cp_workspace_bytes", "cp_power", "cp_power_batch", "cp_propagate", "cp_push", "cp_push_workspace_bytes",
+    "cp_workspace_bytes", "cp_power", "cp_power_noalloc", "cp_power_batch", "cp_propagate", "cp_push", "cp_push_workspace_bytes",
     "cp_push_rw", "cp_push_rw_workspace_bytes", "cp_autotune_batch", "cp_autotune_single", "cp_set_batch_width",
     "cp_status_str", "cp_last_hip_error", "cp_version",
     "cp_server_create", "cp_server_submit", "cp_server_poll", "cp_server_wait", "cp_server_cancel",
@@ -179,6 +180,7 @@ def load() -> ctypes.CDLL:
         "cp_choose_N": (i32, [i32, f64, f64, i32, i32, i32, ctypes.POINTER(i32), ctypes.POINTER(f64)]),
         "cp_workspace_bytes": (sz, [P, i32, i32]),
         "cp_power": (i32, [P, ctypes.POINTER(cp_query), i32, P, P, sz, P, ctypes.POINTER(cp_info)]),
+        "cp_power_noalloc": (i32, [P, ctypes.POINTER(cp_query), i32, P, P, ctypes.POINTER(cp_info)]),
         "cp_power_batch": (i32, [P, i32, ctypes.POINTER(cp_query), i32, P, P, sz, P, ctypes.POINTER(cp_info)]),
         "cp_push": (i32, [P, ctypes.POINTER(cp_query), f64, P, P, sz, P, ctypes.POINTER(cp_info)]),
         "cp_push_workspace_bytes": (sz, [P]),
@@ -284,6 +286,13 @@ def cp_power(handle: int, query: cp_query, prec: int, y_ptr: int, ws_ptr: int, w
     info = cp_info()
     _check(load().cp_power(handle, ctypes.byref(query), prec, y_ptr, ws_ptr, ws_bytes, stream,
                            ctypes.byref(info)), "cp_power")
+    return info
+
+
+def cp_power_noalloc(handle: int, query: cp_query, prec: int, y_ptr: int, stream: int) -> cp_info:
+    info = cp_info()
+    _check(load().cp_power_noalloc(handle, ctypes.byref(query), prec, y_ptr, stream, ctypes.byref(info)),
+           "cp_power_noalloc")
     return info
 
 
@@ -434,6 +443,15 @@ class Graph:
         q = make_query(kind, param, source, tol, kmode, K, flags, method, a)
         info = cp_power(self.handle, q, p, y.data_ptr(), ws.data_ptr(), nbytes, st)
         return Result(y, info.as_dict())
+
+    def power_noalloc(self, kind: str, param: float, source: int, y, tol: float = 1e-6, prec: str = "f32",
+                      kmode: str = "certified", K: int = 0, flags: int = 0, stream=None, method: str = "cheby",
+                      a: float = 0.0) -> dict:
+        """cp_power_noalloc: the query into the caller's tensor y, with the
+        library's static device array as workspace; returns the info dict."""
+        st = stream if stream is not None else self.torch.cuda.current_stream(self.device).cuda_stream
+        q = make_query(kind, param, source, tol, kmode, K, flags, method, a)
+        return cp_power_noalloc(self.handle, q, PRECS[prec], y.data_ptr(), st).as_dict()
 
     def autotune_single(self, kind: str, param: float, source: int, tol: float = 1e-6, prec: str = "f32",
                         stream=None) -> dict:

@@ -561,7 +561,33 @@ hipError_t release_graph(cp_graph* g) {
 
 }  // namespace
 
+// Workspace of cp_power_noalloc: one array per device, held until the
+// process ends.  Host code never uses this name as an address (on the host
+// it stands for the symbol); noalloc_scratch looks up the device address.
+static __device__ __align__(256) unsigned char scratch[CP_NOALLOC_SCRATCH_BYTES];
+
 namespace {
+
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[64] = {};  // device address of `scratch`, per device id
+
+// The device address of `scratch` on device dev (the current device),
+// looked up on the first call for that device.
+cp_status noalloc_scratch(int dev, void** out) {
+  if (dev < 0 || dev >= 64) return CP_EINVAL;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      set_hip_error(e);
+      return CP_EHIP;
+    }
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return CP_OK;
+}
 
 cp_status power_impl(const cp_graph* g, const cp_query* q, int32_t prec, void* y, void* ws, size_t ws_bytes,
                      void* stream, cp_info* info);
@@ -943,6 +969,20 @@ size_t cp_workspace_bytes(const cp_graph* g, int32_t nq, int32_t prec) {
 cp_status cp_power(const cp_graph* g, const cp_query* q, int32_t prec, void* y, void* ws,
                    size_t ws_bytes, void* stream, cp_info* info) {
   return power_impl(g, q, prec, y, ws, ws_bytes, stream, info);
+}
+
+cp_status cp_power_noalloc(const cp_graph* g, const cp_query* q, int32_t prec, void* y, void* stream,
+                           cp_info* info) {
+  if (!g || !q || !y || !valid_prec(prec)) return CP_EINVAL;
+  if (q->flags & CP_Q_TIMING) return CP_EINVAL;
+  int dev = -1;
+  CP_HIP(hipGetDevice(&dev));
+  if (dev != g->device) return CP_EINVAL;
+  if (ws_layout(g, 1, prec).total > CP_NOALLOC_SCRATCH_BYTES) return CP_EWORKSPACE;
+  void* ws = nullptr;
+  const cp_status rc = noalloc_scratch(dev, &ws);
+  if (rc != CP_OK) return rc;
+  return power_impl(g, q, prec, y, ws, CP_NOALLOC_SCRATCH_BYTES, stream, info);
 }
 
 }  // extern "C"
