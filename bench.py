@@ -72,7 +72,12 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def kernel_hash(files=("kernels.hip", "kernels_batch.hip", "common.h")) -> str:
+SINGLE_SOURCES = ("kernels.hip", "common.h")         # the single-source step kernels
+BATCH_SOURCES = ("kernels_batch.hip", "common.h")    # the batched step kernel
+
+
+def kernel_hash(files=SINGLE_SOURCES) -> str:
+    """First 16 hex digits of the sha256 of the given kernel sources."""
     h = hashlib.sha256()
     for f in files:
         with open(os.path.join(ROOT, "paper_2412_10789_amd", "csrc", f), "rb") as fh:
@@ -106,16 +111,16 @@ def clenshaw_step_bytes(n: int, nnz: int, prec: str, sources: int) -> int:
     return 4 * nnz + 8 * (n + 1) + 4 * n * sources * s
 
 
-def measured_traffic(key: str):
+def measured_traffic(key: str, files=SINGLE_SOURCES):
     """HBM bytes per launch from the committed rocprofv3 counter summary,
-    if it was taken with the current kernel sources (else None)."""
+    if it was taken with the current sources of the kernel (else None)."""
     path = os.path.join(ROOT, "profiles", "step_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         rec = json.load(fh)
     e = rec.get(key)
-    if not e or e.get("kernel_hash") != kernel_hash():
+    if not e or e.get("kernel_hash") != kernel_hash(files):
         return None
     return e.get("bytes_per_launch")
 
@@ -312,7 +317,7 @@ def run_headline(args, torch, cp, synth):
         "prec": prec, "source_tile_width": bw, "generate_s": round(gen_s, 1), "create_s": round(create_s, 1),
         "hot_nodes": G.stats["hot_nodes"], "hot_arc_share": round(G.stats["hot_arcs"] / g.nnz, 4),
         "roofline": roofline(R["bytes_per_launch"], R["avg_launch_ms"], f"batch_step_kernel (width {bw})",
-                             traffic=measured_traffic(f"{args.headline}:batch"),
+                             traffic=measured_traffic(f"{args.headline}:batch", BATCH_SOURCES),
                              implementation_bytes_per_launch=int(R["impl_bytes_per_launch"]),
                              launches_timed=R["launches"]),
         "launch_bytes_rule": "4 nnz + 8 (n+1) + 5 n B_k s per launch, B_k the sources still active in launch k",
@@ -546,7 +551,7 @@ def run_batch(args, torch, cp, synth):
         "ms_per_batch": round(R["total_s"] * 1e3 / nb, 3), "batches": nb,
         "n": g.n, "nnz": g.nnz, "source_tile_width": bw, "K_min": min(R["Ks"]), "K_max": max(R["Ks"]),
         "roofline": roofline(R["bytes_per_launch"], R["avg_launch_ms"], f"batch_step_kernel (width {bw})",
-                             traffic=measured_traffic(f"{args.batch_workload}:batch"),
+                             traffic=measured_traffic(f"{args.batch_workload}:batch", BATCH_SOURCES),
                              implementation_bytes_per_launch=int(R["impl_bytes_per_launch"]),
                              launches_timed=R["launches"]),
     }

@@ -148,20 +148,21 @@ __global__ void __launch_bounds__(kThreads) batch_step_kernel(BatchStepArgs a) {
     if (a.deg_rp)
       for (int j = tid; j < nr; j += kThreads) dgl[j] = (int32_t)(drp[r0 + j + 1] - drp[r0 + j]);
     __syncthreads();
-    // rows of this group: those starting in arc range [grp*cnt/G, (grp+1)*cnt/G)
-    auto first_row_at = [&](int target) {  // smallest j with rpl[j] >= target
+    // the groups own consecutive row ranges of about equal work, counting a
+    // row's arcs plus one for the row itself (in a split step every row is
+    // finished, also those without arcs of this pass): group g takes the
+    // rows j whose rpl[j] + j falls in [g tot / G, (g + 1) tot / G)
+    const int tot = cnt + nr;
+    auto first_row_at = [&](int target) {  // smallest j with rpl[j] + j >= target
       int lo = 0, hi = nr;
       while (lo < hi) {
         const int mid = (lo + hi) >> 1;
-        if (rpl[mid] >= target) hi = mid; else lo = mid + 1;
+        if (rpl[mid] + mid >= target) hi = mid; else lo = mid + 1;
       }
       return lo;
     };
-    // in a split step every row is finished (rows without arcs of this pass
-    // too), so the groups own whole row ranges: rows starting at the same
-    // arc go to the first group whose range reaches them
-    const int rlo = grp == 0 ? 0 : first_row_at((grp * cnt + G - 1) / G);
-    const int rhi = grp == G - 1 ? nr : first_row_at(((grp + 1) * cnt + G - 1) / G);
+    const int rlo = grp == 0 ? 0 : first_row_at((grp * tot + G - 1) / G);
+    const int rhi = grp == G - 1 ? nr : first_row_at(((grp + 1) * tot + G - 1) / G);
     for (int r = rlo; r < rhi; ++r) {
       const int pb = rpl[r], pe = rpl[r + 1];
       if (pe == pb && !hp_row) continue;

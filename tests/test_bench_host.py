@@ -55,8 +55,9 @@ def test_traffic_only_for_current_kernels():
     with open(os.path.join(ROOT, "profiles", "step_traffic.json")) as fh:
         rec = json.load(fh)
     for key, e in rec.items():
-        got = b.measured_traffic(key)
-        if e["kernel_hash"] == b.kernel_hash():
+        files = b.BATCH_SOURCES if key.endswith(":batch") else b.SINGLE_SOURCES
+        got = b.measured_traffic(key, files)
+        if e["kernel_hash"] == b.kernel_hash(files):
             assert got == e["bytes_per_launch"] and got > 0
         else:
             assert got is None

@@ -69,8 +69,8 @@ def test_batch_columns_match_oracle(torch, mid_graph, mid_oracle, bw, prec):
             assert m["max_abs"] <= 1e-13, (j, m)
             assert ex <= qs[j].tol, (j, ex, qs[j].tol)
         elif prec == "f32":
-            assert m["l1"] <= f32_bar(Ks[j]), (j, Ks[j], m)
-            assert ex <= qs[j].tol + f32_bar(Ks[j]), (j, ex, qs[j].tol)
+            assert m["l1"] <= f32_bar(Ks[j], *meta[j][:2]), (j, Ks[j], m)
+            assert ex <= qs[j].tol + f32_bar(Ks[j], *meta[j][:2]), (j, ex, qs[j].tol)
         else:  # BF16 storage: reported, about 1e-3
             assert m["l1"] <= BF16_L1, (j, m)
 
@@ -229,7 +229,7 @@ def test_hot_split_batch_matches_oracle(torch, mid_graph, monkeypatch, hot_nodes
                 if prec == "f64":
                     assert m["max_abs"] <= 1e-13, (j, m)
                 else:
-                    assert m["l1"] <= f32_bar(Ks[j]), (j, Ks[j], m)
+                    assert m["l1"] <= f32_bar(Ks[j], *meta[j][:2]), (j, Ks[j], m)
     G.close()
 
 

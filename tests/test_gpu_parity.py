@@ -5,7 +5,8 @@ Alg. 3 at the same K to 1e-12 (only summation order differs).  FP32 storage
 rounds each stored value to 2^-24 relative while the sums run in double;
 measured l1 deviations are about 6e-8 at 4M nodes and smaller on smaller
 graphs, and the tests allow F32_L1 = 1.2e-7 up to K = 30, in proportion to
-K beyond (float sums, measured 1.7e-7 at K = 17, fail it).  BF16 storage measures 1.5e-3 to 5e-3 and is held to 8e-3.  The
+K beyond, twice that for HKPR with t > 5 (float sums, measured 1.7e-7 for
+t = 5 at K = 17, fail it).  BF16 storage measures 1.5e-3 to 5e-3 and is held to 8e-3.  The
 contract against the exact vector (l1 <= tol) is checked with the certified
 K, plus the rounding bar for FP32.
 """
@@ -92,9 +93,9 @@ def test_powerlaw_tiles_and_long_rows(torch, prec, reorder):
             if prec == "f64":
                 assert m["max_abs"] <= 1e-13, m
             else:
-                assert m["l1"] <= f32_bar(r.info["K"]), m
+                assert m["l1"] <= f32_bar(r.info["K"], kind, param), m
             exact = PR.ground_truth(P, int(s), kind, param)
-            assert E.l1(y, exact) <= 1e-6 + (0 if prec == "f64" else f32_bar(r.info["K"]))
+            assert E.l1(y, exact) <= 1e-6 + (0 if prec == "f64" else f32_bar(r.info["K"], kind, param))
 
 
 def test_hub_rows_split_f64(torch):

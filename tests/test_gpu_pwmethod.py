@@ -135,7 +135,7 @@ def test_batch_mixes_algorithms(torch, prec):
         if prec == "f64":
             assert m["max_abs"] <= 1e-13, (j, method, m)
         elif method == "cheby":
-            assert m["l1"] <= f32_bar(K), (j, method, m)
+            assert m["l1"] <= f32_bar(K, kind, param), (j, method, m)
         else:
             # Alg. 1 with FP32 storage: each stored iterate (l1 norm 1) rounds to
             # 2^-24 relative, carried by the later weights: <= 2^-24 (1 - alpha) / alpha

@@ -94,8 +94,8 @@ def test_server_f32_against_oracle(torch, graph):
     for j, q in enumerate(qs):
         y = ys[j].double().cpu().numpy()
         m = compare(y, ref[:, j])
-        assert m["l1"] <= f32_bar(Ks[j]), (j, Ks[j], m)
-        assert E.l1(y, exact[:, j]) <= q.tol + f32_bar(Ks[j]), (j, q.tol)
+        assert m["l1"] <= f32_bar(Ks[j], *metas[j][:2]), (j, Ks[j], m)
+        assert E.l1(y, exact[:, j]) <= q.tol + f32_bar(Ks[j], *metas[j][:2]), (j, q.tol)
 
 
 def test_server_cancel_busy_and_budget(torch, graph):
@@ -172,7 +172,7 @@ def test_server_full_size_mixed_stream_f32(torch):
         kind = "hkpr" if q.kind == 1 else "ppr"
         r = G.power(kind, q.param, q.source, tol=q.tol, prec="f32")
         assert r.info["K"] == info["K"]
-        assert compare(y, r.y.double().cpu().numpy())["l1"] <= f32_bar(info["K"])
+        assert compare(y, r.y.double().cpu().numpy())["l1"] <= f32_bar(info["K"], kind, q.param)
     # every result against the FP64 oracle's Alg. 3 at its K; with the certified K
     # (tail_bound_l1 <= tol, pinned on the CPU) this bounds the distance to the
     # exact vector by tol + the rounding bar
@@ -182,7 +182,7 @@ def test_server_full_size_mixed_stream_f32(torch):
     for j, q in enumerate(qs):
         m = compare(ymat[j], ref[:, j])
         worst = max(worst, m["l1"])
-        assert m["l1"] <= f32_bar(infos[j]["K"]), (j, infos[j]["K"], m)
+        assert m["l1"] <= f32_bar(infos[j]["K"], *metas[j][:2]), (j, infos[j]["K"], m)
         assert infos[j]["tail_bound_l1"] <= q.tol
     print("server full size: worst FP32 l1 against Alg. 3 at the same K", worst, flush=True)
 
