@@ -177,33 +177,43 @@ def worst(rows, keys):
 # ------------------------------------------------------------------ oracle checks
 
 
-def check_same_k_and_exact(g, Yg, kinds, params, srcs, Ks, exact="pwmethod"):
+def exact_vectors(g, kinds, params, srcs, chebyshev_for_ppr=False):
+    """The converged vectors f(P) e_s as columns of an [n][B] array: the
+    plain-C PwMethod with its exact l1 tail below 1e-15, except, with
+    chebyshev_for_ppr, PPR columns (for small alpha PwMethod needs hundreds
+    of steps): the plain-C Alg. 3 with the certified K for l1 1e-12."""
+    from oracle import coefficients as C
+    from oracle import native as NO
+    from oracle import truncation as T
+
+    ex = np.empty((g.n, len(srcs)), dtype=np.float64)
+    cheb = [j for j, k in enumerate(kinds) if chebyshev_for_ppr and k == "ppr"]
+    pw = [j for j in range(len(srcs)) if j not in cheb]
+    if pw:
+        Ns = [T.pwmethod_steps(kinds[j], params[j], 1e-15) for j in pw]
+        ex[:, pw] = NO.power_method_multi(g.row_ptr, g.col_idx, [srcs[j] for j in pw],
+                                          [C.taylor_coeffs(kinds[j], params[j], N) for j, N in zip(pw, Ns)], Ns)
+    if cheb:
+        Kx = [T.choose_K("ppr", params[j], 1e-12, vol=g.nnz, d_s=int(g.degrees[srcs[j]])) for j in cheb]
+        ex[:, cheb] = NO.cheby_power_multi(g.row_ptr, g.col_idx, [srcs[j] for j in cheb],
+                                           [C.ppr_chebyshev_coeffs(params[j], K) for j, K in zip(cheb, Kx)], Kx)
+    return ex
+
+
+def check_same_k_and_exact(g, Yg, kinds, params, srcs, Ks, chebyshev_for_ppr=False):
     """Every column of Yg ([n][B], caller ids) against the FP64 oracle: Alg. 3
     at the GPU's K (the plain-C several-source form; rounding error of the
-    GPU variant) and the converged vector: l1, max-abs, the
-    degree-normalized error of Def. 5 (Normalized RelErr) and mass.  The
-    converged vector is the plain-C PwMethod with its exact l1 tail below
-    1e-15 (exact="pwmethod"), or, where PwMethod needs hundreds of steps
-    (small alpha), the plain-C Alg. 3 with the certified K for l1 1e-13
-    (exact="chebyshev").  Returns the per-column rows and the oracle's wall
-    time."""
+    GPU variant) and the converged vector (exact_vectors): l1, max-abs, the
+    degree-normalized error of Def. 5 (Normalized RelErr) and mass.  Returns
+    the per-column rows and the oracle's wall time."""
     from oracle import coefficients as C
     from oracle import errors as E
     from oracle import native as NO
-    from oracle import truncation as T
 
     t0 = time.perf_counter()
     cs = [C.chebyshev_coeffs(k, p, K) for k, p, K in zip(kinds, params, Ks)]
     ref_K = NO.cheby_power_multi(g.row_ptr, g.col_idx, srcs, cs, Ks)
-    if exact == "pwmethod":
-        Ns = [T.pwmethod_steps(k, p, 1e-15) for k, p in zip(kinds, params)]
-        ex = NO.power_method_multi(g.row_ptr, g.col_idx, srcs,
-                                   [C.taylor_coeffs(k, p, N) for (k, p, N) in zip(kinds, params, Ns)], Ns)
-    else:
-        Kx = [T.choose_K(k, p, 1e-13, vol=g.nnz, d_s=int(g.degrees[s])) for k, p, s in zip(kinds, params, srcs)]
-        ex = NO.cheby_power_multi(g.row_ptr, g.col_idx, srcs,
-                                  [C.chebyshev_coeffs(k, p, K) for k, p, K in zip(kinds, params, Kx)], Kx)
-    exact = ex
+    exact = exact_vectors(g, kinds, params, srcs, chebyshev_for_ppr)
     oracle_s = time.perf_counter() - t0
     deg = g.degrees
     rows = []
@@ -751,7 +761,7 @@ def run_serve(args, torch, cp, synth, g):
         Yh = torch.stack([bufs[k] for k in range(len(idx))], dim=1).double().cpu().numpy()
         rows, oracle_s = check_same_k_and_exact(g, Yh, [tr[i][1] for i in idx], [tr[i][2] for i in idx],
                                                 [tr[i][3] for i in idx], [info["K"] for (_, info), _ in got],
-                                                exact="chebyshev")
+                                                chebyshev_for_ppr=True)
         for r, i in zip(rows, idx):
             r["tol"] = tr[i][4]
             r["meets_tol"] = r["l1_vs_exact"] <= tr[i][4]
@@ -761,8 +771,8 @@ def run_serve(args, torch, cp, synth, g):
             "worst_l1_over_tol": max(r["l1_vs_exact"] / r["tol"] for r in rows),
             "mass_range": [min(r["mass"] for r in rows), max(r["mass"] for r in rows)],
             "method": f"{len(rows)} queries spread over the trace, rerun through the server: plain-C FP64 Alg. 3 at "
-                      f"the same K and the converged vector (plain-C Alg. 3 with the certified K for l1 1e-13), "
-                      f"{oracle_s:.1f} s"}
+                      f"the same K and the converged vector (plain-C PwMethod with tail 1e-15 for HKPR, plain-C "
+                      f"Alg. 3 with the certified K for l1 1e-12 for PPR), {oracle_s:.1f} s"}
         log(f"[serve] accuracy {out['accuracy_vs_fp64_oracle']}")
     S.close()
     G.close()

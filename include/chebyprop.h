@@ -418,11 +418,11 @@ typedef struct {
   int64_t direct;       /* queries run on the single-source path (see below) */
 } cp_server_stats;
 
-/* A query that arrives at an idle server (no query resident, none other
- * waiting) runs on the single-source path (cp_power's kernels on the
- * server's stream) instead of a batched launch, where it would pay a whole
- * tile's gathers for one source; queries that arrive meanwhile wait and are
- * batched.  Results of the two paths differ only in the order of sums.
+/* While no query is resident and at most 3 wait, the server runs the
+ * oldest waiting query on the single-source path (cp_power's kernels on the
+ * server's stream) instead of a batched launch, where a few queries would
+ * pay a whole tile's gathers; longer queues are batched.  Results of the
+ * two paths differ only in the order of sums.
  * g: the graph every query runs on; it must outlive the server.
  * hbm_budget_bytes: HBM the server may use for query state (>= one slot).
  * max_slots: upper bound on resident queries (0: as many as the budget

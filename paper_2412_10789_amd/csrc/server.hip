@@ -29,6 +29,11 @@ namespace {
 
 using Clock = std::chrono::steady_clock;
 
+// Longest queue for which an idle server runs queries one by one on the
+// single-source path (about 0.4 ms a step on a 4M-node graph, against 1.7
+// ms for a 32-wide batched step whatever number of its slots is active).
+constexpr size_t kDirectQueue = 3;
+
 size_t a256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 enum TicketState { kQueued = 0, kRunning = 1, kDone = 2, kCancelled = 3, kFailed = 4 };
@@ -130,10 +135,11 @@ void cp_server::run() {
         return false;
       });
       if (stop) break;
-      // an idle server with one query waiting runs it on the single-source
-      // path: a query alone in a batched launch would pay a whole tile's
-      // gathers for one source
-      if (queue.size() == 1 && std::all_of(slot_ticket.begin(), slot_ticket.end(), [](uint64_t t) { return !t; })) {
+      // an idle server with a short queue runs its oldest query on the
+      // single-source path: a few queries in a batched launch would pay a
+      // whole tile's gathers for a few sources
+      if (!queue.empty() && queue.size() <= kDirectQueue &&
+          std::all_of(slot_ticket.begin(), slot_ticket.end(), [](uint64_t t) { return !t; })) {
         direct_ticket = queue.front();
         queue.pop_front();
         Ticket& tk = tickets[direct_ticket];

@@ -69,3 +69,29 @@ def test_more_than_one_gpu_exits_with_a_message():
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr and r.stdout == ""
+
+
+def test_oracle_checks_run_on_mixed_queries():
+    """The bench's accuracy helpers on a small graph: the converged vectors
+    of PPR (small alpha) and HKPR (large t) queries, with either rule for
+    PPR, match each other and the certificate; checks of exact inputs report
+    errors at rounding level and the certificate bounds the PPR error."""
+    import numpy as np
+
+    import synth
+
+    b = _bench()
+    b.np = np
+    g = synth.chung_lu(5_000, 30_000, 2.3, seed=3)
+    srcs = [int(s) for s in synth.sources(g, 4, seed=4)]
+    kinds, params = ["ppr", "hkpr", "ppr", "hkpr"], [0.1, 10.0, 0.2, 3.0]
+    e1 = b.exact_vectors(g, kinds, params, srcs)
+    e2 = b.exact_vectors(g, kinds, params, srcs, chebyshev_for_ppr=True)
+    assert np.abs(e1 - e2).sum(axis=0).max() <= 1e-11
+    Ks = [40, 30, 30, 20]
+    rows, _ = b.check_same_k_and_exact(g, e1, kinds, params, srcs, Ks, chebyshev_for_ppr=True)
+    for r in rows:
+        assert r["l1_vs_exact"] <= 1e-11 and abs(r["mass"] - 1.0) <= 1e-11
+        assert r["l1_vs_same_K"] <= 1e-4  # the truncated series at these K
+    cert, _ = b.check_ppr_certificate(g, e1[:, [0, 2]], [srcs[0], srcs[2]], [0.1, 0.2])
+    assert all(c["l1_bound_vs_exact"] <= 1e-9 for c in cert)

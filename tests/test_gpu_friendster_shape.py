@@ -11,7 +11,8 @@
 2. The seeded Chung-Lu graph the benchmark's headline runs on (n = 65M
    target nodes, 1.8 billion edges, exponent 2.1, with 11,945 rows above
    16,384 arcs split over several workgroups): its 8-source PPR batch in
-   degree order and one source on the striped layout, each checked against
+   degree order with the hot/cold split, as the headline runs it, and one
+   source on the striped layout, each checked against
    Def. 3's fixed-point equation (plain-C FP64 residual / alpha, a bound on
    the l1 distance to the exact vector) and for mass, and one batch column
    against plain-C FP64 Algorithm 3 at the same K.
@@ -134,10 +135,11 @@ def test_friendster_shaped_chung_lu_batch_and_stripes(torch):
     assert g.nnz > 2**31 + 2**30
     alpha = 0.2
     srcs = [int(s) for s in synth.sources(g, 8, seed=5)]
-    _case("friendster-shaped degree-order create")
-    G = cp.Graph(g.row_ptr, g.col_idx, reorder=True)
+    _case("friendster-shaped degree-order create, hot/cold split as the benchmark's headline")
+    G = cp.Graph(g.row_ptr, g.col_idx, reorder=True, hot_split=True)
     try:
-        assert G.stats["hub_rows"] > 1000
+        assert G.stats["hub_rows"] > 1000 and G.stats["hot_nodes"] == 524_288
+        assert 0.3 < G.stats["hot_arcs"] / g.nnz < 0.5
         _case("friendster-shaped batch of 8 f32")
         Y, infos = G.power_batch([cp.make_query("ppr", alpha, s, TOL) for s in srcs], prec="f32")
         Yh = Y.double().cpu().numpy()
