@@ -639,8 +639,11 @@ def _pct(xs, p):
     return float(np.percentile(np.asarray(xs), p)) if len(xs) else None
 
 
-def _lat_summary(lat, span_s, extra=None):
-    out = {"completed": len(lat), "qps": round(len(lat) / span_s, 1) if span_s > 0 else None,
+def _lat_summary(lat, span_s, extra=None, done=None):
+    """Latency percentiles of lat (ms) and the throughput: done completions
+    (default len(lat)) over span_s seconds."""
+    done = len(lat) if done is None else done
+    out = {"completed": len(lat), "qps": round(done / span_s, 1) if span_s > 0 else None,
            "p50_ms": _pct(lat, 50), "p99_ms": _pct(lat, 99), "mean_ms": float(np.mean(lat)) if lat else None,
            "span_s": round(span_s, 3)}
     if extra:
@@ -687,22 +690,30 @@ def run_serve(args, torch, cp, synth, g):
         return tickets, time.perf_counter() - t0
 
     def server_leg(tr, rate):
-        ticks0 = S.stats()["ticks"]
+        st0 = S.stats()
         tickets, t_end = replay_server(tr)
         counted = [(info["latency_ms"], info["K"]) for (ta, *_), (st, info) in zip(tr, tickets)
                    if st == cp.CP_OK and ta >= warm]
         lat = [x for x, _ in counted]
         span = t_end - warm
+        done = sum(1 for (ta, *_), (st, info) in zip(tr, tickets)
+                   if st == cp.CP_OK and ta + info["latency_ms"] * 1e-3 >= warm)
         st = S.stats()
         return _lat_summary(lat, span, {"offered_qps": rate, "arrivals_counted": sum(1 for x in tr if x[0] >= warm),
-                                        "batched_launches": st["ticks"] - ticks0, "slots": st["slots"],
+                                        "batched_launches": st["ticks"] - st0["ticks"],
+                                        "single_source_path": st["direct"] - st0["direct"],
+                                        "single_source_queue_limit": st["direct_limit"], "slots": st["slots"],
                                         "tile_width": st["tile_width"],
-                                        "mean_K": float(np.mean([k for _, k in counted])) if counted else None})
+                                        "mean_K": float(np.mean([k for _, k in counted])) if counted else None},
+                            done=done)
 
     def plain_leg(tr, rate, limit_s):
         """FIFO, one cp_power at a time; stops once limit_s of wall time has
-        passed (the queue of an overloaded plain path only grows)."""
-        lat, t0, stopped = [], time.perf_counter(), False
+        passed (the queue of an overloaded plain path only grows).  Latency
+        counts the queries that arrive after the warm-up; throughput counts
+        every query completed after it, also those that arrived during it
+        (an overloaded queue still holds them)."""
+        lat, t0, stopped, done = [], time.perf_counter(), False, 0
         for (ta, kind, param, s, tol) in tr:
             now = time.perf_counter() - t0
             if now > limit_s:
@@ -712,8 +723,10 @@ def run_serve(args, torch, cp, synth, g):
                 time.sleep(ta - now)
             G.power(kind, param, s, tol=tol, prec="f32", y=bufs[0], stream=stream)
             torch.cuda.synchronize()
+            t_done = time.perf_counter() - t0
+            done += t_done >= warm
             if ta >= warm:
-                lat.append((time.perf_counter() - t0 - ta) * 1e3)
+                lat.append((t_done - ta) * 1e3)
         span = time.perf_counter() - t0 - warm
         extra = {"offered_qps": rate}
         if stopped:
@@ -721,7 +734,7 @@ def run_serve(args, torch, cp, synth, g):
             extra["note"] = (f"plain falls behind the offered rate, so its queue grows for as long as the trace "
                              f"runs; it was stopped after {limit_s:g} s of wall time, and its latencies are those of "
                              f"the queries completed by then")
-        return _lat_summary(lat, span, extra)
+        return _lat_summary(lat, span, extra, done=done)
 
     out = {"workload": f"Poisson arrivals, PPR alpha in {{0.1, 0.2}}, HKPR t in {{3, 5, 10}} uniformly, tol "
                        f"log-uniform [1e-7, 1e-4] (certified K), FP32 resident state, on the single-source "

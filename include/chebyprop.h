@@ -414,15 +414,19 @@ typedef struct {
   int32_t tile_width;   /* sources per tile in the step kernel */
   int32_t prec;
   int32_t waiters;      /* threads blocked in cp_server_wait */
-  int32_t pad;
+  int32_t direct_limit; /* longest queue an idle server runs one by one (see below) */
   int64_t direct;       /* queries run on the single-source path (see below) */
 } cp_server_stats;
 
-/* While no query is resident and at most 3 wait, the server runs the
- * oldest waiting query on the single-source path (cp_power's kernels on the
- * server's stream) instead of a batched launch, where a few queries would
- * pay a whole tile's gathers; longer queues are batched.  Results of the
- * two paths differ only in the order of sums.
+/* While no query is resident and at most direct_limit wait, the server runs
+ * the oldest waiting query on the single-source path (cp_power's kernels on
+ * the server's stream) instead of a batched launch, where a few queries
+ * would pay a whole tile's gathers; longer queues are batched.
+ * direct_limit starts at 3 and then follows t_b / t_s (at least 1, at most
+ * 16), from running means of the host-clock time of a one-tile batched step
+ * (t_b) and of a single-source query per Chebyshev step (t_s): q queries
+ * one by one take about q K t_s, one batched tile about K t_b.  Results of
+ * the two paths differ only in the order of sums.
  * g: the graph every query runs on; it must outlive the server.
  * hbm_budget_bytes: HBM the server may use for query state (>= one slot).
  * max_slots: upper bound on resident queries (0: as many as the budget

@@ -132,7 +132,7 @@ class cp_server_stats(ctypes.Structure):
         ("tile_width", ctypes.c_int32),
         ("prec", ctypes.c_int32),
         ("waiters", ctypes.c_int32),
-        ("pad", ctypes.c_int32),
+        ("direct_limit", ctypes.c_int32),
         ("direct", ctypes.c_int64),
     ]
 

@@ -29,10 +29,17 @@ namespace {
 
 using Clock = std::chrono::steady_clock;
 
-// Longest queue for which an idle server runs queries one by one on the
-// single-source path (about 0.4 ms a step on a 4M-node graph, against 1.7
-// ms for a 32-wide batched step whatever number of its slots is active).
+// An idle server with q waiting queries can run them one by one on the
+// single-source path, the last one done after about q K t_s, or admit them
+// all to one batched tile, all done after about K t_b (t_s, t_b: the time
+// of a single-source step and of a one-tile batched step, which costs the
+// same whatever number of its slots is active).  One by one wins while
+// q <= t_b / t_s: the worker keeps running means of both times and applies
+// that limit (4.4 on a 4M-node graph: 0.4 against 1.75 ms).  Until both are
+// measured, the limit is kDirectQueue.
 constexpr size_t kDirectQueue = 3;
+constexpr size_t kDirectQueueMax = 16;
+constexpr double kMeanWeight = 0.125;  // weight of a new sample in the running means
 
 size_t a256(size_t b) { return (b + 255) & ~(size_t)255; }
 
@@ -63,6 +70,9 @@ struct cp_server {
   size_t ws1_bytes = 0;       // workspace of the single-source path (idle-server queries)
   uint64_t direct_ticket = 0; // query running on the single-source path, 0 if none
   int64_t direct = 0;         // queries run on the single-source path
+  size_t direct_limit = kDirectQueue;  // longest queue an idle server runs one by one
+  double mean_step_ms = 0;    // single-source path, per Chebyshev step (worker thread)
+  double mean_tick_ms = 0;    // one-tile batched step launch (worker thread)
   std::vector<double> sp;  // host image of the slot parameters [kSlotParams][slots]
 
   std::mutex mu;
@@ -81,6 +91,11 @@ struct cp_server {
   std::thread worker;
 
   void run();
+  static void note_time(double& mean, double ms) { mean = mean > 0 ? mean + kMeanWeight * (ms - mean) : ms; }
+  void update_direct_limit() {  // with mu held
+    if (mean_step_ms > 0 && mean_tick_ms > 0)
+      direct_limit = std::min(kDirectQueueMax, std::max<size_t>(1, (size_t)(mean_tick_ms / mean_step_ms)));
+  }
 };
 
 namespace {
@@ -138,7 +153,7 @@ void cp_server::run() {
       // an idle server with a short queue runs its oldest query on the
       // single-source path: a few queries in a batched launch would pay a
       // whole tile's gathers for a few sources
-      if (!queue.empty() && queue.size() <= kDirectQueue &&
+      if (!queue.empty() && queue.size() <= direct_limit &&
           std::all_of(slot_ticket.begin(), slot_ticket.end(), [](uint64_t t) { return !t; })) {
         direct_ticket = queue.front();
         queue.pop_front();
@@ -151,6 +166,7 @@ void cp_server::run() {
       }
     }
     if (direct_ticket) {
+      const Clock::time_point t0 = Clock::now();
       const cp_status rc = cp_power(g, &direct_q, prec, direct_y, dev + o_ws1, ws1_bytes, st, nullptr);
       hipError_t e = rc == CP_OK ? hipStreamSynchronize(st) : (hipError_t)cp_last_hip_error();
       if (rc != CP_OK && e == hipSuccess) e = hipErrorUnknown;
@@ -158,6 +174,10 @@ void cp_server::run() {
         std::lock_guard<std::mutex> lk(mu);
         Ticket& tk = tickets[direct_ticket];
         direct_ticket = 0;
+        if (e == hipSuccess) {
+          note_time(mean_step_ms, ms_between(t0, Clock::now()) / std::max(1, tk.plan.K));
+          update_direct_limit();
+        }
         if (e != hipSuccess) {
           failed_hip = (int32_t)e;
           for (auto& kv : tickets)
@@ -245,6 +265,8 @@ void cp_server::run() {
     }
 
     // ---- GPU work for this step boundary (no lock held)
+    const Clock::time_point t0 = Clock::now();
+    int32_t step_tiles = 0;
     hipError_t e = hipSuccess;
     char* w = dev;
     void* xbuf = w + (parity ? o_rA : o_rB);  // gathered this launch (holds r~_k)
@@ -263,6 +285,7 @@ void cp_server::run() {
     if (!stepping.empty()) {
       int32_t tiles = 0;
       for (int32_t s : stepping) tiles = std::max(tiles, s / bw + 1);
+      step_tiles = tiles;
       chk(launch_upload(w + o_coef, coef_row.data(), nslot * sizeof(double), st));
       BatchStepArgs sa{};
       set_batch_plan(g, sa, w + o_part);
@@ -306,6 +329,10 @@ void cp_server::run() {
         parity ^= 1;
         ++ticks;
         for (int32_t s : stepping) ++slot_k[s];
+      }
+      if (step_tiles == 1 && admitted.empty() && fin_slots.empty()) {  // a plain one-tile step
+        note_time(mean_tick_ms, ms_between(t0, Clock::now()));
+        update_direct_limit();
       }
       const Clock::time_point now = Clock::now();
       for (size_t i = 0; i < finishing.size(); ++i) {
@@ -500,6 +527,7 @@ cp_status cp_server_get_stats(cp_server* s, cp_server_stats* out) {
   out->active = (int64_t)std::count_if(s->slot_ticket.begin(), s->slot_ticket.end(), [](uint64_t t) { return t; }) +
                 (s->direct_ticket ? 1 : 0);
   out->direct = s->direct;
+  out->direct_limit = (int32_t)s->direct_limit;
   out->queued = (int64_t)s->queue.size();
   out->completed = s->completed;
   out->cancelled = s->cancelled;
@@ -508,7 +536,6 @@ cp_status cp_server_get_stats(cp_server* s, cp_server_stats* out) {
   out->tile_width = s->bw;
   out->prec = s->prec;
   out->waiters = s->waiters;
-  out->pad = 0;
   return CP_OK;
 }
 

@@ -225,7 +225,9 @@ def test_server_destroy_releases_blocked_waiters(torch, graph):
 def test_idle_server_runs_single_source_path(torch, graph):
     """A query that reaches an idle server runs on the single-source path:
     its result is bitwise the cp_power result; a burst that arrives while it
-    runs is batched (stats: direct count, batched launches)."""
+    runs is batched (stats: direct count, batched launches); the queue limit
+    of the single-source path starts at 3 and stays within [1, 16] once
+    both paths have been timed."""
     from paper_2412_10789_amd import chebyprop as cp
 
     g = graph
@@ -236,6 +238,7 @@ def test_idle_server_runs_single_source_path(torch, graph):
     print("CASE server direct path", flush=True)
     st, info = S.wait(S.submit(qs[0], y), timeout_ms=60_000)
     assert st == cp.CP_OK and S.stats()["direct"] == 1 and S.stats()["ticks"] == 0
+    assert S.stats()["direct_limit"] == 3  # no batched step timed yet
     q = qs[0]
     r = G.power("hkpr" if q.kind == 1 else "ppr", q.param, q.source, tol=q.tol, prec="f32")
     assert torch.equal(y, r.y) and info["K"] == r.info["K"]
@@ -245,4 +248,5 @@ def test_idle_server_runs_single_source_path(torch, graph):
         assert S.wait(t, timeout_ms=60_000)[0] == cp.CP_OK
     stats = S.stats()
     assert stats["completed"] == 30 and stats["ticks"] > 0 and stats["direct"] < 30
+    assert 1 <= stats["direct_limit"] <= 16
     S.close()
