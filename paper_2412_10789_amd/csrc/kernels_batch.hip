@@ -73,22 +73,54 @@ __device__ __forceinline__ void row_update(T* z, A* y, size_t e, A acc, int32_t 
   else st_nt(y + e, bn);
 }
 
+// Gathers in flight per lane: a lane issues U gathers (then 4, then 1)
+// before it adds any of them; U = 16 in the DEEP form of the step kernel,
+// else 4 (8 in stream rows of 64-wide tiles).  A wavefront holds 64 / bw
+// lane groups, so with 4 gathers a lane a wavefront has 32 rows in flight
+// at bw = 8 but only 8 at bw = 32.  The
+// launcher takes the DEEP form for tiles of 32 or more sources on graphs
+// whose stream tiles average fewer than 64 rows (more than 32 arcs a row,
+// enough to fill 16-deep chunks): 3% faster a launch on an Orkut-sized
+// degree-ordered graph (78 arcs a row), while on a LiveJournal-sized one
+// (17.5 arcs a row) the 16-deep form was 5% slower, its larger register
+// footprint costing a wavefront per SIMD.  At bw = 8 on a Friendster-sized
+// graph it was 1% slower.
+constexpr int kDeepGathers = 16;
+constexpr int kDeepRowsPerTile = 64;
+
+// Pairwise sum of v[0..U) (a fixed order).
+template <typename A, int U>
+__device__ __forceinline__ A tree_sum(const A* v) {
+  if constexpr (U == 1) {
+    return v[0];
+  } else {
+    return tree_sum<A, U / 2>(v) + tree_sum<A, U / 2>(v + U / 2);
+  }
+}
+
 // Sum over arcs [p0, p1) of x[col[p]][lane]; the workgroup's lane groups
 // take interleaved arcs, partial sums are combined in group order.
 // Result valid in group 0.
-template <typename T, typename A, int BW>
+template <typename T, typename A, int BW, bool DEEP>
 __device__ __forceinline__ A wg_row_sum(const int32_t* __restrict__ col, const T* __restrict__ x,
                                         int64_t p0, int64_t p1, int grp, int lane, A (*part)[BW]) {
   constexpr int G = kThreads / BW;
+  constexpr int U = DEEP ? kDeepGathers : 4;
   A acc = A(0);
   int64_t p = p0 + grp;
+  if constexpr (U > 4) {
+    for (; p + (U - 1) * G < p1; p += U * G) {
+      A v[U];
+#pragma unroll
+      for (int q = 0; q < U; ++q) v[q] = to_acc(x[(size_t)col[p + q * G] * BW + lane]);
+      acc += tree_sum<A, U>(v);
+    }
+  }
   for (; p + 3 * G < p1; p += 4 * G) {
-    const int32_t c0 = col[p], c1 = col[p + G], c2 = col[p + 2 * G], c3 = col[p + 3 * G];
-    const A v0 = to_acc(x[(size_t)c0 * BW + lane]);
-    const A v1 = to_acc(x[(size_t)c1 * BW + lane]);
-    const A v2 = to_acc(x[(size_t)c2 * BW + lane]);
-    const A v3 = to_acc(x[(size_t)c3 * BW + lane]);
-    acc += (v0 + v1) + (v2 + v3);
+    A v[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) v[q] = to_acc(x[(size_t)col[p + q * G] * BW + lane]);
+    acc += tree_sum<A, 4>(v);
   }
   for (; p < p1; p += G) acc += to_acc(x[(size_t)col[p] * BW + lane]);
   part[grp][lane] = acc;
@@ -100,7 +132,7 @@ __device__ __forceinline__ A wg_row_sum(const int32_t* __restrict__ col, const T
   return total;
 }
 
-template <typename T, int BW>
+template <typename T, int BW, bool DEEP>
 __global__ void __launch_bounds__(kThreads) batch_step_kernel(BatchStepArgs a) {
   using A = typename Acc<T>::type;
   constexpr int G = kThreads / BW;
@@ -168,23 +200,21 @@ __global__ void __launch_bounds__(kThreads) batch_step_kernel(BatchStepArgs a) {
       if (pe == pb && !hp_row) continue;
       A acc = A(0);
       int p = pb;
-      if constexpr (BW >= 64) {
-        // one lane group per wavefront: eight gathers per lane keep about
-        // as many cache lines in flight per wavefront as the two groups of a
-        // 32-wide tile do with four
-        for (; p + 8 <= pe; p += 8) {
-          A v[8];
+      // shallow form with one lane group per wavefront (bw 64): chunks of 8
+      constexpr int U = DEEP ? kDeepGathers : BW >= 64 ? 8 : 4;
+      if constexpr (U > 4) {
+        for (; p + U <= pe; p += U) {
+          A v[U];
 #pragma unroll
-          for (int q = 0; q < 8; ++q) v[q] = to_acc(x[(size_t)cols[p + q] * BW + lane]);
-          acc += ((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7]));
+          for (int q = 0; q < U; ++q) v[q] = to_acc(x[(size_t)cols[p + q] * BW + lane]);
+          acc += tree_sum<A, U>(v);
         }
       }
       for (; p + 4 <= pe; p += 4) {
-        const A v0 = to_acc(x[(size_t)cols[p] * BW + lane]);
-        const A v1 = to_acc(x[(size_t)cols[p + 1] * BW + lane]);
-        const A v2 = to_acc(x[(size_t)cols[p + 2] * BW + lane]);
-        const A v3 = to_acc(x[(size_t)cols[p + 3] * BW + lane]);
-        acc += (v0 + v1) + (v2 + v3);
+        A v[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) v[q] = to_acc(x[(size_t)cols[p + q] * BW + lane]);
+        acc += tree_sum<A, 4>(v);
       }
       for (; p < pe; ++p) acc += to_acc(x[(size_t)cols[p] * BW + lane]);
       finish_row(r0 + r, acc, a.deg_rp ? dgl[r] : pe - pb);
@@ -195,7 +225,7 @@ __global__ void __launch_bounds__(kThreads) batch_step_kernel(BatchStepArgs a) {
   if (bd.kind == kLong) {
     const int64_t v = bd.r0;
     const int64_t p0 = rp[v], p1 = rp[v + 1];
-    const A total = wg_row_sum<T, A, BW>(col, x, p0, p1, grp, lane, part);
+    const A total = wg_row_sum<T, A, BW, DEEP>(col, x, p0, p1, grp, lane, part);
     if (grp == 0) finish_row(v, total, (int32_t)(drp[v + 1] - drp[v]));
     return;
   }
@@ -205,7 +235,7 @@ __global__ void __launch_bounds__(kThreads) batch_step_kernel(BatchStepArgs a) {
   const int64_t rb = rp[h.row], re = rp[h.row + 1];
   const int64_t p0 = rb + (int64_t)bd.aux * h.seg;
   const int64_t p1 = p0 + h.seg < re ? p0 + h.seg : re;
-  const A total = wg_row_sum<T, A, BW>(col, x, p0, p1, grp, lane, part);
+  const A total = wg_row_sum<T, A, BW, DEEP>(col, x, p0, p1, grp, lane, part);
   A* hp = static_cast<A*>(a.hub_partial);
   const int slot = tile * BW + lane;
   if (grp == 0) {
@@ -348,11 +378,21 @@ __global__ void upload_kernel(UploadArgs a) {
 template <typename T>
 hipError_t launch_bs(const BatchStepArgs& a, hipStream_t st) {
   dim3 grid((unsigned)a.nblocks, (unsigned)a.ntiles), block(kThreads);
+  // stream tiles hold at most kTileNnz arcs, so fewer than kDeepRowsPerTile
+  // rows a tile on average means rows of more than kTileNnz / kDeepRowsPerTile arcs
+  const int64_t nstream = a.nblocks - a.nspecial;
+  const bool deep = nstream > 0 && a.n < kDeepRowsPerTile * nstream;
   switch (a.bw) {
-    case 8: hipLaunchKernelGGL((batch_step_kernel<T, 8>), grid, block, 0, st, a); break;
-    case 16: hipLaunchKernelGGL((batch_step_kernel<T, 16>), grid, block, 0, st, a); break;
-    case 32: hipLaunchKernelGGL((batch_step_kernel<T, 32>), grid, block, 0, st, a); break;
-    case 64: hipLaunchKernelGGL((batch_step_kernel<T, 64>), grid, block, 0, st, a); break;
+    case 8: hipLaunchKernelGGL((batch_step_kernel<T, 8, false>), grid, block, 0, st, a); break;
+    case 16: hipLaunchKernelGGL((batch_step_kernel<T, 16, false>), grid, block, 0, st, a); break;
+    case 32:
+      if (deep) hipLaunchKernelGGL((batch_step_kernel<T, 32, true>), grid, block, 0, st, a);
+      else hipLaunchKernelGGL((batch_step_kernel<T, 32, false>), grid, block, 0, st, a);
+      break;
+    case 64:
+      if (deep) hipLaunchKernelGGL((batch_step_kernel<T, 64, true>), grid, block, 0, st, a);
+      else hipLaunchKernelGGL((batch_step_kernel<T, 64, false>), grid, block, 0, st, a);
+      break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -115,6 +115,41 @@ def test_batch_hub_split(torch):
             assert compare(Y[:, j], ref)["max_abs"] <= 1e-11
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_deep_gathers_long_rows_and_hubs(torch, prec):
+    """Tiles of 32 and 64 sources on a graph of 80 arcs a row take the
+    16-deep gather form of the step kernel (stream rows, long rows and the
+    segments of a 20,000-arc hub); every column against Alg. 3 in FP64 at
+    its K."""
+    base = synth.chung_lu(30_000, 1_200_000, 1.9, seed=5)
+    n0 = base.n
+    rows = np.repeat(np.arange(n0), base.degrees)
+    e = [(int(a), int(b)) for a, b in zip(rows, base.col_idx) if a < b]
+    e += [(n0, i) for i in range(20_000)]
+    g = synth.from_edges(n0 + 1, e, name="dense-hub")
+    assert g.nnz / g.n > 32 and int(g.degrees.max()) == 20_000
+    P = PR.transition_matrix(g.row_ptr, g.col_idx)
+    G = gpu_graph(g)
+    from paper_2412_10789_amd import chebyprop as cp
+
+    srcs = [n0, 0, 1, 7] + [int(s) for s in synth.sources(g, 36, seed=8)]
+    kinds = [("ppr", 0.2), ("hkpr", 5.0), ("ppr", 0.1), ("hkpr", 3.0)]
+    qs = [cp.make_query(*kinds[i % 4], s, 1e-7) for i, s in enumerate(srcs)]
+    for bw in (32, 64):
+        G.set_batch_width(len(qs), prec, bw)
+        print("CASE deep gathers", prec, bw, flush=True)
+        Y, infos = G.power_batch(qs, prec=prec)
+        Y = Y.double().cpu().numpy()
+        for j, q in enumerate(qs):
+            kind = "hkpr" if q.kind == 1 else "ppr"
+            ref = oracle_yK(g, q.source, kind, q.param, infos[j]["K"], P)
+            m = compare(Y[:, j], ref)
+            if prec == "f64":
+                assert m["max_abs"] <= 1e-11, (bw, j, m)
+            else:
+                assert m["l1"] <= f32_bar(infos[j]["K"], kind, q.param), (bw, j, m)
+
+
 def test_batch_edge_cases(torch):
     from paper_2412_10789_amd import chebyprop as cp
 
