@@ -63,9 +63,9 @@ BATCH_WORKLOADS = {
     "ppr-batch-small": (200_000, 4_000_000, 2.2, 3, 0.2, 64, (1e-4, 1e-6, 1e-7), "f32"),
 }
 
-STORAGE_BYTES = {"f64": 8, "f32": 4, "bf16": 2}
-ACC_BYTES = {"f64": 8, "f32": 8, "bf16": 4}  # estimate as the kernels keep it (FP32 storage: double estimate)
-ARITH_DTYPE = {"f64": "f64", "f32": "f64", "bf16": "f32"}  # what the kernels add and multiply in
+STORAGE_BYTES = {"f64": 8, "f32": 4, "f32f": 4, "bf16": 2}
+ACC_BYTES = {"f64": 8, "f32": 8, "f32f": 4, "bf16": 4}  # estimate as the kernels keep it (f32: double estimate)
+ARITH_DTYPE = {"f64": "f64", "f32": "f64", "f32f": "f32", "bf16": "f32"}  # what the kernels add and multiply in
 
 
 def log(*a):
@@ -200,20 +200,24 @@ def exact_vectors(g, kinds, params, srcs, chebyshev_for_ppr=False):
     return ex
 
 
-def check_same_k_and_exact(g, Yg, kinds, params, srcs, Ks, chebyshev_for_ppr=False):
+def check_same_k_and_exact(g, Yg, kinds, params, srcs, Ks, chebyshev_for_ppr=False, refs=None):
     """Every column of Yg ([n][B], caller ids) against the FP64 oracle: Alg. 3
     at the GPU's K (the plain-C several-source form; rounding error of the
     GPU variant) and the converged vector (exact_vectors): l1, max-abs, the
-    degree-normalized error of Def. 5 (Normalized RelErr) and mass.  Returns
-    the per-column rows and the oracle's wall time."""
+    degree-normalized error of Def. 5 (Normalized RelErr) and mass.  refs, a
+    dict, keeps the oracle's two sets of vectors for later calls on the same
+    queries.  Returns the per-column rows and the oracle's wall time."""
     from oracle import coefficients as C
     from oracle import errors as E
     from oracle import native as NO
 
     t0 = time.perf_counter()
-    cs = [C.chebyshev_coeffs(k, p, K) for k, p, K in zip(kinds, params, Ks)]
-    ref_K = NO.cheby_power_multi(g.row_ptr, g.col_idx, srcs, cs, Ks)
-    exact = exact_vectors(g, kinds, params, srcs, chebyshev_for_ppr)
+    refs = {} if refs is None else refs
+    if "ref_K" not in refs:
+        cs = [C.chebyshev_coeffs(k, p, K) for k, p, K in zip(kinds, params, Ks)]
+        refs["ref_K"] = NO.cheby_power_multi(g.row_ptr, g.col_idx, srcs, cs, Ks)
+        refs["exact"] = exact_vectors(g, kinds, params, srcs, chebyshev_for_ppr)
+    ref_K, exact = refs["ref_K"], refs["exact"]
     oracle_s = time.perf_counter() - t0
     deg = g.degrees
     rows = []
@@ -335,7 +339,7 @@ def run_headline(args, torch, cp, synth):
     results = {"f32": _host(Y)}
     if not args.no_bf16:
         Yb = torch.empty((g.n, nq), dtype=torch.float32, device="cuda")
-        Rb = timed("bf16", Yb, 1, args.bf16_steps)
+        Rb = timed("bf16", Yb, 0, args.bf16_steps)
         if Rb["Ks"] != R["Ks"]:
             raise RuntimeError("BF16 batch took other K than the FP32 one")
         out["storage_bf16"] = {
@@ -345,6 +349,20 @@ def run_headline(args, torch, cp, synth):
             "roofline": roofline(Rb["bytes_per_launch"], Rb["avg_launch_ms"], f"batch_step_kernel (width {bw})")}
         results["bf16"] = _host(Yb)
         del Yb
+    if not args.no_f32f:
+        Yf = torch.empty((g.n, nq), dtype=torch.float32, device="cuda")
+        Rf = timed("f32f", Yf, 0, args.bf16_steps)
+        if Rf["Ks"] != R["Ks"]:
+            raise RuntimeError("FP32-arithmetic batch took other K than the FP32 one")
+        out["arith_f32"] = {
+            "workload": "the same batch with FP32 storage and FP32 arithmetic (float sums, float estimate and "
+                        "float hot-pass partials; CP_F32F)",
+            "value": round(Rf["arcs"] / Rf["total_s"] / 1e9, 3), "unit": "GTEPS",
+            "ms_per_batch": round(Rf["total_s"] * 1e3 / args.bf16_steps, 2), "steps": args.bf16_steps,
+            "roofline": roofline(Rf["bytes_per_launch"], Rf["avg_launch_ms"], f"batch_step_kernel (width {bw})",
+                                 implementation_bytes_per_launch=int(Rf["impl_bytes_per_launch"]))}
+        results["f32f"] = _host(Yf)
+        del Yf
     del Y
     G.close()
     torch.cuda.empty_cache()
@@ -365,8 +383,7 @@ def run_headline(args, torch, cp, synth):
         acc["method"] = (f"plain-C FP64 residual of Def. 3's fixed point, ||alpha e_s + (1-alpha) P y - y||_1 / "
                          f"alpha, for every result ({cert_s:.1f} s for {Yall.shape[1]} columns)")
         out["accuracy_vs_fp64_oracle"] = acc
-        log(f"[headline] accuracy: f32 worst {acc['f32']['worst']}"
-            + (f", bf16 worst {acc['bf16']['worst']}" if "bf16" in acc else ""))
+        log("[headline] accuracy: " + ", ".join(f"{k} worst {acc[k]['worst']}" for k in names))
         del Yall, results
         # CPU baseline: the oracle's several-source Alg. 3 on the same batch, init and one full step
         c2 = [C.ppr_chebyshev_coeffs(alpha, 2)] * nq
@@ -465,15 +482,30 @@ def run_single(args, torch, cp, synth):
             "roofline": roofline(step_bytes(g.n, g.nnz, "bf16"), B["avg_step_ms"], kern)}
         results["bf16"] = Yb.double().cpu().numpy().T
         del Yb
+    if not args.no_f32f:
+        # the same queries with FP32 arithmetic (float sums, float partials and estimate)
+        Yf = torch.empty((nsrc, g.n), dtype=torch.float32, device="cuda")
+        F = timed_run("f32f", Yf, 1)
+        if F["Ks"] != R["Ks"]:
+            raise RuntimeError("FP32-arithmetic query took another K than the FP32 one")
+        out["arith_f32"] = {
+            "workload": "the same queries (graph, sources, steps, layout) with FP32 storage and FP32 arithmetic: "
+                        "float sums, float stripe partials and a float estimate (CP_F32F)",
+            "value": round(F["value"], 3), "unit": "GTEPS", "ms_per_step": round(F["total_s"] * 1e3 / steps, 3),
+            "roofline": roofline(step_bytes(g.n, g.nnz, "f32f"), F["avg_step_ms"], kern,
+                                 implementation_bytes_per_launch=impl_step_bytes(g.n, g.nnz, "f32f"))}
+        results["f32f"] = Yf.double().cpu().numpy().T
+        del Yf
     G.close()
     del Y
     if not args.no_cpu:
         from oracle import coefficients as C
         from oracle import native as NO
 
-        acc = {}
+        acc, refs = {}, {}
         for p, Yh in results.items():
-            rows, oracle_s = check_same_k_and_exact(g, Yh, [kind] * nsrc, [param] * nsrc, srcs, R["Ks"])
+            rows, oracle_s = check_same_k_and_exact(g, Yh, [kind] * nsrc, [param] * nsrc, srcs, R["Ks"],
+                                                    refs=refs)
             acc[p] = {"results": len(rows),
                       "worst": worst(rows, ["l1_vs_same_K", "max_abs_vs_same_K", "l1_vs_exact", "max_abs_vs_exact",
                                             "norm_rel_err_vs_exact"]),
@@ -1141,6 +1173,8 @@ def main() -> int:
     ap.add_argument("--no-push-rw", action="store_true", help="skip the ChebyPush + random walk measurement")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle legs")
     ap.add_argument("--no-bf16", action="store_true", help="skip the BF16-storage variants")
+    ap.add_argument("--no-f32f", action="store_true",
+                    help="skip the FP32-arithmetic variants (CP_F32F) of the headline and single-source legs")
     ap.add_argument("--no-latency", action="store_true",
                     help="skip the small-graph latency measurement (eager vs HIP graph replay)")
     ap.add_argument("--gather-footprint", action="store_true",
@@ -1214,7 +1248,7 @@ def main() -> int:
         "launch_bytes_rule": H["launch_bytes_rule"],
         "copy_ceiling_gbps": round(copy_gbps, 1),
     }
-    for k in ("cpu_baseline", "accuracy_vs_fp64_oracle", "storage_bf16"):
+    for k in ("cpu_baseline", "accuracy_vs_fp64_oracle", "storage_bf16", "arith_f32"):
         if k in H:
             result[k] = H[k]
     del H

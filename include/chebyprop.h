@@ -57,10 +57,14 @@ typedef enum { CP_PPR = 0, CP_HKPR = 1 } cp_kind;
  * the arithmetic.  CP_F64: double storage and arithmetic.  CP_F32: float
  * storage of the recurrence vectors, double arithmetic (gather sums, update)
  * and a double estimate; l1 rounding error is a few 1e-8 on million-node
- * power-law graphs.  CP_BF16: bfloat16 storage, float arithmetic and
- * estimate (l1 error around 1e-3).  Output y is double for CP_F64 and float
- * otherwise. */
-typedef enum { CP_F64 = 0, CP_F32 = 1, CP_BF16 = 2 } cp_prec;
+ * power-law graphs.  CP_F32F: float storage and float arithmetic, with the
+ * estimate and the partial sums in float too (fewer bytes per step than
+ * CP_F32); l1 rounding error about 1e-7 to 3e-7 on million-node graphs, so
+ * it suits tolerances from about 3e-7 up.  CP_BF16: bfloat16 storage,
+ * float arithmetic and estimate (l1 error around 1e-3).  Output y is double
+ * for CP_F64 and float otherwise.  Coefficients, K and the estimate's
+ * final scaling are computed in double in every precision. */
+typedef enum { CP_F64 = 0, CP_F32 = 1, CP_BF16 = 2, CP_F32F = 3 } cp_prec;
 
 /* How K is chosen for a tolerance `tol` (Thm. 2 and its l1 reading):
  *  CP_K_CERTIFIED: smallest K >= 1 with sqrt(vol(G)/d_s) * tail(K) <= tol,
@@ -266,7 +270,7 @@ cp_status cp_power(const cp_graph* g, const cp_query* q, int32_t prec, void* y, 
  * Results are bitwise those of cp_power.
  * Errors: those of cp_power; CP_EWORKSPACE when the query's workspace
  * exceeds CP_NOALLOC_SCRATCH_BYTES: two recurrence vectors of n storage
- * elements, an n-element estimate (double; float for CP_BF16), S n more
+ * elements, an n-element estimate (double; float for CP_F32F and CP_BF16), S n more
  * estimate-width partials on a graph with S XCD stripes, and a few KiB of
  * counters (FP32: 16 n bytes, about 4M nodes, or 16 n + 8 S n with
  * stripes); CP_EINVAL for CP_Q_TIMING (its events would be created per

@@ -34,7 +34,7 @@ CP_EPENDING = -11
 CP_EWORKSPACE = -12
 
 CP_PPR, CP_HKPR = 0, 1
-CP_F64, CP_F32, CP_BF16 = 0, 1, 2
+CP_F64, CP_F32, CP_BF16, CP_F32F = 0, 1, 2, 3
 CP_K_CERTIFIED, CP_K_TAIL, CP_K_PAPER, CP_K_FIXED = 0, 1, 2, 3
 CP_GRAPH_BORROW, CP_GRAPH_VALIDATE, CP_GRAPH_REORDER, CP_GRAPH_HOST = 0x1, 0x2, 0x4, 0x8
 CP_GRAPH_HOT_SPLIT = 0x20
@@ -43,7 +43,7 @@ CP_Q_STATS, CP_Q_TIMING, CP_Q_PWMETHOD, CP_Q_CLENSHAW = 0x1, 0x2, 0x4, 0x8
 CP_NOALLOC_SCRATCH_BYTES = 64 << 20  # the static device array cp_power_noalloc works in
 
 KINDS = {"ppr": CP_PPR, "hkpr": CP_HKPR}
-PRECS = {"f64": CP_F64, "f32": CP_F32, "bf16": CP_BF16}
+PRECS = {"f64": CP_F64, "f32": CP_F32, "f32f": CP_F32F, "bf16": CP_BF16}
 KMODES = {"certified": CP_K_CERTIFIED, "tail": CP_K_TAIL, "paper": CP_K_PAPER, "fixed": CP_K_FIXED}
 # Alg. 3 (ChebyPower), Alg. 1 (PwMethod), Alg. 3's series by Clenshaw's
 # recurrence (cp_propagate only)

@@ -34,9 +34,9 @@ namespace {
 
 size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
-size_t storage_bytes(int32_t prec) { return prec == CP_F64 ? 8 : prec == CP_F32 ? 4 : 2; }
-size_t acc_bytes(int32_t prec) { return prec == CP_BF16 ? 4 : 8; }
-bool valid_prec(int32_t prec) { return prec == CP_F64 || prec == CP_F32 || prec == CP_BF16; }
+size_t storage_bytes(int32_t prec) { return prec == CP_F64 ? 8 : prec == CP_BF16 ? 2 : 4; }
+size_t acc_bytes(int32_t prec) { return prec == CP_F64 || prec == CP_F32 ? 8 : 4; }
+bool valid_prec(int32_t prec) { return prec == CP_F64 || prec == CP_F32 || prec == CP_F32F || prec == CP_BF16; }
 
 int host_threads() {
   unsigned h = std::thread::hardware_concurrency();

@@ -2,8 +2,9 @@
 //
 // Precision: CP_F64 stores and computes in double; CP_F32 stores the
 // recurrence vectors in float (the gathered bytes) but sums, updates and
-// accumulates the estimate in double; CP_BF16 stores bfloat16 and computes
-// in float.
+// accumulates the estimate in double; CP_F32F stores float and sums,
+// updates and accumulates in float (estimate and partial sums in float
+// too); CP_BF16 stores bfloat16 and computes in float.
 //
 // Vectors live in the D^{-1} basis: x = D^{-1} r_k, z = D^{-1} r_{k-1},
 // yacc = D^{-1} y.  Then (P r_k)(v) = sum_{u in N(v)} r_k(u)/d_u is a pure
@@ -29,19 +30,25 @@ namespace {
 struct bf16 {
   uint16_t bits;
 };
+struct f32f {  // CP_F32F storage: a float whose arithmetic stays in float
+  float v;
+};
 
 template <typename T> struct Acc;
 template <> struct Acc<double> { using type = double; };
 template <> struct Acc<float> { using type = double; };  // FP32 storage, FP64 arithmetic
+template <> struct Acc<f32f> { using type = float; };    // FP32 storage, FP32 arithmetic
 template <> struct Acc<bf16> { using type = float; };
 
 __device__ __forceinline__ double to_acc(double v) { return v; }
 __device__ __forceinline__ float to_acc(float v) { return v; }
+__device__ __forceinline__ float to_acc(f32f v) { return v.v; }
 __device__ __forceinline__ float to_acc(bf16 v) { return __uint_as_float((uint32_t)v.bits << 16); }
 
 template <typename T> __device__ __forceinline__ T from_acc(typename Acc<T>::type v);
 template <> __device__ __forceinline__ double from_acc<double>(double v) { return v; }
 template <> __device__ __forceinline__ float from_acc<float>(double v) { return (float)v; }
+template <> __device__ __forceinline__ f32f from_acc<f32f>(float v) { return f32f{v}; }
 // float -> bfloat16, round to nearest even (finite inputs)
 template <> __device__ __forceinline__ bf16 from_acc<bf16>(float v) {
   uint32_t u = __float_as_uint(v);
@@ -55,11 +62,17 @@ template <typename T> __device__ __forceinline__ T ld_stream(const T* p) {
 template <> __device__ __forceinline__ bf16 ld_stream<bf16>(const bf16* p) {
   return bf16{__builtin_nontemporal_load(&p->bits)};
 }
+template <> __device__ __forceinline__ f32f ld_stream<f32f>(const f32f* p) {
+  return f32f{__builtin_nontemporal_load(&p->v)};
+}
 template <typename T> __device__ __forceinline__ void st_stream(T* p, T v) {
   __builtin_nontemporal_store(v, p);
 }
 template <> __device__ __forceinline__ void st_stream<bf16>(bf16* p, bf16 v) {
   __builtin_nontemporal_store(v.bits, &p->bits);
+}
+template <> __device__ __forceinline__ void st_stream<f32f>(f32f* p, f32f v) {
+  __builtin_nontemporal_store(v.v, &p->v);
 }
 
 template <typename A> __device__ __forceinline__ A wave_sum(A v) {
@@ -305,6 +318,7 @@ __global__ void __launch_bounds__(kThreads) step_kernel(StepArgs a) {
 // LDS copy of gathered values: the stored precision (exact), float for bf16.
 template <typename T> struct Lds { using type = T; };
 template <> struct Lds<bf16> { using type = float; };
+template <> struct Lds<f32f> { using type = float; };
 
 // One (row tile, stripe) block of an XCD-striped step: partial row sums of
 // the tile's rows over the stripe's columns.  Workgroup w handles tile
@@ -458,6 +472,7 @@ hipError_t launch_step_t(int32_t prec, const StepArgs& a, hipStream_t st) {
   switch (prec) {
     case CP_F64: hipLaunchKernelGGL((step_kernel<double, MODE>), grid, block, 0, st, a); break;
     case CP_F32: hipLaunchKernelGGL((step_kernel<float, MODE>), grid, block, 0, st, a); break;
+    case CP_F32F: hipLaunchKernelGGL((step_kernel<f32f, MODE>), grid, block, 0, st, a); break;
     case CP_BF16: hipLaunchKernelGGL((step_kernel<bf16, MODE>), grid, block, 0, st, a); break;
     default: return hipErrorInvalidValue;
   }
@@ -486,6 +501,8 @@ hipError_t launch_stripe_gather(int32_t prec, const StripeArgs& a, hipStream_t s
     case CP_F64 * 2 + 1: hipLaunchKernelGGL((stripe_gather_kernel<double, true>), grid, block, 0, st, a); break;
     case CP_F32 * 2: hipLaunchKernelGGL((stripe_gather_kernel<float, false>), grid, block, 0, st, a); break;
     case CP_F32 * 2 + 1: hipLaunchKernelGGL((stripe_gather_kernel<float, true>), grid, block, 0, st, a); break;
+    case CP_F32F * 2: hipLaunchKernelGGL((stripe_gather_kernel<f32f, false>), grid, block, 0, st, a); break;
+    case CP_F32F * 2 + 1: hipLaunchKernelGGL((stripe_gather_kernel<f32f, true>), grid, block, 0, st, a); break;
     case CP_BF16 * 2: hipLaunchKernelGGL((stripe_gather_kernel<bf16, false>), grid, block, 0, st, a); break;
     case CP_BF16 * 2 + 1: hipLaunchKernelGGL((stripe_gather_kernel<bf16, true>), grid, block, 0, st, a); break;
     default: return hipErrorInvalidValue;
@@ -504,6 +521,10 @@ hipError_t launch_stripe_combine_t(int32_t prec, const CombineArgs& a, hipStream
     case CP_F32:
       if constexpr (MODE == kStepAdd) return hipErrorInvalidValue;
       else hipLaunchKernelGGL((stripe_combine_kernel<float, MODE>), grid, block, 0, st, a);
+      break;
+    case CP_F32F:
+      if constexpr (MODE == kStepAdd) return hipErrorInvalidValue;
+      else hipLaunchKernelGGL((stripe_combine_kernel<f32f, MODE>), grid, block, 0, st, a);
       break;
     case CP_BF16:
       if constexpr (MODE == kStepAdd) return hipErrorInvalidValue;
@@ -538,6 +559,7 @@ hipError_t launch_init(int32_t prec, const InitArgs& a, hipStream_t st) {
   switch (prec) {
     case CP_F64: hipLaunchKernelGGL(init_kernel<double>, dim3(1), dim3(kThreads), 0, st, a); break;
     case CP_F32: hipLaunchKernelGGL(init_kernel<float>, dim3(1), dim3(kThreads), 0, st, a); break;
+    case CP_F32F: hipLaunchKernelGGL(init_kernel<f32f>, dim3(1), dim3(kThreads), 0, st, a); break;
     case CP_BF16: hipLaunchKernelGGL(init_kernel<bf16>, dim3(1), dim3(kThreads), 0, st, a); break;
     default: return hipErrorInvalidValue;
   }
@@ -550,7 +572,7 @@ hipError_t launch_finalize(int32_t prec, const FinalArgs& a, hipStream_t st) {
     hipLaunchKernelGGL((finalize_kernel<double, double>), dim3(kFinalBlocks), dim3(kThreads), 0, st, a, block_sums);
   else if (prec == CP_F32)
     hipLaunchKernelGGL((finalize_kernel<double, float>), dim3(kFinalBlocks), dim3(kThreads), 0, st, a, block_sums);
-  else
+  else  // float estimate: CP_F32F, CP_BF16
     hipLaunchKernelGGL((finalize_kernel<float, float>), dim3(kFinalBlocks), dim3(kThreads), 0, st, a, block_sums);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || !a.mass) return e;

@@ -18,10 +18,14 @@ namespace {
 struct bf16 {
   uint16_t bits;
 };
+struct f32f {  // CP_F32F storage: a float whose arithmetic stays in float
+  float v;
+};
 
 template <typename T> struct Acc;
 template <> struct Acc<double> { using type = double; };
 template <> struct Acc<float> { using type = double; };  // FP32 storage, FP64 arithmetic
+template <> struct Acc<f32f> { using type = float; };    // FP32 storage, FP32 arithmetic
 
 template <typename T> struct Out { using type = float; };  // result type handed to the caller
 template <> struct Out<double> { using type = double; };
@@ -29,11 +33,13 @@ template <> struct Acc<bf16> { using type = float; };
 
 __device__ __forceinline__ double to_acc(double v) { return v; }
 __device__ __forceinline__ float to_acc(float v) { return v; }
+__device__ __forceinline__ float to_acc(f32f v) { return v.v; }
 __device__ __forceinline__ float to_acc(bf16 v) { return __uint_as_float((uint32_t)v.bits << 16); }
 
 template <typename T> __device__ __forceinline__ T from_acc(typename Acc<T>::type v);
 template <> __device__ __forceinline__ double from_acc<double>(double v) { return v; }
 template <> __device__ __forceinline__ float from_acc<float>(double v) { return (float)v; }
+template <> __device__ __forceinline__ f32f from_acc<f32f>(float v) { return f32f{v}; }
 template <> __device__ __forceinline__ bf16 from_acc<bf16>(float v) {
   uint32_t u = __float_as_uint(v);
   u += 0x7FFFu + ((u >> 16) & 1u);
@@ -44,9 +50,15 @@ template <typename T> __device__ __forceinline__ T ld_nt(const T* p) { return __
 template <> __device__ __forceinline__ bf16 ld_nt<bf16>(const bf16* p) {
   return bf16{__builtin_nontemporal_load(&p->bits)};
 }
+template <> __device__ __forceinline__ f32f ld_nt<f32f>(const f32f* p) {
+  return f32f{__builtin_nontemporal_load(&p->v)};
+}
 template <typename T> __device__ __forceinline__ void st_nt(T* p, T v) { __builtin_nontemporal_store(v, p); }
 template <> __device__ __forceinline__ void st_nt<bf16>(bf16* p, bf16 v) {
   __builtin_nontemporal_store(v.bits, &p->bits);
+}
+template <> __device__ __forceinline__ void st_nt<f32f>(f32f* p, f32f v) {
+  __builtin_nontemporal_store(v.v, &p->v);
 }
 
 __device__ __forceinline__ int64_t logical_block(int64_t w, int64_t nblocks, int64_t nspecial) {
@@ -407,6 +419,7 @@ hipError_t launch_bs_prec(int32_t prec, const BatchStepArgs& a, hipStream_t st) 
   switch (prec) {
     case CP_F64: return launch_bs<double>(a, st);
     case CP_F32: return launch_bs<float>(a, st);
+    case CP_F32F: return launch_bs<f32f>(a, st);
     case CP_BF16: return launch_bs<bf16>(a, st);
     default: return hipErrorInvalidValue;
   }
@@ -452,6 +465,7 @@ hipError_t launch_batch_init(int32_t prec, const BatchInitArgs& a, int32_t nslot
   switch (prec) {
     case CP_F64: hipLaunchKernelGGL(batch_init_kernel<double>, grid, block, 0, st, a); break;
     case CP_F32: hipLaunchKernelGGL(batch_init_kernel<float>, grid, block, 0, st, a); break;
+    case CP_F32F: hipLaunchKernelGGL(batch_init_kernel<f32f>, grid, block, 0, st, a); break;
     case CP_BF16: hipLaunchKernelGGL(batch_init_kernel<bf16>, grid, block, 0, st, a); break;
     default: return hipErrorInvalidValue;
   }
@@ -472,6 +486,7 @@ hipError_t launch_dense_init(int32_t prec, const DenseInitArgs& a, hipStream_t s
   switch (prec) {
     case CP_F64: hipLaunchKernelGGL(dense_init_kernel<double>, grid, block, 0, st, a); break;
     case CP_F32: hipLaunchKernelGGL(dense_init_kernel<float>, grid, block, 0, st, a); break;
+    case CP_F32F: hipLaunchKernelGGL(dense_init_kernel<f32f>, grid, block, 0, st, a); break;
     case CP_BF16: hipLaunchKernelGGL(dense_init_kernel<bf16>, grid, block, 0, st, a); break;
     default: return hipErrorInvalidValue;
   }
@@ -484,6 +499,7 @@ hipError_t launch_slot_finish(int32_t prec, const SlotFinishArgs& a, int32_t cou
   switch (prec) {
     case CP_F64: hipLaunchKernelGGL(slot_finish_kernel<double>, grid, block, 0, st, a); break;
     case CP_F32: hipLaunchKernelGGL(slot_finish_kernel<float>, grid, block, 0, st, a); break;
+    case CP_F32F: hipLaunchKernelGGL(slot_finish_kernel<f32f>, grid, block, 0, st, a); break;
     case CP_BF16: hipLaunchKernelGGL(slot_finish_kernel<bf16>, grid, block, 0, st, a); break;
     default: return hipErrorInvalidValue;
   }

@@ -100,8 +100,8 @@ struct cp_server {
 
 namespace {
 
-size_t storage_bytes(int32_t prec) { return prec == CP_F64 ? 8 : prec == CP_F32 ? 4 : 2; }
-size_t acc_bytes(int32_t prec) { return prec == CP_BF16 ? 4 : 8; }
+size_t storage_bytes(int32_t prec) { return prec == CP_F64 ? 8 : prec == CP_BF16 ? 2 : 4; }
+size_t acc_bytes(int32_t prec) { return prec == CP_F64 || prec == CP_F32 ? 8 : 4; }
 
 double ms_between(Clock::time_point a, Clock::time_point b) {
   return std::chrono::duration<double, std::milli>(b - a).count();
@@ -354,7 +354,7 @@ extern "C" {
 
 cp_status cp_server_create(const cp_graph* g, size_t hbm_budget_bytes, int32_t max_slots, int32_t max_queue,
                            int32_t prec, cp_server** out) {
-  if (!g || !out || max_queue < 0 || max_slots < 0 || !(prec == CP_F64 || prec == CP_F32 || prec == CP_BF16))
+  if (!g || !out || max_queue < 0 || max_slots < 0 || !(prec == CP_F64 || prec == CP_F32 || prec == CP_F32F || prec == CP_BF16))
     return CP_EINVAL;
   *out = nullptr;
   cp_server* s = nullptr;
@@ -366,7 +366,7 @@ cp_status cp_server_create(const cp_graph* g, size_t hbm_budget_bytes, int32_t m
   s->g = g;
   s->prec = prec;
   // one tile row is one 128-byte line per gathered node
-  s->bw = prec == CP_F64 ? 16 : prec == CP_F32 ? 32 : 64;
+  s->bw = prec == CP_F64 ? 16 : prec == CP_BF16 ? 64 : 32;
   const size_t per_tile = a256((size_t)g->n * s->bw * storage_bytes(prec)) * 2 +
                           a256((size_t)g->n * s->bw * acc_bytes(prec)) * (g->hot_split ? 2 : 1);
   int64_t tiles = (int64_t)(hbm_budget_bytes / per_tile);

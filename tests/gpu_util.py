@@ -69,6 +69,10 @@ def oracle_exact_multi(g, metas, tail=1e-15):
 # 5.0e-3 for the longest recurrences (K near 50) of a 150K-node graph.
 F32_L1 = 1.2e-7
 BF16_L1 = 8e-3
+# FP32 storage with float sums, float partials and a float estimate
+# (CP_F32F) measures 1.7e-7 to 2.9e-7 at 150K and 4M nodes (HKPR t = 10 the
+# largest); this bar is twice the largest, and it rejects BF16-level error.
+F32F_L1 = 6e-7
 
 
 def f32_bar(K: int, kind: str = "ppr", param: float = 0.0) -> float:
@@ -79,3 +83,9 @@ def f32_bar(K: int, kind: str = "ppr", param: float = 0.0) -> float:
     K = 22 on 4M nodes)."""
     bar = F32_L1 * max(1.0, K / 30.0)
     return 2.0 * bar if kind == "hkpr" and param > 5.0 else bar
+
+
+def f32f_bar(K: int) -> float:
+    """The CP_F32F rounding bar for a recurrence of K steps (grows in
+    proportion beyond K = 30, as f32_bar)."""
+    return F32F_L1 * max(1.0, K / 30.0)
