@@ -55,6 +55,8 @@ WORKLOADS = {
     # name: (n, m, gamma, seed, kind, param, tol, sources, prec)
     "hkpr-livejournal": (4_000_000, 35_000_000, 2.3, 2, "hkpr", 5.0, 1e-6, 16, "f32"),
     "hkpr-small": (200_000, 1_750_000, 2.3, 2, "hkpr", 5.0, 1e-6, 16, "f32"),
+    # the Friendster-sized graph of the headline, one source at a time
+    "ppr-friendster": (65_000_000, 1_800_000_000, 2.1, 5, "ppr", 0.2, 1e-6, 4, "f32"),
 }
 
 BATCH_WORKLOADS = {
@@ -407,7 +409,7 @@ def run_single(args, torch, cp, synth):
     host threads and on one."""
     n_t, m_t, gamma, seed, kind, param, tol, nsrc, prec = WORKLOADS[args.workload]
     t0 = time.time()
-    g = chung_lu(synth, n_t, m_t, gamma, seed)
+    g = chung_lu(synth, n_t, m_t, gamma, seed, tune_passes=0 if n_t > 10_000_000 else 3)
     log(f"[single] graph: n={g.n} nnz={g.nnz} d_max={g.meta['d_max']} ({time.time() - t0:.1f}s)")
     t0 = time.time()
     G = cp.Graph(g.row_ptr, g.col_idx, reorder=args.layout == "degree", stripes=args.layout == "stripes")
@@ -457,7 +459,8 @@ def run_single(args, torch, cp, synth):
     R = timed_run(prec, Y, args.warmup)
     kern = "stripe_gather_kernel + stripe_combine_kernel" if args.layout == "stripes" else "step_kernel"
     out = {
-        "workload": f"{args.workload}: HKPR t={param}, {nsrc} sources one at a time, tol {tol} l1 (certified K), "
+        "workload": f"{args.workload}: {'HKPR t' if kind == 'hkpr' else 'PPR alpha'}={param}, {nsrc} sources one "
+                    f"at a time, tol {tol} l1 (certified K), "
                     f"Chung-Lu n={n_t} m={m_t} gamma={gamma} seed={seed}",
         "value": round(R["value"], 3), "unit": "GTEPS", "steps": steps,
         "ms_per_step": round(R["total_s"] * 1e3 / steps, 3),
@@ -1132,6 +1135,29 @@ def run_gather_footprint(args, torch, cp):
                         f"slice_rows rows (one gather = width x 4 bytes), K = 8", "rows": rows}
 
 
+def run_legs(args, torch, cp, synth, result) -> None:
+    """The workloads beside the headline, each into its key of result."""
+    g_main = None
+    if args.workload != "none":
+        result["single"], g_main = run_single(args, torch, cp, synth)
+    if not args.no_latency:
+        result["latency"] = run_latency(args, torch, cp, synth)
+    if g_main is not None:
+        if args.kvn_tol > 0:
+            result["cheby_vs_power"] = run_kvn(args, torch, cp, synth, g_main)
+        if args.propagate_cols > 0:
+            result["propagate"] = run_propagate(args, torch, cp, synth, g_main)
+        if args.push_eps:
+            result["push"] = run_push(args, torch, cp, synth, g_main)
+        if not args.no_push_rw:
+            result["push_rw"] = run_push_rw(args, torch, cp, synth, g_main)
+        if args.serve_seconds > 0:
+            result["served"] = run_serve(args, torch, cp, synth, g_main)
+    del g_main
+    if args.batch_workload != "none":
+        result["batched"] = run_batch(args, torch, cp, synth)
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -1214,13 +1240,7 @@ def main() -> int:
 
     if args.headline == "none":
         result = {"metric": METRIC, "n_gpus": 1, "note": "headline skipped (--headline none)"}
-        if args.workload != "none":
-            result["single"], g_main = run_single(args, torch, cp, synth)
-            if args.serve_seconds > 0:
-                result["served"] = run_serve(args, torch, cp, synth, g_main)
-            del g_main
-        if args.batch_workload != "none":
-            result["batched"] = run_batch(args, torch, cp, synth)
+        run_legs(args, torch, cp, synth, result)
         print(json.dumps(result), flush=True)
         return 0
     H = run_headline(args, torch, cp, synth)
@@ -1252,25 +1272,7 @@ def main() -> int:
         if k in H:
             result[k] = H[k]
     del H
-    g_main = None
-    if args.workload != "none":
-        result["single"], g_main = run_single(args, torch, cp, synth)
-    if not args.no_latency:
-        result["latency"] = run_latency(args, torch, cp, synth)
-    if g_main is not None:
-        if args.kvn_tol > 0:
-            result["cheby_vs_power"] = run_kvn(args, torch, cp, synth, g_main)
-        if args.propagate_cols > 0:
-            result["propagate"] = run_propagate(args, torch, cp, synth, g_main)
-        if args.push_eps:
-            result["push"] = run_push(args, torch, cp, synth, g_main)
-        if not args.no_push_rw:
-            result["push_rw"] = run_push_rw(args, torch, cp, synth, g_main)
-        if args.serve_seconds > 0:
-            result["served"] = run_serve(args, torch, cp, synth, g_main)
-    del g_main
-    if args.batch_workload != "none":
-        result["batched"] = run_batch(args, torch, cp, synth)
+    run_legs(args, torch, cp, synth, result)
     print(json.dumps(result), flush=True)
     return 0
 
