@@ -121,12 +121,33 @@ __device__ __forceinline__ void row_update_loaded(T* z, A* yacc, int64_t v, A ac
   st_stream(yacc + v, yold + c * zn);
 }
 
+// Running sum of a long chain of terms.  A float chain uses Kahan's
+// compensated summation (Kahan, 1965): the low-order part lost by each add
+// is carried into the next, so the chain's rounding does not grow with its
+// length (a hub row's stripe segment can be tens of thousands of arcs, one
+// chain of d / 256 terms per thread).  Double chains are plain sums.
+template <typename A> struct ChainSum {
+  A s = A(0);
+  __device__ __forceinline__ void add(A v) { s += v; }
+  __device__ __forceinline__ A value() const { return s; }
+};
+template <> struct ChainSum<float> {
+  float s = 0.0f, c = 0.0f;  // c: what the last add lost, with its sign
+  __device__ __forceinline__ void add(float v) {
+    const float y = v - c;
+    const float t = s + y;
+    c = (t - s) - y;
+    s = t;
+  }
+  __device__ __forceinline__ float value() const { return s - c; }
+};
+
 // Whole-workgroup gather-sum of x over arcs [p0, p1); result valid in thread 0.
 template <typename T, typename A>
 __device__ __forceinline__ A block_gather_sum(const int32_t* __restrict__ col, const T* __restrict__ x,
                                               int64_t p0, int64_t p1, A* wsum) {
   const int tid = threadIdx.x;
-  A acc = A(0);
+  ChainSum<A> chain;
   for (int64_t base = p0; base < p1; base += kTileNnz) {
     int32_t idx[kPerThread];
 #pragma unroll
@@ -138,9 +159,9 @@ __device__ __forceinline__ A block_gather_sum(const int32_t* __restrict__ col, c
 #pragma unroll
     for (int u = 0; u < kPerThread; ++u) v[u] = idx[u] >= 0 ? to_acc(x[idx[u]]) : A(0);
 #pragma unroll
-    for (int u = 0; u < kPerThread; ++u) acc += v[u];
+    for (int u = 0; u < kPerThread; ++u) chain.add(v[u]);
   }
-  acc = wave_sum(acc);
+  A acc = wave_sum(chain.value());
   if ((tid & 63) == 0) wsum[tid >> 6] = acc;
   __syncthreads();
   A total = A(0);

@@ -100,6 +100,26 @@ __device__ __forceinline__ void row_update(T* z, A* y, size_t e, A acc, int32_t 
 constexpr int kDeepGathers = 16;
 constexpr int kDeepRowsPerTile = 64;
 
+// Running sum of a long chain of terms.  A float chain uses Kahan's
+// compensated summation (Kahan, 1965), so its rounding does not grow with
+// the chain's length (a lane group's share of a hub segment is hundreds of
+// terms); double chains are plain sums.
+template <typename A> struct ChainSum {
+  A s = A(0);
+  __device__ __forceinline__ void add(A v) { s += v; }
+  __device__ __forceinline__ A value() const { return s; }
+};
+template <> struct ChainSum<float> {
+  float s = 0.0f, c = 0.0f;  // c: what the last add lost, with its sign
+  __device__ __forceinline__ void add(float v) {
+    const float y = v - c;
+    const float t = s + y;
+    c = (t - s) - y;
+    s = t;
+  }
+  __device__ __forceinline__ float value() const { return s - c; }
+};
+
 // Pairwise sum of v[0..U) (a fixed order).
 template <typename A, int U>
 __device__ __forceinline__ A tree_sum(const A* v) {
@@ -118,24 +138,24 @@ __device__ __forceinline__ A wg_row_sum(const int32_t* __restrict__ col, const T
                                         int64_t p0, int64_t p1, int grp, int lane, A (*part)[BW]) {
   constexpr int G = kThreads / BW;
   constexpr int U = DEEP ? kDeepGathers : 4;
-  A acc = A(0);
+  ChainSum<A> chain;
   int64_t p = p0 + grp;
   if constexpr (U > 4) {
     for (; p + (U - 1) * G < p1; p += U * G) {
       A v[U];
 #pragma unroll
       for (int q = 0; q < U; ++q) v[q] = to_acc(x[(size_t)col[p + q * G] * BW + lane]);
-      acc += tree_sum<A, U>(v);
+      chain.add(tree_sum<A, U>(v));
     }
   }
   for (; p + 3 * G < p1; p += 4 * G) {
     A v[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) v[q] = to_acc(x[(size_t)col[p + q * G] * BW + lane]);
-    acc += tree_sum<A, 4>(v);
+    chain.add(tree_sum<A, 4>(v));
   }
-  for (; p < p1; p += G) acc += to_acc(x[(size_t)col[p] * BW + lane]);
-  part[grp][lane] = acc;
+  for (; p < p1; p += G) chain.add(to_acc(x[(size_t)col[p] * BW + lane]));
+  part[grp][lane] = chain.value();
   __syncthreads();
   A total = A(0);
   if (grp == 0) {

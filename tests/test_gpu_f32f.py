@@ -95,6 +95,41 @@ def test_batch_columns(torch, mid_graph, hot_split, monkeypatch):
             assert m["l1"] <= f32f_bar(Ks[j]), (bw, j, Ks[j], m)
 
 
+def test_hub_rows(torch):
+    """A 40,000-arc hub row (split into segments whose float partials the
+    last workgroup adds) on the single CSR, the XCD stripes and in a batch;
+    against Alg. 3 in FP64 at the same K."""
+    leaves = 40_000
+    base = synth.erdos_renyi(1_500, 0.005, seed=9)
+    e = [(0, i) for i in range(1, leaves + 1)]
+    rows = np.repeat(np.arange(base.n), base.degrees)
+    e += [(int(a) + 1, int(b) + 1) for a, b in zip(rows, base.col_idx) if a < b]
+    g = synth.from_edges(leaves + 1, e, name="hub")
+    P = PR.transition_matrix(g.row_ptr, g.col_idx)
+    from paper_2412_10789_amd import chebyprop as cp
+
+    srcs = [0, 3, leaves, 1200]
+    for stripes in (False, True):
+        G = gpu_graph(g, stripes=stripes)
+        if not stripes:
+            assert G.stats["hub_rows"] > 0
+        for s in srcs:
+            _case("f32f hub single", stripes, s)
+            r = G.power("hkpr", 3.0, s, tol=1e-7, prec="f32f")
+            ref = oracle_yK(g, s, "hkpr", 3.0, r.info["K"], P)
+            assert compare(r.y.double().cpu().numpy(), ref)["l1"] <= f32f_bar(r.info["K"]), (stripes, s)
+        G.close()
+    G = gpu_graph(g)
+    qs = [cp.make_query("ppr", 0.2, s, 1e-7) for s in srcs]
+    _case("f32f hub batch")
+    Y, infos = G.power_batch(qs, prec="f32f")
+    Y = Y.double().cpu().numpy()
+    for j, s in enumerate(srcs):
+        ref = oracle_yK(g, s, "ppr", 0.2, infos[j]["K"], P)
+        assert compare(Y[:, j], ref)["l1"] <= f32f_bar(infos[j]["K"]), s
+    G.close()
+
+
 def test_server(torch, mid_graph):
     """Served CP_F32F queries (batched launches and the idle server's
     single-source path) against Alg. 3 in FP64 at their K."""

@@ -1,7 +1,8 @@
 """cp_power_noalloc (the workspace is the library's static device array)
 against cp_power (caller workspace), through the C ABI: bitwise equal
 results on two calls in a row, the second on a smaller graph, for the
-single-CSR and XCD-striped layouts in FP64, FP32 and BF16; a graph whose
+single-CSR and XCD-striped layouts in FP64, FP32 (double and float
+arithmetic) and BF16; a graph whose
 workspace exceeds the array is refused with CP_EWORKSPACE, and CP_Q_TIMING
 with CP_EINVAL."""
 
@@ -30,7 +31,7 @@ def test_noalloc_equals_power_on_two_calls_second_smaller(torch, stripes):
     big = synth.chung_lu(300_000, 3_000_000, 2.1, seed=41)
     small = synth.chung_lu(20_000, 100_000, 2.5, seed=1)
     Gb, Gs = gpu_graph(big, stripes=stripes), gpu_graph(small, stripes=stripes)
-    for prec in ("f64", "f32", "bf16"):
+    for prec in ("f64", "f32", "f32f", "bf16"):
         for g, G, s, kind, param in ((big, Gb, int(synth.sources(big, 1, seed=2)[0]), "hkpr", 5.0),
                                      (small, Gs, int(synth.sources(small, 1, seed=3)[0]), "ppr", 0.2)):
             _case("noalloc", stripes, prec, g.n, kind, s)
