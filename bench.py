@@ -20,7 +20,10 @@ Beside it:
              200 queries/s after a 5-s warm-up, and 50 queries/s), the
              batched server against plain one-query-at-a-time runs;
   and the PwMethod, feature-matrix, ChebyPush and small-graph latency
-  measurements.
+  measurements.  The headline and "single" also time their workload with
+  BF16 storage ("storage_bf16") and with FP32 arithmetic ("arith_f32",
+  CP_F32F: float sums, partials and estimate); the FP32 runs themselves
+  store float vectors and compute in double.
 
 Prints one JSON line: GTEPS (CSR arcs traversed per second, summed over
 sources), the roofline of the dominant kernel against MI355X's 8 TB/s HBM
@@ -1165,7 +1168,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=2, help="untimed headline batches before them")
     ap.add_argument("--headline", default="ppr-batch-friendster", choices=sorted(HEADLINES) + ["none"],
                     help="the headline workload (none: only the other legs, e.g. for profiler runs)")
-    ap.add_argument("--bf16-steps", type=int, default=3, help="timed batches of the headline's BF16 variant")
+    ap.add_argument("--bf16-steps", type=int, default=3,
+                    help="timed batches of each of the headline's variants (BF16 storage, FP32 arithmetic)")
     ap.add_argument("--no-hot-split", action="store_true",
                     help="run the headline's batched steps without the hot/cold split (CP_GRAPH_HOT_SPLIT)")
     ap.add_argument("--workload", default="hkpr-livejournal", choices=sorted(WORKLOADS) + ["none"],
