@@ -558,7 +558,8 @@ def run_batch(args, torch, cp, synth):
     t0 = time.time()
     g = chung_lu(synth, n_t, m_t, gamma, seed)
     log(f"[batch] graph: n={g.n} nnz={g.nnz} d_max={g.meta['d_max']} ({time.time() - t0:.1f}s)")
-    G = cp.Graph(g.row_ptr, g.col_idx, reorder=args.layout != "native")
+    G = cp.Graph(g.row_ptr, g.col_idx, reorder=args.layout != "native" or args.batch_hot_split,
+                 hot_split=args.batch_hot_split)
     srcs = [int(s) for s in synth.sources(g, nq, seed=seed)]
     tols = [float(t) for t in synth.tolerance_choice(seed, nq, tol_choices)]
     qs = [cp.make_query("ppr", alpha, s, t) for s, t in zip(srcs, tols)]
@@ -594,12 +595,15 @@ def run_batch(args, torch, cp, synth):
     R = timed_batches(prec, Yb)
     out = {
         "workload": f"{args.batch_workload}: {nq} PPR alpha={alpha} sources in one batch, tol per source from "
-                    f"{list(tol_choices)} (certified K), Chung-Lu n={n_t} m={m_t} gamma={gamma} seed={seed}",
+                    f"{list(tol_choices)} (certified K), Chung-Lu n={n_t} m={m_t} gamma={gamma} seed={seed}"
+                    + (f", hot/cold split ({G.stats['hot_nodes']} hot nodes, "
+                       f"{G.stats['hot_arcs'] / g.nnz:.3f} of the arcs)" if args.batch_hot_split else ""),
         "value": round(R["arcs"] / R["total_s"] / 1e9, 3), "unit": "GTEPS",
         "ms_per_batch": round(R["total_s"] * 1e3 / nb, 3), "batches": nb,
         "n": g.n, "nnz": g.nnz, "source_tile_width": bw, "K_min": min(R["Ks"]), "K_max": max(R["Ks"]),
         "roofline": roofline(R["bytes_per_launch"], R["avg_launch_ms"], f"batch_step_kernel (width {bw})",
-                             traffic=measured_traffic(f"{args.batch_workload}:batch", BATCH_SOURCES),
+                             traffic=None if args.batch_hot_split else
+                             measured_traffic(f"{args.batch_workload}:batch", BATCH_SOURCES),
                              implementation_bytes_per_launch=int(R["impl_bytes_per_launch"]),
                              launches_timed=R["launches"]),
     }
@@ -1170,6 +1174,8 @@ def main() -> int:
                     help="the headline workload (none: only the other legs, e.g. for profiler runs)")
     ap.add_argument("--bf16-steps", type=int, default=3,
                     help="timed batches of each of the headline's variants (BF16 storage, FP32 arithmetic)")
+    ap.add_argument("--batch-hot-split", action="store_true",
+                    help="run the batched workload on the hot/cold split too (hot nodes: CHEBYPROP_HOT_NODES)")
     ap.add_argument("--no-hot-split", action="store_true",
                     help="run the headline's batched steps without the hot/cold split (CP_GRAPH_HOT_SPLIT)")
     ap.add_argument("--workload", default="hkpr-livejournal", choices=sorted(WORKLOADS) + ["none"],
