@@ -434,7 +434,7 @@ typedef struct {
  * g: the graph every query runs on; it must outlive the server.
  * hbm_budget_bytes: HBM the server may use for query state (>= one slot).
  * max_slots: upper bound on resident queries (0: as many as the budget
- * allows, at most 1024).  max_queue: waiting-queue capacity.  prec: CP_F32 /
+ * allows, at most 1024).  max_queue: waiting-queue capacity.  prec: CP_F32 / CP_F32F /
  * CP_F64 / CP_BF16 for all slots.  Errors: CP_EINVAL, CP_ENOMEM (budget below
  * one slot or allocation failure), CP_EHIP.  Besides the slots, the server
  * holds one cp_power workspace in HBM. */
