@@ -134,6 +134,7 @@ class cp_server_stats(ctypes.Structure):
         ("waiters", ctypes.c_int32),
         ("direct_limit", ctypes.c_int32),
         ("direct", ctypes.c_int64),
+        ("narrow_ticks", ctypes.c_int64),
     ]
 
 

@@ -133,10 +133,10 @@ __device__ __forceinline__ A tree_sum(const A* v) {
 // Sum over arcs [p0, p1) of x[col[p]][lane]; the workgroup's lane groups
 // take interleaved arcs, partial sums are combined in group order.
 // Result valid in group 0.
-template <typename T, typename A, int BW, bool DEEP>
+template <typename T, typename A, int BW, int NL, bool DEEP>
 __device__ __forceinline__ A wg_row_sum(const int32_t* __restrict__ col, const T* __restrict__ x,
-                                        int64_t p0, int64_t p1, int grp, int lane, A (*part)[BW]) {
-  constexpr int G = kThreads / BW;
+                                        int64_t p0, int64_t p1, int grp, int lane, A (*part)[NL]) {
+  constexpr int G = kThreads / NL;
   constexpr int U = DEEP ? kDeepGathers : 4;
   ChainSum<A> chain;
   int64_t p = p0 + grp;
@@ -164,17 +164,19 @@ __device__ __forceinline__ A wg_row_sum(const int32_t* __restrict__ col, const T
   return total;
 }
 
-template <typename T, int BW, bool DEEP>
+// NL: lanes per group, one per slot the launch updates; NL = BW except in a
+// narrow launch (kNarrowLanes lanes over rows BW apart).
+template <typename T, int BW, bool DEEP, int NL = BW>
 __global__ void __launch_bounds__(kThreads) batch_step_kernel(BatchStepArgs a) {
   using A = typename Acc<T>::type;
-  constexpr int G = kThreads / BW;
+  constexpr int G = kThreads / NL;
   __shared__ int32_t cols[kTileNnz];
   __shared__ int32_t rpl[kTileRows + 1];
   __shared__ int32_t dgl[kTileRows];
-  __shared__ A part[G][BW];
+  __shared__ A part[G][NL];
   __shared__ int32_t last_flag;
 
-  const int tid = threadIdx.x, grp = tid / BW, lane = tid % BW;
+  const int tid = threadIdx.x, grp = tid / NL, lane = tid % NL;
   const int tile = blockIdx.y;
   const size_t toff = (size_t)tile * (size_t)a.n * BW;
   const T* __restrict__ x = static_cast<const T*>(a.x) + toff;
@@ -233,7 +235,7 @@ __global__ void __launch_bounds__(kThreads) batch_step_kernel(BatchStepArgs a) {
       A acc = A(0);
       int p = pb;
       // shallow form with one lane group per wavefront (bw 64): chunks of 8
-      constexpr int U = DEEP ? kDeepGathers : BW >= 64 ? 8 : 4;
+      constexpr int U = DEEP ? kDeepGathers : NL >= 64 ? 8 : 4;
       if constexpr (U > 4) {
         for (; p + U <= pe; p += U) {
           A v[U];
@@ -257,7 +259,7 @@ __global__ void __launch_bounds__(kThreads) batch_step_kernel(BatchStepArgs a) {
   if (bd.kind == kLong) {
     const int64_t v = bd.r0;
     const int64_t p0 = rp[v], p1 = rp[v + 1];
-    const A total = wg_row_sum<T, A, BW, DEEP>(col, x, p0, p1, grp, lane, part);
+    const A total = wg_row_sum<T, A, BW, NL, DEEP>(col, x, p0, p1, grp, lane, part);
     if (grp == 0) finish_row(v, total, (int32_t)(drp[v + 1] - drp[v]));
     return;
   }
@@ -267,7 +269,7 @@ __global__ void __launch_bounds__(kThreads) batch_step_kernel(BatchStepArgs a) {
   const int64_t rb = rp[h.row], re = rp[h.row + 1];
   const int64_t p0 = rb + (int64_t)bd.aux * h.seg;
   const int64_t p1 = p0 + h.seg < re ? p0 + h.seg : re;
-  const A total = wg_row_sum<T, A, BW, DEEP>(col, x, p0, p1, grp, lane, part);
+  const A total = wg_row_sum<T, A, BW, NL, DEEP>(col, x, p0, p1, grp, lane, part);
   A* hp = static_cast<A*>(a.hub_partial);
   const int slot = tile * BW + lane;
   if (grp == 0) {
@@ -414,6 +416,16 @@ hipError_t launch_bs(const BatchStepArgs& a, hipStream_t st) {
   // rows a tile on average means rows of more than kTileNnz / kDeepRowsPerTile arcs
   const int64_t nstream = a.nblocks - a.nspecial;
   const bool deep = nstream > 0 && a.n < kDeepRowsPerTile * nstream;
+  if (a.lanes == kNarrowLanes && a.bw > kNarrowLanes) {
+    if (a.ntiles != 1) return hipErrorInvalidValue;
+    switch (a.bw) {
+      case 16: hipLaunchKernelGGL((batch_step_kernel<T, 16, false, kNarrowLanes>), grid, block, 0, st, a); break;
+      case 32: hipLaunchKernelGGL((batch_step_kernel<T, 32, false, kNarrowLanes>), grid, block, 0, st, a); break;
+      case 64: hipLaunchKernelGGL((batch_step_kernel<T, 64, false, kNarrowLanes>), grid, block, 0, st, a); break;
+      default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+  }
   switch (a.bw) {
     case 8: hipLaunchKernelGGL((batch_step_kernel<T, 8, false>), grid, block, 0, st, a); break;
     case 16: hipLaunchKernelGGL((batch_step_kernel<T, 16, false>), grid, block, 0, st, a); break;

@@ -32,11 +32,12 @@ using Clock = std::chrono::steady_clock;
 // An idle server with q waiting queries can run them one by one on the
 // single-source path, the last one done after about q K t_s, or admit them
 // all to one batched tile, all done after about K t_b (t_s, t_b: the time
-// of a single-source step and of a one-tile batched step, which costs the
-// same whatever number of its slots is active).  One by one wins while
-// q <= t_b / t_s: the worker keeps running means of both times and applies
-// that limit (4.4 on a 4M-node graph: 0.4 against 1.75 ms).  Until both are
-// measured, the limit is kDirectQueue.
+// of a single-source step and of a one-tile batched step; a few queries
+// sit in the first slots, whose narrow launch costs 1.1 ms on a 4M-node
+// graph against 1.75 ms for a whole 32-wide tile and 0.4 ms for a
+// single-source step).  One by one wins while q <= t_b / t_s: the worker
+// keeps running means of both times and applies that limit.  Until both
+// are measured, the limit is kDirectQueue.
 constexpr size_t kDirectQueue = 3;
 constexpr size_t kDirectQueueMax = 16;
 constexpr double kMeanWeight = 0.125;  // weight of a new sample in the running means
@@ -87,7 +88,7 @@ struct cp_server {
   std::vector<int32_t> slot_k;        // current k of the slot's query
   uint64_t next_ticket = 1;
   int parity = 0;
-  int64_t completed = 0, cancelled = 0, ticks = 0;
+  int64_t completed = 0, cancelled = 0, ticks = 0, narrow_ticks = 0;
   std::thread worker;
 
   void run();
@@ -267,6 +268,7 @@ void cp_server::run() {
     // ---- GPU work for this step boundary (no lock held)
     const Clock::time_point t0 = Clock::now();
     int32_t step_tiles = 0;
+    bool narrow = false;
     hipError_t e = hipSuccess;
     char* w = dev;
     void* xbuf = w + (parity ? o_rA : o_rB);  // gathered this launch (holds r~_k)
@@ -286,6 +288,11 @@ void cp_server::run() {
       int32_t tiles = 0;
       for (int32_t s : stepping) tiles = std::max(tiles, s / bw + 1);
       step_tiles = tiles;
+      // only the first kNarrowLanes slots step (admission takes the lowest free
+      // slots, so a lightly loaded server keeps its queries there): a narrow
+      // launch gathers kNarrowLanes values of each row instead of bw
+      narrow = bw > kNarrowLanes &&
+               std::all_of(stepping.begin(), stepping.end(), [](int32_t s) { return s < kNarrowLanes; });
       chk(launch_upload(w + o_coef, coef_row.data(), nslot * sizeof(double), st));
       BatchStepArgs sa{};
       set_batch_plan(g, sa, w + o_part);
@@ -301,6 +308,7 @@ void cp_server::run() {
       sa.hub_partial = w + o_hpart;
       sa.hub_count = reinterpret_cast<int32_t*>(w + o_hcount);
       sa.ntiles_total = ntiles;
+      sa.lanes = narrow ? kNarrowLanes : 0;
       chk(launch_batch_step(prec, sa, st));
     }
     if (!fin_slots.empty()) {
@@ -328,6 +336,7 @@ void cp_server::run() {
       if (!stepping.empty()) {
         parity ^= 1;
         ++ticks;
+        narrow_ticks += narrow ? 1 : 0;
         for (int32_t s : stepping) ++slot_k[s];
       }
       if (step_tiles == 1 && admitted.empty() && fin_slots.empty()) {  // a plain one-tile step
@@ -528,6 +537,7 @@ cp_status cp_server_get_stats(cp_server* s, cp_server_stats* out) {
                 (s->direct_ticket ? 1 : 0);
   out->direct = s->direct;
   out->direct_limit = (int32_t)s->direct_limit;
+  out->narrow_ticks = s->narrow_ticks;
   out->queued = (int64_t)s->queue.size();
   out->completed = s->completed;
   out->cancelled = s->cancelled;

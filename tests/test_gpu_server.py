@@ -7,7 +7,7 @@ import numpy as np
 import pytest
 
 import synth
-from gpu_util import F32_L1, compare, f32_bar, gpu_graph, oracle_exact_multi, oracle_yK_multi, require_gpu  # noqa: F401
+from gpu_util import F32_L1, compare, f32_bar, f32f_bar, gpu_graph, oracle_exact_multi, oracle_yK_multi, require_gpu  # noqa: F401
 from oracle import errors as E
 
 pytestmark = pytest.mark.gpu
@@ -249,4 +249,46 @@ def test_idle_server_runs_single_source_path(torch, graph):
     stats = S.stats()
     assert stats["completed"] == 30 and stats["ticks"] > 0 and stats["direct"] < 30
     assert 1 <= stats["direct_limit"] <= 16
+    S.close()
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "f32f"])
+def test_narrow_launches_of_the_first_slots(torch, graph, prec):
+    """A few queries arriving together take the first slots, so the batched
+    launches update only those (narrow launches of the first tile); their
+    results equal single-source runs (FP64) or the FP64 oracle at the same K
+    (float storage), and a larger burst runs whole-tile launches too."""
+    from paper_2412_10789_amd import chebyprop as cp
+
+    g = graph
+    G = gpu_graph(g, stripes=True)
+    S = cp.Server(G, hbm_budget_bytes=1 << 30, max_slots=64, prec=prec)
+    dt = torch.float64 if prec == "f64" else torch.float32
+    for nq in (6, 20):
+        qs = _mixed_queries(g, nq, seed=50 + nq)
+        ys = [torch.empty(g.n, dtype=dt, device="cuda") for _ in qs]
+        before = S.stats()
+        print("CASE server narrow", prec, nq, flush=True)
+        got = [S.wait(t, timeout_ms=60_000) for t in [S.submit(q, y) for q, y in zip(qs, ys)]]
+        assert all(st == cp.CP_OK for st, _ in got)
+        st = S.stats()
+        narrow, ticks = st["narrow_ticks"] - before["narrow_ticks"], st["ticks"] - before["ticks"]
+        if nq == 6:
+            assert narrow > 0 and narrow == ticks, (narrow, ticks)
+        else:
+            assert ticks > narrow, (narrow, ticks)
+        metas = [("hkpr" if q.kind == 1 else "ppr", q.param, q.source) for q in qs]
+        Ks = [info["K"] for _, info in got]
+        if prec == "f64":
+            for q, y, (_, info) in zip(qs, ys, got):
+                r = G.power("hkpr" if q.kind == 1 else "ppr", q.param, q.source, tol=q.tol, prec="f64")
+                assert r.info["K"] == info["K"]
+                np.testing.assert_allclose(y.cpu().numpy(), r.y.cpu().numpy(), atol=1e-14, rtol=1e-12)
+        else:
+            ref = oracle_yK_multi(g, metas, Ks)
+            bar = f32f_bar if prec == "f32f" else (lambda K, kind, param: f32_bar(K, kind, param))
+            for j, y in enumerate(ys):
+                m = compare(y.double().cpu().numpy(), ref[:, j])
+                b = bar(Ks[j]) if prec == "f32f" else bar(Ks[j], metas[j][0], metas[j][1])
+                assert m["l1"] <= b, (prec, nq, j, Ks[j], m)
     S.close()
