@@ -743,6 +743,7 @@ def run_serve(args, torch, cp, synth, g):
         st = S.stats()
         return _lat_summary(lat, span, {"offered_qps": rate, "arrivals_counted": sum(1 for x in tr if x[0] >= warm),
                                         "batched_launches": st["ticks"] - st0["ticks"],
+                                        "narrow_launches": st["narrow_ticks"] - st0["narrow_ticks"],
                                         "single_source_path": st["direct"] - st0["direct"],
                                         "single_source_queue_limit": st["direct_limit"], "slots": st["slots"],
                                         "tile_width": st["tile_width"],
