@@ -434,7 +434,7 @@ typedef struct {
  * the two paths differ only in the order of sums.  Queries take the lowest
  * free slots, and while only the first 8 slots hold stepping queries a
  * batched launch updates just those (8 values of each tile row gathered
- * instead of a whole row: 1.1 instead of 1.75 ms a step on a 4M-node
+ * instead of a whole row: 1.3 instead of 1.75 ms a step on a 4M-node
  * graph in FP32).
  * g: the graph every query runs on; it must outlive the server.
  * hbm_budget_bytes: HBM the server may use for query state (>= one slot).

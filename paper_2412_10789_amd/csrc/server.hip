@@ -33,7 +33,7 @@ using Clock = std::chrono::steady_clock;
 // single-source path, the last one done after about q K t_s, or admit them
 // all to one batched tile, all done after about K t_b (t_s, t_b: the time
 // of a single-source step and of a one-tile batched step; a few queries
-// sit in the first slots, whose narrow launch costs 1.1 ms on a 4M-node
+// sit in the first slots, whose narrow launch costs 1.3 ms on a 4M-node
 // graph against 1.75 ms for a whole 32-wide tile and 0.4 ms for a
 // single-source step).  One by one wins while q <= t_b / t_s: the worker
 // keeps running means of both times and applies that limit.  Until both
