@@ -420,7 +420,7 @@ typedef struct {
   int32_t waiters;      /* threads blocked in cp_server_wait */
   int32_t direct_limit; /* longest queue an idle server runs one by one (see below) */
   int64_t direct;       /* queries run on the single-source path (see below) */
-  int64_t narrow_ticks; /* batched launches that updated only the first 8 slots (see below) */
+  int64_t narrow_ticks; /* batched launches that updated only the first 8 or 16 slots (see below) */
 } cp_server_stats;
 
 /* While no query is resident and at most direct_limit wait, the server runs
@@ -432,10 +432,10 @@ typedef struct {
  * (t_b) and of a single-source query per Chebyshev step (t_s): q queries
  * one by one take about q K t_s, one batched tile about K t_b.  Results of
  * the two paths differ only in the order of sums.  Queries take the lowest
- * free slots, and while only the first 8 slots hold stepping queries a
- * batched launch updates just those (8 values of each tile row gathered
- * instead of a whole row: 1.3 instead of 1.75 ms a step on a 4M-node
- * graph in FP32).
+ * free slots, and while only the first 8 (or 16) slots hold stepping
+ * queries a batched launch updates just those (8 or 16 values of each tile
+ * row gathered instead of a whole row: 1.3 instead of 1.75 ms a step with 8
+ * on a 4M-node graph in FP32).
  * g: the graph every query runs on; it must outlive the server.
  * hbm_budget_bytes: HBM the server may use for query state (>= one slot).
  * max_slots: upper bound on resident queries (0: as many as the budget

@@ -277,13 +277,13 @@ struct BatchStepArgs {
   int32_t* hub_count;    // int32[nhubs][ntiles_total]
   int32_t ntiles_total;
   int32_t mode;          // kBatchForward, kClenshawStep or kClenshawLast
-  int32_t lanes;         // 0: every slot of the launched tiles; kNarrowLanes: only the first
-                         // kNarrowLanes slots of tile 0 (the others hold no query)
+  int32_t lanes;         // 0: every slot of the launched tiles; one of kNarrowLanes below bw:
+                         // only the first `lanes` slots of tile 0 (the others hold no query)
 };
-// Slots a narrow launch of a wider tile updates: rows are still bw apart,
-// but the lane groups are kNarrowLanes wide and gather kNarrowLanes * s
-// bytes of each row.
-constexpr int32_t kNarrowLanes = 8;
+// Slot counts a narrow launch of a wider tile can update: rows are still bw
+// apart, but the lane groups are `lanes` wide and gather lanes * s bytes of
+// each row.
+constexpr int32_t kNarrowLanes[2] = {8, 16};
 // Row update of a batched step.  Forward (Alg. 3 / Alg. 1): z = u acc / d -
 // (u - 1) z and yacc += c z.  Clenshaw's backward form of the same series,
 // with yacc holding the start vector x~: a step writes b_k = c x~ + u acc / d

@@ -165,7 +165,7 @@ __device__ __forceinline__ A wg_row_sum(const int32_t* __restrict__ col, const T
 }
 
 // NL: lanes per group, one per slot the launch updates; NL = BW except in a
-// narrow launch (kNarrowLanes lanes over rows BW apart).
+// narrow launch (8 or 16 lanes over rows BW apart).
 template <typename T, int BW, bool DEEP, int NL = BW>
 __global__ void __launch_bounds__(kThreads) batch_step_kernel(BatchStepArgs a) {
   using A = typename Acc<T>::type;
@@ -416,12 +416,14 @@ hipError_t launch_bs(const BatchStepArgs& a, hipStream_t st) {
   // rows a tile on average means rows of more than kTileNnz / kDeepRowsPerTile arcs
   const int64_t nstream = a.nblocks - a.nspecial;
   const bool deep = nstream > 0 && a.n < kDeepRowsPerTile * nstream;
-  if (a.lanes == kNarrowLanes && a.bw > kNarrowLanes) {
+  if (a.lanes != 0 && a.lanes < a.bw) {
     if (a.ntiles != 1) return hipErrorInvalidValue;
-    switch (a.bw) {
-      case 16: hipLaunchKernelGGL((batch_step_kernel<T, 16, false, kNarrowLanes>), grid, block, 0, st, a); break;
-      case 32: hipLaunchKernelGGL((batch_step_kernel<T, 32, false, kNarrowLanes>), grid, block, 0, st, a); break;
-      case 64: hipLaunchKernelGGL((batch_step_kernel<T, 64, false, kNarrowLanes>), grid, block, 0, st, a); break;
+    switch (a.lanes * 1000 + a.bw) {
+      case 8016: hipLaunchKernelGGL((batch_step_kernel<T, 16, false, 8>), grid, block, 0, st, a); break;
+      case 8032: hipLaunchKernelGGL((batch_step_kernel<T, 32, false, 8>), grid, block, 0, st, a); break;
+      case 8064: hipLaunchKernelGGL((batch_step_kernel<T, 64, false, 8>), grid, block, 0, st, a); break;
+      case 16032: hipLaunchKernelGGL((batch_step_kernel<T, 32, false, 16>), grid, block, 0, st, a); break;
+      case 16064: hipLaunchKernelGGL((batch_step_kernel<T, 64, false, 16>), grid, block, 0, st, a); break;
       default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

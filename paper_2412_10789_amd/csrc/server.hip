@@ -267,7 +267,7 @@ void cp_server::run() {
 
     // ---- GPU work for this step boundary (no lock held)
     const Clock::time_point t0 = Clock::now();
-    int32_t step_tiles = 0;
+    int32_t step_tiles = 0, lanes = 0;
     bool narrow = false;
     hipError_t e = hipSuccess;
     char* w = dev;
@@ -288,11 +288,13 @@ void cp_server::run() {
       int32_t tiles = 0;
       for (int32_t s : stepping) tiles = std::max(tiles, s / bw + 1);
       step_tiles = tiles;
-      // only the first kNarrowLanes slots step (admission takes the lowest free
+      // only the first 8 or 16 slots step (admission takes the lowest free
       // slots, so a lightly loaded server keeps its queries there): a narrow
-      // launch gathers kNarrowLanes values of each row instead of bw
-      narrow = bw > kNarrowLanes &&
-               std::all_of(stepping.begin(), stepping.end(), [](int32_t s) { return s < kNarrowLanes; });
+      // launch gathers that many values of each row instead of bw
+      const int32_t top_slot = *std::max_element(stepping.begin(), stepping.end());
+      for (int32_t l : kNarrowLanes)
+        if (!lanes && l < bw && top_slot < l) lanes = l;
+      narrow = lanes != 0;
       chk(launch_upload(w + o_coef, coef_row.data(), nslot * sizeof(double), st));
       BatchStepArgs sa{};
       set_batch_plan(g, sa, w + o_part);
@@ -308,7 +310,7 @@ void cp_server::run() {
       sa.hub_partial = w + o_hpart;
       sa.hub_count = reinterpret_cast<int32_t*>(w + o_hcount);
       sa.ntiles_total = ntiles;
-      sa.lanes = narrow ? kNarrowLanes : 0;
+      sa.lanes = lanes;
       chk(launch_batch_step(prec, sa, st));
     }
     if (!fin_slots.empty()) {

@@ -255,16 +255,18 @@ def test_idle_server_runs_single_source_path(torch, graph):
 @pytest.mark.parametrize("prec", ["f64", "f32", "f32f"])
 def test_narrow_launches_of_the_first_slots(torch, graph, prec):
     """A few queries arriving together take the first slots, so the batched
-    launches update only those (narrow launches of the first tile); their
-    results equal single-source runs (FP64) or the FP64 oracle at the same K
-    (float storage), and a larger burst runs whole-tile launches too."""
+    launches update only those (narrow launches of 8 or 16 lanes over the
+    first tile); their results equal single-source runs (FP64) or the FP64
+    oracle at the same K (float storage), and a larger burst runs whole-tile
+    launches too."""
     from paper_2412_10789_amd import chebyprop as cp
 
     g = graph
     G = gpu_graph(g, stripes=True)
     S = cp.Server(G, hbm_budget_bytes=1 << 30, max_slots=64, prec=prec)
     dt = torch.float64 if prec == "f64" else torch.float32
-    for nq in (6, 20):
+    bw = S.stats()["tile_width"]
+    for nq in (6, 12, 40):
         qs = _mixed_queries(g, nq, seed=50 + nq)
         ys = [torch.empty(g.n, dtype=dt, device="cuda") for _ in qs]
         before = S.stats()
@@ -273,10 +275,10 @@ def test_narrow_launches_of_the_first_slots(torch, graph, prec):
         assert all(st == cp.CP_OK for st, _ in got)
         st = S.stats()
         narrow, ticks = st["narrow_ticks"] - before["narrow_ticks"], st["ticks"] - before["ticks"]
-        if nq == 6:
-            assert narrow > 0 and narrow == ticks, (narrow, ticks)
+        if nq == 6 or (nq == 12 and bw > 16):
+            assert narrow > 0 and narrow == ticks, (nq, narrow, ticks)
         else:
-            assert ticks > narrow, (narrow, ticks)
+            assert ticks > narrow, (nq, narrow, ticks)
         metas = [("hkpr" if q.kind == 1 else "ppr", q.param, q.source) for q in qs]
         Ks = [info["K"] for _, info in got]
         if prec == "f64":
